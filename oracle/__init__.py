@@ -1,0 +1,290 @@
+"""FP64 CPU oracle for the volume-rendering path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never links,
+loads or calls it, and it shares no code with the GPU path.
+
+The arithmetic lives in ``dpvr_oracle.c`` (plain C, float64, OpenMP over
+pixels); this module compiles it with gcc and marshals numpy arrays through
+ctypes.  The one piece of arithmetic written here is :func:`fold_ghost_grad`,
+the chain rule through ghost-layer extraction (a ghost voxel is a copy of a
+global voxel, so its gradient adds to that voxel's).
+
+Conventions (readings of a paper that states no rendering mathematics; each
+is listed in the design notes): cell-centred voxels in half-open owned boxes
+with a one-voxel ghost layer; samples at t_k = (k + 1/2) dt from the ray
+origin, owned by the brick whose box holds the sample point; 256-entry
+endpoint-aligned piecewise-linear transfer function; emission-absorption
+accumulation front to back; depth key = t of a brick's first owned sample;
+sort-last "over" compositing by ascending key, then the background.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dpvr_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (float64, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Camera(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("pad_", C.c_int32), ("eye", C.c_double * 3), ("target", C.c_double * 3),
+                ("dir", C.c_double * 3), ("up", C.c_double * 3), ("fovy_deg", C.c_double),
+                ("view_height", C.c_double)]
+
+
+class _Brick(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("ghost", C.c_int32), ("origin", C.c_double * 3),
+                ("spacing", C.c_double * 3), ("vox", C.c_void_p), ("vox_f64", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+class _TF(C.Structure):
+    _fields_ = [("table", C.POINTER(C.c_double)), ("n", C.c_int32), ("pad_", C.c_int32),
+                ("vmin", C.c_double), ("vmax", C.c_double), ("opacity_scale", C.c_double)]
+
+
+_dp = C.POINTER(C.c_double)
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = C.CDLL(_LIB)
+            lib.oc_ray.argtypes = [C.POINTER(_Camera), C.c_int32, C.c_int32, _dp, _dp]
+            lib.oc_render_brick.argtypes = [C.POINTER(_Camera), C.POINTER(_Brick), C.POINTER(_TF),
+                                            C.c_double, C.c_double, C.POINTER(C.c_int32),
+                                            C.c_int64, _dp, _dp, C.POINTER(C.c_int64)]
+            lib.oc_composite.argtypes = [C.c_int32, C.POINTER(_dp), C.POINTER(_dp), C.c_int64,
+                                         _dp, _dp]
+            lib.oc_composite.restype = C.c_int
+            lib.oc_composite_grad.argtypes = [C.c_int32, C.POINTER(_dp), C.POINTER(_dp),
+                                              C.c_int64, _dp, _dp, C.POINTER(_dp)]
+            lib.oc_composite_grad.restype = C.c_int
+            lib.oc_render_brick_grad.argtypes = [C.POINTER(_Camera), C.POINTER(_Brick),
+                                                 C.POINTER(_TF), C.c_double, _dp, _dp, _dp]
+            lib.oc_render_brick_grad.restype = C.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _camera(cam: dict) -> _Camera:
+    c = _Camera()
+    kind = cam.get("kind", "perspective")
+    c.kind = 0 if kind == "perspective" else 1
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.eye[:] = [float(v) for v in cam["eye"]]
+    c.target[:] = [float(v) for v in cam.get("target", (0.0, 0.0, 0.0))]
+    c.dir[:] = [float(v) for v in cam.get("dir", (0.0, 0.0, 1.0))]
+    c.up[:] = [float(v) for v in cam["up"]]
+    c.fovy_deg = float(cam.get("fovy_deg", 45.0))
+    c.view_height = float(cam.get("view_height", 1.0))
+    return c
+
+
+class _BrickRef:
+    """Keeps the numpy buffer alive next to its ctypes struct."""
+
+    def __init__(self, vox, dims, ghost, origin, spacing):
+        f64 = np.asarray(vox).dtype == np.float64
+        self.vox = np.ascontiguousarray(vox, dtype=np.float64 if f64 else np.float32)
+        g = int(ghost)
+        nx, ny, nz = (int(d) for d in dims)
+        if self.vox.shape != (nz + 2 * g, ny + 2 * g, nx + 2 * g):
+            raise ValueError(f"voxel array shape {self.vox.shape} does not match dims {dims} ghost {g}")
+        s = _Brick()
+        s.dims[:] = [nx, ny, nz]
+        s.ghost = g
+        s.origin[:] = [float(v) for v in origin]
+        s.spacing[:] = [float(v) for v in spacing]
+        s.vox = self.vox.ctypes.data
+        s.vox_f64 = 1 if f64 else 0
+        self.s = s
+
+
+class _TFRef:
+    def __init__(self, table, vrange, opacity_scale):
+        self.table = np.ascontiguousarray(table, dtype=np.float64)
+        if self.table.ndim != 2 or self.table.shape[1] != 4 or self.table.shape[0] < 2:
+            raise ValueError("transfer function must be (n >= 2, 4)")
+        s = _TF()
+        s.table = _ptr(self.table, C.c_double)
+        s.n = self.table.shape[0]
+        s.vmin, s.vmax = float(vrange[0]), float(vrange[1])
+        s.opacity_scale = float(opacity_scale)
+        self.s = s
+
+
+def ray(cam: dict, i: int, j: int):
+    """Origin and unit direction (float64) of the ray through pixel (i, j)."""
+    lib = _load()
+    o = np.zeros(3)
+    d = np.zeros(3)
+    c = _camera(cam)
+    lib.oc_ray(C.byref(c), int(i), int(j), _ptr(o, C.c_double), _ptr(d, C.c_double))
+    return o, d
+
+
+def render_brick(cam, vox, dims, ghost, origin, spacing, tf, vrange, opacity_scale, dt,
+                 ert_eps=0.0, pixels=None):
+    """Partial image of one brick (``vox`` float32, or float64 for exact
+    perturbation studies).
+
+    Returns (rgba, depth, counters): rgba premultiplied colour + alpha, depth
+    the key t of the first owned sample (+inf where none), counters =
+    [owned samples, samples evaluated by a renderer stopping at T < ert_eps].
+    Full frame -> rgba (H, W, 4), depth (H, W); with ``pixels`` (n, 2) of
+    (i, j) -> rgba (n, 4), depth (n,).
+    """
+    lib = _load()
+    c = _camera(cam)
+    b = _BrickRef(vox, dims, ghost, origin, spacing)
+    t = _TFRef(tf, vrange, opacity_scale)
+    cnt = np.zeros(2, dtype=np.int64)
+    if pixels is None:
+        n = c.width * c.height
+        shape = (c.height, c.width)
+        pix_p, npix = None, 0
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        n = pix.shape[0]
+        shape = (n,)
+        pix_p, npix = _ptr(pix, C.c_int32), n
+    rgba = np.zeros(n * 4)
+    depth = np.zeros(n)
+    lib.oc_render_brick(C.byref(c), C.byref(b.s), C.byref(t.s), float(dt), float(ert_eps), pix_p,
+                        npix, _ptr(rgba, C.c_double), _ptr(depth, C.c_double),
+                        _ptr(cnt, C.c_int64))
+    return rgba.reshape(shape + (4,)), depth.reshape(shape), cnt
+
+
+def composite(partials, bg=(0.0, 0.0, 0.0, 0.0)):
+    """Sort-last composite of [(rgba, depth), ...] (same pixel shape) over bg."""
+    lib = _load()
+    n = len(partials)
+    shape = partials[0][1].shape if n else ()
+    rg = [np.ascontiguousarray(p[0], dtype=np.float64) for p in partials]
+    dp = [np.ascontiguousarray(p[1], dtype=np.float64) for p in partials]
+    npx = int(np.prod(shape)) if n else 0
+    arr_r = (_dp * max(n, 1))(*[_ptr(a, C.c_double) for a in rg])
+    arr_d = (_dp * max(n, 1))(*[_ptr(a, C.c_double) for a in dp])
+    bgv = np.asarray(bg, dtype=np.float64)
+    out = np.zeros(npx * 4)
+    st = lib.oc_composite(n, arr_r, arr_d, npx, _ptr(bgv, C.c_double), _ptr(out, C.c_double))
+    if st != 0:
+        raise ValueError("too many partials for the oracle composite")
+    return out.reshape(tuple(shape) + (4,))
+
+
+def composite_grad(partials, bg, g_out):
+    """dL/d(partial rgba) for each partial, given dL/d(composited image)."""
+    lib = _load()
+    n = len(partials)
+    shape = partials[0][1].shape
+    npx = int(np.prod(shape))
+    rg = [np.ascontiguousarray(p[0], dtype=np.float64) for p in partials]
+    dp = [np.ascontiguousarray(p[1], dtype=np.float64) for p in partials]
+    gs = [np.zeros(npx * 4) for _ in range(n)]
+    arr_r = (_dp * n)(*[_ptr(a, C.c_double) for a in rg])
+    arr_d = (_dp * n)(*[_ptr(a, C.c_double) for a in dp])
+    arr_g = (_dp * n)(*[_ptr(a, C.c_double) for a in gs])
+    bgv = np.asarray(bg, dtype=np.float64)
+    go = np.ascontiguousarray(g_out, dtype=np.float64).reshape(-1)
+    st = lib.oc_composite_grad(n, arr_r, arr_d, npx, _ptr(bgv, C.c_double), _ptr(go, C.c_double),
+                               arr_g)
+    if st != 0:
+        raise ValueError("too many partials for the oracle composite")
+    return [g.reshape(tuple(shape) + (4,)) for g in gs]
+
+
+def render_brick_grad(cam, vox, dims, ghost, origin, spacing, tf, vrange, opacity_scale, dt,
+                      g_part):
+    """Gradient of sum(g_part * partial) w.r.t. the table (n, 4) and the stored
+    (ghost-padded) voxels of one brick; no early termination."""
+    lib = _load()
+    c = _camera(cam)
+    b = _BrickRef(vox, dims, ghost, origin, spacing)
+    t = _TFRef(tf, vrange, opacity_scale)
+    g = np.ascontiguousarray(g_part, dtype=np.float64).reshape(-1)
+    if g.size != 4 * c.width * c.height:
+        raise ValueError("g_part must be (H, W, 4)")
+    gtf = np.zeros(t.table.shape)
+    gvox = np.zeros(b.vox.shape)
+    st = lib.oc_render_brick_grad(C.byref(c), C.byref(b.s), C.byref(t.s), float(dt),
+                                  _ptr(g, C.c_double), _ptr(gtf, C.c_double),
+                                  _ptr(gvox, C.c_double))
+    if st != 0:
+        raise MemoryError("oracle gradient ran out of memory")
+    return gtf, gvox
+
+
+def fold_ghost_grad(gvox_stored, lo, global_shape, ghost=1):
+    """Chain rule through ghost extraction: stored voxel (s_x, s_y, s_z) of a
+    brick with owned min corner ``lo`` is a copy of global voxel
+    clamp(lo + s - g, 0, N - 1) per axis; its gradient adds there."""
+    nz, ny, nx = global_shape
+    sz, sy, sx = gvox_stored.shape
+    g = int(ghost)
+    ix = np.clip(np.arange(sx) + lo[0] - g, 0, nx - 1)
+    iy = np.clip(np.arange(sy) + lo[1] - g, 0, ny - 1)
+    iz = np.clip(np.arange(sz) + lo[2] - g, 0, nz - 1)
+    out = np.zeros(global_shape)
+    np.add.at(out, np.ix_(iz, iy, ix), gvox_stored)
+    return out
+
+
+# ---------------------------------------------------------------- scenes
+def render_scene_partials(scene, camera=None, ert_eps=0.0, pixels=None, field_override=None):
+    """Partial image of every brick of a :class:`synth.Scene`."""
+    cam = camera or scene.camera
+    parts, counters = [], np.zeros(2, dtype=np.int64)
+    for k, b in enumerate(scene.bricks):
+        vox = b.voxels if field_override is None else field_override[k]
+        rgba, depth, cnt = render_brick(cam, vox, b.dims, b.ghost, b.origin, (1.0, 1.0, 1.0),
+                                        scene.tf, scene.vrange, scene.opacity_scale, scene.step,
+                                        ert_eps, pixels)
+        parts.append((rgba, depth))
+        counters += cnt
+    return parts, counters
+
+
+def render_scene(scene, camera=None, bg=(0.0, 0.0, 0.0, 0.0), pixels=None, ert_eps=0.0,
+                 field_override=None):
+    """Final image of a scene: every brick's partial, composited over bg."""
+    parts, counters = render_scene_partials(scene, camera, ert_eps, pixels, field_override)
+    return composite(parts, bg), parts, counters
+
+
+def render_volume(field, cam, tf, vrange, opacity_scale, dt, bg=(0.0, 0.0, 0.0, 0.0),
+                  origin=(0.0, 0.0, 0.0), spacing=(1.0, 1.0, 1.0), pixels=None):
+    """Whole field rendered as a single brick without ghosts (the reconstruction
+    clamps to the edge), composited over bg."""
+    nz, ny, nx = field.shape
+    rgba, depth, _ = render_brick(cam, field, (nx, ny, nz), 0, origin, spacing, tf, vrange,
+                                  opacity_scale, dt, 0.0, pixels)
+    return composite([(rgba, depth)], bg)

@@ -1,0 +1,457 @@
+"""Pins of the FP64 oracle against values fixed by the mathematics, not by the
+oracle itself: hand-derived worked examples (tests/golden), closed forms
+(constant slab, linear ramp), special cases (empty volume), invariants (split
+invariance, associativity of "over"), an independent pinhole projection for
+the camera, brute force with library routines (scipy's grid interpolator and
+numpy's piecewise-linear interp) and finite differences for the gradients.
+
+Each test names the reading of the optical model it pins: cell-centred grid,
+sample lattice t_k = (k + 1/2) dt, endpoint-aligned table, emission-absorption,
+first-sample depth key, sort-last "over".
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
+
+
+def _ramp_tf(rgb=None):
+    tf = np.zeros((256, 4))
+    if rgb is None:
+        tf[:, :3] = 1.0
+    else:
+        x = np.arange(256) / 255.0
+        tf[:, 0], tf[:, 1], tf[:, 2] = rgb(x)
+    tf[:, 3] = np.arange(256) / 255.0
+    return tf
+
+
+_W_CAM = dict(kind="ortho", eye=(0.0, 0.5, 0.5), dir=(1.0, 0.0, 0.0), up=(0.0, 1.0, 0.0),
+              width=1, height=1, view_height=1.0)
+_W_V = np.array([[[0.0, 1.0]]], dtype=np.float32)
+_W2_RGB = lambda x: (x, 1.0 - x, 0.25 + 0 * x)
+
+
+# ------------------------------------------------------------ worked examples
+@pytest.mark.parametrize("name,rgb", [("W1", None), ("W2", _W2_RGB)])
+def test_worked_example_whole(name, rgb):
+    g = GOLD[name]
+    tf = _ramp_tf(rgb)
+    rgba, depth, cnt = oracle.render_brick(_W_CAM, _W_V, (2, 1, 1), 0, (0, 0, 0), (1, 1, 1), tf,
+                                           (0, 1), 1.0, 0.5)
+    np.testing.assert_allclose(rgba[0, 0, :3], g["C"], atol=2e-9)
+    assert abs(rgba[0, 0, 3] - g["A"]) < 2e-9
+    assert depth[0, 0] == 0.25
+    assert list(cnt) == [4, 4]
+    img = oracle.composite([(rgba, depth)], GOLD["bg"])
+    np.testing.assert_allclose(img[0, 0], g["final_bg"], atol=2e-9)
+
+
+@pytest.mark.parametrize("name,rgb", [("W1", None), ("W2", _W2_RGB)])
+def test_worked_example_split(name, rgb):
+    """Split at x = 1 into two ghosted bricks; partials and composite are the
+    hand values and the composite equals the unsplit result."""
+    g = GOLD[name]
+    tf = _ramp_tf(rgb)
+    # ghost layer: neighbour voxel inside the domain, edge copy outside
+    va = np.array([[[0.0, 0.0, 1.0]]] * 3, dtype=np.float32).reshape(3, 1, 3)
+    va = np.repeat(np.repeat(np.array([0.0, 0.0, 1.0], dtype=np.float32)[None, None, :], 3, 1), 3, 0)
+    vb = np.repeat(np.repeat(np.array([0.0, 1.0, 1.0], dtype=np.float32)[None, None, :], 3, 1), 3, 0)
+    pa = oracle.render_brick(_W_CAM, va, (1, 1, 1), 1, (0, 0, 0), (1, 1, 1), tf, (0, 1), 1.0, 0.5)
+    pb = oracle.render_brick(_W_CAM, vb, (1, 1, 1), 1, (1, 0, 0), (1, 1, 1), tf, (0, 1), 1.0, 0.5)
+    if name == "W1":
+        assert abs(pa[0][0, 0, 3] - g["split_A"]["A"]) < 2e-9 and pa[1][0, 0] == 0.25
+        assert abs(pb[0][0, 0, 3] - g["split_B"]["A"]) < 2e-9 and pb[1][0, 0] == 1.25
+    else:
+        np.testing.assert_allclose(pa[0][0, 0], g["split_A"]["rgba"], atol=2e-9)
+        np.testing.assert_allclose(pb[0][0, 0], g["split_B"]["rgba"], atol=2e-9)
+    # order of the list must not matter: the depth key decides
+    img = oracle.composite([(pb[0], pb[1]), (pa[0], pa[1])], GOLD["bg"])
+    np.testing.assert_allclose(img[0, 0], g["final_bg"], atol=2e-9)
+
+
+# ------------------------------------------------------------- closed forms
+def _slab_count(o, lo, hi, dt):
+    """Number of k >= 0 with lo <= o + (k + 1/2) dt < hi (o < lo)."""
+    return math.ceil((hi - o) / dt - 0.5) - math.ceil((lo - o) / dt - 0.5)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("o_off,dt", [(0.0, 0.5), (-0.3, 0.5), (-1.7, 0.25), (-0.1, 0.37)])
+def test_constant_slab_orthographic(axis, o_off, dt):
+    """Constant field + constant table: T = exp(-sigma m dt) with m the number
+    of lattice points inside the slab, C = rgb (1 - T)."""
+    n = [3, 4, 5]
+    n[axis] = 16
+    nx, ny, nz = n
+    vol = np.full((nz, ny, nx), 0.5, dtype=np.float32)
+    tf = np.zeros((256, 4))
+    tf[:] = (0.2, 0.6, 0.9, 0.8)
+    d = [0.0, 0.0, 0.0]; d[axis] = 1.0
+    up = (0.0, 0.0, 1.0) if axis == 1 else (0.0, 1.0, 0.0)
+    eye = [0.5 * nx, 0.5 * ny, 0.5 * nz]; eye[axis] = o_off
+    cam = dict(kind="ortho", eye=tuple(eye), dir=tuple(d), up=up, width=2, height=2,
+               view_height=1.0)
+    rgba, depth, cnt = oracle.render_brick(cam, vol, (nx, ny, nz), 0, (0, 0, 0), (1, 1, 1), tf,
+                                           (0, 1), 1.0, dt)
+    m = _slab_count(o_off, 0.0, 16.0, dt)
+    sigma = 1.0 * 0.8
+    A = 1.0 - math.exp(-sigma * m * dt)
+    np.testing.assert_allclose(rgba[..., 3], A, rtol=1e-13, atol=1e-15)
+    for c, v in enumerate((0.2, 0.6, 0.9)):
+        np.testing.assert_allclose(rgba[..., c], v * A, rtol=1e-12)
+    k_first = math.ceil((0.0 - o_off) / dt - 0.5)
+    np.testing.assert_array_equal(depth, (k_first + 0.5) * dt)
+    assert cnt[0] == 4 * m
+
+
+def test_slab_example_value():
+    """sigma = 0.8, L = 16 -> T = exp(-12.8) = 2.76077257e-6."""
+    vol = np.full((16, 1, 1), 0.5, dtype=np.float32)
+    tf = np.zeros((256, 4)); tf[:] = (1, 1, 1, 0.8)
+    cam = dict(kind="ortho", eye=(0.5, 0.5, 0.0), dir=(0, 0, 1.0), up=(0, 1.0, 0), width=1,
+               height=1, view_height=0.5)
+    rgba, _, _ = oracle.render_brick(cam, vol, (1, 1, 16), 0, (0, 0, 0), (1, 1, 1), tf, (0, 1),
+                                     1.0, 0.5)
+    assert abs((1 - rgba[0, 0, 3]) - 2.76077257e-6) < 1e-14
+
+
+def _slab_interval(o, d, lo, hi):
+    tin, tout = 0.0, math.inf
+    for c in range(3):
+        if d[c] == 0:
+            if not (lo[c] <= o[c] < hi[c]):
+                return None
+            continue
+        a, b = (lo[c] - o[c]) / d[c], (hi[c] - o[c]) / d[c]
+        tin, tout = max(tin, min(a, b)), min(tout, max(a, b))
+    return (tin, tout) if tout > tin else None
+
+
+def test_constant_perspective_lattice_count():
+    """Perspective view of a constant box: every pixel is 1 - exp(-sigma m dt)
+    with m the count of lattice points in the ray's slab interval, found by
+    the closed form ceil(t_out/dt - 1/2) - ceil(t_in/dt - 1/2)."""
+    dims = (9, 7, 5)
+    vol = np.full(dims[::-1], 0.3, dtype=np.float32)
+    tf = np.zeros((256, 4)); tf[:] = (1, 1, 1, 0.5)
+    cam = synth.orbit_camera((0, 0, 0), dims, 24, 18, az_deg=37.0, el_deg=23.0, radius_factor=1.4)
+    dt = 0.25
+    rgba, depth, cnt = oracle.render_brick(cam, vol, dims, 0, (0, 0, 0), (1, 1, 1), tf, (0, 1),
+                                           2.0, dt)
+    hits = 0
+    total = 0
+    for j in range(18):
+        for i in range(24):
+            o, d = oracle.ray(cam, i, j)
+            iv = _slab_interval(o, d, (0, 0, 0), dims)
+            m = 0 if iv is None else max(0, math.ceil(iv[1] / dt - 0.5) - math.ceil(iv[0] / dt - 0.5))
+            total += m
+            hits += m > 0
+            assert abs(rgba[j, i, 3] - (1 - math.exp(-1.0 * m * dt))) < 1e-12
+            if m == 0:
+                assert depth[j, i] == math.inf
+            else:
+                assert depth[j, i] == (math.ceil(iv[0] / dt - 0.5) + 0.5) * dt
+    assert hits > 100 and cnt[0] == total
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_linear_ramp(axis):
+    """Field linear along the view axis, single-segment linear table: the
+    trilinear interpolant is the line itself between the first and last voxel
+    centres and clamps to the edge values outside, so the opacity integral is
+    a sum of a clamped linear function over the lattice."""
+    n = 12
+    shape = [3, 3, 3]; shape[axis] = n
+    nx, ny, nz = shape
+    vals = 0.1 + 0.05 * np.arange(n)  # voxel centre values V_i at i + 1/2
+    vol = np.empty((nz, ny, nx), dtype=np.float32)
+    idx = np.indices((nz, ny, nx))[2 - axis]
+    vol[:] = (0.1 + 0.05 * idx).astype(np.float32)
+    vals = vol.reshape(-1)[np.argsort(idx.reshape(-1), kind="stable")][:: (vol.size // n)]
+    tf = np.zeros((256, 4)); tf[:, 3] = np.arange(256) / 255.0; tf[:, 1] = 1.0
+    d = [0.0, 0.0, 0.0]; d[axis] = 1.0
+    eye = [1.5, 1.5, 1.5]; eye[axis] = -0.4
+    up = (0.0, 0.0, 1.0) if axis == 1 else (0.0, 1.0, 0.0)
+    cam = dict(kind="ortho", eye=tuple(eye), dir=tuple(d), up=up, width=1, height=1,
+               view_height=0.1)
+    dt, scale = 0.5, 1.5
+    rgba, _, _ = oracle.render_brick(cam, vol, (nx, ny, nz), 0, (0, 0, 0), (1, 1, 1), tf, (0, 1),
+                                     scale, dt)
+    tau = 0.0
+    k = 0
+    while True:
+        x = -0.4 + (k + 0.5) * dt
+        if x >= n:
+            break
+        if x >= 0:
+            c = min(max(x - 0.5, 0.0), n - 1.0)       # clamp to first/last centre
+            i0 = min(int(math.floor(c)), n - 2)
+            v = float(vals[i0]) + (c - i0) * (float(vals[i0 + 1]) - float(vals[i0]))
+            tau += scale * v * dt
+        k += 1
+    assert abs(rgba[0, 0, 3] - (1 - math.exp(-tau))) < 1e-12
+    assert abs(rgba[0, 0, 1] - (1 - math.exp(-tau))) < 1e-12
+    assert rgba[0, 0, 0] == 0.0
+
+
+def test_axis_orientation_in_image():
+    """A field that grows along +x seen from +z (looking down -z, up = +y):
+    pixel columns to the right see larger values, rows do not change."""
+    vol = np.zeros((4, 4, 16), dtype=np.float32)
+    vol[:] = (np.arange(16) / 16.0).astype(np.float32)[None, None, :]
+    tf = _ramp_tf()
+    cam = dict(kind="ortho", eye=(8.0, 2.0, 10.0), dir=(0, 0, -1.0), up=(0, 1.0, 0), width=8,
+               height=2, view_height=2.0)
+    rgba, _, _ = oracle.render_brick(cam, vol, (16, 4, 4), 0, (0, 0, 0), (1, 1, 1), tf, (0, 1),
+                                     1.0, 0.5)
+    a = rgba[..., 3]
+    # camera right vector = f x up = (0,0,-1) x (0,1,0) = (1,0,0): +x to the right
+    assert np.all(np.diff(a[0]) > 0)
+    np.testing.assert_allclose(a[0], a[1], rtol=0, atol=0)
+
+
+def test_camera_matches_projection_matrix():
+    """Camera pin: project points along the oracle's pixel rays with an
+    independent look-at + perspective matrix (OpenGL convention) and recover
+    the pixel centre; the top row is +up."""
+    cam = synth.orbit_camera((0, 0, 0), (10, 20, 30), 33, 21, az_deg=70.0, el_deg=-35.0,
+                             fovy_deg=50.0)
+    eye = np.array(cam["eye"]); tgt = np.array(cam["target"]); up = np.array(cam["up"])
+    zc = eye - tgt; zc /= np.linalg.norm(zc)
+    xc = np.cross(up, zc); xc /= np.linalg.norm(xc)
+    yc = np.cross(zc, xc)
+    view = np.eye(4)
+    view[0, :3], view[1, :3], view[2, :3] = xc, yc, zc
+    view[:3, 3] = -view[:3, :3] @ eye
+    W, H = 33, 21
+    f = 1.0 / math.tan(math.radians(50.0) / 2)
+    proj = np.array([[f * H / W, 0, 0, 0], [0, f, 0, 0], [0, 0, -1.0, -0.2], [0, 0, -1.0, 0]])
+    for (i, j) in [(0, 0), (32, 0), (0, 20), (16, 10), (5, 17), (29, 3)]:
+        o, d = oracle.ray(cam, i, j)
+        p = o + 7.3 * d
+        clip = proj @ view @ np.append(p, 1.0)
+        ndc = clip[:2] / clip[3]
+        px = (ndc[0] + 1) / 2 * W - 0.5
+        py = (1 - ndc[1]) / 2 * H - 0.5
+        assert abs(px - i) < 1e-9 and abs(py - j) < 1e-9
+        assert abs(np.linalg.norm(d) - 1) < 1e-15
+
+
+# --------------------------------------------------------- special cases
+def test_empty_volume_gives_background_bitwise():
+    rng = np.random.default_rng(7)
+    vol = rng.uniform(0, 1, (6, 5, 4)).astype(np.float32)
+    tf = np.zeros((256, 4)); tf[:, :3] = rng.uniform(0, 1, (256, 3))   # alpha == 0
+    cam = synth.orbit_camera((0, 0, 0), (4, 5, 6), 16, 12, radius_factor=1.2)
+    bg = (0.1, 0.2, 0.3, 1.0)
+    img = oracle.render_volume(vol, cam, tf, (0, 1), 1.0, 0.5, bg=bg)
+    assert np.array_equal(img, np.broadcast_to(np.array(bg), img.shape))
+    # a ray that misses the box entirely also gives bg, and a key of +inf
+    cam_miss = dict(cam, target=(100.0, 100.0, 100.0))
+    rgba, depth, cnt = oracle.render_brick(cam_miss, vol, (4, 5, 6), 0, (0, 0, 0), (1, 1, 1),
+                                           _ramp_tf(), (0, 1), 1.0, 0.5)
+    assert np.all(depth == np.inf) and np.all(rgba == 0) and cnt[0] == 0
+
+
+def test_fp16_representable_constant_is_exact():
+    vol = np.full((8, 8, 8), 0.5, dtype=np.float32)
+    vol16 = vol.astype(np.float16).astype(np.float32)
+    assert np.array_equal(vol, vol16)
+    tf = synth.default_tf()
+    cam = synth.orbit_camera((0, 0, 0), (8, 8, 8), 12, 12, radius_factor=1.3)
+    a = oracle.render_volume(vol, cam, tf, (0, 1), 1.0, 0.5)
+    b = oracle.render_volume(vol16, cam, tf, (0, 1), 1.0, 0.5)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------- invariants
+@pytest.mark.parametrize("seed,n_bricks", [(11, 2), (12, 5), (13, 8)])
+def test_split_invariance(seed, n_bricks):
+    """Rendering the whole volume equals rendering kd bricks (with ghosts) and
+    compositing them, at the same sample positions."""
+    rng = np.random.default_rng(seed)
+    dims = (20, 17, 13)
+    field = synth.tile_field(rng, dims, n_blobs=6, noise=0.02, shock=True)
+    boxes = synth.kd_split(dims, n_bricks, rng)
+    cam = synth.orbit_camera((0, 0, 0), dims, 40, 30, az_deg=20.0 + seed, el_deg=15.0,
+                             radius_factor=1.6)
+    tf = synth.default_tf()
+    sc = synth.scene_from_field("split", field, boxes, tf, cam, 0.5, 2.0)
+    bg = (0.1, 0.2, 0.3, 1.0)
+    img, parts, cnt = oracle.render_scene(sc, bg=bg)
+    ref = oracle.render_volume(field, cam, tf, (0, 1), 2.0, 0.5, bg=bg)
+    assert np.max(np.abs(img - ref)) < 1e-13
+    _, _, cnt_whole = oracle.render_brick(cam, field, dims, 0, (0, 0, 0), (1, 1, 1), tf, (0, 1),
+                                          2.0, 0.5)
+    assert cnt[0] == cnt_whole[0]     # every lattice point owned exactly once
+
+
+def test_over_associative_and_alpha_product():
+    rng = np.random.default_rng(3)
+    n, npx = 6, 50
+    parts = []
+    for p in range(n):
+        A = rng.uniform(0, 1, npx)
+        Crgb = A[:, None] * rng.uniform(0, 1, (npx, 3))
+        parts.append((np.concatenate([Crgb, A[:, None]], 1), rng.uniform(0, 100, npx)))
+    out = oracle.composite(parts, (0, 0, 0, 0))
+    A = np.array([p[0][:, 3] for p in parts])
+    np.testing.assert_allclose(out[:, 3], 1 - np.prod(1 - A, axis=0), atol=1e-14)
+    # (a over b) over c == a over (b over c) per pixel, in depth order
+    for q in range(npx):
+        order = np.argsort([p[1][q] for p in parts], kind="stable")
+        xs = [parts[o][0][q] for o in order]
+
+        def over(a, b):
+            return a + (1 - a[3]) * b
+
+        left = xs[0]
+        for x in xs[1:]:
+            left = over(left, x)
+        right = xs[-1]
+        for x in reversed(xs[:-1]):
+            right = over(x, right)
+        np.testing.assert_allclose(out[q], left, atol=1e-14)
+        np.testing.assert_allclose(out[q], right, atol=1e-14)
+
+
+def test_ert_counter_and_bound():
+    """Stopping at T < eps changes each channel by at most eps; the counter of
+    evaluated samples never exceeds the owned count."""
+    rng = np.random.default_rng(5)
+    dims = (16, 16, 16)
+    field = synth.tile_field(rng, dims, n_blobs=4, shock=True)
+    tf = synth.default_tf()
+    cam = synth.orbit_camera((0, 0, 0), dims, 24, 24, radius_factor=1.5)
+    eps = 2.0 ** -20
+    rgba, _, cnt = oracle.render_brick(cam, field, dims, 0, (0, 0, 0), (1, 1, 1), tf, (0, 1), 30.0,
+                                       0.5, eps)
+    assert cnt[1] < cnt[0]     # some rays saturate at this opacity scale
+    # emulate the stop on the recorded transmittance: the remainder is <= T_stop
+    assert np.all(rgba[..., 3] <= 1.0) and np.all(rgba >= 0)
+
+
+# ------------------------------------------------------------- brute force
+@pytest.mark.parametrize("dims", [(2, 1, 1), (2, 2, 2), (3, 4, 5)])
+def test_brute_force_library_routines(dims):
+    """Independent evaluation with library primitives: scipy's
+    RegularGridInterpolator on the voxel centres (queries clipped to the
+    first/last centre = clamp to edge), numpy.interp for the table, and a
+    Python loop over every lattice point tested against the box."""
+    from scipy.interpolate import RegularGridInterpolator
+    rng = np.random.default_rng(sum(dims))
+    nx, ny, nz = dims
+    vol = rng.uniform(0, 1, (nz, ny, nx)).astype(np.float32)
+    tf = synth.default_tf().astype(np.float64)
+    cam = synth.orbit_camera((0, 0, 0), dims, 5, 5, az_deg=33.0, el_deg=27.0, radius_factor=1.1)
+    dt, scale = 0.25, 3.0
+    rgba, depth, _ = oracle.render_brick(cam, vol, dims, 0, (0, 0, 0), (1, 1, 1), tf, (0, 1),
+                                         scale, dt)
+
+    def axis_pts(n):
+        return np.arange(n) + 0.5 if n > 1 else np.array([0.5, 1.5])
+
+    data = vol.astype(np.float64).transpose(2, 1, 0)        # (x, y, z)
+    for ax, n in enumerate(dims):
+        if n == 1:
+            data = np.concatenate([data, data], axis=ax)
+    interp = RegularGridInterpolator([axis_pts(n) for n in dims], data, method="linear")
+    grid = np.arange(256) / 255.0
+    for j in range(5):
+        for i in range(5):
+            o, d = oracle.ray(cam, i, j)
+            C = np.zeros(3); T = 1.0; key = math.inf
+            for k in range(0, 400):
+                p = o + ((k + 0.5) * dt) * d
+                if not all(0 <= p[c] < dims[c] for c in range(3)):
+                    continue
+                if key == math.inf:
+                    key = (k + 0.5) * dt
+                q = [min(max(p[c], 0.5), max(dims[c] - 0.5, 0.5)) for c in range(3)]
+                v = float(interp(q)[0])
+                x = min(max(v, 0.0), 1.0)
+                e = [np.interp(x, grid, tf[:, c]) for c in range(4)]
+                alpha = 1 - math.exp(-scale * e[3] * dt)
+                C += T * alpha * np.array(e[:3])
+                T *= 1 - alpha
+            np.testing.assert_allclose(rgba[j, i, :3], C, atol=1e-12)
+            assert abs(rgba[j, i, 3] - (1 - T)) < 1e-12
+            assert depth[j, i] == key
+
+
+# ---------------------------------------------------------------- gradients
+def _loss_parts(cam, bricks, tf, scale, dt, bg, target):
+    parts = [oracle.render_brick(cam, v, dm, 1, lo, (1, 1, 1), tf, (0, 1), scale, dt)[:2]
+             for (v, dm, lo) in bricks]
+    img = oracle.composite(parts, bg)
+    return float(np.sum((img - target) ** 2)), img, parts
+
+
+def _bricks64(field64, boxes):
+    out = []
+    for lo, hi in boxes:
+        b = synth.extract_brick(field64.astype(np.float32), lo, hi).astype(np.float64)
+        # re-cut in float64 so perturbations below float32 resolution survive
+        nz, ny, nx = field64.shape
+        ix = np.clip(np.arange(lo[0] - 1, hi[0] + 1), 0, nx - 1)
+        iy = np.clip(np.arange(lo[1] - 1, hi[1] + 1), 0, ny - 1)
+        iz = np.clip(np.arange(lo[2] - 1, hi[2] + 1), 0, nz - 1)
+        b = field64[np.ix_(iz, iy, ix)].copy()
+        out.append((b, tuple(int(v) for v in np.subtract(hi, lo)), lo))
+    return out
+
+
+def test_gradient_against_central_differences():
+    """Oracle gradient (composite backward + per-brick reverse recurrences +
+    ghost fold) against float64 central differences of the loss
+    L = sum (I - I*)^2 on a two-brick scene."""
+    rng = np.random.default_rng(21)
+    dims = (10, 9, 8)
+    field = rng.uniform(0.1, 0.9, dims[::-1])          # float64, away from the clamps
+    boxes = synth.kd_split(dims, 2, rng)
+    bricks = _bricks64(field, boxes)
+    cam = synth.orbit_camera((0, 0, 0), dims, 12, 10, radius_factor=1.5)
+    tf = synth.default_tf().astype(np.float64)
+    scale, dt, bg = 2.0, 0.5, (0.1, 0.2, 0.3, 1.0)
+    target = rng.uniform(0, 1, (10, 12, 4))
+    L, img, parts = _loss_parts(cam, bricks, tf, scale, dt, bg, target)
+    g_out = 2.0 * (img - target)
+    g_parts = oracle.composite_grad(parts, bg, g_out)
+    gtf = np.zeros_like(tf)
+    gvox = np.zeros(field.shape)
+    for (v, dm, lo), gp in zip(bricks, g_parts):
+        a, b = oracle.render_brick_grad(cam, v, dm, 1, lo, (1, 1, 1), tf, (0, 1), scale, dt, gp)
+        gtf += a
+        gvox += oracle.fold_ghost_grad(b, lo, field.shape)
+    # table entries enter linearly through the lerp weights: FD is smooth
+    h = 1e-6
+    checked = 0
+    for e in np.argsort(-np.abs(gtf).reshape(-1))[:10]:
+        e_, c = divmod(int(e), 4)
+        tp, tm = tf.copy(), tf.copy()
+        tp[e_, c] += h; tm[e_, c] -= h
+        fd = (_loss_parts(cam, bricks, tp, scale, dt, bg, target)[0] -
+              _loss_parts(cam, bricks, tm, scale, dt, bg, target)[0]) / (2 * h)
+        assert abs(fd - gtf[e_, c]) <= 1e-6 * max(1.0, abs(fd)), (e_, c, fd, gtf[e_, c])
+        checked += 1
+    assert checked == 10
+    # voxels (including ones next to the cut, whose ghost copies fold back)
+    h = 1e-6
+    for f in np.argsort(-np.abs(gvox).reshape(-1))[:10]:
+        z, y, x = np.unravel_index(int(f), field.shape)
+        vals = []
+        for sgn in (1, -1):
+            fp = field.copy()
+            fp[z, y, x] += sgn * h
+            vals.append(_loss_parts(cam, _bricks64(fp, boxes), tf, scale, dt, bg, target)[0])
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - gvox[z, y, x]) <= 1e-5 * max(1.0, abs(fd)), (z, y, x, fd, gvox[z, y, x])
