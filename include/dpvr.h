@@ -1,0 +1,287 @@
+/*
+ * dpvr.h -- C-ABI of the MI355X data-parallel volume renderer.
+ *
+ * The library renders a volume that is split into bricks (the "ranks" of a
+ * data-parallel decomposition, several of which can live on one GPU): each
+ * brick is ray cast on its own into a partial image (premultiplied RGBA plus
+ * a depth key), and the partial images are then combined by sort-last,
+ * visibility-ordered compositing.  The call set follows the paper's
+ * ANARI-style problem statement (Zellmann, "Data Parallel Visualization and
+ * Rendering on the RAMSES Supercomputer with ANARI", Sec. 3): the
+ * application describes the scene (bricks = the locally owned part of the
+ * world, a transfer function, a camera), calls render, and finds the image
+ * in memory it owns; rendering a partial image is the per-rank local step,
+ * compositing is the step that runs as a collective across ranks and leaves
+ * the framebuffer with the main rank (Sec. 3, DP-ANARI conventions).
+ *
+ * Conventions for every call
+ *   - Device memory is always owned by the caller.  The library allocates no
+ *     device memory: bricks live in caller-provided workspaces, partial and
+ *     final images in caller-provided buffers.  Pointers are borrowed for the
+ *     duration of the work the call enqueues.
+ *   - Work is enqueued asynchronously on the context's HIP stream; nothing
+ *     returns to the host until the caller synchronises (vr_synchronize or
+ *     its own stream/device synchronisation).
+ *   - Every call returns a vr_status.  Arguments are validated on the host
+ *     before anything is enqueued; an invalid call enqueues nothing.
+ *     Asynchronous device faults surface as VR_ERR_DEVICE at the next call
+ *     that checks the HIP runtime (vr_synchronize always does).
+ *     vr_last_error() returns a message for the last failing call.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *
+ * Optical model (cited per call below; all readings of the paper, which
+ * gives no rendering mathematics):
+ *   grid     voxel (i, j, k) of a brick is a cell centred at
+ *            origin + spacing * (i + 1/2, j + 1/2, k + 1/2); a brick owns the
+ *            half-open box [origin, origin + dims * spacing) per axis and
+ *            stores one ghost layer (copies of the neighbours' voxels, or of
+ *            its own edge voxels at the domain boundary) on every face.
+ *   lattice  along each camera ray (origin o, unit direction d) samples sit
+ *            at t_k = (k + 1/2) dt, k = 0, 1, ...; sample k is evaluated by
+ *            the brick whose owned box contains o + t_k d, so the sample set
+ *            does not depend on how the volume is split.
+ *   sample   trilinear interpolation of the stored voxels.
+ *   classify 256-entry RGBA table over [vmin, vmax], endpoint aligned,
+ *            piecewise linear; extinction sigma = opacity_scale * alpha.
+ *   shade    emission-absorption front to back: a = 1 - exp(-sigma dt),
+ *            C += T a rgb, T *= 1 - a (premultiplied colour, alpha 1 - T).
+ *   depth    the partial's depth key is t of the first sample the brick
+ *            owns on that ray (+inf if it owns none).
+ *   over     partials are combined per pixel in ascending key order,
+ *            C += (1 - A) C_i, A += (1 - A) A_i, then put over a background.
+ */
+#ifndef DPVR_H
+#define DPVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPVR_ABI_VERSION 1
+#define DPVR_TF_ENTRIES 256          /* transfer-function table size */
+#define DPVR_MAX_PARTIALS 64         /* partials per vr_composite call */
+
+typedef struct vr_context_s* vr_context;
+typedef struct vr_brick_s* vr_brick;
+
+typedef enum {
+    VR_OK = 0,
+    VR_ERR_INVALID_ARG = -1,     /* argument out of range or inconsistent */
+    VR_ERR_INVALID_HANDLE = -2,  /* NULL or released handle */
+    VR_ERR_WORKSPACE = -3,       /* caller workspace too small or misaligned */
+    VR_ERR_UNSUPPORTED = -4,     /* valid request this build does not implement */
+    VR_ERR_DEVICE = -5,          /* HIP runtime error (launch or asynchronous fault) */
+    VR_ERR_STATE = -6            /* required state (camera, transfer function) not set */
+} vr_status;
+
+/* Storage precision of a brick's internal copy.  VR_F16 stores IEEE
+ * binary16 (round to nearest even) and reconstructs in FP32; accumulation is
+ * FP32 either way. */
+typedef enum { VR_F32 = 0, VR_F16 = 1 } vr_dtype;
+
+/* A partial image: a region of interest (ROI) of the frame, in pixels, and
+ * caller-owned device buffers for it.  rgba holds h * w * 4 floats
+ * (premultiplied r, g, b, alpha), row-major with row 0 at the top; depth
+ * holds h * w floats (the depth key, +inf where the brick owns no sample).
+ * Pixels of the frame outside the ROI count as (0, 0, 0, 0) at depth +inf.
+ * samples is optional (NULL = off): a device counter to which a render call
+ * adds the number of samples it evaluated (owned samples up to and including
+ * the one at which early termination stopped the ray); the caller zeroes it. */
+typedef struct {
+    int32_t x0, y0, w, h;
+    float* rgba;
+    float* depth;
+    unsigned long long* samples;
+} vr_partial;
+
+/* ------------------------------------------------------------------ misc */
+/* Returns DPVR_ABI_VERSION of the loaded library. */
+int32_t vr_abi_version(void);
+
+/* Static English name of a status code (never NULL). */
+const char* vr_status_string(vr_status status);
+
+/* Message of the last failing call on ctx; with ctx == NULL, of the last
+ * failing call on this thread that had no usable context (e.g. a failed
+ * vr_context_create).  Valid until the next call on the same context /
+ * thread.  Never NULL (empty string when there was no error). */
+const char* vr_last_error(vr_context ctx);
+
+/* --------------------------------------------------------------- context */
+/* Create a context bound to HIP device `device` and HIP stream `stream`
+ * (a hipStream_t; NULL = the device's default stream).  The stream is
+ * borrowed: the caller keeps it alive for the context's lifetime.
+ * Errors: VR_ERR_INVALID_ARG (out == NULL, bad device), VR_ERR_DEVICE. */
+vr_status vr_context_create(int32_t device, void* stream, vr_context* out);
+
+/* Release a context.  Bricks created on it must be released first
+ * (VR_ERR_STATE otherwise).  Does not synchronise the stream. */
+vr_status vr_context_release(vr_context ctx);
+
+/* Re-bind the context to another stream of the same device. */
+vr_status vr_context_set_stream(vr_context ctx, void* stream);
+
+/* Block until all work enqueued on the context's stream has finished and
+ * report any asynchronous device error (VR_ERR_DEVICE). */
+vr_status vr_synchronize(vr_context ctx);
+
+/* ---------------------------------------------------------------- bricks */
+/* Bytes of device workspace a brick of `dims` owned voxels (nx, ny, nz, each
+ * >= 1) with `ghost` ghost layers (must be 1) needs at precision `storage`.
+ * Host-only; needs no context.  Errors: VR_ERR_INVALID_ARG. */
+vr_status vr_brick_workspace_size(const int32_t dims[3], int32_t ghost, vr_dtype storage,
+                                  size_t* bytes);
+
+/* Create a brick: the part of the world one rank owns (paper Sec. 2.2:
+ * the data is spatially distributed, each rank owning a share; Sec. 3:
+ * world updates are local).  dims = owned voxels (nx, ny, nz); ghost = 1;
+ * origin = world position of the owned box's min corner; spacing = world
+ * size of a voxel (> 0, finite); storage = internal precision.  workspace is
+ * a caller-owned device buffer of at least vr_brick_workspace_size() bytes,
+ * 256-byte aligned, that must outlive the brick.  The brick has no voxel
+ * data until vr_brick_set_data() is called.
+ * Errors: VR_ERR_INVALID_HANDLE, VR_ERR_INVALID_ARG, VR_ERR_WORKSPACE. */
+vr_status vr_brick_create(vr_context ctx, const int32_t dims[3], int32_t ghost,
+                          const double origin[3], const double spacing[3], vr_dtype storage,
+                          void* workspace, size_t workspace_bytes, vr_brick* out);
+
+/* Ingest voxel values (a new time step or field): voxels is a device array of
+ * (nz + 2g) * (ny + 2g) * (nx + 2g) floats, x fastest, including the ghost
+ * layer.  The values are converted into the brick's workspace by a kernel
+ * enqueued on the context stream; `voxels` is borrowed until that kernel has
+ * run (the next synchronisation of the stream).  FP16 storage rounds to
+ * nearest even; values beyond the binary16 range become +-inf. */
+vr_status vr_brick_set_data(vr_brick brick, const float* voxels);
+
+/* Ingest the brick's data straight out of a global voxel array: volume is a
+ * device array of vol_dims = (NX, NY, NZ) floats, x fastest; lo = global
+ * index of the brick's owned min corner.  The brick's box plus its ghost
+ * layer is gathered, with indices clamped to the grid (so ghosts at the
+ * domain boundary replicate the edge voxel), into the workspace at the
+ * brick's storage precision.  `volume` is borrowed until the enqueued kernel
+ * has run.  Errors: VR_ERR_INVALID_ARG (box outside the grid). */
+vr_status vr_brick_set_data_global(vr_brick brick, const float* volume, const int32_t vol_dims[3],
+                                   const int32_t lo[3]);
+
+/* Release a brick (host state only; the caller frees the workspace). */
+vr_status vr_brick_release(vr_brick brick);
+
+/* ----------------------------------------------------------------- state */
+/* Transfer function (classification): rgba is a device array of n = 256
+ * entries (r, g, b, alpha) as floats, colour non-premultiplied, alpha >= 0.
+ * Entry i sits at value vmin + i (vmax - vmin) / 255; values in between are
+ * linearly interpolated, values outside [vmin, vmax] clamp to the end
+ * entries.  Extinction per world unit is opacity_scale * alpha.  The table is
+ * read by render calls enqueued after this call: it is borrowed until they
+ * have run.  Errors: VR_ERR_INVALID_ARG (n != 256, vmin >= vmax, non-finite
+ * values, opacity_scale < 0). */
+vr_status vr_set_transfer_function(vr_context ctx, const float* rgba, int32_t n, float vmin,
+                                   float vmax, float opacity_scale);
+
+/* Pinhole camera: forward f = normalize(target - eye), right r =
+ * normalize(f x up), true up u = r x f; pixel (i, j) (row 0 at the top)
+ * casts o = eye, d = normalize(f + x r + y u) with
+ * x = (2 (i + 1/2) / width - 1) tan(fovy / 2) width / height,
+ * y = (1 - 2 (j + 1/2) / height) tan(fovy / 2).  fovy in (0, 180) degrees.
+ * Errors: VR_ERR_INVALID_ARG (degenerate frame: eye == target, up parallel
+ * to the view direction, non-finite values, size < 1). */
+vr_status vr_set_camera_perspective(vr_context ctx, const double eye[3], const double target[3],
+                                    const double up[3], double fovy_deg, int32_t width,
+                                    int32_t height);
+
+/* Orthographic camera: d = normalize(dir); pixel (i, j) casts from
+ * o = pos + x r + y u with x, y as above but scaled so that the image is
+ * view_height world units tall (pos is the image centre). */
+vr_status vr_set_camera_orthographic(vr_context ctx, const double pos[3], const double dir[3],
+                                     const double up[3], double view_height, int32_t width,
+                                     int32_t height);
+
+/* Sample spacing dt along each ray in world units (> 0; the samples sit at
+ * (k + 1/2) dt from the ray origin), and the early-termination threshold: a
+ * ray stops once its transmittance drops below ert_epsilon (0 disables; the
+ * neglected remainder is at most ert_epsilon per channel).  Defaults:
+ * dt = 0.5, ert_epsilon = 2^-20. */
+vr_status vr_set_render_params(vr_context ctx, double dt, float ert_epsilon);
+
+/* --------------------------------------------------------------- render */
+/* Host-only: the smallest pixel rectangle of the current camera's frame that
+ * holds every pixel whose ray can own a sample of `brick` (its owned box
+ * projected to the image, plus one pixel of margin), clipped to the frame;
+ * the whole frame when the eye is inside or behind the box's projection
+ * plane.  roi = (x0, y0, w, h); w or h may be 0 when the box is off-screen.
+ * Errors: VR_ERR_STATE (no camera). */
+vr_status vr_partial_roi(vr_context ctx, vr_brick brick, int32_t roi[4]);
+
+/* Render the partial image of one brick (paper Sec. 2.2: each rank traces
+ * the rays through the data it owns) into part->rgba / part->depth for the
+ * pixels of part's ROI.  The ROI must lie within the frame; rays of pixels
+ * outside it are not cast.  Enqueued on the context stream.
+ * Errors: VR_ERR_INVALID_HANDLE, VR_ERR_INVALID_ARG (ROI, NULL buffers),
+ * VR_ERR_STATE (no camera, no transfer function, brick has no data),
+ * VR_ERR_DEVICE. */
+vr_status vr_render_partial(vr_context ctx, vr_brick brick, const vr_partial* part);
+
+/* Sort-last composite (paper Sec. 3: the framebuffer ends up on the main
+ * rank): for every pixel of the frame, the n partials (0 <= n <=
+ * DPVR_MAX_PARTIALS) are ordered by ascending depth key (ties: lower index
+ * first) and combined front to back with "over", then over the background
+ * bg (host array, 4 floats, premultiplied).  out is a device array of
+ * height * width * 4 floats, row 0 at the top.  parts is a host array; its
+ * buffers are borrowed until the enqueued kernel has run.
+ * Errors: VR_ERR_INVALID_ARG, VR_ERR_STATE (no camera), VR_ERR_DEVICE. */
+vr_status vr_composite(vr_context ctx, const vr_partial* parts, int32_t n, const float bg[4],
+                       float* out);
+
+/* -------------------------------------------------------------- adjoint */
+/* Differentiable rendering: gradients of a scalar loss L of the frame with
+ * respect to the transfer-function table and the voxel values, for
+ * transfer-function and inverse-volume fitting.  The forward pass stores the
+ * transmittance in front of every `interval`-th owned sample of every ray
+ * (segment checkpoints, 1 <= interval <= DPVR_MAX_CKPT_INTERVAL); the
+ * backward re-marches each segment from its checkpoint, last segment first.
+ * Early termination is off in both passes.  Gradients are exact derivatives
+ * of the rendered image (readings: emission-absorption as above; the table
+ * lookup is differentiated on the segment it uses, min(floor(s), 254), and
+ * has zero derivative in v outside [vmin, vmax]). */
+#define DPVR_MAX_CKPT_INTERVAL 64
+
+/* Host-only: bytes of checkpoint storage vr_render_partial_checkpointed needs
+ * for `part`'s ROI with this interval (ROI pixels x ceil((max owned samples
+ * per ray) / interval) floats, the maximum taken over the brick's diagonal). */
+vr_status vr_checkpoint_size(vr_context ctx, vr_brick brick, const vr_partial* part,
+                             int32_t interval, size_t* bytes);
+
+/* Forward march of one partial without early termination, writing the same
+ * partial image as vr_render_partial with ert_epsilon = 0 and the
+ * checkpoints into ckpt (device, >= vr_checkpoint_size bytes). */
+vr_status vr_render_partial_checkpointed(vr_context ctx, vr_brick brick, const vr_partial* part,
+                                         int32_t interval, float* ckpt, size_t ckpt_bytes);
+
+/* Backward of vr_composite: given d_out = dL/d(frame) (device, height * width
+ * * 4 floats), writes dL/d(partial p) into d_parts[p] (device, part p's ROI,
+ * h * w * 4 floats: dL/dC_r, dL/dC_g, dL/dC_b, dL/dA); pixels where partial
+ * p's key is +inf get zeros.  parts must hold the forward's partial images. */
+vr_status vr_composite_backward(vr_context ctx, const vr_partial* parts, int32_t n,
+                                const float bg[4], const float* d_out, float* const* d_parts);
+
+/* Backward of one partial: d_part (device, ROI h * w * 4) = dL/d(partial);
+ * ckpt = the checkpoints of vr_render_partial_checkpointed with the same
+ * interval, camera, transfer function and brick data.  Accumulates (adds
+ * to) dL/d(table) into grad_tf (device, 256 x 4, same layout as the table)
+ * and dL/d(voxel) into grad_volume (device, vol_dims floats, x fastest): a
+ * stored voxel (ghosts included) is a copy of the global voxel
+ * clamp(lo + s - 1), so its gradient lands there.  Uses float atomics, so
+ * the summation order (last bits) varies from run to run. */
+vr_status vr_render_partial_backward(vr_context ctx, vr_brick brick, const vr_partial* part,
+                                     int32_t interval, const float* ckpt, size_t ckpt_bytes,
+                                     const float* d_part, float* grad_tf, float* grad_volume,
+                                     const int32_t vol_dims[3], const int32_t lo[3]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPVR_H */

@@ -1,0 +1,326 @@
+"""MI355X data-parallel volume renderer: Python binding of ``libdpvr.so``.
+
+Every ``vr_*`` function here has the name and meaning of the C entry point
+declared in ``include/dpvr.h`` and only marshals arguments (torch tensors
+for device memory, torch streams, host arrays); a non-OK status raises
+:class:`VRError` with the library's message.  All rendering work runs in the
+HIP kernels of the library -- there is no fallback: importing this package
+raises if the library has not been built.
+
+:class:`Renderer` is plumbing on top: it keeps the caller-owned device
+buffers (brick workspaces, partial images, the frame) as torch tensors and
+issues the calls of one frame: render every brick's partial, then composite.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpvr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2501_01628_amd.build` "
+                      "(hipcc, gfx950); there is no CPU fallback")
+
+# torch brings its own HIP runtime (SONAME libamdhip64.so.7).  Loading it
+# first makes libdpvr.so's dependency on libamdhip64.so.7 resolve to that same
+# runtime, so device memory and streams from torch are valid in the library;
+# two runtimes in one process would not see each other's devices.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+VR_OK, VR_ERR_INVALID_ARG, VR_ERR_INVALID_HANDLE, VR_ERR_WORKSPACE = 0, -1, -2, -3
+VR_ERR_UNSUPPORTED, VR_ERR_DEVICE, VR_ERR_STATE = -4, -5, -6
+VR_F32, VR_F16 = 0, 1
+TF_ENTRIES = 256
+MAX_PARTIALS = 64
+
+
+class vr_partial(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("w", C.c_int32), ("h", C.c_int32),
+                ("rgba", C.c_void_p), ("depth", C.c_void_p), ("samples", C.c_void_p)]
+
+
+_i3 = C.c_int32 * 3
+_d3 = C.c_double * 3
+_f4 = C.c_float * 4
+_st = C.c_int
+
+_SIGS = {
+    "vr_abi_version": ([], C.c_int32),
+    "vr_status_string": ([C.c_int], C.c_char_p),
+    "vr_last_error": ([C.c_void_p], C.c_char_p),
+    "vr_context_create": ([C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)], _st),
+    "vr_context_release": ([C.c_void_p], _st),
+    "vr_context_set_stream": ([C.c_void_p, C.c_void_p], _st),
+    "vr_synchronize": ([C.c_void_p], _st),
+    "vr_brick_workspace_size": ([_i3, C.c_int32, C.c_int, C.POINTER(C.c_size_t)], _st),
+    "vr_brick_create": ([C.c_void_p, _i3, C.c_int32, _d3, _d3, C.c_int, C.c_void_p, C.c_size_t,
+                         C.POINTER(C.c_void_p)], _st),
+    "vr_brick_set_data": ([C.c_void_p, C.c_void_p], _st),
+    "vr_brick_release": ([C.c_void_p], _st),
+    "vr_set_transfer_function": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float,
+                                  C.c_float], _st),
+    "vr_set_camera_perspective": ([C.c_void_p, _d3, _d3, _d3, C.c_double, C.c_int32, C.c_int32],
+                                  _st),
+    "vr_set_camera_orthographic": ([C.c_void_p, _d3, _d3, _d3, C.c_double, C.c_int32, C.c_int32],
+                                   _st),
+    "vr_set_render_params": ([C.c_void_p, C.c_double, C.c_float], _st),
+    "vr_partial_roi": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)], _st),
+    "vr_render_partial": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial)], _st),
+    "vr_composite": ([C.c_void_p, C.POINTER(vr_partial), C.c_int32, _f4, C.c_void_p], _st),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class VRError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_lib.vr_status_string(status).decode()}: {message}")
+        self.status = status
+
+
+def _check(status, ctx=None):
+    if status != VR_OK:
+        raise VRError(status, _lib.vr_last_error(ctx).decode(errors="replace"))
+
+
+def _ptr(x):
+    """Device (or host) address of a torch tensor / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ----------------------------------------------------------- C entry points
+def vr_abi_version():
+    return _lib.vr_abi_version()
+
+
+def vr_status_string(status):
+    return _lib.vr_status_string(status).decode()
+
+
+def vr_last_error(ctx=None):
+    return _lib.vr_last_error(ctx).decode(errors="replace")
+
+
+def vr_context_create(device=0, stream=None):
+    h = C.c_void_p()
+    _check(_lib.vr_context_create(int(device), _stream_ptr(stream), C.byref(h)))
+    return h.value
+
+
+def vr_context_release(ctx):
+    _check(_lib.vr_context_release(ctx))
+
+
+def vr_context_set_stream(ctx, stream):
+    _check(_lib.vr_context_set_stream(ctx, _stream_ptr(stream)), ctx)
+
+
+def vr_synchronize(ctx):
+    _check(_lib.vr_synchronize(ctx), ctx)
+
+
+def vr_brick_workspace_size(dims, ghost=1, storage=VR_F32):
+    n = C.c_size_t()
+    _check(_lib.vr_brick_workspace_size(_i3(*dims), int(ghost), int(storage), C.byref(n)))
+    return n.value
+
+
+def vr_brick_create(ctx, dims, ghost, origin, spacing, storage, workspace, workspace_bytes):
+    h = C.c_void_p()
+    _check(_lib.vr_brick_create(ctx, _i3(*dims), int(ghost), _d3(*origin), _d3(*spacing),
+                                int(storage), _ptr(workspace), int(workspace_bytes), C.byref(h)),
+           ctx)
+    return h.value
+
+
+def vr_brick_set_data(brick, voxels, ctx=None):
+    _check(_lib.vr_brick_set_data(brick, _ptr(voxels)), ctx)
+
+
+def vr_brick_release(brick):
+    _check(_lib.vr_brick_release(brick))
+
+
+def vr_set_transfer_function(ctx, rgba, n=TF_ENTRIES, vmin=0.0, vmax=1.0, opacity_scale=1.0):
+    _check(_lib.vr_set_transfer_function(ctx, _ptr(rgba), int(n), float(vmin), float(vmax),
+                                         float(opacity_scale)), ctx)
+
+
+def vr_set_camera_perspective(ctx, eye, target, up, fovy_deg, width, height):
+    _check(_lib.vr_set_camera_perspective(ctx, _d3(*eye), _d3(*target), _d3(*up), float(fovy_deg),
+                                          int(width), int(height)), ctx)
+
+
+def vr_set_camera_orthographic(ctx, pos, dir, up, view_height, width, height):
+    _check(_lib.vr_set_camera_orthographic(ctx, _d3(*pos), _d3(*dir), _d3(*up),
+                                           float(view_height), int(width), int(height)), ctx)
+
+
+def vr_set_render_params(ctx, dt=0.5, ert_epsilon=2.0 ** -20):
+    _check(_lib.vr_set_render_params(ctx, float(dt), float(ert_epsilon)), ctx)
+
+
+def vr_partial_roi(ctx, brick):
+    roi = (C.c_int32 * 4)()
+    _check(_lib.vr_partial_roi(ctx, brick, roi), ctx)
+    return tuple(roi)
+
+
+def make_partial(roi, rgba, depth, samples=None):
+    x0, y0, w, h = roi
+    return vr_partial(int(x0), int(y0), int(w), int(h), _ptr(rgba), _ptr(depth), _ptr(samples))
+
+
+def vr_render_partial(ctx, brick, part):
+    _check(_lib.vr_render_partial(ctx, brick, C.byref(part)), ctx)
+
+
+def vr_composite(ctx, parts, bg, out):
+    n = len(parts)
+    arr = (vr_partial * max(n, 1))(*parts)
+    _check(_lib.vr_composite(ctx, arr, n, _f4(*bg), _ptr(out)), ctx)
+
+
+def set_camera(ctx, cam: dict):
+    """Apply a camera dict (``kind``, ``eye``, ``target``/``dir``, ``up``,
+    ``fovy_deg``/``view_height``, ``width``, ``height``)."""
+    if cam.get("kind", "perspective") == "perspective":
+        vr_set_camera_perspective(ctx, cam["eye"], cam["target"], cam["up"], cam["fovy_deg"],
+                                  cam["width"], cam["height"])
+    else:
+        vr_set_camera_orthographic(ctx, cam["eye"], cam["dir"], cam["up"], cam["view_height"],
+                                   cam["width"], cam["height"])
+
+
+# ------------------------------------------------------------ frame helper
+class Renderer:
+    """Owns the torch buffers of one scene on one device and issues the
+    C-ABI calls of a frame.  ``bricks`` is a list of (voxels, lo) with voxels a
+    ghost-padded float32 array (numpy or torch, (nz+2, ny+2, nx+2)) and lo
+    the owned box's integer min corner; spacing is 1 (voxel units)."""
+
+    def __init__(self, bricks, tf, vrange=(0.0, 1.0), opacity_scale=1.0, dt=0.5,
+                 ert_eps=2.0 ** -20, storage=VR_F32, device=0, stream=None, spacing=(1.0, 1.0, 1.0)):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = vr_context_create(device, self.stream)
+        self.storage = storage
+        self.bricks, self.workspaces, self.meta = [], [], []
+        self.tf = torch.as_tensor(np.ascontiguousarray(tf, dtype=np.float32)).to(self.device)
+        vr_set_transfer_function(self.ctx, self.tf, TF_ENTRIES, vrange[0], vrange[1], opacity_scale)
+        vr_set_render_params(self.ctx, dt, ert_eps)
+        for vox, lo in bricks:
+            self.add_brick(vox, lo, spacing)
+        self._parts = {}
+        self.frame = None
+        self.samples = torch.zeros(max(len(self.bricks), 1), dtype=torch.int64, device=self.device)
+
+    def add_brick(self, vox, lo, spacing=(1.0, 1.0, 1.0)):
+        torch = self.torch
+        v = torch.as_tensor(vox).to(self.device, torch.float32).contiguous()
+        nz, ny, nx = (int(s) - 2 for s in v.shape)
+        dims = (nx, ny, nz)
+        nbytes = vr_brick_workspace_size(dims, 1, self.storage)
+        ws = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=self.device)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        h = vr_brick_create(self.ctx, dims, 1, tuple(float(x) for x in lo), spacing, self.storage,
+                            base + off, nbytes)
+        vr_brick_set_data(h, v, self.ctx)
+        self.bricks.append(h)
+        self.workspaces.append((ws, v))       # source kept alive until the next sync
+        self.meta.append((dims, tuple(lo)))
+        return h
+
+    def set_data(self, k, vox):
+        v = self.torch.as_tensor(vox).to(self.device, self.torch.float32).contiguous()
+        vr_brick_set_data(self.bricks[k], v, self.ctx)
+        self.workspaces[k] = (self.workspaces[k][0], v)
+
+    def set_camera(self, cam):
+        set_camera(self.ctx, cam)
+        self.width, self.height = int(cam["width"]), int(cam["height"])
+        self.rois = [vr_partial_roi(self.ctx, b) for b in self.bricks]
+        torch = self.torch
+        self.partials = []
+        for k, roi in enumerate(self.rois):
+            key = (k, roi[2], roi[3])
+            if key not in self._parts:
+                n = max(roi[2] * roi[3], 1)
+                self._parts[key] = (torch.empty(n * 4, dtype=torch.float32, device=self.device),
+                                    torch.empty(n, dtype=torch.float32, device=self.device))
+            rgba, depth = self._parts[key]
+            if self.samples.numel() < len(self.bricks):
+                self.samples = torch.zeros(len(self.bricks), dtype=torch.int64, device=self.device)
+            self.partials.append(make_partial(roi, rgba, depth, self.samples[k:k + 1]))
+        if self.frame is None or self.frame.numel() != self.width * self.height * 4:
+            self.frame = torch.empty(self.height, self.width, 4, dtype=torch.float32,
+                                     device=self.device)
+
+    def render_partials(self):
+        for b, p in zip(self.bricks, self.partials):
+            vr_render_partial(self.ctx, b, p)
+
+    def reset_samples(self):
+        self.samples.zero_()
+
+    def sample_counts(self):
+        """Samples evaluated per brick since the last reset (synchronises)."""
+        return self.samples[: len(self.bricks)].cpu().numpy().astype(np.int64)
+
+    def composite(self, bg=(0.0, 0.0, 0.0, 0.0)):
+        vr_composite(self.ctx, self.partials, bg, self.frame)
+        return self.frame
+
+    def render(self, bg=(0.0, 0.0, 0.0, 0.0)):
+        self.render_partials()
+        return self.composite(bg)
+
+    def partial_arrays(self, k):
+        """(rgba (h, w, 4), depth (h, w)) torch views of partial k."""
+        x0, y0, w, h = self.rois[k]
+        rgba, depth = self._parts[(k, w, h)]
+        return rgba[: w * h * 4].view(h, w, 4), depth[: w * h].view(h, w)
+
+    def synchronize(self):
+        vr_synchronize(self.ctx)
+
+    def close(self):
+        if self.ctx is None:
+            return
+        self.synchronize()
+        for b in self.bricks:
+            vr_brick_release(b)
+        vr_context_release(self.ctx)
+        self.ctx = None
+        self.bricks = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

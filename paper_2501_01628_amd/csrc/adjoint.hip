@@ -1,0 +1,169 @@
+// Adjoint of the per-brick ray march for gfx950: gradients of a loss with
+// respect to the transfer-function table and the global voxel array, given
+// the loss gradient of the brick's partial image (dL/dC_rgb, dL/dA per ROI
+// pixel) and the transmittance checkpoints written by the checkpointing
+// forward march.
+//
+// One wavefront per 8x8 tile, one lane per ray, as in the forward.  A ray's
+// owned samples are cut into segments of ckpt_interval (<= 64) samples.
+// Segments are processed last to first: the segment is re-marched forward
+// from its checkpoint, storing the transmittance T_k in front of each sample
+// in LDS (no division by T anywhere), then walked backwards with
+//   R_k = a_k rgb_k + (1 - a_k) R_{k+1},  Q_k = (1 - a_k) Q_{k+1}
+// (R = colour, Q = transmittance of what lies behind sample k in the brick),
+//   dC/drgb_k = T_k a_k,  dC/da_k = T_k (rgb_k - R_{k+1}),  dA/da_k = T_k Q_{k+1}.
+// The opacity a_k = 1 - exp2(-a'_k) with a' the pre-scaled table opacity;
+// table gradients are accumulated per workgroup in LDS (ds_add_f32) and
+// flushed with one global atomic per touched entry; voxel gradients are
+// scattered with the 8 trilinear weights to the global voxels that the stored
+// (ghost-padded) voxels copy, so ghost contributions fold back to their source.
+#include "march_common.h"
+
+namespace dpvr {
+namespace {
+
+constexpr int kTile = 8;
+constexpr float kLn2 = 0.6931471805599453f;
+
+template <typename TS>
+__global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardParams bp) {
+    __shared__ TFTable tft;
+    __shared__ float gtf[256 * 4];
+    __shared__ float tbuf[kMaxCkptInterval * 64];
+    const int lane = threadIdx.x;
+    load_tf(tft, p.tf, p.dt, lane, 64);
+    for (int e = lane; e < 1024; e += 64) gtf[e] = 0.0f;
+    __syncthreads();
+
+    const int tile = blockIdx.x;
+    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+    const int lx = tx * kTile + (lane & 7), ly = ty * kTile + (lane >> 3);
+    const bool valid = lx < p.roi_w && ly < p.roi_h;
+    const int px = p.roi_x0 + lx, py = p.roi_y0 + ly;
+    const long long pix = (long long)ly * p.roi_w + lx;
+
+    const BrickK& b = p.brick;
+    const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
+    const int snx = b.sdim[0], sny = b.sdim[1], snz = b.sdim[2];
+    const long long sxy = (long long)snx * sny;
+    const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
+    const float tf_o = -p.tf.vmin * tf_k;
+    // d a' / d alpha_table: converts pre-scaled opacity gradients to table units
+    const float a_scale = p.tf.opacity_scale * (float)p.dt * kLog2e;
+    const int I = p.ckpt_interval;
+    const long long gnx = bp.vol_dims[0], gny = bp.vol_dims[1], gnz = bp.vol_dims[2];
+
+    RaySetup rs;
+    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool has = valid && setup_ray(p.cam, b, p.dt, px, py, rs);
+    if (has) {
+        g = reinterpret_cast<const float4*>(bp.d_part)[pix];
+        has = g.x != 0.f || g.y != 0.f || g.z != 0.f || g.w != 0.f;
+    }
+    if (has) {
+        const Step st = make_step(rs, b, p.dt);
+        const long long N = rs.kl - rs.kf + 1;
+        const int nseg = (int)min((N + I - 1) / I, (long long)p.ckpt_nseg);
+        float R0 = 0.f, R1 = 0.f, R2 = 0.f, Q = 1.f;
+        for (int s = nseg - 1; s >= 0; --s) {
+            const long long q0 = (long long)s * I;
+            const int n = (int)min((long long)I, N - q0);
+            // forward over the segment from its checkpoint
+            float T = p.ckpt[pix * p.ckpt_nseg + s];
+            long long cur_blk = -1;
+            Anchor an{};
+            for (int j = 0; j < n; ++j) {
+                const long long q = q0 + j;
+                const long long blk = q / kAnchor;
+                if (blk != cur_blk) {
+                    an = make_anchor(rs, b, p.dt, rs.kf + blk * kAnchor);
+                    cur_blk = blk;
+                }
+                tbuf[j * 64 + lane] = T;
+                const Cell c = locate(an, st, (int)(q - blk * kAnchor), snx, sny, snz);
+                const Classified e = classify(tft, trilinear(vox, c, snx, sxy), tf_k, tf_o);
+                T = T * exp2f(-e.a);
+            }
+            // reverse over the segment
+            for (int j = n - 1; j >= 0; --j) {
+                const long long q = q0 + j;
+                const long long blk = q / kAnchor;
+                if (blk != cur_blk) {
+                    an = make_anchor(rs, b, p.dt, rs.kf + blk * kAnchor);
+                    cur_blk = blk;
+                }
+                const Cell c = locate(an, st, (int)(q - blk * kAnchor), snx, sny, snz);
+                const Classified e = classify(tft, trilinear(vox, c, snx, sxy), tf_k, tf_o);
+                const float Tk = tbuf[j * 64 + lane];
+                const float om = exp2f(-e.a);          // 1 - alpha
+                const float al = 1.0f - om;
+                const float ta = Tk * al;
+                const float d_r = g.x * ta, d_g = g.y * ta, d_b = g.z * ta;
+                const float d_al = Tk * (g.x * (e.r - R0) + g.y * (e.g - R1) + g.z * (e.b - R2) +
+                                         g.w * Q);
+                const float d_ap = d_al * kLn2 * om;   // dL/da'
+                const float w1 = e.phi, w0 = 1.0f - e.phi;
+                float* g0 = &gtf[4 * e.seg];
+                atomicAdd(g0 + 0, w0 * d_r);
+                atomicAdd(g0 + 1, w0 * d_g);
+                atomicAdd(g0 + 2, w0 * d_b);
+                atomicAdd(g0 + 3, w0 * d_ap * a_scale);
+                if (w1 != 0.0f) {
+                    atomicAdd(g0 + 4, w1 * d_r);
+                    atomicAdd(g0 + 5, w1 * d_g);
+                    atomicAdd(g0 + 6, w1 * d_b);
+                    atomicAdd(g0 + 7, w1 * d_ap * a_scale);
+                }
+                if (e.inside) {
+                    const float4 D = tft.diff[e.seg];
+                    const float dv = tf_k * (d_r * D.x + d_g * D.y + d_b * D.z + d_ap * D.w);
+                    if (dv != 0.0f) {
+                        // stored index s -> global index clamp(lo + s - ghost)
+                        const long long gx0 = min(max((long long)bp.lo[0] + c.ix - b.ghost, 0LL), gnx - 1);
+                        const long long gx1 = min(max((long long)bp.lo[0] + c.ix + 1 - b.ghost, 0LL), gnx - 1);
+                        const long long gy0 = min(max((long long)bp.lo[1] + c.iy - b.ghost, 0LL), gny - 1);
+                        const long long gy1 = min(max((long long)bp.lo[1] + c.iy + 1 - b.ghost, 0LL), gny - 1);
+                        const long long gz0 = min(max((long long)bp.lo[2] + c.iz - b.ghost, 0LL), gnz - 1);
+                        const long long gz1 = min(max((long long)bp.lo[2] + c.iz + 1 - b.ghost, 0LL), gnz - 1);
+                        const float ux = 1.0f - c.fx, uy = 1.0f - c.fy, uz = 1.0f - c.fz;
+                        float* G = bp.grad_vox;
+                        const long long r00 = (gz0 * gny + gy0) * gnx, r10 = (gz0 * gny + gy1) * gnx;
+                        const long long r01 = (gz1 * gny + gy0) * gnx, r11 = (gz1 * gny + gy1) * gnx;
+                        atomicAdd(G + r00 + gx0, dv * ux * uy * uz);
+                        atomicAdd(G + r00 + gx1, dv * c.fx * uy * uz);
+                        atomicAdd(G + r10 + gx0, dv * ux * c.fy * uz);
+                        atomicAdd(G + r10 + gx1, dv * c.fx * c.fy * uz);
+                        atomicAdd(G + r01 + gx0, dv * ux * uy * c.fz);
+                        atomicAdd(G + r01 + gx1, dv * c.fx * uy * c.fz);
+                        atomicAdd(G + r11 + gx0, dv * ux * c.fy * c.fz);
+                        atomicAdd(G + r11 + gx1, dv * c.fx * c.fy * c.fz);
+                    }
+                }
+                R0 = fmaf(al, e.r, om * R0);
+                R1 = fmaf(al, e.g, om * R1);
+                R2 = fmaf(al, e.b, om * R2);
+                Q = om * Q;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = lane; e < 1024; e += 64) {
+        const float v = gtf[e];
+        if (v != 0.0f) atomicAdd(bp.grad_tf + e, v);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp, StorageK storage,
+                                 hipStream_t stream) {
+    const int blocks = p.tiles_x * p.tiles_y;
+    if (blocks == 0) return hipSuccess;
+    if (storage == kF16)
+        hipLaunchKernelGGL(march_backward<__half>, dim3(blocks), dim3(64), 0, stream, p, bp);
+    else
+        hipLaunchKernelGGL(march_backward<float>, dim3(blocks), dim3(64), 0, stream, p, bp);
+    return hipGetLastError();
+}
+
+}  // namespace dpvr

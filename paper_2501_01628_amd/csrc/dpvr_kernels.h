@@ -1,0 +1,114 @@
+// Internal interface between the host-side C-ABI (api.cpp) and the HIP
+// kernels (*.hip).  Plain structs passed to kernels by value.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace dpvr {
+
+// Camera frame, float64 (computed once per frame on the host).  Pixel (i, j)
+// maps to sx = 2 (i + 1/2) / W - 1, sy = 1 - 2 (j + 1/2) / H and
+//   perspective:  o = eye, d = normalize(f + (sx ax) r + (sy ay) u)
+//   orthographic: o = eye + (sx ax) r + (sy ay) u, d = f
+struct CameraK {
+    double eye[3], f[3], r[3], u[3];
+    double ax, ay;
+    int32_t kind;          // 0 perspective, 1 orthographic
+    int32_t width, height;
+    int32_t pad_;
+};
+
+// A brick as the kernels see it.
+struct BrickK {
+    const void* data;      // stored voxels (with ghost layer), x fastest
+    int32_t sdim[3];       // stored extents (owned + 2 ghost) in x, y, z
+    int32_t ghost;
+    double lo[3], hi[3];   // owned world box [lo, hi)
+    double origin[3];      // == lo
+    double spacing[3];
+};
+
+struct TFK {
+    const float* rgba;     // 256 x 4, device
+    float vmin, vmax, opacity_scale;
+    int32_t n;
+};
+
+struct MarchParams {
+    CameraK cam;
+    BrickK brick;
+    TFK tf;
+    double dt;
+    float ert_eps;
+    int32_t roi_x0, roi_y0, roi_w, roi_h;
+    int32_t tiles_x, tiles_y;
+    float* out_rgba;       // roi_h x roi_w x 4
+    float* out_depth;      // roi_h x roi_w
+    unsigned long long* samples;  // optional evaluated-sample counter
+    // checkpoints of the transmittance (adjoint support): when ckpt != NULL
+    // the forward writes, and the backward reads, T in front of every
+    // ckpt_interval-th owned sample, ckpt_nseg slots per ROI pixel
+    float* ckpt;
+    int32_t ckpt_interval;
+    int32_t ckpt_nseg;
+};
+
+constexpr int kMaxCkptInterval = 64;
+
+struct BackwardParams {
+    const float* d_part;   // roi_h x roi_w x 4: dL/dC_rgb, dL/dA
+    float* grad_tf;        // 256 x 4, accumulated (table units: raw alpha)
+    float* grad_vox;       // global voxel array, accumulated
+    int32_t vol_dims[3];   // global voxel grid (nx, ny, nz)
+    int32_t lo[3];         // global index of the brick's owned min corner
+};
+
+constexpr int kMaxPartials = 64;
+
+struct PartialK {
+    int32_t x0, y0, w, h;
+    const float* rgba;
+    const float* depth;
+};
+
+struct CompositeParams {
+    PartialK parts[kMaxPartials];
+    int32_t n;
+    int32_t width, height;
+    int32_t tiles_x;
+    float bg[4];
+    float* out;
+};
+
+// Backward of the composite: upstream dL/d(frame) and one ROI-sized output
+// buffer (h x w x 4) per partial.
+struct CompositeBackParams {
+    const float* d_out;
+    float* d_parts[kMaxPartials];
+};
+
+// Ingest from a global voxel array: gather the brick's ghost-padded box
+// (clamped to the grid) into its workspace.
+struct GatherParams {
+    const float* volume;
+    int32_t vol_dims[3];
+    int32_t lo[3];         // owned min corner, global index
+    int32_t sdim[3];       // stored extents (owned + 2 ghost)
+    int32_t ghost;
+};
+
+enum StorageK : int32_t { kF32 = 0, kF16 = 1 };
+
+// Launchers (return the hipError_t of the launch).
+hipError_t launch_ingest(const float* src, void* dst, int64_t count, StorageK storage,
+                         hipStream_t stream);
+hipError_t launch_march(const MarchParams& p, StorageK storage, hipStream_t stream);
+hipError_t launch_composite(const CompositeParams& p, hipStream_t stream);
+hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp, StorageK storage,
+                                 hipStream_t stream);
+hipError_t launch_composite_backward(const CompositeParams& p, const CompositeBackParams& bp,
+                                     hipStream_t stream);
+hipError_t launch_gather(const GatherParams& g, void* dst, StorageK storage, hipStream_t stream);
+
+}  // namespace dpvr

@@ -1,0 +1,198 @@
+// Device-side pieces shared by every kernel that marches rays through a
+// brick (forward, checkpointed forward, adjoint, batched): the float64 ray
+// setup and ownership scan, the float64 re-anchoring of float32 stored-index
+// coordinates, the trilinear sample and the classification table.  Sharing
+// them keeps the sample positions and values of all paths bit-identical.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <math.h>
+
+#include "dpvr_kernels.h"
+
+namespace dpvr {
+
+constexpr int kAnchor = 32;       // samples between float64 re-anchors
+constexpr float kLog2e = 1.4426950408889634f;
+
+struct RaySetup {
+    double o[3], d[3];
+    long long kf, kl;             // first / last owned sample index
+};
+
+__device__ inline bool owned(const double o[3], const double d[3], double t, const double lo[3],
+                             const double hi[3]) {
+#pragma clang fp contract(off)
+    double p0 = o[0] + t * d[0], p1 = o[1] + t * d[1], p2 = o[2] + t * d[2];
+    return p0 >= lo[0] && p0 < hi[0] && p1 >= lo[1] && p1 < hi[1] && p2 >= lo[2] && p2 < hi[2];
+}
+
+// Camera ray through pixel (px, py) and the brick's owned run [kf, kl] of the
+// global lattice t_k = (k + 1/2) dt.  float64, no contraction, in the
+// operation order of the documented formulas.
+__device__ inline bool setup_ray(const CameraK& cam, const BrickK& b, double dt, int px, int py,
+                                 RaySetup& rs) {
+#pragma clang fp contract(off)
+    const double W = (double)cam.width, H = (double)cam.height;
+    const double sx = (2.0 * ((double)px + 0.5)) / W - 1.0;
+    const double sy = 1.0 - (2.0 * ((double)py + 0.5)) / H;
+    const double x = sx * cam.ax, y = sy * cam.ay;
+    if (cam.kind == 0) {
+        double d0 = (cam.f[0] + x * cam.r[0]) + y * cam.u[0];
+        double d1 = (cam.f[1] + x * cam.r[1]) + y * cam.u[1];
+        double d2 = (cam.f[2] + x * cam.r[2]) + y * cam.u[2];
+        double n = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        rs.d[0] = d0 / n; rs.d[1] = d1 / n; rs.d[2] = d2 / n;
+        rs.o[0] = cam.eye[0]; rs.o[1] = cam.eye[1]; rs.o[2] = cam.eye[2];
+    } else {
+        rs.o[0] = (cam.eye[0] + x * cam.r[0]) + y * cam.u[0];
+        rs.o[1] = (cam.eye[1] + x * cam.r[1]) + y * cam.u[1];
+        rs.o[2] = (cam.eye[2] + x * cam.r[2]) + y * cam.u[2];
+        rs.d[0] = cam.f[0]; rs.d[1] = cam.f[1]; rs.d[2] = cam.f[2];
+    }
+    double tin = 0.0, tout = INFINITY;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (rs.d[c] == 0.0) {
+            if (rs.o[c] < b.lo[c] || rs.o[c] >= b.hi[c]) return false;
+            continue;
+        }
+        double ta = (b.lo[c] - rs.o[c]) / rs.d[c], tb = (b.hi[c] - rs.o[c]) / rs.d[c];
+        tin = fmax(tin, fmin(ta, tb));
+        tout = fmin(tout, fmax(ta, tb));
+    }
+    if (!(tout >= tin - 2.0 * dt)) return false;
+    long long k0 = (long long)fmax(floor(tin / dt - 0.5) - 2.0, 0.0);
+    long long k1 = (long long)(ceil(tout / dt - 0.5) + 2.0);
+    if (k1 < k0) return false;
+    // The owned samples form one contiguous run (convex box; every rounded
+    // coordinate is monotone in k); scan in from both ends of the widened range.
+    long long kf = k0;
+    while (kf <= k1 && !owned(rs.o, rs.d, ((double)kf + 0.5) * dt, b.lo, b.hi)) ++kf;
+    if (kf > k1) return false;
+    long long kl = k1;
+    while (kl > kf && !owned(rs.o, rs.d, ((double)kl + 0.5) * dt, b.lo, b.hi)) --kl;
+    rs.kf = kf;
+    rs.kl = kl;
+    return true;
+}
+
+// float32 stored-index coordinate of sample k = kb + j is  anchor + j * step,
+// with the anchor (integer part ia, fraction uf) computed in float64 at kb.
+struct Anchor {
+    int ia0, ia1, ia2;
+    float uf0, uf1, uf2;
+};
+
+__device__ inline Anchor make_anchor(const RaySetup& rs, const BrickK& b, double dt, long long kb) {
+#pragma clang fp contract(off)
+    const double t = ((double)kb + 0.5) * dt;
+    Anchor a;
+    double s0 = (rs.o[0] + t * rs.d[0] - b.origin[0]) / b.spacing[0] - 0.5 + (double)b.ghost;
+    double s1 = (rs.o[1] + t * rs.d[1] - b.origin[1]) / b.spacing[1] - 0.5 + (double)b.ghost;
+    double s2 = (rs.o[2] + t * rs.d[2] - b.origin[2]) / b.spacing[2] - 0.5 + (double)b.ghost;
+    double f0 = floor(s0), f1 = floor(s1), f2 = floor(s2);
+    a.ia0 = (int)f0; a.ia1 = (int)f1; a.ia2 = (int)f2;
+    a.uf0 = (float)(s0 - f0); a.uf1 = (float)(s1 - f1); a.uf2 = (float)(s2 - f2);
+    return a;
+}
+
+struct Step {
+    float s0, s1, s2;
+};
+
+__device__ inline Step make_step(const RaySetup& rs, const BrickK& b, double dt) {
+    Step s;
+    s.s0 = (float)(dt * rs.d[0] / b.spacing[0]);
+    s.s1 = (float)(dt * rs.d[1] / b.spacing[1]);
+    s.s2 = (float)(dt * rs.d[2] / b.spacing[2]);
+    return s;
+}
+
+// Position of sample j after the anchor: base stored index (clamped so that
+// the +1 neighbours stay inside the stored array) and trilinear fractions.
+struct Cell {
+    int ix, iy, iz;
+    float fx, fy, fz;
+};
+
+__device__ inline Cell locate(const Anchor& a, const Step& st, int j, int snx, int sny, int snz) {
+    const float fj = (float)j;
+    const float x = fmaf(fj, st.s0, a.uf0);
+    const float y = fmaf(fj, st.s1, a.uf1);
+    const float z = fmaf(fj, st.s2, a.uf2);
+    const float flx = floorf(x), fly = floorf(y), flz = floorf(z);
+    Cell c;
+    c.fx = x - flx; c.fy = y - fly; c.fz = z - flz;
+    c.ix = min(max(a.ia0 + (int)flx, 0), snx - 2);
+    c.iy = min(max(a.ia1 + (int)fly, 0), sny - 2);
+    c.iz = min(max(a.ia2 + (int)flz, 0), snz - 2);
+    return c;
+}
+
+template <typename TS>
+__device__ inline float ld(const TS* p, long long i);
+template <>
+__device__ inline float ld<float>(const float* p, long long i) { return p[i]; }
+template <>
+__device__ inline float ld<__half>(const __half* p, long long i) { return __half2float(p[i]); }
+
+template <typename TS>
+__device__ inline float trilinear(const TS* __restrict__ vox, const Cell& c, int snx, long long sxy) {
+    const long long base = (long long)c.iz * sxy + (long long)c.iy * snx + c.ix;
+    const float v000 = ld(vox, base), v100 = ld(vox, base + 1);
+    const float v010 = ld(vox, base + snx), v110 = ld(vox, base + snx + 1);
+    const float v001 = ld(vox, base + sxy), v101 = ld(vox, base + sxy + 1);
+    const float v011 = ld(vox, base + sxy + snx), v111 = ld(vox, base + sxy + snx + 1);
+    const float v00 = fmaf(c.fx, v100 - v000, v000);
+    const float v10 = fmaf(c.fx, v110 - v010, v010);
+    const float v01 = fmaf(c.fx, v101 - v001, v001);
+    const float v11 = fmaf(c.fx, v111 - v011, v011);
+    const float v0 = fmaf(c.fy, v10 - v00, v00);
+    const float v1 = fmaf(c.fy, v11 - v01, v01);
+    return fmaf(c.fz, v1 - v0, v0);
+}
+
+// Classification table in LDS: entry i = (r, g, b, a') with a' = alpha *
+// opacity_scale * dt * log2(e), and the difference to entry i + 1.
+struct TFTable {
+    float4 base[256];
+    float4 diff[256];
+};
+
+__device__ inline void load_tf(TFTable& t, const TFK& tf, double dt, int tid, int nthreads) {
+    const float a_scale = tf.opacity_scale * (float)dt * kLog2e;
+    for (int e = tid; e < 256; e += nthreads) {
+        float4 v0 = reinterpret_cast<const float4*>(tf.rgba)[e];
+        float4 v1 = reinterpret_cast<const float4*>(tf.rgba)[e < 255 ? e + 1 : 255];
+        v0.w *= a_scale;
+        v1.w *= a_scale;
+        t.base[e] = v0;
+        t.diff[e] = make_float4(v1.x - v0.x, v1.y - v0.y, v1.z - v0.z, v1.w - v0.w);
+    }
+}
+
+struct Classified {
+    float r, g, b, a;   // a = pre-scaled opacity a'
+    float phi;
+    int seg;
+    bool inside;        // v within [vmin, vmax] (the lookup is not clamped)
+};
+
+__device__ inline Classified classify(const TFTable& t, float v, float tf_k, float tf_o) {
+    Classified c;
+    const float sr = fmaf(v, tf_k, tf_o);
+    c.inside = sr >= 0.0f && sr <= 255.0f;
+    const float s = fminf(fmaxf(sr, 0.0f), 255.0f);
+    c.seg = min((int)s, 254);
+    c.phi = s - (float)c.seg;
+    const float4 eb = t.base[c.seg], ed = t.diff[c.seg];
+    c.r = fmaf(c.phi, ed.x, eb.x);
+    c.g = fmaf(c.phi, ed.y, eb.y);
+    c.b = fmaf(c.phi, ed.z, eb.z);
+    c.a = fmaf(c.phi, ed.w, eb.w);
+    return c;
+}
+
+}  // namespace dpvr

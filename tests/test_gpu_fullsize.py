@@ -1,0 +1,95 @@
+"""Parity at the full benchmark size (1024x1024x512 float32 field, 16 uneven
+kd bricks, 1920x1080, step 0.5, opacity 0.05), in the launch configuration
+the benchmark times: the whole frame is rendered on the GPU, and a seeded
+sample of pixels (random, plus every pixel of a few rows crossing brick
+boundaries) is recomputed one by one by the oracle.  Also checks the
+device-side sample counter against the oracle's count on a smaller case."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_01628_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.config_c2()
+
+
+def _pixels(W, H, seed, n=2500):
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(W * H, n, replace=False)
+    pix = [np.stack([idx % W, idx // W], 1)]
+    for row in (int(H * 0.37), int(H * 0.5), int(H * 0.61)):
+        pix.append(np.stack([np.arange(0, W, 3), np.full(len(range(0, W, 3)), row)], 1))
+    return np.concatenate(pix).astype(np.int32)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 2e-3)])
+def test_c2_fullsize_sampled(dp, c2, storage, tol):
+    sc = c2
+    st = dp.VR_F16 if storage == "f16" else dp.VR_F32
+    r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange, sc.opacity_scale,
+                    sc.step, storage=st)
+    r.set_camera(sc.camera)
+    bg = (0.1, 0.2, 0.3, 1.0)
+    img = r.render(bg)
+    r.synchronize()
+    W, H = sc.camera["width"], sc.camera["height"]
+    pix = _pixels(W, H, 7)
+    got = img.cpu().numpy()[pix[:, 1], pix[:, 0]].astype(np.float64)
+    parts_gpu = [r.partial_arrays(k) for k in range(len(r.bricks))]
+    rois = list(r.rois)
+    parts_np = [(a.cpu().numpy(), d.cpu().numpy()) for a, d in parts_gpu]
+    r.close()
+    ref, ref_parts, cnt = oracle.render_scene(sc, bg=bg, pixels=pix)
+    err = float(np.max(np.abs(got - ref)))
+    print(f"c2 {storage}: {len(pix)} sampled pixels, max err {err:.3e}, {cnt[0]} samples")
+    assert err <= tol, err
+    # per-partial check at the sampled pixels (depth keys exact)
+    for (x0, y0, w, h), (pr, pd), (rr, rd) in zip(rois, parts_np, ref_parts):
+        inside = (pix[:, 0] >= x0) & (pix[:, 0] < x0 + w) & (pix[:, 1] >= y0) & (pix[:, 1] < y0 + h)
+        assert np.all(np.isinf(rd[~inside]))
+        q = pix[inside]
+        g_r = pr[q[:, 1] - y0, q[:, 0] - x0].astype(np.float64)
+        g_d = pd[q[:, 1] - y0, q[:, 0] - x0].astype(np.float64)
+        assert np.array_equal(g_d, rd[inside].astype(np.float32).astype(np.float64))
+        if storage == "f32":
+            assert np.max(np.abs(g_r - rr[inside]), initial=0.0) <= tol
+
+
+def test_sample_counter_matches_oracle(dp):
+    """ERT off: the device count of evaluated samples equals the oracle's
+    count of owned lattice points exactly (an integer, decided in float64
+    on both sides); ERT on: equal up to float32-vs-float64 stopping decisions."""
+    sc = synth.config_c1()
+    for ert in (0.0, 2.0 ** -20):
+        r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange,
+                        30.0, sc.step, ert)
+        r.set_camera(sc.camera)
+        r.reset_samples()
+        r.render()
+        got = r.sample_counts()
+        r.close()
+        counts = []
+        for b in sc.bricks:
+            _, _, cnt = oracle.render_brick(sc.camera, b.voxels, b.dims, 1, b.origin, (1, 1, 1),
+                                            sc.tf, sc.vrange, 30.0, sc.step, 2.0 ** -20)
+            counts.append(cnt)
+        if ert == 0.0:
+            assert [int(g) for g in got] == [int(c[0]) for c in counts]
+        else:
+            for g, c in zip(got, counts):
+                assert c[1] < c[0]
+                assert abs(int(g) - int(c[1])) <= 1e-4 * c[1] + 16
