@@ -73,6 +73,16 @@ _SIGS = {
     "vr_partial_roi": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)], _st),
     "vr_render_partial": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial)], _st),
     "vr_composite": ([C.c_void_p, C.POINTER(vr_partial), C.c_int32, _f4, C.c_void_p], _st),
+    "vr_brick_set_data_global": ([C.c_void_p, C.c_void_p, _i3, _i3], _st),
+    "vr_checkpoint_size": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
+                            C.POINTER(C.c_size_t)], _st),
+    "vr_render_partial_checkpointed": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
+                                        C.c_void_p, C.c_size_t], _st),
+    "vr_composite_backward": ([C.c_void_p, C.POINTER(vr_partial), C.c_int32, _f4, C.c_void_p,
+                               C.POINTER(C.c_void_p)], _st),
+    "vr_render_partial_backward": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
+                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    _i3, _i3], _st),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -203,6 +213,35 @@ def vr_composite(ctx, parts, bg, out):
     _check(_lib.vr_composite(ctx, arr, n, _f4(*bg), _ptr(out)), ctx)
 
 
+def vr_brick_set_data_global(brick, volume, vol_dims, lo, ctx=None):
+    _check(_lib.vr_brick_set_data_global(brick, _ptr(volume), _i3(*vol_dims), _i3(*lo)), ctx)
+
+
+def vr_checkpoint_size(ctx, brick, part, interval):
+    n = C.c_size_t()
+    _check(_lib.vr_checkpoint_size(ctx, brick, C.byref(part), int(interval), C.byref(n)), ctx)
+    return n.value
+
+
+def vr_render_partial_checkpointed(ctx, brick, part, interval, ckpt, ckpt_bytes):
+    _check(_lib.vr_render_partial_checkpointed(ctx, brick, C.byref(part), int(interval), _ptr(ckpt),
+                                               int(ckpt_bytes)), ctx)
+
+
+def vr_composite_backward(ctx, parts, bg, d_out, d_parts):
+    n = len(parts)
+    arr = (vr_partial * max(n, 1))(*parts)
+    dps = (C.c_void_p * max(n, 1))(*[_ptr(d) for d in d_parts])
+    _check(_lib.vr_composite_backward(ctx, arr, n, _f4(*bg), _ptr(d_out), dps), ctx)
+
+
+def vr_render_partial_backward(ctx, brick, part, interval, ckpt, ckpt_bytes, d_part, grad_tf,
+                               grad_volume, vol_dims, lo):
+    _check(_lib.vr_render_partial_backward(ctx, brick, C.byref(part), int(interval), _ptr(ckpt),
+                                           int(ckpt_bytes), _ptr(d_part), _ptr(grad_tf),
+                                           _ptr(grad_volume), _i3(*vol_dims), _i3(*lo)), ctx)
+
+
 def set_camera(ctx, cam: dict):
     """Apply a camera dict (``kind``, ``eye``, ``target``/``dir``, ``up``,
     ``fovy_deg``/``view_height``, ``width``, ``height``)."""
@@ -324,3 +363,124 @@ class Renderer:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------- differentiable path
+class DiffRenderer:
+    """Differentiable frame of a bricked volume: ``render(tf, volume, cam)``
+    returns the composited frame as a torch tensor whose backward runs the
+    library's composite backward and adjoint march, giving gradients with
+    respect to the (256, 4) transfer-function table and the (nz, ny, nx)
+    global voxel array.  ``boxes`` = [(lo, hi), ...] integer owned boxes of
+    the global grid (x, y, z order); early termination is off."""
+
+    def __init__(self, vol_dims, boxes, vrange=(0.0, 1.0), opacity_scale=1.0, dt=0.5,
+                 interval=64, storage=VR_F32, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = vr_context_create(device, self.stream)
+        self.vol_dims = tuple(int(v) for v in vol_dims)
+        self.vrange, self.opacity_scale, self.dt = vrange, float(opacity_scale), float(dt)
+        self.interval = int(interval)
+        self.bricks, self.los, self._ws = [], [], []
+        vr_set_render_params(self.ctx, self.dt, 0.0)
+        for lo, hi in boxes:
+            dims = tuple(int(h - l) for l, h in zip(lo, hi))
+            nbytes = vr_brick_workspace_size(dims, 1, storage)
+            ws = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=self.device)
+            base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+            self.bricks.append(vr_brick_create(self.ctx, dims, 1, tuple(float(x) for x in lo),
+                                               (1.0, 1.0, 1.0), storage, base, nbytes))
+            self.los.append(tuple(int(x) for x in lo))
+            self._ws.append(ws)
+
+    def _load(self, tf, volume, cam):
+        vr_set_transfer_function(self.ctx, tf, TF_ENTRIES, self.vrange[0], self.vrange[1],
+                                 self.opacity_scale)
+        for b, lo in zip(self.bricks, self.los):
+            vr_brick_set_data_global(b, volume, self.vol_dims, lo, self.ctx)
+        set_camera(self.ctx, cam)
+
+    def render(self, tf, volume, cam, bg=(0.0, 0.0, 0.0, 0.0)):
+        return _RenderFn.apply(tf, volume, self, cam, tuple(float(x) for x in bg))
+
+    def close(self):
+        if self.ctx is None:
+            return
+        vr_synchronize(self.ctx)
+        for b in self.bricks:
+            vr_brick_release(b)
+        vr_context_release(self.ctx)
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autograd_function():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, tf, volume, dr, cam, bg):
+            torch_ = dr.torch
+            tf_c = tf.detach().to(dr.device, torch_.float32).contiguous()
+            vol_c = volume.detach().to(dr.device, torch_.float32).contiguous()
+            dr._load(tf_c, vol_c, cam)
+            W, H = int(cam["width"]), int(cam["height"])
+            parts, keep, ckpts = [], [], []
+            for b in dr.bricks:
+                roi = vr_partial_roi(dr.ctx, b)
+                n = max(roi[2] * roi[3], 1)
+                rgba = torch_.empty(n * 4, dtype=torch_.float32, device=dr.device)
+                depth = torch_.empty(n, dtype=torch_.float32, device=dr.device)
+                part = make_partial(roi, rgba, depth)
+                nb = max(vr_checkpoint_size(dr.ctx, b, part, dr.interval), 4)
+                ck = torch_.empty(nb // 4, dtype=torch_.float32, device=dr.device)
+                vr_render_partial_checkpointed(dr.ctx, b, part, dr.interval, ck, nb)
+                parts.append(part)
+                keep.append((rgba, depth))
+                ckpts.append((ck, nb))
+            out = torch_.empty(H, W, 4, dtype=torch_.float32, device=dr.device)
+            vr_composite(dr.ctx, parts, bg, out)
+            fctx.dr, fctx.cam, fctx.bg = dr, cam, bg
+            fctx.parts, fctx.keep, fctx.ckpts = parts, keep, ckpts
+            fctx.save_for_backward(tf_c, vol_c)
+            return out
+
+        @staticmethod
+        def backward(fctx, g_out):
+            dr = fctx.dr
+            torch_ = dr.torch
+            tf_c, vol_c = fctx.saved_tensors
+            # another forward may have changed the context state since
+            dr._load(tf_c, vol_c, fctx.cam)
+            g = g_out.detach().to(dr.device, torch_.float32).contiguous()
+            d_parts = [torch_.empty(max(p.w * p.h, 1) * 4, dtype=torch_.float32, device=dr.device)
+                       for p in fctx.parts]
+            vr_composite_backward(dr.ctx, fctx.parts, fctx.bg, g, d_parts)
+            grad_tf = torch_.zeros(TF_ENTRIES, 4, dtype=torch_.float32, device=dr.device)
+            grad_vol = torch_.zeros_like(vol_c)
+            for b, lo, part, (ck, nb), dp in zip(dr.bricks, dr.los, fctx.parts, fctx.ckpts, d_parts):
+                vr_render_partial_backward(dr.ctx, b, part, dr.interval, ck, nb, dp, grad_tf,
+                                           grad_vol, dr.vol_dims, lo)
+            return grad_tf, grad_vol, None, None, None
+
+    return RenderFn
+
+
+class _LazyFn:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFn._fn is None:
+            _LazyFn._fn = _autograd_function()
+        return _LazyFn._fn.apply(*args)
+
+
+_RenderFn = _LazyFn()
