@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c1"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c1", "c3"], default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
@@ -91,12 +91,110 @@ def cpu_baseline(sc, target_s):
                       f"composite, {samples} samples (no early termination) in {t:.1f} s"}
 
 
+def bench_batch(args):
+    """Batched workload: 14 uneven bricks x 6 time steps x 3 fields x 4 cameras
+    at 1024^2 (1008 partial images, 72 frames): the plain path (per frame,
+    one launch per brick + one composite) against the batch (one graph:
+    persistent queued march + one composite launch for all frames), for
+    float32 and float16 storage."""
+    import numpy as np
+    import torch
+
+    import paper_2501_01628_amd as dp
+    import synth
+    t0 = time.perf_counter()
+    d = synth.config_c3()
+    log(f"generated c3 ({len(d['bricks'])} brick-volumes) in {time.perf_counter() - t0:.1f} s")
+    keys = sorted({(t, f) for t, f, _, _, _ in d["bricks"]})
+    out = {"metric": "Msamples/s (batched render+composite, samples evaluated per batch x batches/s)",
+           "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "c3: 14 uneven bricks (U{64..320}^3) x 6 time steps x 3 fields x "
+                                  "4 cameras at 1024x1024, step 0.5, opacity 0.1; 1008 partials, "
+                                  "72 frames of 14-partial sort-last composites"}}
+    results = {}
+    for storage in ("f32", "f16"):
+        st = dp.VR_F16 if storage == "f16" else dp.VR_F32
+        br = dp.BatchRenderer(dt=d["step"])
+        tfi = br.add_tf(d["tf"], (0, 1), d["opacity_scale"])
+        for (t, f, b, lo, vox) in d["bricks"]:
+            br.add_brick(vox, lo, storage=st)
+        br.drop_uploads()
+        cams = [br.add_camera(c) for c in d["cameras"]]
+        for (t, f) in keys:
+            ids = [i for i, (tt, ff, _, _, _) in enumerate(d["bricks"]) if (tt, ff) == (t, f)]
+            for c in cams:
+                br.add_frame(c, ids, tfi)
+        br.build()
+        tuned_ms = br.autotune(reps=2)
+        for _ in range(args.warmup):
+            br.launch()
+        br.samples.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(br.stream)
+        for _ in range(args.steps):
+            br.launch()
+        e1.record(br.stream)
+        torch.cuda.synchronize()
+        batch_ms = e0.elapsed_time(e1) / args.steps
+        samples = int(br.samples.sum().item()) // args.steps
+        wg, order = br.config()
+        # plain path on the same bricks: per frame, one march launch per brick + a composite
+        ctx = br.ctx
+        dp.vr_set_transfer_function(ctx, br._tf_keep[0], 256, 0.0, 1.0, d["opacity_scale"])
+        frame_parts = []
+        fi = 0
+        for (t, f) in keys:
+            ids = [i for i, (tt, ff, _, _, _) in enumerate(d["bricks"]) if (tt, ff) == (t, f)]
+            for c in cams:
+                frame_parts.append((c, [br.bricks[i] for i in ids],
+                                    [dp.make_partial(*br.parts[fi * len(ids) + k]) for k in range(len(ids))],
+                                    br.frames[fi]))
+                fi += 1
+
+        def plain_pass():
+            for c, bricks, parts, outf in frame_parts:
+                dp.set_camera(ctx, d["cameras"][c])
+                for b, p in zip(bricks, parts):
+                    dp.vr_render_partial(ctx, b, p)
+                dp.vr_composite(ctx, parts, (0.0, 0.0, 0.0, 0.0), outf)
+        plain_pass()
+        torch.cuda.synchronize()
+        e0.record(br.stream)
+        plain_steps = max(1, args.steps // 4)
+        for _ in range(plain_steps):
+            plain_pass()
+        e1.record(br.stream)
+        torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1) / plain_steps
+        results[storage] = {"batch_ms": batch_ms, "plain_ms": plain_ms, "samples": samples,
+                            "autotune": {"wg_per_cu": wg, "order": ["as given", "by brick"][order],
+                                         "tuned_ms": tuned_ms},
+                            "msamples_per_s": samples / (batch_ms * 1e-3) / 1e6,
+                            "speedup_vs_plain": plain_ms / batch_ms}
+        log(f"c3 {storage}: batch {batch_ms:.3f} ms, plain {plain_ms:.3f} ms, {samples} samples, "
+            f"wg/cu {wg}, order {order}")
+        br.close()
+        torch.cuda.empty_cache()
+    out["value"] = results["f32"]["msamples_per_s"]
+    out["ms_per_step"] = results["f32"]["batch_ms"]
+    out["storage"] = results
+    out["f16_vs_f32_batch_speedup"] = results["f32"]["batch_ms"] / results["f16"]["batch_ms"]
+    out["f16_batch_vs_f32_plain_speedup"] = results["f32"]["plain_ms"] / results["f16"]["batch_ms"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes, not built)"}))
         return 2
+    if args.workload == "c3":
+        return bench_batch(args)
     import numpy as np
     import torch
 
@@ -130,29 +228,28 @@ def main():
     log(f"warmup {args.warmup} done")
 
     nb = len(r.bricks)
+    # one march launch per frame (all partials through one work queue), then the composite
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(nb + 1)] for _ in range(args.steps)]
+           for _ in range(2)] for _ in range(args.steps)]
     r.reset_samples()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for s in range(args.steps):
-        for k, (b, p) in enumerate(zip(r.bricks, r.partials)):
-            ev[s][k][0].record(stream)
-            dp.vr_render_partial(r.ctx, b, p)
-            ev[s][k][1].record(stream)
-        ev[s][nb][0].record(stream)
+        ev[s][0][0].record(stream)
+        r.render_partials()
+        ev[s][0][1].record(stream)
+        ev[s][1][0].record(stream)
         r.composite(bg)
-        ev[s][nb][1].record(stream)
+        ev[s][1][1].record(stream)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_per_step = t_total / args.steps * 1e3
     samples = int(r.sample_counts().sum()) // args.steps
-    march_ms = np.zeros(nb)
+    march_ms = np.zeros(1)
     comp_ms = 0.0
     for s in range(args.steps):
-        for k in range(nb):
-            march_ms[k] += ev[s][k][0].elapsed_time(ev[s][k][1])
-        comp_ms += ev[s][nb][0].elapsed_time(ev[s][nb][1])
+        march_ms[0] += ev[s][0][0].elapsed_time(ev[s][0][1])
+        comp_ms += ev[s][1][0].elapsed_time(ev[s][1][1])
     march_ms /= args.steps
     comp_ms /= args.steps
     log(f"timed {args.steps} frames: {ms_per_step:.3f} ms/frame, march {march_ms.sum():.3f} ms, "
@@ -181,14 +278,14 @@ def main():
         "march_ms_per_frame": float(march_ms.sum()),
         "composite_ms_per_frame": comp_ms,
         "roofline": {
-            "kernel": "march_direct (per-brick ray cast)",
+            "kernel": "march_queue (all bricks' partials, one persistent launch)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "launches_per_frame": nb,
+            "launches_per_frame": 1,
             "algorithmic_bytes_per_frame": int(sum(march_alg)),
         },
         "composite_roofline": {"achieved": comp_alg / (comp_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,

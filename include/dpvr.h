@@ -130,7 +130,8 @@ vr_status vr_synchronize(vr_context ctx);
 
 /* ---------------------------------------------------------------- bricks */
 /* Bytes of device workspace a brick of `dims` owned voxels (nx, ny, nz, each
- * >= 1) with `ghost` ghost layers (must be 1) needs at precision `storage`.
+ * >= 1) with `ghost` ghost layers (must be 1) needs at precision `storage`:
+ * the ghost-padded voxels with rows padded to a multiple of 8 elements.
  * Host-only; needs no context.  Errors: VR_ERR_INVALID_ARG. */
 vr_status vr_brick_workspace_size(const int32_t dims[3], int32_t ghost, vr_dtype storage,
                                   size_t* bytes);
@@ -206,6 +207,14 @@ vr_status vr_set_camera_orthographic(vr_context ctx, const double pos[3], const 
  * dt = 0.5, ert_epsilon = 2^-20. */
 vr_status vr_set_render_params(vr_context ctx, double dt, float ert_epsilon);
 
+/* Launch path of the forward march; every path computes bit-identical
+ * images (the sample positions and values do not depend on it):
+ *   VR_PATH_STAGED  a workgroup per 16x16 pixel tile stages each slab of
+ *                   brick slices its rays cross through LDS (default);
+ *   VR_PATH_DIRECT  one wavefront per 8x8 tile reads voxels from HBM. */
+typedef enum { VR_PATH_STAGED = 0, VR_PATH_DIRECT = 1 } vr_path;
+vr_status vr_set_march_path(vr_context ctx, vr_path path);
+
 /* --------------------------------------------------------------- render */
 /* Host-only: the smallest pixel rectangle of the current camera's frame that
  * holds every pixel whose ray can own a sample of `brick` (its owned box
@@ -224,6 +233,22 @@ vr_status vr_partial_roi(vr_context ctx, vr_brick brick, int32_t roi[4]);
  * VR_ERR_DEVICE. */
 vr_status vr_render_partial(vr_context ctx, vr_brick brick, const vr_partial* part);
 
+/* Device workspace vr_render_partials needs for n partials (a job table and
+ * a work-queue counter).  Host-only.  Errors: VR_ERR_INVALID_ARG (n < 0). */
+vr_status vr_frame_workspace_size(int32_t n, size_t* bytes);
+
+/* Render the partial images of n bricks in one persistent launch (per
+ * storage precision): the 16x16 tiles of all n ROIs form one device work
+ * queue, so bricks that are small on screen still fill the GPU.  Results are
+ * bit-identical to n calls of vr_render_partial.  bricks and parts are host
+ * arrays of n entries; workspace is caller device memory of at least
+ * vr_frame_workspace_size(n) bytes, 256-byte aligned, written by this call
+ * (the job table is copied from host memory, so the call is not meant for
+ * stream capture; the batch API below is) and borrowed until the enqueued
+ * work has run.  Errors: as vr_render_partial, and VR_ERR_WORKSPACE. */
+vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
+                             const vr_partial* parts, void* workspace, size_t workspace_bytes);
+
 /* Sort-last composite (paper Sec. 3: the framebuffer ends up on the main
  * rank): for every pixel of the frame, the n partials (0 <= n <=
  * DPVR_MAX_PARTIALS) are ordered by ascending depth key (ties: lower index
@@ -234,6 +259,89 @@ vr_status vr_render_partial(vr_context ctx, vr_brick brick, const vr_partial* pa
  * Errors: VR_ERR_INVALID_ARG, VR_ERR_STATE (no camera), VR_ERR_DEVICE. */
 vr_status vr_composite(vr_context ctx, const vr_partial* parts, int32_t n, const float bg[4],
                        float* out);
+
+/* -------------------------------------------------------------- batches */
+/* Many partial images -- bricks x time steps x fields x cameras -- and the
+ * frames composited from them, as one unit of work: one persistent march
+ * launch per storage precision over a device work queue of (job, tile)
+ * tickets, then one launch compositing every frame, captured once into a
+ * HIP graph and replayed by vr_batch_launch.  The paper's data-parallel
+ * renderers queue and batch work to amortise latency (Sec. 2.2); here the
+ * unit is a 16x16 tile of a partial image. */
+typedef struct vr_batch_s* vr_batch;
+
+typedef struct {
+    int32_t kind;          /* 0 perspective (pinhole), 1 orthographic */
+    int32_t width, height;
+    int32_t pad_;
+    double eye[3];         /* perspective eye / orthographic image centre */
+    double target[3];      /* perspective look-at point / orthographic view direction */
+    double up[3];
+    double fovy_deg;       /* perspective vertical field of view / orthographic view height */
+} vr_camera_desc;
+
+typedef struct {
+    const float* rgba;     /* device, 256 x 4, as for vr_set_transfer_function */
+    float vmin, vmax, opacity_scale;
+    int32_t pad_;
+} vr_tf_desc;
+
+typedef struct {
+    vr_brick brick;        /* the brick, with the data this job renders */
+    int32_t camera;        /* index into the batch's cameras */
+    int32_t tf;            /* index into the batch's transfer functions */
+    vr_partial part;       /* ROI (see vr_camera_roi) and output buffers */
+} vr_batch_job;
+
+typedef struct {
+    int32_t camera;        /* the frame's camera (all its jobs use it) */
+    int32_t first_job;     /* its partials are jobs [first_job, first_job + n_jobs) */
+    int32_t n_jobs;        /* 0 .. DPVR_MAX_PARTIALS */
+    int32_t pad_;
+    float bg[4];
+    float* out;            /* device, height * width * 4 floats */
+} vr_batch_frame;
+
+/* Host-only: the ROI of `brick` in the frame of camera `cam` (as
+ * vr_partial_roi does for the context camera). */
+vr_status vr_camera_roi(vr_context ctx, vr_brick brick, const vr_camera_desc* cam,
+                        int32_t roi[4]);
+
+/* Device workspace a batch of n_jobs jobs and n_frames frames needs. */
+vr_status vr_batch_workspace_size(int32_t n_jobs, int32_t n_frames, size_t* bytes);
+
+/* Build a batch: validates every job and frame, writes the job tables into
+ * workspace (caller device memory, >= vr_batch_workspace_size, 256-byte
+ * aligned, borrowed for the batch's lifetime; a synchronous copy), and
+ * captures the launches into a HIP graph.  dt and ert_epsilon come from the
+ * context at creation.  Bricks' data must not change while the batch may
+ * run; output and TF buffers are borrowed for its lifetime.
+ * Errors: VR_ERR_INVALID_HANDLE, VR_ERR_INVALID_ARG, VR_ERR_WORKSPACE,
+ * VR_ERR_STATE (a brick without data), VR_ERR_DEVICE. */
+vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_desc* cameras,
+                          int32_t n_tfs, const vr_tf_desc* tfs, int32_t n_jobs,
+                          const vr_batch_job* jobs, int32_t n_frames, const vr_batch_frame* frames,
+                          void* workspace, size_t workspace_bytes, vr_batch* out);
+
+/* Enqueue the whole batch on the context stream (one graph launch).  Every
+ * partial and frame equals what vr_render_partial / vr_composite would
+ * produce, bit for bit, whatever launch configuration the batch uses. */
+vr_status vr_batch_launch(vr_batch batch);
+
+/* Launch-configuration search: time each candidate configuration (persistent
+ * workgroups per CU x job order: as given, or grouped by brick so that the
+ * cameras of one brick run together and share L2) over `reps` replays, keep
+ * the fastest and report its average time per launch in *best_ms.  When the
+ * environment variable DPVR_AUTOTUNE_CACHE names a file, a configuration
+ * found earlier for the same batch shape and device is reused from it (and
+ * new results are appended).  Synchronises the context stream. */
+vr_status vr_batch_autotune(vr_batch batch, int32_t reps, double* best_ms);
+
+/* The batch's current configuration: workgroups per CU and job order
+ * (0 = as given, 1 = grouped by brick). */
+vr_status vr_batch_config(vr_batch batch, int32_t* wg_per_cu, int32_t* order);
+
+vr_status vr_batch_release(vr_batch batch);
 
 /* -------------------------------------------------------------- adjoint */
 /* Differentiable rendering: gradients of a scalar loss L of the frame with

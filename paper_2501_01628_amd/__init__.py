@@ -36,6 +36,7 @@ _lib = C.CDLL(LIB_PATH)
 VR_OK, VR_ERR_INVALID_ARG, VR_ERR_INVALID_HANDLE, VR_ERR_WORKSPACE = 0, -1, -2, -3
 VR_ERR_UNSUPPORTED, VR_ERR_DEVICE, VR_ERR_STATE = -4, -5, -6
 VR_F32, VR_F16 = 0, 1
+VR_PATH_STAGED, VR_PATH_DIRECT = 0, 1
 TF_ENTRIES = 256
 MAX_PARTIALS = 64
 
@@ -43,6 +44,26 @@ MAX_PARTIALS = 64
 class vr_partial(C.Structure):
     _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("w", C.c_int32), ("h", C.c_int32),
                 ("rgba", C.c_void_p), ("depth", C.c_void_p), ("samples", C.c_void_p)]
+
+
+class vr_camera_desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("pad_", C.c_int32),
+                ("eye", C.c_double * 3), ("target", C.c_double * 3), ("up", C.c_double * 3),
+                ("fovy_deg", C.c_double)]
+
+
+class vr_tf_desc(C.Structure):
+    _fields_ = [("rgba", C.c_void_p), ("vmin", C.c_float), ("vmax", C.c_float),
+                ("opacity_scale", C.c_float), ("pad_", C.c_int32)]
+
+
+class vr_batch_job(C.Structure):
+    _fields_ = [("brick", C.c_void_p), ("camera", C.c_int32), ("tf", C.c_int32), ("part", vr_partial)]
+
+
+class vr_batch_frame(C.Structure):
+    _fields_ = [("camera", C.c_int32), ("first_job", C.c_int32), ("n_jobs", C.c_int32),
+                ("pad_", C.c_int32), ("bg", C.c_float * 4), ("out", C.c_void_p)]
 
 
 _i3 = C.c_int32 * 3
@@ -74,6 +95,19 @@ _SIGS = {
     "vr_render_partial": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial)], _st),
     "vr_composite": ([C.c_void_p, C.POINTER(vr_partial), C.c_int32, _f4, C.c_void_p], _st),
     "vr_brick_set_data_global": ([C.c_void_p, C.c_void_p, _i3, _i3], _st),
+    "vr_set_march_path": ([C.c_void_p, C.c_int], _st),
+    "vr_frame_workspace_size": ([C.c_int32, C.POINTER(C.c_size_t)], _st),
+    "vr_camera_roi": ([C.c_void_p, C.c_void_p, C.POINTER(vr_camera_desc), C.POINTER(C.c_int32)], _st),
+    "vr_batch_workspace_size": ([C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], _st),
+    "vr_batch_create": ([C.c_void_p, C.c_int32, C.POINTER(vr_camera_desc), C.c_int32,
+                         C.POINTER(vr_tf_desc), C.c_int32, C.POINTER(vr_batch_job), C.c_int32,
+                         C.POINTER(vr_batch_frame), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)], _st),
+    "vr_batch_launch": ([C.c_void_p], _st),
+    "vr_batch_autotune": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double)], _st),
+    "vr_batch_config": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], _st),
+    "vr_batch_release": ([C.c_void_p], _st),
+    "vr_render_partials": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_partial),
+                            C.c_void_p, C.c_size_t], _st),
     "vr_checkpoint_size": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
                             C.POINTER(C.c_size_t)], _st),
     "vr_render_partial_checkpointed": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
@@ -213,6 +247,79 @@ def vr_composite(ctx, parts, bg, out):
     _check(_lib.vr_composite(ctx, arr, n, _f4(*bg), _ptr(out)), ctx)
 
 
+def vr_set_march_path(ctx, path):
+    _check(_lib.vr_set_march_path(ctx, int(path)), ctx)
+
+
+def vr_frame_workspace_size(n):
+    b = C.c_size_t()
+    _check(_lib.vr_frame_workspace_size(int(n), C.byref(b)))
+    return b.value
+
+
+def vr_render_partials(ctx, bricks, parts, workspace, workspace_bytes):
+    n = len(bricks)
+    hb = (C.c_void_p * max(n, 1))(*bricks)
+    hp = (vr_partial * max(n, 1))(*parts)
+    _check(_lib.vr_render_partials(ctx, n, hb, hp, _ptr(workspace), int(workspace_bytes)), ctx)
+
+
+def camera_desc(cam: dict) -> vr_camera_desc:
+    d = vr_camera_desc()
+    persp = cam.get("kind", "perspective") == "perspective"
+    d.kind = 0 if persp else 1
+    d.width, d.height = int(cam["width"]), int(cam["height"])
+    d.eye[:] = [float(v) for v in cam["eye"]]
+    d.target[:] = [float(v) for v in (cam["target"] if persp else cam["dir"])]
+    d.up[:] = [float(v) for v in cam["up"]]
+    d.fovy_deg = float(cam["fovy_deg"] if persp else cam["view_height"])
+    return d
+
+
+def vr_camera_roi(ctx, brick, cam):
+    roi = (C.c_int32 * 4)()
+    d = cam if isinstance(cam, vr_camera_desc) else camera_desc(cam)
+    _check(_lib.vr_camera_roi(ctx, brick, C.byref(d), roi), ctx)
+    return tuple(roi)
+
+
+def vr_batch_workspace_size(n_jobs, n_frames):
+    b = C.c_size_t()
+    _check(_lib.vr_batch_workspace_size(int(n_jobs), int(n_frames), C.byref(b)))
+    return b.value
+
+
+def vr_batch_create(ctx, cameras, tfs, jobs, frames, workspace, workspace_bytes):
+    hc = (vr_camera_desc * max(len(cameras), 1))(*cameras)
+    ht = (vr_tf_desc * max(len(tfs), 1))(*tfs)
+    hj = (vr_batch_job * max(len(jobs), 1))(*jobs)
+    hf = (vr_batch_frame * max(len(frames), 1))(*frames)
+    h = C.c_void_p()
+    _check(_lib.vr_batch_create(ctx, len(cameras), hc, len(tfs), ht, len(jobs), hj, len(frames), hf,
+                                _ptr(workspace), int(workspace_bytes), C.byref(h)), ctx)
+    return h.value
+
+
+def vr_batch_launch(batch, ctx=None):
+    _check(_lib.vr_batch_launch(batch), ctx)
+
+
+def vr_batch_autotune(batch, reps=3, ctx=None):
+    ms = C.c_double()
+    _check(_lib.vr_batch_autotune(batch, int(reps), C.byref(ms)), ctx)
+    return ms.value
+
+
+def vr_batch_config(batch, ctx=None):
+    w, o = C.c_int32(), C.c_int32()
+    _check(_lib.vr_batch_config(batch, C.byref(w), C.byref(o)), ctx)
+    return w.value, o.value
+
+
+def vr_batch_release(batch):
+    _check(_lib.vr_batch_release(batch))
+
+
 def vr_brick_set_data_global(brick, volume, vol_dims, lo, ctx=None):
     _check(_lib.vr_brick_set_data_global(brick, _ptr(volume), _i3(*vol_dims), _i3(*lo)), ctx)
 
@@ -261,7 +368,8 @@ class Renderer:
     the owned box's integer min corner; spacing is 1 (voxel units)."""
 
     def __init__(self, bricks, tf, vrange=(0.0, 1.0), opacity_scale=1.0, dt=0.5,
-                 ert_eps=2.0 ** -20, storage=VR_F32, device=0, stream=None, spacing=(1.0, 1.0, 1.0)):
+                 ert_eps=2.0 ** -20, storage=VR_F32, device=0, stream=None, spacing=(1.0, 1.0, 1.0),
+                 path=VR_PATH_STAGED):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -272,6 +380,7 @@ class Renderer:
         self.tf = torch.as_tensor(np.ascontiguousarray(tf, dtype=np.float32)).to(self.device)
         vr_set_transfer_function(self.ctx, self.tf, TF_ENTRIES, vrange[0], vrange[1], opacity_scale)
         vr_set_render_params(self.ctx, dt, ert_eps)
+        vr_set_march_path(self.ctx, path)
         for vox, lo in bricks:
             self.add_brick(vox, lo, spacing)
         self._parts = {}
@@ -321,6 +430,17 @@ class Renderer:
                                      device=self.device)
 
     def render_partials(self):
+        """All partials of the frame in one persistent launch."""
+        n = len(self.bricks)
+        need = vr_frame_workspace_size(n)
+        if getattr(self, "_fws", None) is None or self._fws_bytes < need:
+            buf = self.torch.empty(need // 4 + 64, dtype=self.torch.float32, device=self.device)
+            self._fws, self._fws_bytes = buf, need
+        base = self._fws.data_ptr() + ((-self._fws.data_ptr()) % 256)
+        vr_render_partials(self.ctx, self.bricks, self.partials, base, need)
+
+    def render_partials_each(self):
+        """One launch per partial (vr_render_partial)."""
         for b, p in zip(self.bricks, self.partials):
             vr_render_partial(self.ctx, b, p)
 
@@ -357,6 +477,124 @@ class Renderer:
         vr_context_release(self.ctx)
         self.ctx = None
         self.bricks = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ batch helper
+class BatchRenderer:
+    """Plumbing for the batch entry points: bricks (each with its own data:
+    a brick x time step x field), cameras, transfer functions and frames
+    (a camera, the bricks composited into it and a background).  build()
+    allocates every caller-owned buffer as a torch tensor and creates the
+    batch; launch() enqueues it."""
+
+    def __init__(self, dt=0.5, ert_eps=2.0 ** -20, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = vr_context_create(device, self.stream)
+        vr_set_render_params(self.ctx, dt, ert_eps)
+        self.bricks, self._keep, self.cameras, self.cam_dicts = [], [], [], []
+        self.tfs, self._tf_keep, self.frame_specs = [], [], []
+        self.batch = None
+
+    def add_brick(self, vox, lo, storage=VR_F32, spacing=(1.0, 1.0, 1.0)):
+        torch = self.torch
+        v = torch.as_tensor(vox).to(self.device, torch.float32).contiguous()
+        nz, ny, nx = (int(x) - 2 for x in v.shape)
+        nbytes = vr_brick_workspace_size((nx, ny, nz), 1, storage)
+        ws = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=self.device)
+        base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+        h = vr_brick_create(self.ctx, (nx, ny, nz), 1, tuple(float(x) for x in lo), spacing, storage,
+                            base, nbytes)
+        vr_brick_set_data(h, v, self.ctx)
+        self.bricks.append(h)
+        self._keep.append((ws, v))
+        return len(self.bricks) - 1
+
+    def drop_uploads(self):
+        """Free the float32 upload copies once ingest has run (synchronises)."""
+        vr_synchronize(self.ctx)
+        self._keep = [(ws, None) for ws, _ in self._keep]
+
+    def add_camera(self, cam):
+        self.cameras.append(camera_desc(cam))
+        self.cam_dicts.append(cam)
+        return len(self.cameras) - 1
+
+    def add_tf(self, table, vrange=(0.0, 1.0), opacity_scale=1.0):
+        t = self.torch.as_tensor(np.ascontiguousarray(table, dtype=np.float32)).to(self.device)
+        self._tf_keep.append(t)
+        self.tfs.append(vr_tf_desc(t.data_ptr(), float(vrange[0]), float(vrange[1]),
+                                   float(opacity_scale), 0))
+        return len(self.tfs) - 1
+
+    def add_frame(self, camera, bricks, tf=0, bg=(0.0, 0.0, 0.0, 0.0)):
+        self.frame_specs.append((int(camera), list(bricks), tf, tuple(float(x) for x in bg)))
+        return len(self.frame_specs) - 1
+
+    def build(self):
+        torch = self.torch
+        jobs, frames, self.parts, self.frames, self.job_meta = [], [], [], [], []
+        self.samples = torch.zeros(sum(len(b) for _, b, _, _ in self.frame_specs) + 1,
+                                   dtype=torch.int64, device=self.device)
+        for cam, bricks, tf, bg in self.frame_specs:
+            first = len(jobs)
+            for k, bi in enumerate(bricks):
+                roi = vr_camera_roi(self.ctx, self.bricks[bi], self.cameras[cam])
+                n = max(roi[2] * roi[3], 1)
+                rgba = torch.empty(n * 4, dtype=torch.float32, device=self.device)
+                depth = torch.empty(n, dtype=torch.float32, device=self.device)
+                t = tf[k] if isinstance(tf, (list, tuple)) else tf
+                part = make_partial(roi, rgba, depth, self.samples[len(jobs):len(jobs) + 1])
+                jobs.append(vr_batch_job(self.bricks[bi], cam, int(t), part))
+                self.parts.append((roi, rgba, depth))
+                self.job_meta.append((bi, cam))
+            W, H = self.cameras[cam].width, self.cameras[cam].height
+            out = torch.empty(H, W, 4, dtype=torch.float32, device=self.device)
+            self.frames.append(out)
+            f = vr_batch_frame(cam, first, len(bricks), 0, (C.c_float * 4)(*bg), out.data_ptr())
+            frames.append(f)
+        need = vr_batch_workspace_size(len(jobs), len(frames))
+        self._ws = torch.empty(need // 4 + 64, dtype=torch.float32, device=self.device)
+        base = self._ws.data_ptr() + ((-self._ws.data_ptr()) % 256)
+        self.batch = vr_batch_create(self.ctx, self.cameras, self.tfs, jobs, frames, base, need)
+        self.n_jobs = len(jobs)
+        return self
+
+    def launch(self):
+        vr_batch_launch(self.batch, self.ctx)
+
+    def autotune(self, reps=3):
+        return vr_batch_autotune(self.batch, reps, self.ctx)
+
+    def config(self):
+        return vr_batch_config(self.batch, self.ctx)
+
+    def partial_arrays(self, j):
+        (x0, y0, w, h), rgba, depth = self.parts[j]
+        return rgba[: w * h * 4].view(h, w, 4), depth[: w * h].view(h, w)
+
+    def synchronize(self):
+        vr_synchronize(self.ctx)
+
+    def close(self):
+        if self.ctx is None:
+            return
+        vr_synchronize(self.ctx)
+        if self.batch is not None:
+            vr_batch_release(self.batch)
+            self.batch = None
+        for b in self.bricks:
+            vr_brick_release(b)
+        vr_context_release(self.ctx)
+        self.ctx = None
 
     def __del__(self):
         try:

@@ -45,7 +45,8 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
     const BrickK& b = p.brick;
     const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
     const int snx = b.sdim[0], sny = b.sdim[1], snz = b.sdim[2];
-    const long long sxy = (long long)snx * sny;
+    const int pitch = row_pitch(snx);
+    const long long sxy = (long long)pitch * sny;
     const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
     const float tf_o = -p.tf.vmin * tf_k;
     // d a' / d alpha_table: converts pre-scaled opacity gradients to table units
@@ -62,40 +63,41 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
     }
     if (has) {
         const Step st = make_step(rs, b, p.dt);
+        const Blocks bl = make_blocks(rs, b);
         const long long N = rs.kl - rs.kf + 1;
         const int nseg = (int)min((N + I - 1) / I, (long long)p.ckpt_nseg);
         float R0 = 0.f, R1 = 0.f, R2 = 0.f, Q = 1.f;
+        // anchor cursor: block n holds samples [kA, kNext) anchored at kA
+        long long bn = 0, kA = 0, kNext = 0;
+        Anchor an{};
+        auto seek = [&](long long k) {
+            bn = block_of(bl, p.dt, k);
+            kA = max(rs.kf, block_start(bl, p.dt, bn));
+            kNext = block_start(bl, p.dt, bn + 1);
+            an = make_anchor(rs, b, p.dt, kA);
+        };
+        auto sample = [&](long long k) {
+            if (k < kA || k >= kNext) seek(k);
+            const Cell c = locate(an, st, (int)(k - kA), snx, sny, snz);
+            return c;
+        };
         for (int s = nseg - 1; s >= 0; --s) {
-            const long long q0 = (long long)s * I;
-            const int n = (int)min((long long)I, N - q0);
+            const long long k0 = rs.kf + (long long)s * I;
+            const int n = (int)min((long long)I, rs.kl - k0 + 1);
             // forward over the segment from its checkpoint
             float T = p.ckpt[pix * p.ckpt_nseg + s];
-            long long cur_blk = -1;
-            Anchor an{};
             for (int j = 0; j < n; ++j) {
-                const long long q = q0 + j;
-                const long long blk = q / kAnchor;
-                if (blk != cur_blk) {
-                    an = make_anchor(rs, b, p.dt, rs.kf + blk * kAnchor);
-                    cur_blk = blk;
-                }
                 tbuf[j * 64 + lane] = T;
-                const Cell c = locate(an, st, (int)(q - blk * kAnchor), snx, sny, snz);
-                const Classified e = classify(tft, trilinear(vox, c, snx, sxy), tf_k, tf_o);
-                T = T * exp2f(-e.a);
+                const Cell c = sample(k0 + j);
+                const Classified e = classify(tft, trilinear(vox, c, pitch, sxy), tf_k, tf_o);
+                T = T * trans_exp2(-e.a);
             }
             // reverse over the segment
             for (int j = n - 1; j >= 0; --j) {
-                const long long q = q0 + j;
-                const long long blk = q / kAnchor;
-                if (blk != cur_blk) {
-                    an = make_anchor(rs, b, p.dt, rs.kf + blk * kAnchor);
-                    cur_blk = blk;
-                }
-                const Cell c = locate(an, st, (int)(q - blk * kAnchor), snx, sny, snz);
-                const Classified e = classify(tft, trilinear(vox, c, snx, sxy), tf_k, tf_o);
+                const Cell c = sample(k0 + j);
+                const Classified e = classify(tft, trilinear(vox, c, pitch, sxy), tf_k, tf_o);
                 const float Tk = tbuf[j * 64 + lane];
-                const float om = exp2f(-e.a);          // 1 - alpha
+                const float om = trans_exp2(-e.a);          // 1 - alpha
                 const float al = 1.0f - om;
                 const float ta = Tk * al;
                 const float d_r = g.x * ta, d_g = g.y * ta, d_b = g.z * ta;

@@ -11,6 +11,10 @@
 #include <new>
 #include <string>
 #include <unordered_set>
+#include <algorithm>
+#include <cstdlib>
+#include <memory>
+#include <vector>
 
 #include "../../include/dpvr.h"
 #include "dpvr_kernels.h"
@@ -19,12 +23,15 @@ using namespace dpvr;
 
 struct vr_context_s {
     int32_t device = 0;
+    int32_t cus = 0;               // compute units of the device
+    int32_t queue_wg[2] = {0, 0};  // persistent march workgroups (F32, F16), 0 = not yet queried
     hipStream_t stream = nullptr;
     bool has_camera = false, has_tf = false;
     CameraK cam{};
     TFK tf{};
     double dt = 0.5;
     float ert_eps = 0x1p-20f;
+    int32_t path = kPathStaged;
     int32_t live_bricks = 0;
     std::string err;
 };
@@ -87,8 +94,11 @@ bool finite3(const double v[3]) {
     return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
 }
 
+// Stored elements of a brick: rows of (nx + 2g) voxels padded to a pitch of a
+// multiple of 8 elements, (ny + 2g) * (nz + 2g) rows.
 int64_t stored_count(const int32_t dims[3], int32_t ghost) {
-    return (int64_t)(dims[0] + 2 * ghost) * (dims[1] + 2 * ghost) * (dims[2] + 2 * ghost);
+    const int64_t pitch = ((int64_t)dims[0] + 2 * ghost + 7) & ~(int64_t)7;
+    return pitch * (dims[1] + 2 * ghost) * (dims[2] + 2 * ghost);
 }
 
 // float64 vector helpers; the operation order matches the documented camera
@@ -155,9 +165,13 @@ vr_status vr_context_create(int32_t device, void* stream, vr_context* out) {
     if (device < 0 || device >= count)
         return fail(nullptr, VR_ERR_INVALID_ARG, "vr_context_create: device %d out of range [0, %d)",
                     device, count);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        return fail(nullptr, VR_ERR_DEVICE, "vr_context_create: cannot query device %d", device);
     vr_context c = new (std::nothrow) vr_context_s;
     if (!c) return fail(nullptr, VR_ERR_INVALID_ARG, "vr_context_create: out of host memory");
     c->device = device;
+    c->cus = cus;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -256,8 +270,9 @@ vr_status vr_brick_set_data(vr_brick b, const float* voxels) {
     if (!voxels) return fail(ctx, VR_ERR_INVALID_ARG, "vr_brick_set_data: voxels is NULL");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_brick_set_data: cannot select device %d", ctx->device);
-    hipError_t e = launch_ingest(voxels, b->ws, stored_count(b->dims, b->ghost),
-                                 b->storage == VR_F16 ? kF16 : kF32, ctx->stream);
+    int32_t sdim[3];
+    for (int c = 0; c < 3; ++c) sdim[c] = b->dims[c] + 2 * b->ghost;
+    hipError_t e = launch_ingest(voxels, b->ws, sdim, b->storage == VR_F16 ? kF16 : kF32, ctx->stream);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_brick_set_data: %s", hipGetErrorString(e));
     b->has_data = true;
     return ok(ctx);
@@ -295,30 +310,54 @@ vr_status vr_set_transfer_function(vr_context ctx, const float* rgba, int32_t n,
     return ok(ctx);
 }
 
+// Camera frame from its description (kind 0: eye, look-at point, fovy in
+// degrees; kind 1: image centre, view direction, view height), validated.
+static vr_status build_camera(vr_context ctx, int kind, const double eye[3], const double tgt[3],
+                              const double up[3], double fov_or_h, int32_t width, int32_t height,
+                              const char* who, CameraK& cam) {
+    if (!eye || !tgt || !up) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
+    if (kind != 0 && kind != 1) return fail(ctx, VR_ERR_INVALID_ARG, "%s: unknown camera kind %d", who, kind);
+    if (!finite3(eye) || !finite3(tgt) || !finite3(up))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: non-finite vector", who);
+    if (kind == 0 && !(fov_or_h > 0 && fov_or_h < 180))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: fovy must be in (0, 180)", who);
+    if (kind == 1 && (!(fov_or_h > 0) || !std::isfinite(fov_or_h)))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: view_height must be > 0", who);
+    if (width < 1 || height < 1 || width > 32768 || height > 32768)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: bad image size %dx%d", who, width, height);
+    cam = CameraK{};
+    double fwd[3];
+    if (kind == 0)
+        sub3(tgt, eye, fwd);
+    else
+        for (int c = 0; c < 3; ++c) fwd[c] = tgt[c];
+    vr_status st = make_frame(ctx, fwd, up, cam);
+    if (st != VR_OK) return st;
+    const double W = (double)width, H = (double)height;
+    if (kind == 0) {
+        const double th = std::tan(0.5 * fov_or_h * (M_PI / 180.0));
+        cam.ax = (th * W) / H;
+        cam.ay = th;
+    } else {
+        const double hh = 0.5 * fov_or_h;
+        cam.ax = (hh * W) / H;
+        cam.ay = hh;
+    }
+    for (int c = 0; c < 3; ++c) cam.eye[c] = eye[c];
+    cam.kind = kind;
+    cam.width = width;
+    cam.height = height;
+    return VR_OK;
+}
+
 vr_status vr_set_camera_perspective(vr_context ctx, const double eye[3], const double target[3],
                                     const double up[3], double fovy_deg, int32_t width,
                                     int32_t height) {
     if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_set_camera_perspective: invalid context");
-    if (!eye || !target || !up) return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_camera_perspective: NULL argument");
-    if (!finite3(eye) || !finite3(target) || !finite3(up))
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_camera_perspective: non-finite vector");
-    if (!(fovy_deg > 0 && fovy_deg < 180))
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_camera_perspective: fovy must be in (0, 180)");
-    if (width < 1 || height < 1 || width > 32768 || height > 32768)
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_camera_perspective: bad image size %dx%d", width, height);
-    CameraK cam{};
-    double fwd[3];
-    sub3(target, eye, fwd);
-    vr_status st = make_frame(ctx, fwd, up, cam);
+    CameraK cam;
+    vr_status st = build_camera(ctx, 0, eye, target, up, fovy_deg, width, height,
+                                "vr_set_camera_perspective", cam);
     if (st != VR_OK) return st;
-    const double W = (double)width, H = (double)height;
-    const double th = std::tan(0.5 * fovy_deg * (M_PI / 180.0));
-    cam.ax = (th * W) / H;
-    cam.ay = th;
-    for (int c = 0; c < 3; ++c) cam.eye[c] = eye[c];
-    cam.kind = 0;
-    cam.width = width;
-    cam.height = height;
     ctx->cam = cam;
     ctx->has_camera = true;
     return ok(ctx);
@@ -328,24 +367,10 @@ vr_status vr_set_camera_orthographic(vr_context ctx, const double pos[3], const 
                                      const double up[3], double view_height, int32_t width,
                                      int32_t height) {
     if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_set_camera_orthographic: invalid context");
-    if (!pos || !dir || !up) return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_camera_orthographic: NULL argument");
-    if (!finite3(pos) || !finite3(dir) || !finite3(up))
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_camera_orthographic: non-finite vector");
-    if (!(view_height > 0) || !std::isfinite(view_height))
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_camera_orthographic: view_height must be > 0");
-    if (width < 1 || height < 1 || width > 32768 || height > 32768)
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_camera_orthographic: bad image size %dx%d", width, height);
-    CameraK cam{};
-    vr_status st = make_frame(ctx, dir, up, cam);
+    CameraK cam;
+    vr_status st = build_camera(ctx, 1, pos, dir, up, view_height, width, height,
+                                "vr_set_camera_orthographic", cam);
     if (st != VR_OK) return st;
-    const double W = (double)width, H = (double)height;
-    const double hh = 0.5 * view_height;
-    cam.ax = (hh * W) / H;
-    cam.ay = hh;
-    for (int c = 0; c < 3; ++c) cam.eye[c] = pos[c];
-    cam.kind = 1;
-    cam.width = width;
-    cam.height = height;
     ctx->cam = cam;
     ctx->has_camera = true;
     return ok(ctx);
@@ -361,12 +386,18 @@ vr_status vr_set_render_params(vr_context ctx, double dt, float ert_epsilon) {
     return ok(ctx);
 }
 
-vr_status vr_partial_roi(vr_context ctx, vr_brick b, int32_t roi[4]) {
-    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_partial_roi: invalid context");
-    if (!live(b) || b->ctx != ctx) return fail(ctx, VR_ERR_INVALID_HANDLE, "vr_partial_roi: invalid brick");
-    if (!roi) return fail(ctx, VR_ERR_INVALID_ARG, "vr_partial_roi: roi is NULL");
-    if (!ctx->has_camera) return fail(ctx, VR_ERR_STATE, "vr_partial_roi: no camera set");
-    const CameraK& cam = ctx->cam;
+vr_status vr_set_march_path(vr_context ctx, vr_path path) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_set_march_path: invalid context");
+    if (path != VR_PATH_STAGED && path != VR_PATH_DIRECT)
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_march_path: unknown path %d", (int)path);
+    ctx->path = path == VR_PATH_DIRECT ? kPathDirect : kPathStaged;
+    return ok(ctx);
+}
+
+// Pixel rectangle of the frame of `cam` whose rays can own samples of brick b:
+// the owned box's corners projected to the image plus one pixel of margin,
+// the whole frame when a corner lies at or behind the eye plane.
+static void roi_for(const CameraK& cam, vr_brick b, int32_t roi[4]) {
     const int W = cam.width, H = cam.height;
     double lo[3], hi[3];
     for (int c = 0; c < 3; ++c) {
@@ -374,16 +405,17 @@ vr_status vr_partial_roi(vr_context ctx, vr_brick b, int32_t roi[4]) {
         hi[c] = b->origin[c] + (double)b->dims[c] * b->spacing[c];
     }
     double imin = INFINITY, imax = -INFINITY, jmin = INFINITY, jmax = -INFINITY;
-    bool full = false;
-    for (int k = 0; k < 8 && !full; ++k) {
+    for (int k = 0; k < 8; ++k) {
         double p[3] = {(k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2]};
         double v[3];
         sub3(p, cam.eye, v);
         double x, y;
         if (cam.kind == 0) {
             double z = dot3(v, cam.f);
-            // corner at or behind the eye plane: the projection is unbounded
-            if (!(z > 1e-9 * (1.0 + norm3(v)))) { full = true; break; }
+            if (!(z > 1e-9 * (1.0 + norm3(v)))) {   // unbounded projection
+                roi[0] = 0; roi[1] = 0; roi[2] = W; roi[3] = H;
+                return;
+            }
             x = dot3(v, cam.r) / z;
             y = dot3(v, cam.u) / z;
         } else {
@@ -396,27 +428,48 @@ vr_status vr_partial_roi(vr_context ctx, vr_brick b, int32_t roi[4]) {
         imin = std::fmin(imin, i); imax = std::fmax(imax, i);
         jmin = std::fmin(jmin, j); jmax = std::fmax(jmax, j);
     }
-    if (full) {
-        roi[0] = 0; roi[1] = 0; roi[2] = W; roi[3] = H;
-        return ok(ctx);
-    }
     double x0 = std::floor(imin) - 1, x1 = std::ceil(imax) + 1;
     double y0 = std::floor(jmin) - 1, y1 = std::ceil(jmax) + 1;
     x0 = std::fmax(x0, 0.0); y0 = std::fmax(y0, 0.0);
     x1 = std::fmin(x1, (double)W - 1); y1 = std::fmin(y1, (double)H - 1);
     if (x1 < x0 || y1 < y0) {
         roi[0] = 0; roi[1] = 0; roi[2] = 0; roi[3] = 0;
-        return ok(ctx);
+        return;
     }
     roi[0] = (int32_t)x0;
     roi[1] = (int32_t)y0;
     roi[2] = (int32_t)(x1 - x0) + 1;
     roi[3] = (int32_t)(y1 - y0) + 1;
+}
+
+vr_status vr_partial_roi(vr_context ctx, vr_brick b, int32_t roi[4]) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_partial_roi: invalid context");
+    if (!live(b) || b->ctx != ctx) return fail(ctx, VR_ERR_INVALID_HANDLE, "vr_partial_roi: invalid brick");
+    if (!roi) return fail(ctx, VR_ERR_INVALID_ARG, "vr_partial_roi: roi is NULL");
+    if (!ctx->has_camera) return fail(ctx, VR_ERR_STATE, "vr_partial_roi: no camera set");
+    roi_for(ctx->cam, b, roi);
     return ok(ctx);
 }
 
-static vr_status check_partial(vr_context ctx, const vr_partial* part, const char* who, bool need_buffers) {
-    const int W = ctx->cam.width, H = ctx->cam.height;
+static vr_status camera_from_desc(vr_context ctx, const vr_camera_desc* d, const char* who, CameraK& cam) {
+    if (!d) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL camera", who);
+    return build_camera(ctx, d->kind, d->eye, d->target, d->up, d->fovy_deg, d->width, d->height, who, cam);
+}
+
+vr_status vr_camera_roi(vr_context ctx, vr_brick b, const vr_camera_desc* cam, int32_t roi[4]) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_camera_roi: invalid context");
+    if (!live(b) || b->ctx != ctx) return fail(ctx, VR_ERR_INVALID_HANDLE, "vr_camera_roi: invalid brick");
+    if (!roi) return fail(ctx, VR_ERR_INVALID_ARG, "vr_camera_roi: roi is NULL");
+    CameraK c;
+    vr_status st = camera_from_desc(ctx, cam, "vr_camera_roi", c);
+    if (st != VR_OK) return st;
+    roi_for(c, b, roi);
+    return ok(ctx);
+}
+
+static vr_status check_partial(vr_context ctx, const CameraK& cam, const vr_partial* part, const char* who,
+                               bool need_buffers) {
+    const int W = cam.width, H = cam.height;
     if (part->w < 0 || part->h < 0 || part->x0 < 0 || part->y0 < 0 ||
         (int64_t)part->x0 + part->w > W || (int64_t)part->y0 + part->h > H)
         return fail(ctx, VR_ERR_INVALID_ARG, "%s: ROI (%d, %d, %d, %d) outside the %dx%d frame", who,
@@ -432,18 +485,16 @@ static vr_status check_partial(vr_context ctx, const vr_partial* part, const cha
     return VR_OK;
 }
 
-static vr_status prepare_march(vr_context ctx, vr_brick b, const vr_partial* part, const char* who,
-                               MarchParams& p) {
-    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+// Kernel parameters of one partial for camera `cam` and transfer function `tf`.
+static vr_status prepare_march_with(vr_context ctx, vr_brick b, const vr_partial* part, const CameraK& cam,
+                                    const TFK& tf, const char* who, MarchParams& p) {
     if (!live(b) || b->ctx != ctx) return fail(ctx, VR_ERR_INVALID_HANDLE, "%s: invalid brick", who);
     if (!part) return fail(ctx, VR_ERR_INVALID_ARG, "%s: part is NULL", who);
-    if (!ctx->has_camera) return fail(ctx, VR_ERR_STATE, "%s: no camera set", who);
-    if (!ctx->has_tf) return fail(ctx, VR_ERR_STATE, "%s: no transfer function set", who);
     if (!b->has_data) return fail(ctx, VR_ERR_STATE, "%s: brick has no voxel data", who);
-    vr_status st = check_partial(ctx, part, who, true);
+    vr_status st = check_partial(ctx, cam, part, who, true);
     if (st != VR_OK) return st;
     p = MarchParams{};
-    p.cam = ctx->cam;
+    p.cam = cam;
     p.brick.data = b->ws;
     for (int c = 0; c < 3; ++c) {
         p.brick.sdim[c] = b->dims[c] + 2 * b->ghost;
@@ -453,7 +504,7 @@ static vr_status prepare_march(vr_context ctx, vr_brick b, const vr_partial* par
         p.brick.spacing[c] = b->spacing[c];
     }
     p.brick.ghost = b->ghost;
-    p.tf = ctx->tf;
+    p.tf = tf;
     p.dt = ctx->dt;
     p.ert_eps = ctx->ert_eps;
     p.roi_x0 = part->x0;
@@ -465,7 +516,114 @@ static vr_status prepare_march(vr_context ctx, vr_brick b, const vr_partial* par
     p.out_rgba = part->rgba;
     p.out_depth = part->depth;
     p.samples = part->samples;
+    p.path = ctx->path;
     return VR_OK;
+}
+
+// ... with the context's camera and transfer function.
+static vr_status prepare_march(vr_context ctx, vr_brick b, const vr_partial* part, const char* who,
+                               MarchParams& p) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (!ctx->has_camera) return fail(ctx, VR_ERR_STATE, "%s: no camera set", who);
+    if (!ctx->has_tf) return fail(ctx, VR_ERR_STATE, "%s: no transfer function set", who);
+    return prepare_march_with(ctx, b, part, ctx->cam, ctx->tf, who, p);
+}
+
+// Layout of a frame workspace: [2 queue counters | 256 B] [tile_start[n + 2] | 256-aligned]
+// [MarchParams jobs[n] | 256-aligned].
+static size_t frame_ws_bytes(int32_t n, size_t* off_tiles, size_t* off_jobs) {
+    const size_t a = 256;
+    size_t t = a;
+    size_t j = t + (((size_t)(n + 2) * sizeof(int32_t) + a - 1) / a) * a;
+    size_t end = j + (((size_t)n * sizeof(MarchParams) + a - 1) / a) * a;
+    if (off_tiles) *off_tiles = t;
+    if (off_jobs) *off_jobs = j;
+    return end;
+}
+
+vr_status vr_frame_workspace_size(int32_t n, size_t* bytes) {
+    if (n < 0 || !bytes) return fail(nullptr, VR_ERR_INVALID_ARG, "vr_frame_workspace_size: bad argument");
+    *bytes = frame_ws_bytes(n, nullptr, nullptr);
+    return VR_OK;
+}
+
+static int queue_workgroups(vr_context ctx, StorageK st) {
+    int& n = ctx->queue_wg[st == kF16 ? 1 : 0];
+    if (n == 0) n = march_queue_workgroups_per_cu(st) * ctx->cus;
+    return n;
+}
+
+vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
+                             const vr_partial* parts, void* workspace, size_t workspace_bytes) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_render_partials: invalid context");
+    if (n < 0 || (n > 0 && (!bricks || !parts)))
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_render_partials: bad n or NULL arrays");
+    if (n == 0) return ok(ctx);
+    size_t off_t = 0, off_j = 0;
+    const size_t need = frame_ws_bytes(n, &off_t, &off_j);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(ctx, VR_ERR_WORKSPACE, "vr_render_partials: workspace of %zu bytes (256-aligned), need %zu",
+                    workspace_bytes, need);
+    // job table grouped by storage precision (float32 jobs first): each group
+    // is one queue with its own exclusive tile prefix and counter
+    std::vector<MarchParams> jobs;
+    jobs.reserve(n);
+    std::vector<int32_t> prefix(n + 2, 0);
+    int n32 = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t acc = 0;
+        const int base = pass == 0 ? 0 : n32 + 1;   // prefix offset of this group
+        int cnt = 0;
+        for (int i = 0; i < n; ++i) {
+            if (!live(bricks[i]) || bricks[i]->ctx != ctx)
+                return fail(ctx, VR_ERR_INVALID_HANDLE, "vr_render_partials: invalid brick %d", i);
+            if ((bricks[i]->storage == VR_F16) != (pass == 1)) continue;
+            MarchParams p;
+            vr_status st = prepare_march(ctx, bricks[i], &parts[i], "vr_render_partials", p);
+            if (st != VR_OK) return st;
+            p.tiles_x = (parts[i].w + 15) / 16;
+            p.tiles_y = (parts[i].h + 15) / 16;
+            prefix[base + cnt] = acc;
+            acc += staged_tiles(parts[i].w, parts[i].h);
+            jobs.push_back(p);
+            ++cnt;
+        }
+        prefix[base + cnt] = acc;
+        if (pass == 0) n32 = cnt;
+    }
+    char* ws = reinterpret_cast<char*>(workspace);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: cannot select device %d", ctx->device);
+    if (ctx->path == kPathDirect) {   // one direct launch per partial (same images)
+        for (int j = 0; j < n; ++j) {
+            MarchParams p = jobs[j];
+            p.tiles_x = (p.roi_w + 7) / 8;
+            p.tiles_y = (p.roi_h + 7) / 8;
+            hipError_t e = launch_march(p, j < n32 ? kF32 : kF16, ctx->stream);
+            if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: %s", hipGetErrorString(e));
+        }
+        return ok(ctx);
+    }
+    // pageable host source: the runtime stages the data before returning
+    hipError_t e = hipMemcpyAsync(ws + off_t, prefix.data(), prefix.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + off_j, jobs.data(), (size_t)n * sizeof(MarchParams), hipMemcpyHostToDevice,
+                           ctx->stream);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: %s", hipGetErrorString(e));
+    const MarchParams* djobs = reinterpret_cast<const MarchParams*>(ws + off_j);
+    const int32_t* dtiles = reinterpret_cast<const int32_t*>(ws + off_t);
+    int32_t* heads = reinterpret_cast<int32_t*>(ws);
+    if (n32 > 0) {
+        QueueParams q{djobs, dtiles, n32, prefix[n32], heads};
+        e = launch_march_queue(q, kF32, queue_workgroups(ctx, kF32), ctx->stream);
+    }
+    if (e == hipSuccess && n - n32 > 0) {
+        QueueParams q{djobs + n32, dtiles + n32 + 1, n - n32, prefix[n + 1], heads + 1};
+        e = launch_march_queue(q, kF16, queue_workgroups(ctx, kF16), ctx->stream);
+    }
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: %s", hipGetErrorString(e));
+    return ok(ctx);
 }
 
 vr_status vr_render_partial(vr_context ctx, vr_brick b, const vr_partial* part) {
@@ -480,18 +638,17 @@ vr_status vr_render_partial(vr_context ctx, vr_brick b, const vr_partial* part) 
     return ok(ctx);
 }
 
-static vr_status prepare_composite(vr_context ctx, const vr_partial* parts, int32_t n,
-                                   const float bg[4], const char* who, CompositeParams& p) {
-    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+// Kernel parameters of one frame composite for camera `cam`'s frame.
+static vr_status prepare_composite_with(vr_context ctx, const CameraK& cam, const vr_partial* parts,
+                                        int32_t n, const float bg[4], const char* who, CompositeParams& p) {
     if (n < 0 || n > DPVR_MAX_PARTIALS)
         return fail(ctx, VR_ERR_INVALID_ARG, "%s: n = %d outside [0, %d]", who, n, DPVR_MAX_PARTIALS);
     if ((n > 0 && !parts) || !bg) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
-    if (!ctx->has_camera) return fail(ctx, VR_ERR_STATE, "%s: no camera set", who);
     for (int c = 0; c < 4; ++c)
         if (!std::isfinite(bg[c])) return fail(ctx, VR_ERR_INVALID_ARG, "%s: background not finite", who);
     p = CompositeParams{};
     for (int i = 0; i < n; ++i) {
-        vr_status st = check_partial(ctx, &parts[i], who, true);
+        vr_status st = check_partial(ctx, cam, &parts[i], who, true);
         if (st != VR_OK) return st;
         p.parts[i].x0 = parts[i].x0;
         p.parts[i].y0 = parts[i].y0;
@@ -501,11 +658,18 @@ static vr_status prepare_composite(vr_context ctx, const vr_partial* parts, int3
         p.parts[i].depth = parts[i].depth;
     }
     p.n = n;
-    p.width = ctx->cam.width;
-    p.height = ctx->cam.height;
+    p.width = cam.width;
+    p.height = cam.height;
     p.tiles_x = (p.width + 7) / 8;
     for (int c = 0; c < 4; ++c) p.bg[c] = bg[c];
     return VR_OK;
+}
+
+static vr_status prepare_composite(vr_context ctx, const vr_partial* parts, int32_t n,
+                                   const float bg[4], const char* who, CompositeParams& p) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (!ctx->has_camera) return fail(ctx, VR_ERR_STATE, "%s: no camera set", who);
+    return prepare_composite_with(ctx, ctx->cam, parts, n, bg, who, p);
 }
 
 vr_status vr_composite(vr_context ctx, const vr_partial* parts, int32_t n, const float bg[4],
@@ -663,6 +827,360 @@ vr_status vr_render_partial_backward(vr_context ctx, vr_brick b, const vr_partia
     hipError_t e = launch_march_backward(p, bp, b->storage == VR_F16 ? kF16 : kF32, ctx->stream);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partial_backward: %s", hipGetErrorString(e));
     return ok(ctx);
+}
+
+// ---------------------------------------------------------------- batches
+struct vr_batch_s {
+    vr_context ctx = nullptr;
+    std::vector<MarchParams> jobs;        // as given
+    std::vector<int32_t> f16;             // storage of each job (0 / 1)
+    std::vector<const void*> brick_of;    // brick identity of each job (grouping key)
+    std::vector<CompositeParams> frames;
+    char* ws = nullptr;
+    size_t off_mprefix = 0, off_mjobs = 0, off_cprefix = 0, off_cframes = 0;
+    int32_t n32 = 0, total32 = 0, total16 = 0, ctotal = 0;
+    int32_t wg_per_cu = 0, order = 0;
+    uint64_t shape_key = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace layout: [2 counters | 256] [march prefix (n_jobs + 2)] [march jobs]
+// [composite prefix (n_frames + 1)] [composite frames].
+size_t batch_layout(int32_t n_jobs, int32_t n_frames, size_t* mp, size_t* mj, size_t* cp, size_t* cf) {
+    size_t o = 256;
+    *mp = o; o = align256(o + (size_t)(n_jobs + 2) * sizeof(int32_t));
+    *mj = o; o = align256(o + (size_t)n_jobs * sizeof(MarchParams));
+    *cp = o; o = align256(o + (size_t)(n_frames + 1) * sizeof(int32_t));
+    *cf = o; o = align256(o + (size_t)n_frames * sizeof(CompositeParams));
+    return o;
+}
+
+void fnv(uint64_t& h, const void* p, size_t n) {
+    const unsigned char* c = reinterpret_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+}
+
+// Upload the job table in the given order (float32 jobs first, then float16).
+vr_status batch_upload(vr_batch b, int order) {
+    const int n = (int)b->jobs.size();
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    if (order == 1) {   // group the jobs of each brick, bricks in order of first appearance
+        std::vector<int> first(n);
+        for (int i = 0; i < n; ++i) {
+            first[i] = i;
+            for (int j = 0; j < i; ++j)
+                if (b->brick_of[j] == b->brick_of[i]) { first[i] = first[j]; break; }
+        }
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return first[x] < first[y]; });
+    }
+    std::vector<MarchParams> table;
+    table.reserve(n);
+    std::vector<int32_t> prefix(n + 2, 0);
+    int n32 = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int base = pass == 0 ? 0 : n32 + 1;
+        int cnt = 0;
+        int32_t acc = 0;
+        for (int k = 0; k < n; ++k) {
+            const int i = idx[k];
+            if (b->f16[i] != pass) continue;
+            prefix[base + cnt] = acc;
+            acc += staged_tiles(b->jobs[i].roi_w, b->jobs[i].roi_h);
+            table.push_back(b->jobs[i]);
+            ++cnt;
+        }
+        prefix[base + cnt] = acc;
+        if (pass == 0) { n32 = cnt; b->total32 = acc; } else b->total16 = acc;
+    }
+    b->n32 = n32;
+    hipError_t e = hipMemcpy(b->ws + b->off_mprefix, prefix.data(), prefix.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpy(b->ws + b->off_mjobs, table.data(), (size_t)n * sizeof(MarchParams), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(b->ctx, VR_ERR_DEVICE, "batch upload: %s", hipGetErrorString(e));
+    b->order = order;
+    return VR_OK;
+}
+
+void batch_drop_graph(vr_batch b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Capture the batch's launches (queue counters are reset by a kernel, so the
+// graph holds kernel nodes only) with `wg_per_cu` persistent workgroups per CU.
+vr_status batch_capture(vr_batch b, int wg_per_cu) {
+    vr_context ctx = b->ctx;
+    batch_drop_graph(b);
+    const int n = (int)b->jobs.size();
+    const MarchParams* djobs = reinterpret_cast<const MarchParams*>(b->ws + b->off_mjobs);
+    const int32_t* dprefix = reinterpret_cast<const int32_t*>(b->ws + b->off_mprefix);
+    int32_t* heads = reinterpret_cast<int32_t*>(b->ws);
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "batch capture: %s", hipGetErrorString(e));
+    hipError_t le = hipSuccess;
+    if (b->n32 > 0) {
+        QueueParams q{djobs, dprefix, b->n32, b->total32, heads};
+        le = launch_march_queue(q, kF32, wg_per_cu * ctx->cus, b->cap);
+    }
+    if (le == hipSuccess && n - b->n32 > 0) {
+        QueueParams q{djobs + b->n32, dprefix + b->n32 + 1, n - b->n32, b->total16, heads + 1};
+        le = launch_march_queue(q, kF16, wg_per_cu * ctx->cus, b->cap);
+    }
+    if (le == hipSuccess && !b->frames.empty())
+        le = launch_composite_many(reinterpret_cast<const CompositeParams*>(b->ws + b->off_cframes),
+                                   reinterpret_cast<const int32_t*>(b->ws + b->off_cprefix),
+                                   (int32_t)b->frames.size(), b->ctotal, b->cap);
+    e = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        batch_drop_graph(b);
+        return fail(ctx, VR_ERR_DEVICE, "batch capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        batch_drop_graph(b);
+        return fail(ctx, VR_ERR_DEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
+    }
+    b->wg_per_cu = wg_per_cu;
+    return VR_OK;
+}
+
+int max_wg_per_cu(vr_context ctx, const vr_batch b) {
+    int m = 0;
+    if (b->n32 > 0) m = std::max(m, march_queue_workgroups_per_cu(kF32));
+    if ((int)b->jobs.size() > b->n32) m = std::max(m, march_queue_workgroups_per_cu(kF16));
+    (void)ctx;
+    return std::max(m, 1);
+}
+
+}  // namespace
+
+vr_status vr_batch_workspace_size(int32_t n_jobs, int32_t n_frames, size_t* bytes) {
+    if (n_jobs < 0 || n_frames < 0 || !bytes)
+        return fail(nullptr, VR_ERR_INVALID_ARG, "vr_batch_workspace_size: bad argument");
+    size_t a, b2, c, d;
+    *bytes = batch_layout(n_jobs, n_frames, &a, &b2, &c, &d);
+    return VR_OK;
+}
+
+vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_desc* cameras,
+                          int32_t n_tfs, const vr_tf_desc* tfs, int32_t n_jobs,
+                          const vr_batch_job* jobs, int32_t n_frames, const vr_batch_frame* frames,
+                          void* workspace, size_t workspace_bytes, vr_batch* out) {
+    static const char* who = "vr_batch_create";
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (!out) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out is NULL", who);
+    *out = nullptr;
+    if (n_cameras < 1 || !cameras || n_tfs < 1 || !tfs || n_jobs < 0 || (n_jobs > 0 && !jobs) ||
+        n_frames < 0 || (n_frames > 0 && !frames))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: bad counts or NULL arrays", who);
+    size_t mp, mj, cp, cf;
+    const size_t need = batch_layout(n_jobs, n_frames, &mp, &mj, &cp, &cf);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes (256-aligned), need %zu", who,
+                    workspace_bytes, need);
+    std::vector<CameraK> cams(n_cameras);
+    for (int i = 0; i < n_cameras; ++i) {
+        vr_status st = camera_from_desc(ctx, &cameras[i], who, cams[i]);
+        if (st != VR_OK) return st;
+    }
+    std::vector<TFK> tfk(n_tfs);
+    for (int i = 0; i < n_tfs; ++i) {
+        const vr_tf_desc& t = tfs[i];
+        if (!t.rgba || (reinterpret_cast<uintptr_t>(t.rgba) & 15) != 0 || !std::isfinite(t.vmin) ||
+            !std::isfinite(t.vmax) || !(t.vmin < t.vmax) || !(t.opacity_scale >= 0) ||
+            !std::isfinite(t.opacity_scale))
+            return fail(ctx, VR_ERR_INVALID_ARG, "%s: transfer function %d invalid", who, i);
+        tfk[i] = TFK{t.rgba, t.vmin, t.vmax, t.opacity_scale, DPVR_TF_ENTRIES};
+    }
+    std::unique_ptr<vr_batch_s> b(new (std::nothrow) vr_batch_s);
+    if (!b) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out of host memory", who);
+    b->ctx = ctx;
+    uint64_t key = 1469598103934665603ull;
+    for (int i = 0; i < n_jobs; ++i) {
+        const vr_batch_job& j = jobs[i];
+        if (j.camera < 0 || j.camera >= n_cameras || j.tf < 0 || j.tf >= n_tfs)
+            return fail(ctx, VR_ERR_INVALID_ARG, "%s: job %d: camera or tf index out of range", who, i);
+        if (!live(j.brick) || j.brick->ctx != ctx)
+            return fail(ctx, VR_ERR_INVALID_HANDLE, "%s: job %d: invalid brick", who, i);
+        if (!j.brick->has_data) return fail(ctx, VR_ERR_STATE, "%s: job %d: brick has no data", who, i);
+        MarchParams p;
+        vr_status st = prepare_march_with(ctx, j.brick, &j.part, cams[j.camera], tfk[j.tf], who, p);
+        if (st != VR_OK) return st;
+        p.tiles_x = (j.part.w + 15) / 16;
+        p.tiles_y = (j.part.h + 15) / 16;
+        b->jobs.push_back(p);
+        b->f16.push_back(j.brick->storage == VR_F16 ? 1 : 0);
+        b->brick_of.push_back(j.brick);
+        const int32_t sig[8] = {j.brick->dims[0], j.brick->dims[1], j.brick->dims[2], j.part.w, j.part.h,
+                                cams[j.camera].width, cams[j.camera].height, (int32_t)j.brick->storage};
+        fnv(key, sig, sizeof sig);
+    }
+    std::vector<int32_t> cprefix(n_frames + 1, 0);
+    for (int f = 0; f < n_frames; ++f) {
+        const vr_batch_frame& fr = frames[f];
+        if (fr.camera < 0 || fr.camera >= n_cameras || fr.first_job < 0 || fr.n_jobs < 0 ||
+            fr.n_jobs > DPVR_MAX_PARTIALS || fr.first_job + fr.n_jobs > n_jobs || !fr.out ||
+            (reinterpret_cast<uintptr_t>(fr.out) & 15) != 0)
+            return fail(ctx, VR_ERR_INVALID_ARG, "%s: frame %d invalid", who, f);
+        std::vector<vr_partial> parts(fr.n_jobs);
+        for (int k = 0; k < fr.n_jobs; ++k) {
+            const vr_batch_job& j = jobs[fr.first_job + k];
+            if (j.camera != fr.camera)
+                return fail(ctx, VR_ERR_INVALID_ARG, "%s: frame %d: job %d uses another camera", who, f,
+                            fr.first_job + k);
+            parts[k] = j.part;
+        }
+        CompositeParams cpar;
+        vr_status st = prepare_composite_with(ctx, cams[fr.camera], parts.data(), fr.n_jobs, fr.bg, who, cpar);
+        if (st != VR_OK) return st;
+        cpar.out = fr.out;
+        b->frames.push_back(cpar);
+        cprefix[f + 1] = cprefix[f] + composite_tiles(cams[fr.camera].width, cams[fr.camera].height);
+        fnv(key, &cams[fr.camera].width, 2 * sizeof(int32_t));
+    }
+    b->ctotal = cprefix[n_frames];
+    int dev_id[2] = {ctx->device, ctx->cus};
+    fnv(key, dev_id, sizeof dev_id);
+    b->shape_key = key;
+    b->ws = reinterpret_cast<char*>(workspace);
+    b->off_mprefix = mp;
+    b->off_mjobs = mj;
+    b->off_cprefix = cp;
+    b->off_cframes = cf;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+    hipError_t e = hipMemcpy(b->ws + cp, cprefix.data(), cprefix.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_frames > 0)
+        e = hipMemcpy(b->ws + cf, b->frames.data(), b->frames.size() * sizeof(CompositeParams),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    vr_status st = batch_upload(b.get(), 0);
+    if (st == VR_OK) st = batch_capture(b.get(), max_wg_per_cu(ctx, b.get()));
+    if (st != VR_OK) {
+        batch_drop_graph(b.get());
+        (void)hipStreamDestroy(b->cap);
+        return st;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(b.get());
+    }
+    ctx->live_bricks++;   // a batch pins the context like a brick does
+    *out = b.release();
+    return ok(ctx);
+}
+
+vr_status vr_batch_launch(vr_batch b) {
+    if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_launch: invalid batch");
+    vr_context ctx = b->ctx;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_batch_launch: cannot select device %d", ctx->device);
+    hipError_t e = hipGraphLaunch(b->exec, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_batch_launch: %s", hipGetErrorString(e));
+    return ok(ctx);
+}
+
+vr_status vr_batch_config(vr_batch b, int32_t* wg_per_cu, int32_t* order) {
+    if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_config: invalid batch");
+    if (wg_per_cu) *wg_per_cu = b->wg_per_cu;
+    if (order) *order = b->order;
+    return ok(b->ctx);
+}
+
+static bool cache_lookup(const char* path, uint64_t key, int* wg, int* order) {
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    unsigned long long k;
+    int w, o;
+    double ms;
+    bool found = false;
+    while (std::fscanf(f, "%llx %d %d %lf", &k, &w, &o, &ms) == 4)
+        if (k == key) { *wg = w; *order = o; found = true; }
+    std::fclose(f);
+    return found;
+}
+
+static void cache_store(const char* path, uint64_t key, int wg, int order, double ms) {
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%llx %d %d %.6f\n", (unsigned long long)key, wg, order, ms);
+    std::fclose(f);
+}
+
+vr_status vr_batch_autotune(vr_batch b, int32_t reps, double* best_ms) {
+    if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_autotune: invalid batch");
+    vr_context ctx = b->ctx;
+    if (reps < 1) return fail(ctx, VR_ERR_INVALID_ARG, "vr_batch_autotune: reps must be >= 1");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_batch_autotune: cannot select device %d", ctx->device);
+    const char* path = std::getenv("DPVR_AUTOTUNE_CACHE");
+    int cwg = 0, cord = 0;
+    const int maxwg = max_wg_per_cu(ctx, b);
+    if (cache_lookup(path, b->shape_key, &cwg, &cord) && cwg >= 1 && cwg <= maxwg && (cord == 0 || cord == 1)) {
+        vr_status st = batch_upload(b, cord);
+        if (st == VR_OK) st = batch_capture(b, cwg);
+        if (best_ms) *best_ms = -1.0;   // taken from the cache, not timed
+        return st == VR_OK ? ok(ctx) : st;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ctx, VR_ERR_DEVICE, "vr_batch_autotune: cannot create events");
+    double best = 1e300;
+    int bw = b->wg_per_cu, bo = b->order;
+    vr_status st = VR_OK;
+    for (int order = 0; order < 2 && st == VR_OK; ++order) {
+        st = batch_upload(b, order);
+        for (int wg = 1; wg <= maxwg && st == VR_OK; ++wg) {
+            st = batch_capture(b, wg);
+            if (st != VR_OK) break;
+            hipError_t e = hipGraphLaunch(b->exec, ctx->stream);   // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, ctx->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { st = fail(ctx, VR_ERR_DEVICE, "vr_batch_autotune: %s", hipGetErrorString(e)); break; }
+            const double per = ms / reps;
+            if (per < best) { best = per; bw = wg; bo = order; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != VR_OK) return st;
+    st = batch_upload(b, bo);
+    if (st == VR_OK) st = batch_capture(b, bw);
+    if (st != VR_OK) return st;
+    cache_store(path, b->shape_key, bw, bo, best);
+    if (best_ms) *best_ms = best;
+    return ok(ctx);
+}
+
+vr_status vr_batch_release(vr_batch b) {
+    if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_release: invalid batch");
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.erase(b);
+    }
+    batch_drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (live(b->ctx)) b->ctx->live_bricks--;
+    delete b;
+    return VR_OK;
 }
 
 }  // extern "C"

@@ -47,11 +47,10 @@ __device__ int sort_keys(const CompositeParams& p, int t0x, int t0y, int px, int
     return m;
 }
 
-__global__ __launch_bounds__(64) void composite_kernel(CompositeParams p) {
-    __shared__ float key_s[kMaxPartials * 64];
-    __shared__ unsigned char idx_s[kMaxPartials * 64];
+// One 8x8 tile of one frame (one wavefront).
+__device__ inline void composite_tile(const CompositeParams& p, int tile, float* key_s,
+                                      unsigned char* idx_s) {
     const int lane = threadIdx.x;
-    const int tile = blockIdx.x;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int t0x = tx * 8, t0y = ty * 8;
     const int px = t0x + (lane & 7), py = t0y + (lane >> 3);
@@ -73,6 +72,29 @@ __global__ __launch_bounds__(64) void composite_kernel(CompositeParams p) {
     reinterpret_cast<float4*>(p.out)[(long long)py * p.width + px] =
         make_float4(fmaf(w, p.bg[0], C0), fmaf(w, p.bg[1], C1), fmaf(w, p.bg[2], C2),
                     fmaf(w, p.bg[3], A));
+}
+
+__global__ __launch_bounds__(64) void composite_kernel(CompositeParams p) {
+    __shared__ float key_s[kMaxPartials * 64];
+    __shared__ unsigned char idx_s[kMaxPartials * 64];
+    composite_tile(p, blockIdx.x, key_s, idx_s);
+}
+
+// Many frames in one launch: workgroup b composites tile b - tile_start[i]
+// of frame i (the last i with tile_start[i] <= b); frame descriptors in
+// device memory.
+__global__ __launch_bounds__(64) void composite_many_kernel(const CompositeParams* __restrict__ frames,
+                                                            const int32_t* __restrict__ tile_start,
+                                                            int32_t n_frames) {
+    __shared__ float key_s[kMaxPartials * 64];
+    __shared__ unsigned char idx_s[kMaxPartials * 64];
+    const int b = blockIdx.x;
+    int lo = 0, hi = n_frames - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    composite_tile(frames[lo], b - tile_start[lo], key_s, idx_s);
 }
 
 // Backward of the composite.  With the partials of a pixel in visibility
@@ -135,6 +157,14 @@ hipError_t launch_composite_backward(const CompositeParams& p, const CompositeBa
     const int blocks = p.tiles_x * tiles_y;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(composite_backward_kernel, dim3(blocks), dim3(64), 0, stream, p, bp);
+    return hipGetLastError();
+}
+
+hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* tile_start,
+                                 int32_t n_frames, int32_t total_tiles, hipStream_t stream) {
+    if (total_tiles <= 0 || n_frames <= 0) return hipSuccess;
+    hipLaunchKernelGGL(composite_many_kernel, dim3(total_tiles), dim3(64), 0, stream, frames,
+                       tile_start, n_frames);
     return hipGetLastError();
 }
 

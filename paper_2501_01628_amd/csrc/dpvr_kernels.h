@@ -52,7 +52,22 @@ struct MarchParams {
     float* ckpt;
     int32_t ckpt_interval;
     int32_t ckpt_nseg;
+    int32_t path;          // kPathStaged or kPathDirect (bit-identical results)
 };
+
+enum : int32_t { kPathStaged = 0, kPathDirect = 1 };
+
+// A device work queue of march jobs (partial images): tickets
+// tile_start[j] .. tile_start[j + 1] - 1 are the 16x16 tiles of job j.
+struct QueueParams {
+    const MarchParams* jobs;   // device, n_jobs entries
+    const int32_t* tile_start; // device, n_jobs + 1 entries (exclusive prefix of tiles)
+    int32_t n_jobs;
+    int32_t total_tiles;
+    int32_t* head;             // device ticket counter (reset by the launcher)
+};
+
+inline int32_t staged_tiles(int32_t w, int32_t h) { return ((w + 15) / 16) * ((h + 15) / 16); }
 
 constexpr int kMaxCkptInterval = 64;
 
@@ -101,10 +116,16 @@ struct GatherParams {
 enum StorageK : int32_t { kF32 = 0, kF16 = 1 };
 
 // Launchers (return the hipError_t of the launch).
-hipError_t launch_ingest(const float* src, void* dst, int64_t count, StorageK storage,
+hipError_t launch_ingest(const float* src, void* dst, const int32_t sdim[3], StorageK storage,
                          hipStream_t stream);
 hipError_t launch_march(const MarchParams& p, StorageK storage, hipStream_t stream);
+hipError_t launch_march_queue(const QueueParams& q, StorageK storage, int workgroups,
+                              hipStream_t stream);
+int march_queue_workgroups_per_cu(StorageK storage);
 hipError_t launch_composite(const CompositeParams& p, hipStream_t stream);
+hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* tile_start,
+                                 int32_t n_frames, int32_t total_tiles, hipStream_t stream);
+inline int32_t composite_tiles(int32_t w, int32_t h) { return ((w + 7) / 8) * ((h + 7) / 8); }
 hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp, StorageK storage,
                                  hipStream_t stream);
 hipError_t launch_composite_backward(const CompositeParams& p, const CompositeBackParams& bp,

@@ -1,27 +1,118 @@
 // Per-brick volume ray casting into a partial image (RGBA premultiplied +
 // depth key) for gfx950.
 //
-// One wavefront per 8x8 pixel tile of the brick's region of interest, one
-// lane per ray.  Per ray, in float64 and without FMA contraction (so that
-// ownership decisions are bit-identical however the volume is split):
-// camera ray, slab test against the brick's owned box, first/last owned
-// sample of the global lattice t_k = (k + 1/2) dt.  Per sample, in float32,
-// in the brick's stored-index coordinates re-anchored to a float64 position
-// every kAnchor samples (keeps the float32 coordinates small, so position
-// error stays ~1e-6 voxel even far from the brick origin): trilinear
-// reconstruction, transfer-function lookup from an LDS table, emission-
-// absorption update, early termination once T < eps.
+// Per ray, in float64 and without FMA contraction (so that ownership
+// decisions are bit-identical however the volume is split): camera ray, slab
+// test against the brick's owned box, first/last owned sample of the global
+// lattice t_k = (k + 1/2) dt.  Per sample, in float32, in the brick's
+// stored-index coordinates re-anchored from float64 at the start of every
+// anchor block (slab of kSlab slices, see march_common.h), so the float32
+// coordinates stay small: trilinear reconstruction, transfer-function lookup
+// from an LDS table, emission-absorption update, early termination once
+// T < eps.
 //
-// The checkpointing variant (used by the adjoint) runs without early
-// termination and stores the transmittance in front of every
-// ckpt_interval-th owned sample of each ray.
+// Two kernels compute bit-identical images:
+//  * march_staged (default): a 256-thread workgroup owns a 16x16 pixel tile,
+//    one wavefront per 8x8 quarter.  The workgroup walks the slabs of the
+//    tile's common slab axis w (y or z; rows along x stay contiguous in HBM)
+//    in ray order; for each slab it stages, per slice, the sheared rectangle
+//    the tile's rays cross (16-byte loads, converted to float32) into LDS,
+//    then every lane marches its samples of that slab out of LDS.  Tiles
+//    whose rays do not share a slab axis and direction, or whose slab does
+//    not fit in LDS, march from HBM directly.
+//  * march_direct: one wavefront per 8x8 tile, corner values straight from
+//    HBM; also writes transmittance checkpoints for the adjoint.
 #include "march_common.h"
 
 namespace dpvr {
 namespace {
 
-constexpr int kTile = 8;          // 8x8 pixels per wavefront
+constexpr int kSlices = kSlab + 3;       // staged slices per slab: [wlo - 1, whi + 1]
+constexpr int kStageFloats = 11008;      // 43 KB of LDS for the staged slab
+constexpr float kMinStageDw = 0.25f;     // |d_w| below this: march from HBM
 
+struct LaneState {
+    float C0, C1, C2, T;
+    long long evaluated;
+    bool stopped;
+};
+
+// March samples kb .. kb + n - 1 of one anchor block; fetch(cell) returns the
+// interpolated value.  Returns false once early termination stops the ray.
+template <bool kCkpt, typename Fetch>
+__device__ inline bool march_block(const MarchParams& p, const TFTable& tft, const RaySetup& rs,
+                                   const BrickK& b, const Step& st, long long kb, int n,
+                                   long long pix, float tf_k, float tf_o, float eps, LaneState& s,
+                                   Fetch fetch) {
+    const Anchor an = make_anchor(rs, b, p.dt, kb);
+    const int snx = b.sdim[0], sny = b.sdim[1], snz = b.sdim[2];
+    for (int j = 0; j < n; ++j) {
+        if (kCkpt) {
+            const long long q = kb + j - rs.kf;
+            if (q % p.ckpt_interval == 0 && q / p.ckpt_interval < p.ckpt_nseg)
+                p.ckpt[pix * p.ckpt_nseg + q / p.ckpt_interval] = s.T;
+        }
+        const Cell c = locate(an, st, j, snx, sny, snz);
+        const float v = fetch(c);
+        const Classified e = classify(tft, v, tf_k, tf_o);
+        // emission-absorption: T_next = T exp2(-a'), weight = T - T_next
+        const float Tn = s.T * trans_exp2(-e.a);
+        const float w = s.T - Tn;
+        s.C0 = fmaf(w, e.r, s.C0);
+        s.C1 = fmaf(w, e.g, s.C1);
+        s.C2 = fmaf(w, e.b, s.C2);
+        s.T = Tn;
+        if (s.T < eps) {
+            s.evaluated += j + 1;
+            s.stopped = true;
+            return false;
+        }
+    }
+    s.evaluated += n;
+    return true;
+}
+
+// Whole ray from HBM, block by block.
+template <typename TS, bool kCkpt>
+__device__ inline void march_ray_direct(const MarchParams& p, const TFTable& tft,
+                                        const RaySetup& rs, long long pix, float tf_k, float tf_o,
+                                        float eps, LaneState& s) {
+    const BrickK& b = p.brick;
+    const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
+    const int pitch = row_pitch(b.sdim[0]);
+    const long long sxy = (long long)pitch * b.sdim[1];
+    const Step st = make_step(rs, b, p.dt);
+    const Blocks bl = make_blocks(rs, b);
+    long long n = block_of(bl, p.dt, rs.kf);
+    long long k = rs.kf;
+    auto fetch = [&](const Cell& c) { return trilinear(vox, c, pitch, sxy); };
+    while (k <= rs.kl) {
+        const long long knext = block_start(bl, p.dt, n + 1);
+        const long long kend = min(knext - 1, rs.kl);
+        if (kend >= k) {
+            if (!march_block<kCkpt>(p, tft, rs, b, st, k, (int)(kend - k + 1), pix, tf_k, tf_o, eps,
+                                    s, fetch))
+                return;
+            k = kend + 1;
+        }
+        ++n;
+    }
+}
+
+__device__ inline void finish(const MarchParams& p, bool valid, long long pix, float depth,
+                              const LaneState& s, int lane) {
+    if (valid) {
+        reinterpret_cast<float4*>(p.out_rgba)[pix] = make_float4(s.C0, s.C1, s.C2, 1.0f - s.T);
+        p.out_depth[pix] = depth;
+    }
+    if (p.samples) {
+        unsigned long long cnt = (unsigned long long)s.evaluated;
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if (lane == 0 && cnt) atomicAdd(p.samples, cnt);
+    }
+}
+
+// ------------------------------------------------------------ direct kernel
 template <typename TS, bool kCkpt>
 __global__ __launch_bounds__(64) void march_direct(MarchParams p) {
     __shared__ TFTable tft;
@@ -31,68 +122,354 @@ __global__ __launch_bounds__(64) void march_direct(MarchParams p) {
 
     const int tile = blockIdx.x;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-    const int lx = tx * kTile + (lane & 7), ly = ty * kTile + (lane >> 3);
+    const int lx = tx * 8 + (lane & 7), ly = ty * 8 + (lane >> 3);
     const bool valid = lx < p.roi_w && ly < p.roi_h;
-    const int px = p.roi_x0 + lx, py = p.roi_y0 + ly;
     const long long pix = (long long)ly * p.roi_w + lx;
-
-    const BrickK& b = p.brick;
-    const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
-    const int snx = b.sdim[0], sny = b.sdim[1], snz = b.sdim[2];
-    const long long sxy = (long long)snx * sny;
     const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
     const float tf_o = -p.tf.vmin * tf_k;
     const float eps = kCkpt ? 0.0f : p.ert_eps;
 
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+    LaneState s{0.f, 0.f, 0.f, 1.f, 0, false};
     float depth = INFINITY;
-    long long evaluated = 0;
     RaySetup rs;
-    if (valid && setup_ray(p.cam, b, p.dt, px, py, rs)) {
+    if (valid && setup_ray(p.cam, p.brick, p.dt, p.roi_x0 + lx, p.roi_y0 + ly, rs)) {
         depth = (float)(((double)rs.kf + 0.5) * p.dt);
-        const Step st = make_step(rs, b, p.dt);
-        for (long long kb = rs.kf; kb <= rs.kl; kb += kAnchor) {
-            const Anchor an = make_anchor(rs, b, p.dt, kb);
-            const int n = (int)min((long long)kAnchor, rs.kl - kb + 1);
-            evaluated += n;
-            for (int j = 0; j < n; ++j) {
-                if (kCkpt) {
-                    const long long q = kb + j - rs.kf;
-                    if (q % p.ckpt_interval == 0 && q / p.ckpt_interval < p.ckpt_nseg)
-                        p.ckpt[pix * p.ckpt_nseg + q / p.ckpt_interval] = T;
-                }
-                const Cell c = locate(an, st, j, snx, sny, snz);
-                const float v = trilinear(vox, c, snx, sxy);
-                const Classified e = classify(tft, v, tf_k, tf_o);
-                // emission-absorption: T_next = T exp2(-a'), weight = T - T_next
-                const float Tn = T * exp2f(-e.a);
-                const float w = T - Tn;
-                C0 = fmaf(w, e.r, C0);
-                C1 = fmaf(w, e.g, C1);
-                C2 = fmaf(w, e.b, C2);
-                T = Tn;
-                if (T < eps) {
-                    evaluated -= n - 1 - j;   // samples of this block not taken
-                    goto done;
-                }
-            }
+        march_ray_direct<TS, kCkpt>(p, tft, rs, pix, tf_k, tf_o, eps, s);
+    }
+    finish(p, valid, pix, depth, s, lane);
+}
+
+// ------------------------------------------------------------ staged kernel
+// Workgroup-wide reduction of kRed values: wave reduction by shuffles, one
+// LDS round trip (double-buffered by `buf`, so one barrier per call).
+constexpr int kRed = 12;
+
+template <int N>
+__device__ inline void wg_reduce(float (&v)[N], const bool (&is_max)[N], float (*red)[4][kRed],
+                                 int buf, int lane, int wave) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        float x = v[i];
+        for (int off = 32; off > 0; off >>= 1) {
+            const float y = __shfl_xor(x, off);
+            x = is_max[i] ? fmaxf(x, y) : fminf(x, y);
         }
+        v[i] = x;
     }
-done:
-    if (valid) {
-        reinterpret_cast<float4*>(p.out_rgba)[pix] = make_float4(C0, C1, C2, 1.0f - T);
-        p.out_depth[pix] = depth;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) red[buf][wave][i] = v[i];
     }
-    if (p.samples) {
-        // wave-wide sum, one atomic per wave
-        unsigned long long cnt = (unsigned long long)evaluated;
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-        if (lane == 0 && cnt) atomicAdd(p.samples, cnt);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        float x = red[buf][0][i];
+        for (int w = 1; w < 4; ++w) x = is_max[i] ? fmaxf(x, red[buf][w][i]) : fminf(x, red[buf][w][i]);
+        v[i] = x;
     }
 }
 
+template <typename TS>
+struct StageVec;
+template <>
+struct StageVec<float> {
+    static constexpr int V = 4;
+    __device__ static void copy(const float* __restrict__ src, float* dst) {
+        *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(src);
+    }
+};
+template <>
+struct StageVec<__half> {
+    static constexpr int V = 8;
+    __device__ static void copy(const __half* __restrict__ src, float* dst) {
+        const uint4 raw = *reinterpret_cast<const uint4*>(src);
+        const __half2* h = reinterpret_cast<const __half2*>(&raw);
+        const float2 a = __half22float2(h[0]), b = __half22float2(h[1]);
+        const float2 c = __half22float2(h[2]), d = __half22float2(h[3]);
+        reinterpret_cast<float4*>(dst)[0] = make_float4(a.x, a.y, b.x, b.y);
+        reinterpret_cast<float4*>(dst)[1] = make_float4(c.x, c.y, d.x, d.y);
+    }
+};
+
+// LDS of a staged-march workgroup.
+struct StagedShared {
+    TFTable tft;
+    __align__(16) float stage[kStageFloats];
+    int tab_off[kSlices], tab_x0[kSlices], tab_b0[kSlices];
+    float red[2][4][kRed];
+    int axis_sg[2];
+};
+
+// One 16x16 tile of one partial image, by the whole 256-thread workgroup.
+// The classification table must already be in sh.tft; `buf` selects the
+// reduction buffer and is carried between calls.  Every thread of the
+// workgroup must call it with the same arguments.
+template <typename TS>
+__device__ void staged_tile(const MarchParams& p, int tile, StagedShared& sh, int& buf) {
+    TFTable& tft = sh.tft;
+    float* stage = sh.stage;
+    int* tab_off = sh.tab_off;
+    int* tab_x0 = sh.tab_x0;
+    int* tab_b0 = sh.tab_b0;
+    float (*red)[4][kRed] = sh.red;
+    constexpr int V = StageVec<TS>::V;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x16 = (p.roi_w + 15) / 16;
+    const int tx = tile % tiles_x16, ty = tile / tiles_x16;
+    const int lx = tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int ly = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const bool valid = tile < p.tiles_x * p.tiles_y && lx < p.roi_w && ly < p.roi_h;
+    const long long pix = (long long)ly * p.roi_w + lx;
+
+    const BrickK& b = p.brick;
+    const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
+    const int snx = b.sdim[0], sny = b.sdim[1];
+    const int pitch = row_pitch(snx);
+    const long long sxy = (long long)pitch * sny;
+    const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
+    const float tf_o = -p.tf.vmin * tf_k;
+    const float eps = p.ert_eps;
+
+    LaneState s{0.f, 0.f, 0.f, 1.f, 0, false};
+    float depth = INFINITY;
+    RaySetup rs;
+    const bool has = valid && setup_ray(p.cam, b, p.dt, p.roi_x0 + lx, p.roi_y0 + ly, rs);
+    Blocks bl{0.0, 1.0, 0, 1};
+    float dw_abs = 1.0f;
+    if (has) {
+        depth = (float)(((double)rs.kf + 0.5) * p.dt);
+        bl = make_blocks(rs, b);
+        dw_abs = (float)fabs(pick3(rs.d, bl.axis));
+    }
+    // eligibility: every ray of the tile shares slab axis (y or z) and direction
+    {
+        const float key = has ? (float)(bl.axis * 2 + (bl.sg > 0 ? 1 : 0)) : -1.0f;
+        float v[4] = {has ? key : 1e9f, has ? key : -1e9f, has ? dw_abs : 1e9f, has ? 1.0f : 0.0f};
+        const bool mx[4] = {false, true, false, true};
+        wg_reduce(v, mx, red, buf, lane, wave);
+        buf ^= 1;
+        if (v[3] == 0.0f) {                       // no ray of this tile hits the brick
+            finish(p, valid, pix, depth, s, lane);
+            return;
+        }
+        const bool eligible = v[0] == v[1] && v[0] >= 2.0f && v[2] >= kMinStageDw;
+        if (!eligible) {
+            if (has) march_ray_direct<TS, false>(p, tft, rs, pix, tf_k, tf_o, eps, s);
+            finish(p, valid, pix, depth, s, lane);
+            return;
+        }
+    }
+    // the tile's common slab axis and direction (every ray agrees; any one writes)
+    if (has) {
+        sh.axis_sg[0] = bl.axis;
+        sh.axis_sg[1] = bl.sg;
+    }
+    __syncthreads();
+    const int w_axis = sh.axis_sg[0], sg = sh.axis_sg[1];
+    const int b_axis = 3 - w_axis;           // the other of y (1) and z (2)
+    const int snw = pick3(b.sdim, w_axis), snb = pick3(b.sdim, b_axis);
+    // the ray's coordinates along b (origin, direction, grid), selected once
+    const double o_b = has ? pick3(rs.o, b_axis) : 0.0, d_b = has ? pick3(rs.d, b_axis) : 0.0;
+    const double org_b = pick3(b.origin, b_axis), sp_b = pick3(b.spacing, b_axis);
+    // slopes of x and b per unit of s_w along each ray (stored-index units)
+    float kx = 0.f, kb = 0.f;
+    if (has) {
+        const double dwu = pick3(rs.d, w_axis) / pick3(b.spacing, w_axis);
+        kx = (float)((rs.d[0] / b.spacing[0]) / dwu);
+        kb = (float)((d_b / sp_b) / dwu);
+    }
+    const Step st = has ? make_step(rs, b, p.dt) : Step{0.f, 0.f, 0.f};
+    long long n_cur = 0, k_cur = 0, k_next = 0;
+    bool alive = has;
+    if (has) {
+        n_cur = block_of(bl, p.dt, rs.kf);
+        k_cur = rs.kf;
+        k_next = block_start(bl, p.dt, n_cur + 1);
+    }
+    // first slab: the smallest block index of the tile
+    long long n_chunk;
+    {
+        float v[1] = {has ? (float)n_cur : 3e38f};
+        const bool mx[1] = {false};
+        wg_reduce(v, mx, red, buf, lane, wave);
+        buf ^= 1;
+        n_chunk = (long long)v[0];
+    }
+    auto fetch_hbm = [&](const Cell& c) { return trilinear(vox, c, pitch, sxy); };
+
+    // at most snw / kSlab + 3 slabs intersect the brick; the bound only guards
+    // against a logic error turning into a hang
+    const int max_iter = 2 * (snw / kSlab + 4);
+    for (int iter = 0; iter < max_iter; ++iter) {
+        const bool part = alive && n_cur == n_chunk;
+        // slab [wlo, wlo + kSlab] of stored w; crossing of plane wlo per ray
+        const long long wlo = sg > 0 ? (long long)kSlab * n_chunk : -(long long)kSlab * (n_chunk + 1);
+        float xr = 0.f, br = 0.f;
+        if (part) {
+#pragma clang fp contract(off)
+            const double t = bl.c0 + (double)(sg > 0 ? n_chunk : n_chunk + 1) * bl.c1;
+            xr = (float)((rs.o[0] + t * rs.d[0] - b.origin[0]) / b.spacing[0] - 0.5 + (double)b.ghost);
+            br = (float)((o_b + t * d_b - org_b) / sp_b - 0.5 + (double)b.ghost);
+        }
+        float v[11] = {part ? xr : 3e38f, part ? xr : -3e38f, part ? br : 3e38f, part ? br : -3e38f,
+                       part ? kx : 3e38f, part ? kx : -3e38f, part ? kb : 3e38f, part ? kb : -3e38f,
+                       part ? 1.0f : 0.0f, alive ? 1.0f : 0.0f,
+                       (alive && !part) ? (float)n_cur : 3e38f};
+        const bool mx[11] = {false, true, false, true, false, true, false, true, true, true, false};
+        wg_reduce(v, mx, red, buf, lane, wave);
+        buf ^= 1;
+        if (v[9] == 0.0f) break;                   // every ray of the tile is done
+        if (v[8] == 0.0f) {                        // gap: jump to the next slab someone needs
+            n_chunk = (long long)v[10];
+            continue;
+        }
+        // uniform slab geometry (stored-index units)
+        const float xmin0 = v[0], xmax0 = v[1], bmin0 = v[2], bmax0 = v[3];
+        const float kxmin = v[4], kxmax = v[5], kbmin = v[6], kbmax = v[7];
+        const float Kx = fmaxf(fabsf(kxmin), fabsf(kxmax)), Kb = fmaxf(fabsf(kbmin), fabsf(kbmax));
+        // rectangle extents bounding every slice's footprint (clamped before the
+        // conversion so that absurd spans cannot overflow an int)
+        const float span_x = fminf((xmax0 - xmin0) + 2.0f * Kx + (float)kSlices * (kxmax - kxmin), 65536.0f);
+        const float span_b = fminf((bmax0 - bmin0) + 2.0f * Kb + (float)kSlices * (kbmax - kbmin), 65536.0f);
+        int RW = (int)ceilf(span_x) + 6 + V;
+        RW = (RW + V - 1) / V * V;
+        if (RW > pitch) RW = pitch;
+        int RH = (int)ceilf(span_b) + 6;
+        if (RH > snb) RH = snb;
+        const bool use_lds = (long long)kSlices * RW * RH <= kStageFloats && RW > 0 && RH > 0;
+        if (use_lds) {
+            if (tid < kSlices) {
+                const int i = tid;
+                const float da = (float)(i - 2), db = (float)i;
+                const float xl = xmin0 + fminf(fminf(da * kxmin, da * kxmax), fminf(db * kxmin, db * kxmax));
+                const float bl0 = bmin0 + fminf(fminf(da * kbmin, da * kbmax), fminf(db * kbmin, db * kbmax));
+                int x0 = (int)floorf(xl) - 1;
+                x0 = max(x0, 0) / V * V;
+                if (x0 + RW > pitch) x0 = pitch - RW;
+                int b0 = max((int)floorf(bl0) - 1, 0);
+                tab_x0[i] = x0;
+                tab_b0[i] = b0;
+                tab_off[i] = i * RH * RW - b0 * RW - x0;
+            }
+            __syncthreads();
+            // stage slices wlo - 1 .. wlo + kSlab + 1 (rows along x, 16-byte vectors)
+            const int cols = RW / V;
+            const int total = kSlices * RH * cols;
+            const float inv_cols = 1.0f / (float)cols, inv_rh = 1.0f / (float)RH;
+            for (int e = tid; e < total; e += 256) {
+                const int q = (int)(((float)e + 0.5f) * inv_cols);
+                const int c = e - q * cols;
+                const int i = (int)(((float)q + 0.5f) * inv_rh);
+                const int r = q - i * RH;
+                const int wabs = min(max((int)wlo - 1 + i, 0), snw - 1);
+                const int babs = min(tab_b0[i] + r, snb - 1);
+                const int x = tab_x0[i] + c * V;
+                const long long yz = w_axis == 2 ? ((long long)wabs * sny + babs)
+                                                 : ((long long)babs * sny + wabs);
+                StageVec<TS>::copy(vox + yz * pitch + x, &stage[(i * RH + r) * RW + c * V]);
+            }
+            __syncthreads();
+        }
+        if (part) {
+            const long long kend = min(k_next - 1, rs.kl);
+            const int n = (int)(kend - k_cur + 1);
+            bool cont = true;
+            if (n > 0) {
+                if (use_lds) {
+                    const int wbase = (int)wlo - 1;
+                    auto fetch_lds = [&](const Cell& c) {
+                        const int ib = w_axis == 2 ? c.iy : c.iz;
+                        const int iw = w_axis == 2 ? c.iz : c.iy;
+                        const int si = min(max(iw - wbase, 0), kSlices - 2);
+                        const int row = ib * RW + c.ix;
+                        const int a0 = min(max(tab_off[si] + row, 0), kStageFloats - RW - 2);
+                        const int a1 = min(max(tab_off[si + 1] + row, 0), kStageFloats - RW - 2);
+                        const float p00 = stage[a0], p01 = stage[a0 + 1];
+                        const float p10 = stage[a0 + RW], p11 = stage[a0 + RW + 1];
+                        const float q00 = stage[a1], q01 = stage[a1 + 1];
+                        const float q10 = stage[a1 + RW], q11 = stage[a1 + RW + 1];
+                        // (p: slice w, q: slice w+1; second index: row b+1)
+                        return w_axis == 2 ? lerp3(c, p00, p01, p10, p11, q00, q01, q10, q11)
+                                           : lerp3(c, p00, p01, q00, q01, p10, p11, q10, q11);
+                    };
+                    cont = march_block<false>(p, tft, rs, b, st, k_cur, n, pix, tf_k, tf_o, eps, s,
+                                              fetch_lds);
+                } else {
+                    cont = march_block<false>(p, tft, rs, b, st, k_cur, n, pix, tf_k, tf_o, eps, s,
+                                              fetch_hbm);
+                }
+            }
+            k_cur = max(k_cur, kend + 1);
+            ++n_cur;
+            k_next = block_start(bl, p.dt, n_cur + 1);
+            alive = cont && k_cur <= rs.kl;
+        }
+        ++n_chunk;
+    }
+    finish(p, valid, pix, depth, s, lane);
+}
+
+
+template <typename TS>
+__global__ __launch_bounds__(256) void march_staged(MarchParams p) {
+    __shared__ StagedShared sh;
+    load_tf(sh.tft, p.tf, p.dt, threadIdx.x, 256);
+    // XCD-aware order: workgroup i runs on XCD i mod 8, so give each XCD a
+    // contiguous run of tiles (neighbouring tiles share L2 lines); the map is
+    // a bijection on [0, gridDim.x)
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int per = nb / 8, rem = nb % 8, xcd = bid % 8;
+    const int tile = xcd * per + min(xcd, rem) + bid / 8;
+    int buf = 0;
+    staged_tile<TS>(p, tile, sh, buf);
+}
+
+// Persistent work-queue march: each workgroup repeatedly takes the next
+// ticket of the queue (one 16x16 tile of one job = one partial image) until
+// the tickets run out, so many small partials (bricks x time steps x fields
+// x cameras) fill the GPU together.  The table is reloaded only when a job's
+// transfer function (or dt) differs from the previous ticket's.
+template <typename TS>
+__global__ __launch_bounds__(256) void march_queue(QueueParams q) {
+    __shared__ StagedShared sh;
+    __shared__ int ticket;
+    const int tid = threadIdx.x;
+    const float* tf_loaded = nullptr;
+    float scale_loaded = -1.0f;
+    double dt_loaded = -1.0;
+    int buf = 0;
+    for (;;) {
+        if (tid == 0) ticket = atomicAdd(q.head, 1);
+        __syncthreads();
+        const int t = ticket;
+        __syncthreads();
+        if (t >= q.total_tiles) break;
+        // job of ticket t: the last j with tile_start[j] <= t
+        int lo = 0, hi = q.n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (q.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const MarchParams& p = q.jobs[lo];
+        if (p.tf.rgba != tf_loaded || p.tf.opacity_scale != scale_loaded || p.dt != dt_loaded) {
+            load_tf(sh.tft, p.tf, p.dt, tid, 256);
+            tf_loaded = p.tf.rgba;
+            scale_loaded = p.tf.opacity_scale;
+            dt_loaded = p.dt;
+            // (staged_tile's first reduction barrier orders these writes before use)
+        }
+        staged_tile<TS>(p, t - q.tile_start[lo], sh, buf);
+        __syncthreads();
+    }
+}
+
+__global__ void queue_reset(int* head) {
+    if (threadIdx.x == 0) *head = 0;
+}
+
 template <bool kCkpt>
-hipError_t launch(const MarchParams& p, StorageK storage, hipStream_t stream) {
+hipError_t launch_direct(const MarchParams& p, StorageK storage, hipStream_t stream) {
     const int blocks = p.tiles_x * p.tiles_y;
     if (blocks == 0) return hipSuccess;
     if (storage == kF16)
@@ -104,8 +481,40 @@ hipError_t launch(const MarchParams& p, StorageK storage, hipStream_t stream) {
 
 }  // namespace
 
+hipError_t launch_march_queue(const QueueParams& q, StorageK storage, int workgroups,
+                              hipStream_t stream) {
+    if (q.total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, stream, q.head);
+    const int grid = min(workgroups, q.total_tiles);
+    if (storage == kF16)
+        hipLaunchKernelGGL(march_queue<__half>, dim3(grid), dim3(256), 0, stream, q);
+    else
+        hipLaunchKernelGGL(march_queue<float>, dim3(grid), dim3(256), 0, stream, q);
+    return hipGetLastError();
+}
+
+int march_queue_workgroups_per_cu(StorageK storage) {
+    int n = 0;
+    hipError_t e = storage == kF16
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue<__half>, 256, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue<float>, 256, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 hipError_t launch_march(const MarchParams& p, StorageK storage, hipStream_t stream) {
-    return p.ckpt ? launch<true>(p, storage, stream) : launch<false>(p, storage, stream);
+    if (p.ckpt) return launch_direct<true>(p, storage, stream);
+    if (p.path == kPathDirect) return launch_direct<false>(p, storage, stream);
+    // staged: one workgroup per 16x16 tile; tiles_x/tiles_y count 16x16 tiles
+    MarchParams q = p;
+    q.tiles_x = (p.roi_w + 15) / 16;
+    q.tiles_y = (p.roi_h + 15) / 16;
+    const int blocks = q.tiles_x * q.tiles_y;
+    if (blocks == 0) return hipSuccess;
+    if (storage == kF16)
+        hipLaunchKernelGGL(march_staged<__half>, dim3(blocks), dim3(256), 0, stream, q);
+    else
+        hipLaunchKernelGGL(march_staged<float>, dim3(blocks), dim3(256), 0, stream, q);
+    return hipGetLastError();
 }
 
 }  // namespace dpvr

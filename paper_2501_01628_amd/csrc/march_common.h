@@ -13,7 +13,7 @@
 
 namespace dpvr {
 
-constexpr int kAnchor = 32;       // samples between float64 re-anchors
+constexpr int kSlab = 8;          // anchor block = slab of kSlab slices along the ray's w axis
 constexpr float kLog2e = 1.4426950408889634f;
 
 struct RaySetup {
@@ -78,6 +78,60 @@ __device__ inline bool setup_ray(const CameraK& cam, const BrickK& b, double dt,
     return true;
 }
 
+// Anchor blocks.  Every ray picks a slab axis w (z or y, whichever has the
+// larger direction component; x only if both are below 1/16) and cuts its
+// owned samples at the planes s_w = kSlab * m of the brick's stored-index
+// coordinate (s = (p - origin) / spacing - 1/2 + ghost).  In ray order the
+// planes are numbered n (plane s_w = kSlab * sg * n, sg = sign d_w); the ray
+// crosses plane n at t_n = c0 + n * c1 (c1 > 0), and block n holds the samples
+// k with k_n <= k < k_{n+1}, k_n = ceil(t_n / dt - 1/2).  A block's float32
+// positions are anchored (float64) at its first owned sample max(kf, k_n).
+// The rule depends on the ray alone, so every kernel and every launch
+// configuration evaluates every sample at the same float32 position.
+struct Blocks {
+    double c0, c1;
+    int axis, sg;
+};
+
+// v[i] for a run-time i without indexing a register array (which would spill
+// the array to scratch memory).
+template <typename T>
+__device__ inline T pick3(const T (&v)[3], int i) {
+    return i == 2 ? v[2] : (i == 1 ? v[1] : v[0]);
+}
+
+__device__ inline Blocks make_blocks(const RaySetup& rs, const BrickK& b) {
+#pragma clang fp contract(off)
+    Blocks bl;
+    const double ay = fabs(rs.d[1]), az = fabs(rs.d[2]);
+    bl.axis = (az >= ay) ? 2 : 1;
+    if (fmax(ay, az) < 0.0625) bl.axis = 0;
+    const int w = bl.axis;
+    const double dw = pick3(rs.d, w);
+    bl.sg = dw > 0.0 ? 1 : -1;
+    // s_w(t) = (o_w + t d_w - origin_w) / sp_w - 1/2 + g = kSlab sg n
+    const double spw = pick3(b.spacing, w);
+    bl.c0 = ((0.5 - (double)b.ghost) * spw + pick3(b.origin, w) - pick3(rs.o, w)) / dw;
+    bl.c1 = ((double)(kSlab * bl.sg) * spw) / dw;
+    return bl;
+}
+
+__device__ inline long long block_start(const Blocks& bl, double dt, long long n) {
+#pragma clang fp contract(off)
+    const double t = bl.c0 + (double)n * bl.c1;
+    return (long long)ceil(t / dt - 0.5);
+}
+
+// Block (plane index n) holding sample k: the largest n with k_n <= k.
+__device__ inline long long block_of(const Blocks& bl, double dt, long long k) {
+#pragma clang fp contract(off)
+    const double t = ((double)k + 0.5) * dt;
+    long long n = (long long)floor((t - bl.c0) / bl.c1);
+    while (block_start(bl, dt, n) > k) --n;
+    while (block_start(bl, dt, n + 1) <= k) ++n;
+    return n;
+}
+
 // float32 stored-index coordinate of sample k = kb + j is  anchor + j * step,
 // with the anchor (integer part ia, fraction uf) computed in float64 at kb.
 struct Anchor {
@@ -118,6 +172,7 @@ struct Cell {
 };
 
 __device__ inline Cell locate(const Anchor& a, const Step& st, int j, int snx, int sny, int snz) {
+    // snx = stored extent in x (not the row pitch)
     const float fj = (float)j;
     const float x = fmaf(fj, st.s0, a.uf0);
     const float y = fmaf(fj, st.s1, a.uf1);
@@ -131,20 +186,33 @@ __device__ inline Cell locate(const Anchor& a, const Step& st, int j, int snx, i
     return c;
 }
 
+// Transmittance factor exp2(-a') with the hardware exp2 (1 ulp).  a' >= 0,
+// so the result lies in (0, 1]; results below the smallest normal float
+// flush to 0, which only affects transmittances below 2^-126.  Every kernel
+// uses this one function, so all paths agree bit for bit.
+__device__ inline float trans_exp2(float neg_a) { return __builtin_amdgcn_exp2f(neg_a); }
+
+// Voxel loads through global-address-space pointers (the brick pointer comes
+// from a job table in memory, where the compiler cannot infer the address
+// space and would emit flat loads).
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef __attribute__((address_space(1))) const unsigned short ghalf_bits;
+
 template <typename TS>
 __device__ inline float ld(const TS* p, long long i);
 template <>
-__device__ inline float ld<float>(const float* p, long long i) { return p[i]; }
+__device__ inline float ld<float>(const float* p, long long i) {
+    return ((gfloat*)p)[i];
+}
 template <>
-__device__ inline float ld<__half>(const __half* p, long long i) { return __half2float(p[i]); }
+__device__ inline float ld<__half>(const __half* p, long long i) {
+    return __half2float(__ushort_as_half(((ghalf_bits*)p)[i]));
+}
 
-template <typename TS>
-__device__ inline float trilinear(const TS* __restrict__ vox, const Cell& c, int snx, long long sxy) {
-    const long long base = (long long)c.iz * sxy + (long long)c.iy * snx + c.ix;
-    const float v000 = ld(vox, base), v100 = ld(vox, base + 1);
-    const float v010 = ld(vox, base + snx), v110 = ld(vox, base + snx + 1);
-    const float v001 = ld(vox, base + sxy), v101 = ld(vox, base + sxy + 1);
-    const float v011 = ld(vox, base + sxy + snx), v111 = ld(vox, base + sxy + snx + 1);
+// Trilinear interpolation of the 8 corner values, x first, then y, then z
+// (the one order every path uses).
+__device__ inline float lerp3(const Cell& c, float v000, float v100, float v010, float v110,
+                              float v001, float v101, float v011, float v111) {
     const float v00 = fmaf(c.fx, v100 - v000, v000);
     const float v10 = fmaf(c.fx, v110 - v010, v010);
     const float v01 = fmaf(c.fx, v101 - v001, v001);
@@ -153,6 +221,20 @@ __device__ inline float trilinear(const TS* __restrict__ vox, const Cell& c, int
     const float v1 = fmaf(c.fy, v11 - v01, v01);
     return fmaf(c.fz, v1 - v0, v0);
 }
+
+// Corner values straight from the brick in HBM: pitch = row pitch (elements),
+// sxy = pitch * stored y extent.
+template <typename TS>
+__device__ inline float trilinear(const TS* __restrict__ vox, const Cell& c, int pitch, long long sxy) {
+    const long long base = (long long)c.iz * sxy + (long long)c.iy * pitch + c.ix;
+    return lerp3(c, ld(vox, base), ld(vox, base + 1), ld(vox, base + pitch),
+                 ld(vox, base + pitch + 1), ld(vox, base + sxy), ld(vox, base + sxy + 1),
+                 ld(vox, base + sxy + pitch), ld(vox, base + sxy + pitch + 1));
+}
+
+// Row pitch of the stored brick (elements): x extent rounded up to 8, so that
+// every row starts 16-byte aligned for both storage precisions.
+__host__ __device__ inline int row_pitch(int snx) { return (snx + 7) & ~7; }
 
 // Classification table in LDS: entry i = (r, g, b, a') with a' = alpha *
 // opacity_scale * dt * log2(e), and the difference to entry i + 1.

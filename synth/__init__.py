@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Brick", "Scene", "default_tf", "hidden_tf", "orbit_camera", "inside_camera",
     "draw_blobs", "add_blobs", "add_shock", "kd_split", "extract_brick",
-    "config_c1", "config_c2", "config_c4", "tile_field", "scene_from_field",
+    "config_c1", "config_c2", "config_c3", "config_c4", "tile_field", "scene_from_field",
 ]
 
 _THREADS = max(1, min(16, os.cpu_count() or 1))
@@ -341,3 +341,42 @@ def tile_field(rng, dims, n_blobs=8, noise=0.0, shock=False):
     if noise > 0:
         acc += rng.uniform(0.0, noise, acc.shape)
     return _finish(acc)
+
+
+def config_c3(extent=(64, 320), pitch=336, n_bricks=14, steps=6, fields=3, size=1024,
+              n_blobs=64, seed=3):
+    """Batched case: ``n_bricks`` bricks of uneven extents (each axis
+    U{extent[0]..extent[1]}), placed at the min corners of the slots of a
+    4 x 2 x 2 grid of pitch ``pitch``; ``steps`` time steps x ``fields``
+    fields (density, pressure, velocity magnitude stand-ins: independent
+    blob sets, seeds 30, 31, 32, ...; blob centres advected by t * v with
+    v U(-4, 4)^3 per blob, scaled with the extent); 4 orbit cameras at az =
+    30 + 90 c, ``size`` x ``size``, step 0.5, opacity scale 0.1.  Ghost
+    voxels are evaluated from the analytic field (the bricks do not touch).
+
+    Returns dict(bricks=[(t, f, b, lo, voxels)], cameras=[...], tf, dims,
+    step, opacity_scale).  Draw order: extents (seed), then per field: blobs,
+    velocities (seed 30 + f)."""
+    rng = np.random.default_rng(seed)
+    ext = rng.integers(extent[0], extent[1] + 1, (n_bricks, 3))
+    slots = [(s % 4, (s // 4) % 2, s // 8) for s in range(16)]
+    dims = (4 * pitch, 2 * pitch, 2 * pitch)
+    vscale = extent[1] / 320.0
+    bricks = []
+    for f in range(fields):
+        frng = np.random.default_rng(30 + f)
+        centres, sig, amps = draw_blobs(frng, n_blobs, dims, sigma=(4.0 * vscale, 12.0 * vscale))
+        vel = frng.uniform(-4.0, 4.0, (n_blobs, 3)) * vscale
+        for t in range(steps):
+            c_t = centres + t * vel
+            for b in range(n_bricks):
+                lo = tuple(int(v) * pitch for v in slots[b])
+                e = ext[b]
+                shape = (int(e[2]) + 2, int(e[1]) + 2, int(e[0]) + 2)
+                acc = np.zeros(shape, dtype=np.float64)
+                add_blobs(acc, c_t, sig, amps, offset=(lo[0] - 1, lo[1] - 1, lo[2] - 1))
+                np.clip(acc, 0.0, 1.0, out=acc)
+                bricks.append((t, f, b, lo, acc.astype(np.float32)))
+    cams = [orbit_camera((0, 0, 0), dims, size, size, az_deg=30.0 + 90.0 * c) for c in range(4)]
+    return dict(bricks=bricks, cameras=cams, tf=default_tf(), dims=dims, step=0.5,
+                opacity_scale=0.1, extents=ext)

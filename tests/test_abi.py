@@ -49,8 +49,10 @@ def test_workspace_size_rejects(dims, ghost, storage, status):
 
 
 def test_workspace_size_values():
-    assert dp.vr_brick_workspace_size((32, 64, 64), 1, dp.VR_F32) == ((34 * 66 * 66 * 4 + 255) // 256) * 256
-    assert dp.vr_brick_workspace_size((32, 64, 64), 1, dp.VR_F16) == ((34 * 66 * 66 * 2 + 255) // 256) * 256
+    # rows of nx + 2 voxels padded to a multiple of 8 elements
+    assert dp.vr_brick_workspace_size((32, 64, 64), 1, dp.VR_F32) == ((40 * 66 * 66 * 4 + 255) // 256) * 256
+    assert dp.vr_brick_workspace_size((32, 64, 64), 1, dp.VR_F16) == ((40 * 66 * 66 * 2 + 255) // 256) * 256
+    assert dp.vr_brick_workspace_size((6, 1, 1), 1, dp.VR_F32) == 512   # 8 x 3 x 3 x 4 B
 
 
 def test_null_handles_are_rejected():

@@ -269,3 +269,72 @@ def test_state_errors(dp):
     assert e.value.status == dp.VR_ERR_STATE
     dp.vr_brick_release(b)
     dp.vr_context_release(ctx)
+
+
+# ----------------------------------------------------- launch-path invariance
+@pytest.mark.parametrize("seed,dims,nb,w,h,az,el,radius,step", [
+    (201, (64, 48, 40), 6, 96, 80, 30.0, 20.0, 2.0, 0.5),     # z slabs, every tile staged
+    (202, (48, 64, 40), 5, 80, 72, 120.0, 20.0, 1.8, 0.5),    # x-dominant view, y/z slabs
+    (203, (40, 40, 40), 4, 72, 64, 90.0, 0.0, 2.0, 0.5),      # view along -x: HBM fallback
+    (204, (60, 40, 30), 7, 64, 64, 200.0, -50.0, 1.3, 0.25),  # y slabs, negative direction
+])
+def test_staged_equals_direct_bitwise(dp, seed, dims, nb, w, h, az, el, radius, step):
+    """The LDS-staged march and the direct march evaluate every sample at the
+    same float32 position from the same voxel values, so partial images and
+    sample counts are bit-identical; both match the oracle."""
+    sc = _scene_small(seed, dims, nb, w, h, az, el, radius, scale=3.0, step=step)
+    out = []
+    for path in (dp.VR_PATH_STAGED, dp.VR_PATH_DIRECT):
+        bricks = [(b.voxels, b.lo) for b in sc.bricks]
+        r = dp.Renderer(bricks, sc.tf, sc.vrange, sc.opacity_scale, sc.step, path=path)
+        r.reset_samples()
+        img, parts = _gpu_frame(r, sc.camera, BG)
+        counts = r.sample_counts()
+        r.close()
+        out.append((img, parts, counts))
+    (ia, pa, ca), (ib, pb, cb) = out
+    assert np.array_equal(ia, ib)
+    for (ra, rga, da), (rb, rgb, db) in zip(pa, pb):
+        assert ra == rb and np.array_equal(rga, rgb) and np.array_equal(da, db)
+    assert np.array_equal(ca, cb)
+    ref, ref_parts, _ = oracle.render_scene(sc, bg=BG)
+    _check_partials(pa, ref_parts, TOL32)
+    assert np.max(np.abs(ia - ref)) <= TOL32
+
+
+def test_staged_fp16_and_inside_camera(dp):
+    """FP16 storage (staged as float32) and a camera inside the volume (large
+    per-slab footprints that may exceed LDS and fall back)."""
+    sc = _scene_small(205, (48, 40, 36), 6, 64, 56, scale=3.0)
+    cam = synth.inside_camera((0, 0, 0), (48, 40, 36), 64, 56, fovy_deg=80.0)
+    outs = []
+    for path in (dp.VR_PATH_STAGED, dp.VR_PATH_DIRECT):
+        r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange, sc.opacity_scale,
+                        sc.step, storage=dp.VR_F16, path=path)
+        outs.append(_gpu_frame(r, cam, BG)[0])
+        r.close()
+    assert np.array_equal(outs[0], outs[1])
+    dec = [b.voxels.astype(np.float16).astype(np.float32) for b in sc.bricks]
+    ref, _, _ = oracle.render_scene(sc, camera=cam, bg=BG, field_override=dec)
+    assert np.max(np.abs(outs[0] - ref)) <= TOL32
+
+
+def test_queued_frame_equals_per_brick_launches(dp):
+    """All partials of a frame through one work-queue launch (mixed float32 and
+    float16 bricks: two queues) equal one launch per brick, bitwise."""
+    sc = _scene_small(206, (56, 44, 36), 9, 88, 72, az=65.0, scale=3.0)
+    bricks = [(b.voxels, b.lo) for b in sc.bricks]
+    r = dp.Renderer([], sc.tf, sc.vrange, sc.opacity_scale, sc.step)
+    for k, (v, lo) in enumerate(bricks):
+        r.storage = dp.VR_F16 if k % 3 == 0 else dp.VR_F32
+        r.add_brick(v, lo)
+    r.set_camera(sc.camera)
+    r.render_partials()
+    r.synchronize()
+    a = [tuple(t.cpu().numpy().copy() for t in r.partial_arrays(k)) for k in range(len(bricks))]
+    r.render_partials_each()
+    r.synchronize()
+    b = [tuple(t.cpu().numpy().copy() for t in r.partial_arrays(k)) for k in range(len(bricks))]
+    r.close()
+    for (ra, da), (rb, db) in zip(a, b):
+        assert np.array_equal(ra, rb) and np.array_equal(da, db)
