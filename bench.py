@@ -70,25 +70,32 @@ def traffic_for(kernel_src, workload, storage):
     return rec.get("hbm_bytes_per_frame")
 
 
-def cpu_baseline(sc, target_s):
+def cpu_baseline(sc, target_s, frame=None):
+    """The oracle timed on a random pixel sample of the frame; with the GPU
+    frame given, also its max error against the oracle at those pixels."""
     import numpy as np
     import oracle
     W, H = sc.camera["width"], sc.camera["height"]
     rng = np.random.default_rng(0)
-    # calibrate on a small sample, then size the measured sample
+    # calibrate on a sample of ~1 s, then size the measured sample
     def run(npix):
         idx = rng.choice(W * H, npix, replace=False)
         pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
         t0 = time.perf_counter()
-        _, _, cnt = oracle.render_scene(sc, pixels=pix)
-        return time.perf_counter() - t0, int(cnt[0])
-    t, _ = run(512)
-    npix = int(min(W * H, max(1024, 512 * target_s / max(t, 1e-3))))
-    t, samples = run(npix)
+        img, _, cnt = oracle.render_scene(sc, pixels=pix)
+        return time.perf_counter() - t0, int(cnt[0]), pix, img
+    t, _, _, _ = run(20000)
+    npix = int(min(W * H, max(20000, 20000 * target_s / max(t, 1e-3))))
+    t, samples, pix, img = run(npix)
     cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-    return {"value": samples / t / 1e6, "unit": "Msamples/s", "cores": cores, "kind": "oracle",
-            "sample": f"{npix} random pixels of the same frame, all {len(sc.bricks)} bricks + "
-                      f"composite, {samples} samples (no early termination) in {t:.1f} s"}
+    out = {"value": samples / t / 1e6, "unit": "Msamples/s", "cores": cores, "kind": "oracle",
+           "sample": f"{npix} random pixels of the same frame, all {len(sc.bricks)} bricks + "
+                     f"composite, {samples} samples (no early termination) in {t:.1f} s"}
+    err = None
+    if frame is not None:
+        got = frame[pix[:, 1], pix[:, 0]].astype(np.float64)
+        err = float(np.max(np.abs(got - img)))
+    return out, err
 
 
 def bench_batch(args):
@@ -291,12 +298,15 @@ def main():
         "composite_roofline": {"achieved": comp_alg / (comp_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "algorithmic_bytes": int(comp_alg)},
     }
+    frame = r.frame.cpu().numpy()
     r.close()
     del r
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        out["cpu_baseline"], err = cpu_baseline(sc, args.cpu_seconds, frame)
+        out["max_abs_err_vs_oracle"] = {"value": err, "pixels": "the cpu_baseline sample",
+                                        "bar": 2e-3 if args.storage == "f16" else 1e-5}
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -39,6 +39,9 @@ struct LaneState {
 
 // March samples kb .. kb + n - 1 of one anchor block; fetch(cell) returns the
 // interpolated value.  Returns false once early termination stops the ray.
+// Two samples are fetched and classified before either is accumulated, so
+// the memory round trips of consecutive samples overlap; accumulation stays
+// in sample order, so the result is the same as one sample at a time.
 template <bool kCkpt, typename Fetch>
 __device__ inline bool march_block(const MarchParams& p, const TFTable& tft, const RaySetup& rs,
                                    const BrickK& b, const Step& st, long long kb, int n,
@@ -46,15 +49,12 @@ __device__ inline bool march_block(const MarchParams& p, const TFTable& tft, con
                                    Fetch fetch) {
     const Anchor an = make_anchor(rs, b, p.dt, kb);
     const int snx = b.sdim[0], sny = b.sdim[1], snz = b.sdim[2];
-    for (int j = 0; j < n; ++j) {
+    auto accumulate = [&](const Classified& e, int j) -> bool {
         if (kCkpt) {
             const long long q = kb + j - rs.kf;
             if (q % p.ckpt_interval == 0 && q / p.ckpt_interval < p.ckpt_nseg)
                 p.ckpt[pix * p.ckpt_nseg + q / p.ckpt_interval] = s.T;
         }
-        const Cell c = locate(an, st, j, snx, sny, snz);
-        const float v = fetch(c);
-        const Classified e = classify(tft, v, tf_k, tf_o);
         // emission-absorption: T_next = T exp2(-a'), weight = T - T_next
         const float Tn = s.T * trans_exp2(-e.a);
         const float w = s.T - Tn;
@@ -67,6 +67,23 @@ __device__ inline bool march_block(const MarchParams& p, const TFTable& tft, con
             s.stopped = true;
             return false;
         }
+        return true;
+    };
+    int j = 0;
+    for (; j + 1 < n; j += 2) {
+        const Cell c0 = locate(an, st, j, snx, sny, snz);
+        const Cell c1 = locate(an, st, j + 1, snx, sny, snz);
+        const float v0 = fetch(c0);
+        const float v1 = fetch(c1);
+        const Classified e0 = classify(tft, v0, tf_k, tf_o);
+        const Classified e1 = classify(tft, v1, tf_k, tf_o);
+        if (!accumulate(e0, j)) return false;
+        if (!accumulate(e1, j + 1)) return false;
+    }
+    if (j < n) {
+        const Cell c = locate(an, st, j, snx, sny, snz);
+        const Classified e = classify(tft, fetch(c), tf_k, tf_o);
+        if (!accumulate(e, j)) return false;
     }
     s.evaluated += n;
     return true;
