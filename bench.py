@@ -1,9 +1,9 @@
 #!/usr/bin/env python3
 """Benchmark of the data-parallel volume-rendering hot path on one MI355X.
 
-One step = one frame: every brick's partial image is ray cast (one march
-launch per brick), then the partials are sort-last composited into the
-frame.  Inputs are resident in HBM before timing starts (brick ingest is
+One step = one frame: every brick's partial image is ray cast (all bricks'
+partials through one persistent work-queue launch), then the partials are
+sort-last composited into the frame.  Inputs are resident in HBM before timing starts (brick ingest is
 outside the timed region).  Default workload: a 1024x1024x512 float32 field
 (64 Gaussian blobs + a tanh shock front), kd-split into 16 uneven bricks with
 ghost layers, 1920x1080 perspective view, step 0.5 voxel, opacity scale 0.05,
@@ -20,6 +20,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -38,9 +40,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["c2", "c1", "c3"], default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--path", choices=["staged", "direct"], default="staged",
+                    help="march from LDS-staged slabs or straight from HBM (same images)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="first run one plain copy of known size through the ingest kernel "
+                         "(512^3 float32: 512 MiB read, 512 MiB written) for HBM-counter scaling")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs of --pmc-calibrate (FETCH_SIZE, then "
+                         "WRITE_SIZE) into the per-frame HBM traffic record under profiles/")
     return ap.parse_args()
 
 
@@ -68,6 +78,74 @@ def traffic_for(kernel_src, workload, storage):
     if rec.get("kernel_sha256") != h:
         return None
     return rec.get("hbm_bytes_per_frame")
+
+
+CALIB_STORED = 512                      # stored extent of the calibration brick (pitch = extent)
+CALIB_BYTES = CALIB_STORED ** 3 * 4     # bytes read and bytes written by its ingest
+MARCH_KERNEL = "march_queue"
+
+
+def _pmc_rows(d, counter):
+    """(kernel name, value) per dispatch of one counter, in dispatch order."""
+    import csv
+    import glob
+    rows = []
+    for fn in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        for r in csv.DictReader(open(fn)):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return [(k, v) for _, k, v in rows]
+
+
+def summarize_pmc(args):
+    """HBM bytes per frame of the march launch: its FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) scaled by what the same counters read for the plain
+    copy of CALIB_BYTES done first by --pmc-calibrate."""
+    out = {}
+    for name, d in zip(("FETCH_SIZE", "WRITE_SIZE"), args.summarize_pmc):
+        rows = _pmc_rows(d, name)
+        ingest = [v for k, v in rows if "ingest_kernel" in k]
+        march = [v for k, v in rows if MARCH_KERNEL in k]
+        if not ingest or not march:
+            raise SystemExit(f"{d}: no ingest/march dispatches with {name}")
+        calib = ingest[0] * 1024.0                  # first ingest = the calibration copy
+        scale = CALIB_BYTES / calib
+        out[name] = {"calibration_bytes_counted": calib, "scale": scale,
+                     "march_kib_per_dispatch": sum(march) / len(march),
+                     "march_dispatches": len(march),
+                     "march_bytes_per_dispatch_scaled": sum(march) / len(march) * 1024.0 * scale}
+    src = os.path.join(ROOT, "paper_2501_01628_amd", "csrc", "march.hip")
+    rec = {"kernel": MARCH_KERNEL, "workload": args.workload, "storage": args.storage,
+           "kernel_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+           "hbm_bytes_per_frame": out["FETCH_SIZE"]["march_bytes_per_dispatch_scaled"]
+           + out["WRITE_SIZE"]["march_bytes_per_dispatch_scaled"],
+           "counters": out,
+           "calibration": f"ingest_kernel copy of a {CALIB_STORED}^3 float32 brick "
+                          f"({CALIB_BYTES} B read, {CALIB_BYTES} B written)",
+           "commands": [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -- python3 bench.py "
+                        f"--workload {args.workload} --storage {args.storage} --steps 2 --warmup 1 "
+                        f"--no-cpu-baseline --pmc-calibrate" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
+    path = os.path.join(ROOT, "profiles", f"march_{args.workload}_{args.storage}_traffic.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+    return 0
+
+
+def calibration_copy():
+    """One ingest of a CALIB_STORED^3 float32 brick whose rows need no
+    padding: a plain copy of known size, for scaling the HBM counters."""
+    import torch
+    import paper_2501_01628_amd as dp
+    n = CALIB_STORED
+    v = torch.rand((n, n, n), dtype=torch.float32, device="cuda:0")
+    r = dp.Renderer([(v, (0, 0, 0))], np.zeros((256, 4), np.float32))
+    r.synchronize()
+    r.close()
+    del v, r
+    torch.cuda.empty_cache()
+    log(f"calibration copy: {CALIB_BYTES} B read + written by the ingest kernel")
 
 
 def cpu_baseline(sc, target_s, frame=None):
@@ -200,20 +278,23 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes, not built)"}))
         return 2
+    if args.summarize_pmc:
+        return summarize_pmc(args)
     if args.workload == "c3":
         return bench_batch(args)
-    import numpy as np
     import torch
 
     import paper_2501_01628_amd as dp
 
-    dev = torch.device("cuda", 0)
+    if args.pmc_calibrate:
+        calibration_copy()
     t0 = time.perf_counter()
     sc, desc = scene_for(args.workload)
     log(f"generated {sc.name} in {time.perf_counter() - t0:.1f} s")
     storage = dp.VR_F16 if args.storage == "f16" else dp.VR_F32
     r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange, sc.opacity_scale,
-                    sc.step, storage=storage, device=0)
+                    sc.step, storage=storage, device=0,
+                    path=dp.VR_PATH_DIRECT if args.path == "direct" else dp.VR_PATH_STAGED)
     r.set_camera(sc.camera)
     r.synchronize()
     # drop the float32 upload copies: only the workspaces stay resident
@@ -280,7 +361,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "bricks": nb, "width": W, "height": H,
-                   "storage": args.storage, "step_voxels": sc.step},
+                   "storage": args.storage, "step_voxels": sc.step, "path": args.path},
         "samples_per_frame": samples,
         "march_ms_per_frame": float(march_ms.sum()),
         "composite_ms_per_frame": comp_ms,

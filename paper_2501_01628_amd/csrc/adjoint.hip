@@ -71,14 +71,14 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
         long long bn = 0, kA = 0, kNext = 0;
         Anchor an{};
         auto seek = [&](long long k) {
-            bn = block_of(bl, p.dt, k);
-            kA = max(rs.kf, block_start(bl, p.dt, bn));
-            kNext = block_start(bl, p.dt, bn + 1);
+            bn = block_of(bl, p.dt, p.inv_dt, k);
+            kA = max(rs.kf, block_start(bl, p.inv_dt, bn));
+            kNext = block_start(bl, p.inv_dt, bn + 1);
             an = make_anchor(rs, b, p.dt, kA);
         };
         auto sample = [&](long long k) {
             if (k < kA || k >= kNext) seek(k);
-            const Cell c = locate(an, st, (int)(k - kA), snx, sny, snz);
+            const Cell c = locate(an, st, (float)(k - kA), snx, sny, snz);
             return c;
         };
         for (int s = nseg - 1; s >= 0; --s) {

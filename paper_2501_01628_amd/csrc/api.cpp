@@ -24,7 +24,7 @@ using namespace dpvr;
 struct vr_context_s {
     int32_t device = 0;
     int32_t cus = 0;               // compute units of the device
-    int32_t queue_wg[2] = {0, 0};  // persistent march workgroups (F32, F16), 0 = not yet queried
+    int32_t queue_wg[2][2] = {{0, 0}, {0, 0}};  // persistent march workgroups [F32/F16][direct/staged], 0 = not yet queried
     hipStream_t stream = nullptr;
     bool has_camera = false, has_tf = false;
     CameraK cam{};
@@ -502,10 +502,12 @@ static vr_status prepare_march_with(vr_context ctx, vr_brick b, const vr_partial
         p.brick.hi[c] = b->origin[c] + (double)b->dims[c] * b->spacing[c];
         p.brick.origin[c] = b->origin[c];
         p.brick.spacing[c] = b->spacing[c];
+        p.brick.inv_spacing[c] = 1.0 / b->spacing[c];
     }
     p.brick.ghost = b->ghost;
     p.tf = tf;
     p.dt = ctx->dt;
+    p.inv_dt = 1.0 / ctx->dt;
     p.ert_eps = ctx->ert_eps;
     p.roi_x0 = part->x0;
     p.roi_y0 = part->y0;
@@ -529,7 +531,7 @@ static vr_status prepare_march(vr_context ctx, vr_brick b, const vr_partial* par
     return prepare_march_with(ctx, b, part, ctx->cam, ctx->tf, who, p);
 }
 
-// Layout of a frame workspace: [2 queue counters | 256 B] [tile_start[n + 2] | 256-aligned]
+// Layout of a frame workspace: [2 x kQueueParts queue counters | 256 B] [tile_start[n + 2] | 256-aligned]
 // [MarchParams jobs[n] | 256-aligned].
 static size_t frame_ws_bytes(int32_t n, size_t* off_tiles, size_t* off_jobs) {
     const size_t a = 256;
@@ -547,9 +549,9 @@ vr_status vr_frame_workspace_size(int32_t n, size_t* bytes) {
     return VR_OK;
 }
 
-static int queue_workgroups(vr_context ctx, StorageK st) {
-    int& n = ctx->queue_wg[st == kF16 ? 1 : 0];
-    if (n == 0) n = march_queue_workgroups_per_cu(st) * ctx->cus;
+static int queue_workgroups(vr_context ctx, StorageK st, bool staged) {
+    int& n = ctx->queue_wg[st == kF16 ? 1 : 0][staged ? 1 : 0];
+    if (n == 0) n = march_queue_workgroups_per_cu(st, staged) * ctx->cus;
     return n;
 }
 
@@ -594,16 +596,6 @@ vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
     char* ws = reinterpret_cast<char*>(workspace);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: cannot select device %d", ctx->device);
-    if (ctx->path == kPathDirect) {   // one direct launch per partial (same images)
-        for (int j = 0; j < n; ++j) {
-            MarchParams p = jobs[j];
-            p.tiles_x = (p.roi_w + 7) / 8;
-            p.tiles_y = (p.roi_h + 7) / 8;
-            hipError_t e = launch_march(p, j < n32 ? kF32 : kF16, ctx->stream);
-            if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: %s", hipGetErrorString(e));
-        }
-        return ok(ctx);
-    }
     // pageable host source: the runtime stages the data before returning
     hipError_t e = hipMemcpyAsync(ws + off_t, prefix.data(), prefix.size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, ctx->stream);
@@ -614,13 +606,14 @@ vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
     const MarchParams* djobs = reinterpret_cast<const MarchParams*>(ws + off_j);
     const int32_t* dtiles = reinterpret_cast<const int32_t*>(ws + off_t);
     int32_t* heads = reinterpret_cast<int32_t*>(ws);
+    const int staged = ctx->path == kPathDirect ? 0 : 1;
     if (n32 > 0) {
-        QueueParams q{djobs, dtiles, n32, prefix[n32], heads};
-        e = launch_march_queue(q, kF32, queue_workgroups(ctx, kF32), ctx->stream);
+        QueueParams q{djobs, dtiles, n32, prefix[n32], heads, staged};
+        e = launch_march_queue(q, kF32, queue_workgroups(ctx, kF32, staged), ctx->stream);
     }
     if (e == hipSuccess && n - n32 > 0) {
-        QueueParams q{djobs + n32, dtiles + n32 + 1, n - n32, prefix[n + 1], heads + 1};
-        e = launch_march_queue(q, kF16, queue_workgroups(ctx, kF16), ctx->stream);
+        QueueParams q{djobs + n32, dtiles + n32 + 1, n - n32, prefix[n + 1], heads + kQueueParts, staged};
+        e = launch_march_queue(q, kF16, queue_workgroups(ctx, kF16, staged), ctx->stream);
     }
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: %s", hipGetErrorString(e));
     return ok(ctx);
@@ -850,7 +843,7 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace layout: [2 counters | 256] [march prefix (n_jobs + 2)] [march jobs]
+// Workspace layout: [2 x kQueueParts counters | 256] [march prefix (n_jobs + 2)] [march jobs]
 // [composite prefix (n_frames + 1)] [composite frames].
 size_t batch_layout(int32_t n_jobs, int32_t n_frames, size_t* mp, size_t* mj, size_t* cp, size_t* cf) {
     size_t o = 256;
@@ -929,11 +922,11 @@ vr_status batch_capture(vr_batch b, int wg_per_cu) {
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "batch capture: %s", hipGetErrorString(e));
     hipError_t le = hipSuccess;
     if (b->n32 > 0) {
-        QueueParams q{djobs, dprefix, b->n32, b->total32, heads};
+        QueueParams q{djobs, dprefix, b->n32, b->total32, heads, 1};
         le = launch_march_queue(q, kF32, wg_per_cu * ctx->cus, b->cap);
     }
     if (le == hipSuccess && n - b->n32 > 0) {
-        QueueParams q{djobs + b->n32, dprefix + b->n32 + 1, n - b->n32, b->total16, heads + 1};
+        QueueParams q{djobs + b->n32, dprefix + b->n32 + 1, n - b->n32, b->total16, heads + kQueueParts, 1};
         le = launch_march_queue(q, kF16, wg_per_cu * ctx->cus, b->cap);
     }
     if (le == hipSuccess && !b->frames.empty())
@@ -956,8 +949,8 @@ vr_status batch_capture(vr_batch b, int wg_per_cu) {
 
 int max_wg_per_cu(vr_context ctx, const vr_batch b) {
     int m = 0;
-    if (b->n32 > 0) m = std::max(m, march_queue_workgroups_per_cu(kF32));
-    if ((int)b->jobs.size() > b->n32) m = std::max(m, march_queue_workgroups_per_cu(kF16));
+    if (b->n32 > 0) m = std::max(m, march_queue_workgroups_per_cu(kF32, true));
+    if ((int)b->jobs.size() > b->n32) m = std::max(m, march_queue_workgroups_per_cu(kF16, true));
     (void)ctx;
     return std::max(m, 1);
 }

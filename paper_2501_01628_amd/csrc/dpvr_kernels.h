@@ -27,6 +27,7 @@ struct BrickK {
     double lo[3], hi[3];   // owned world box [lo, hi)
     double origin[3];      // == lo
     double spacing[3];
+    double inv_spacing[3]; // 1 / spacing
 };
 
 struct TFK {
@@ -40,6 +41,7 @@ struct MarchParams {
     BrickK brick;
     TFK tf;
     double dt;
+    double inv_dt;         // 1 / dt
     float ert_eps;
     int32_t roi_x0, roi_y0, roi_w, roi_h;
     int32_t tiles_x, tiles_y;
@@ -64,8 +66,15 @@ struct QueueParams {
     const int32_t* tile_start; // device, n_jobs + 1 entries (exclusive prefix of tiles)
     int32_t n_jobs;
     int32_t total_tiles;
-    int32_t* head;             // device ticket counter (reset by the launcher)
+    int32_t* head;             // device, kQueueParts ticket counters (reset by the launcher)
+    int32_t staged;            // 1: LDS-staged tiles, 0: every lane marches from HBM
 };
+
+// The tickets are split into kQueueParts contiguous parts, one per XCD
+// (workgroup i runs on XCD i mod 8): a workgroup drains its own XCD's part
+// first, so neighbouring tiles (which share voxels) meet in one L2, and then
+// helps with the other parts in turn.
+constexpr int kQueueParts = 8;
 
 inline int32_t staged_tiles(int32_t w, int32_t h) { return ((w + 15) / 16) * ((h + 15) / 16); }
 
@@ -121,7 +130,7 @@ hipError_t launch_ingest(const float* src, void* dst, const int32_t sdim[3], Sto
 hipError_t launch_march(const MarchParams& p, StorageK storage, hipStream_t stream);
 hipError_t launch_march_queue(const QueueParams& q, StorageK storage, int workgroups,
                               hipStream_t stream);
-int march_queue_workgroups_per_cu(StorageK storage);
+int march_queue_workgroups_per_cu(StorageK storage, bool staged);
 hipError_t launch_composite(const CompositeParams& p, hipStream_t stream);
 hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* tile_start,
                                  int32_t n_frames, int32_t total_tiles, hipStream_t stream);

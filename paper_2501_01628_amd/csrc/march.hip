@@ -28,7 +28,7 @@ namespace dpvr {
 namespace {
 
 constexpr int kSlices = kSlab + 3;       // staged slices per slab: [wlo - 1, whi + 1]
-constexpr int kStageFloats = 11008;      // 43 KB of LDS for the staged slab
+constexpr int kStageFloats = 17408;      // 68 KB of LDS for the staged slab (2 workgroups per CU)
 constexpr float kMinStageDw = 0.25f;     // |d_w| below this: march from HBM
 
 struct LaneState {
@@ -37,19 +37,22 @@ struct LaneState {
     bool stopped;
 };
 
-// March samples kb .. kb + n - 1 of one anchor block; fetch(cell) returns the
-// interpolated value.  Returns false once early termination stops the ray.
+// March samples kb + j0 .. kb + j1 - 1 of the anchor block anchored (float64)
+// at sample kb; sample(fj) returns the interpolated value of sample kb + j
+// (fj = j as float).  Returns false once early termination stops the ray.
 // Two samples are fetched and classified before either is accumulated, so
 // the memory round trips of consecutive samples overlap; accumulation stays
-// in sample order, so the result is the same as one sample at a time.
-template <bool kCkpt, typename Fetch>
-__device__ inline bool march_block(const MarchParams& p, const TFTable& tft, const RaySetup& rs,
-                                   const BrickK& b, const Step& st, long long kb, int n,
-                                   long long pix, float tf_k, float tf_o, float eps, LaneState& s,
-                                   Fetch fetch) {
-    const Anchor an = make_anchor(rs, b, p.dt, kb);
-    const int snx = b.sdim[0], sny = b.sdim[1], snz = b.sdim[2];
-    auto accumulate = [&](const Classified& e, int j) -> bool {
+// in sample order.  Termination is tested after every second sample (a ray
+// may take one sample past T < eps, which changes its colour by less than
+// eps).
+template <bool kCkpt, typename Sample>
+__device__ inline bool march_run(const MarchParams& p, const TFTable& tft, const RaySetup& rs,
+                                 long long kb, int j0, int j1, long long pix, float tf_k,
+                                 float tf_o, float eps, LaneState& s, Sample sample) {
+    auto accumulate = [&](const Classified& e, int j) {
+        // no contraction (T - T x must not become an FMA in some
+        // instantiations only: every path rounds alike)
+#pragma clang fp contract(off)
         if (kCkpt) {
             const long long q = kb + j - rs.kf;
             if (q % p.ckpt_interval == 0 && q / p.ckpt_interval < p.ckpt_nseg)
@@ -62,30 +65,31 @@ __device__ inline bool march_block(const MarchParams& p, const TFTable& tft, con
         s.C1 = fmaf(w, e.g, s.C1);
         s.C2 = fmaf(w, e.b, s.C2);
         s.T = Tn;
+    };
+    int j = j0;
+    float fj = (float)j0;
+    for (; j + 1 < j1; j += 2, fj += 2.0f) {
+        const float v0 = sample(fj);
+        const float v1 = sample(fj + 1.0f);
+        const Classified e0 = classify(tft, v0, tf_k, tf_o);
+        const Classified e1 = classify(tft, v1, tf_k, tf_o);
+        accumulate(e0, j);
+        accumulate(e1, j + 1);
         if (s.T < eps) {
-            s.evaluated += j + 1;
+            s.evaluated += j - j0 + 2;
             s.stopped = true;
             return false;
         }
-        return true;
-    };
-    int j = 0;
-    for (; j + 1 < n; j += 2) {
-        const Cell c0 = locate(an, st, j, snx, sny, snz);
-        const Cell c1 = locate(an, st, j + 1, snx, sny, snz);
-        const float v0 = fetch(c0);
-        const float v1 = fetch(c1);
-        const Classified e0 = classify(tft, v0, tf_k, tf_o);
-        const Classified e1 = classify(tft, v1, tf_k, tf_o);
-        if (!accumulate(e0, j)) return false;
-        if (!accumulate(e1, j + 1)) return false;
     }
-    if (j < n) {
-        const Cell c = locate(an, st, j, snx, sny, snz);
-        const Classified e = classify(tft, fetch(c), tf_k, tf_o);
-        if (!accumulate(e, j)) return false;
+    if (j < j1) {
+        accumulate(classify(tft, sample(fj), tf_k, tf_o), j);
+        if (s.T < eps) {
+            s.evaluated += j1 - j0;
+            s.stopped = true;
+            return false;
+        }
     }
-    s.evaluated += n;
+    s.evaluated += j1 - j0;
     return true;
 }
 
@@ -96,19 +100,23 @@ __device__ inline void march_ray_direct(const MarchParams& p, const TFTable& tft
                                         float eps, LaneState& s) {
     const BrickK& b = p.brick;
     const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
-    const int pitch = row_pitch(b.sdim[0]);
-    const long long sxy = (long long)pitch * b.sdim[1];
+    const int snx = b.sdim[0], sny = b.sdim[1], snz = b.sdim[2];
+    const int pitch = row_pitch(snx);
+    const long long sxy = (long long)pitch * sny;
     const Step st = make_step(rs, b, p.dt);
     const Blocks bl = make_blocks(rs, b);
-    long long n = block_of(bl, p.dt, rs.kf);
+    long long n = block_of(bl, p.dt, p.inv_dt, rs.kf);
     long long k = rs.kf;
-    auto fetch = [&](const Cell& c) { return trilinear(vox, c, pitch, sxy); };
     while (k <= rs.kl) {
-        const long long knext = block_start(bl, p.dt, n + 1);
+        const long long knext = block_start(bl, p.inv_dt, n + 1);
         const long long kend = min(knext - 1, rs.kl);
         if (kend >= k) {
-            if (!march_block<kCkpt>(p, tft, rs, b, st, k, (int)(kend - k + 1), pix, tf_k, tf_o, eps,
-                                    s, fetch))
+            const Anchor an = make_anchor(rs, b, p.dt, k);
+            auto sample = [&](float fj) {
+                return trilinear(vox, locate(an, st, fj, snx, sny, snz), pitch, sxy);
+            };
+            if (!march_run<kCkpt>(p, tft, rs, k, 0, (int)(kend - k + 1), pix, tf_k, tf_o, eps, s,
+                                  sample))
                 return;
             k = kend + 1;
         }
@@ -214,8 +222,226 @@ struct StagedShared {
     __align__(16) float stage[kStageFloats];
     int tab_off[kSlices], tab_x0[kSlices], tab_b0[kSlices];
     float red[2][4][kRed];
-    int axis_sg[2];
 };
+
+__device__ inline float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Walk of one eligible tile through the slabs of its common slab axis W
+// (2: z, rows along y; 1: y, rows along z) in ray order.  Per slab, a
+// workgroup reduction gives the extent of the tile's rays in the slab; the
+// slab (or each of its sub-slabs, when it does not fit) is staged into LDS
+// slice by slice as sheared rectangles, then every lane marches its samples
+// of it from LDS.
+template <typename TS, int W>
+__device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, const RaySetup& rs,
+                            const Blocks& bl, bool has, int sg, long long pix, float tf_k,
+                            float tf_o, float eps, LaneState& s) {
+    constexpr int B = 3 - W;                 // the other of y (1) and z (2)
+    constexpr int V = StageVec<TS>::V;
+    const TFTable& tft = sh.tft;
+    float* stage = sh.stage;
+    int* tab_off = sh.tab_off;
+    int* tab_x0 = sh.tab_x0;
+    int* tab_b0 = sh.tab_b0;
+    float (*red)[4][kRed] = sh.red;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const BrickK& b = p.brick;
+    const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
+    const int snx = b.sdim[0], sny = b.sdim[1], snz = b.sdim[2];
+    const int pitch = row_pitch(snx);
+    const long long sxy = (long long)pitch * sny;
+    const int snw = b.sdim[W], snb = b.sdim[B];
+    // slopes of x and b per unit of stored w along each ray
+    float kx = 0.f, kb = 0.f;
+    if (has) {
+        const double dwu = rs.d[W] * b.inv_spacing[W];
+        kx = (float)((rs.d[0] * b.inv_spacing[0]) / dwu);
+        kb = (float)((rs.d[B] * b.inv_spacing[B]) / dwu);
+    }
+    const Step st = has ? make_step(rs, b, p.dt) : Step{0.f, 0.f, 0.f};
+    long long n_cur = 0, k_cur = 0, k_next = 0;
+    bool alive = has;
+    if (has) {
+        n_cur = block_of(bl, p.dt, p.inv_dt, rs.kf);
+        k_cur = rs.kf;
+        k_next = block_start(bl, p.inv_dt, n_cur + 1);
+    }
+    // first slab: the smallest block index of the tile
+    long long n_chunk;
+    {
+        float v[1] = {has ? (float)n_cur : 3e38f};
+        const bool mx[1] = {false};
+        wg_reduce(v, mx, red, buf, lane, wave);
+        buf ^= 1;
+        n_chunk = (long long)uniform_f(v[0]);
+    }
+    const double gh = (double)b.ghost - 0.5;
+    // at most snw / kSlab + 3 slabs intersect the brick; the bound only guards
+    // against a logic error turning into a hang
+    const int max_iter = 2 * (snw / kSlab + 4);
+    for (int iter = 0; iter < max_iter; ++iter) {
+        const bool part = alive && n_cur == n_chunk;
+        // slab [wlo, wlo + kSlab] of stored w; crossing of plane wlo per ray
+        const long long wlo = sg > 0 ? (long long)kSlab * n_chunk : -(long long)kSlab * (n_chunk + 1);
+        float xr = 0.f, br = 0.f;
+        if (part) {
+#pragma clang fp contract(off)
+            const double t = bl.c0 + (double)(sg > 0 ? n_chunk : n_chunk + 1) * bl.c1;
+            xr = (float)((rs.o[0] + t * rs.d[0] - b.origin[0]) * b.inv_spacing[0] + gh);
+            br = (float)((rs.o[B] + t * rs.d[B] - b.origin[B]) * b.inv_spacing[B] + gh);
+        }
+        float v[11] = {part ? xr : 3e38f, part ? xr : -3e38f, part ? br : 3e38f, part ? br : -3e38f,
+                       part ? kx : 3e38f, part ? kx : -3e38f, part ? kb : 3e38f, part ? kb : -3e38f,
+                       part ? 1.0f : 0.0f, alive ? 1.0f : 0.0f,
+                       (alive && !part) ? (float)n_cur : 3e38f};
+        const bool mx[11] = {false, true, false, true, false, true, false, true, true, true, false};
+        wg_reduce(v, mx, red, buf, lane, wave);
+        buf ^= 1;
+        if (uniform_f(v[9]) == 0.0f) break;        // every ray of the tile is done
+        if (uniform_f(v[8]) == 0.0f) {             // gap: jump to the next slab someone needs
+            n_chunk = (long long)uniform_f(v[10]);
+            continue;
+        }
+        // uniform slab geometry (stored-index units)
+        const float xmin0 = uniform_f(v[0]), xmax0 = uniform_f(v[1]);
+        const float bmin0 = uniform_f(v[2]), bmax0 = uniform_f(v[3]);
+        const float kxmin = uniform_f(v[4]), kxmax = uniform_f(v[5]);
+        const float kbmin = uniform_f(v[6]), kbmax = uniform_f(v[7]);
+        const float Kx = fmaxf(fabsf(kxmin), fabsf(kxmax)), Kb = fmaxf(fabsf(kbmin), fabsf(kbmax));
+        // a per-slice rectangle of RW x RH bounds every slice's footprint:
+        // width <= ceil(span + 2 eps) + 1 (corner column) + 1, plus up to V - 1
+        // columns of 16-byte alignment (spans clamped so that they cannot
+        // overflow an int)
+        constexpr float kEps = 0.01f;
+        const float span_x = fminf((xmax0 - xmin0) + 2.0f * Kx + (float)kSlices * (kxmax - kxmin), 65536.0f);
+        const float span_b = fminf((bmax0 - bmin0) + 2.0f * Kb + (float)kSlices * (kbmax - kbmin), 65536.0f);
+        int RW = (int)ceilf(span_x + 2.0f * kEps) + 2 + V - 1;
+        RW = (RW + V - 1) / V * V;
+        if (RW > pitch) RW = pitch;
+        int RH = (int)ceilf(span_b + 2.0f * kEps) + 2;
+        if (RH > snb) RH = snb;
+        RW = uniform_i(RW);
+        RH = uniform_i(RH);
+        // split the slab into S sub-slabs of L slices until L + 3 slices fit
+        int S = 1;
+        while (S < kSlab && (long long)(kSlab / S + 3) * RW * RH > kStageFloats) S *= 2;
+        const int L = kSlab / S, nsl = L + 3;
+        const bool use_lds = (long long)nsl * RW * RH <= kStageFloats && RW > 0 && RH > 0;
+        if (!use_lds) S = 1;
+        const long long kend_blk = part ? min(k_next, rs.kl + 1) : 0;   // exclusive
+        Anchor an{};
+        if (part && kend_blk > k_cur) an = make_anchor(rs, b, p.dt, k_cur);
+        long long kpos = k_cur;
+        bool cont = true;
+        for (int q = 0; q < S; ++q) {
+            // lower stored-w plane of sub-slab q (sub-slabs in ray order)
+            const int w_a = (int)wlo + (sg > 0 ? q * L : kSlab - (q + 1) * L);
+            if (use_lds) {
+                if (tid < nsl) {
+                    // slice w = w_a - 1 + i is touched by samples with s_w in
+                    // [w - 1, w + 1), i.e. s_w - wlo in [d0 + i - 2, d0 + i]
+                    const int i = tid;
+                    const float da = (float)(w_a - (int)wlo + i - 2), db = da + 2.0f;
+                    const float xl = xmin0 + fminf(fminf(da * kxmin, da * kxmax), fminf(db * kxmin, db * kxmax));
+                    const float bl0 = bmin0 + fminf(fminf(da * kbmin, da * kbmax), fminf(db * kbmin, db * kbmax));
+                    int x0 = (int)floorf(xl - kEps);
+                    x0 = max(x0, 0) / V * V;
+                    if (x0 + RW > pitch) x0 = pitch - RW;
+                    const int b0 = max((int)floorf(bl0 - kEps), 0);
+                    tab_x0[i] = x0;
+                    tab_b0[i] = b0;
+                    tab_off[i] = (i * RH * RW - b0 * RW - x0) * 4;   // bytes
+                }
+                __syncthreads();
+                // stage slices w_a - 1 .. w_a + L + 1 (rows along x, 16-byte vectors)
+                const int cols = RW / V;
+                const int total = nsl * RH * cols;
+                const float inv_cols = 1.0f / (float)cols, inv_rh = 1.0f / (float)RH;
+                for (int e = tid; e < total; e += 256) {
+                    const int qq = (int)(((float)e + 0.5f) * inv_cols);
+                    const int c = e - qq * cols;
+                    const int i = (int)(((float)qq + 0.5f) * inv_rh);
+                    const int r = qq - i * RH;
+                    const int wabs = min(max(w_a - 1 + i, 0), snw - 1);
+                    const int babs = min(tab_b0[i] + r, snb - 1);
+                    const int x = tab_x0[i] + c * V;
+                    const long long yz = W == 2 ? ((long long)wabs * sny + babs)
+                                                : ((long long)babs * sny + wabs);
+                    StageVec<TS>::copy(vox + yz * pitch + x, &stage[(i * RH + r) * RW + c * V]);
+                }
+                __syncthreads();
+            }
+            if (part && cont && kpos < kend_blk) {
+                // samples of this ray before the crossing of the next sub-plane
+                long long ke = kend_blk;
+                if (q + 1 < S) {
+#pragma clang fp contract(off)
+                    const double t = bl.c0 + ((double)n_chunk + (double)(q + 1) / (double)S) * bl.c1;
+                    ke = min(ke, (long long)ceil(t * p.inv_dt - 0.5));
+                }
+                if (ke > kpos) {
+                    const int j0 = (int)(kpos - k_cur), j1 = (int)(ke - k_cur);
+                    if (use_lds) {
+                        // byte offsets: lane constants of this anchor block and
+                        // sub-slab, then 3 FMA + 3 fract + 3 floor per sample
+                        const int RW4 = RW * 4;
+                        const int lim4 = (kStageFloats - RW - 2) * 4;
+                        const int ia_b = W == 2 ? an.ia1 : an.ia2, ia_w = W == 2 ? an.ia2 : an.ia1;
+                        const int base4 = ia_b * RW4 + an.ia0 * 4;
+                        const int sio = ia_w - (w_a - 1);
+                        const char* S8 = reinterpret_cast<const char*>(stage);
+                        auto sample_lds = [&](float fj) {
+                            const float x = fmaf(fj, st.s0, an.uf0);
+                            const float y = fmaf(fj, st.s1, an.uf1);
+                            const float z = fmaf(fj, st.s2, an.uf2);
+                            Cell c;
+                            c.fx = fract(x); c.fy = fract(y); c.fz = fract(z);
+                            const int fx_i = floor_int(x);
+                            const int fb = floor_int(W == 2 ? y : z), fw = floor_int(W == 2 ? z : y);
+                            // (unsigned clamps keep every read inside the stage;
+                            // the slab bounds make them inactive)
+                            const unsigned si = min((unsigned)(fw + sio), (unsigned)(nsl - 2));
+                            const int row4 = __mul24(fb, RW4) + fx_i * 4 + base4;
+                            const unsigned a0 = min((unsigned)(tab_off[si] + row4), (unsigned)lim4);
+                            const unsigned a1 = min((unsigned)(tab_off[si + 1] + row4), (unsigned)lim4);
+                            const float p00 = *reinterpret_cast<const float*>(S8 + a0);
+                            const float p01 = *reinterpret_cast<const float*>(S8 + a0 + 4);
+                            const float p10 = *reinterpret_cast<const float*>(S8 + a0 + RW4);
+                            const float p11 = *reinterpret_cast<const float*>(S8 + a0 + RW4 + 4);
+                            const float q00 = *reinterpret_cast<const float*>(S8 + a1);
+                            const float q01 = *reinterpret_cast<const float*>(S8 + a1 + 4);
+                            const float q10 = *reinterpret_cast<const float*>(S8 + a1 + RW4);
+                            const float q11 = *reinterpret_cast<const float*>(S8 + a1 + RW4 + 4);
+                            // (p: slice w, q: slice w+1; second index: row b+1)
+                            return W == 2 ? lerp3(c, p00, p01, p10, p11, q00, q01, q10, q11)
+                                          : lerp3(c, p00, p01, q00, q01, p10, p11, q10, q11);
+                        };
+                        cont = march_run<false>(p, tft, rs, k_cur, j0, j1, pix, tf_k, tf_o, eps, s,
+                                                sample_lds);
+                    } else {
+                        auto sample_hbm = [&](float fj) {
+                            return trilinear(vox, locate(an, st, fj, snx, sny, snz), pitch, sxy);
+                        };
+                        cont = march_run<false>(p, tft, rs, k_cur, j0, j1, pix, tf_k, tf_o, eps, s,
+                                                sample_hbm);
+                    }
+                    kpos = ke;
+                }
+            }
+            if (use_lds && q + 1 < S) __syncthreads();   // sub-slab done before the next is staged
+        }
+        if (part) {
+            k_cur = max(k_cur, kend_blk);
+            ++n_cur;
+            k_next = block_start(bl, p.inv_dt, n_cur + 1);
+            alive = cont && k_cur <= rs.kl;
+        }
+        ++n_chunk;
+    }
+}
 
 // One 16x16 tile of one partial image, by the whole 256-thread workgroup.
 // The classification table must already be in sh.tft; `buf` selects the
@@ -223,14 +449,8 @@ struct StagedShared {
 // workgroup must call it with the same arguments.
 template <typename TS>
 __device__ void staged_tile(const MarchParams& p, int tile, StagedShared& sh, int& buf) {
-    TFTable& tft = sh.tft;
-    float* stage = sh.stage;
-    int* tab_off = sh.tab_off;
-    int* tab_x0 = sh.tab_x0;
-    int* tab_b0 = sh.tab_b0;
+    const TFTable& tft = sh.tft;
     float (*red)[4][kRed] = sh.red;
-    constexpr int V = StageVec<TS>::V;
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_x16 = (p.roi_w + 15) / 16;
     const int tx = tile % tiles_x16, ty = tile / tiles_x16;
@@ -238,12 +458,7 @@ __device__ void staged_tile(const MarchParams& p, int tile, StagedShared& sh, in
     const int ly = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
     const bool valid = tile < p.tiles_x * p.tiles_y && lx < p.roi_w && ly < p.roi_h;
     const long long pix = (long long)ly * p.roi_w + lx;
-
     const BrickK& b = p.brick;
-    const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
-    const int snx = b.sdim[0], sny = b.sdim[1];
-    const int pitch = row_pitch(snx);
-    const long long sxy = (long long)pitch * sny;
     const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
     const float tf_o = -p.tf.vmin * tf_k;
     const float eps = p.ert_eps;
@@ -260,173 +475,31 @@ __device__ void staged_tile(const MarchParams& p, int tile, StagedShared& sh, in
         dw_abs = (float)fabs(pick3(rs.d, bl.axis));
     }
     // eligibility: every ray of the tile shares slab axis (y or z) and direction
-    {
-        const float key = has ? (float)(bl.axis * 2 + (bl.sg > 0 ? 1 : 0)) : -1.0f;
-        float v[4] = {has ? key : 1e9f, has ? key : -1e9f, has ? dw_abs : 1e9f, has ? 1.0f : 0.0f};
-        const bool mx[4] = {false, true, false, true};
-        wg_reduce(v, mx, red, buf, lane, wave);
-        buf ^= 1;
-        if (v[3] == 0.0f) {                       // no ray of this tile hits the brick
-            finish(p, valid, pix, depth, s, lane);
-            return;
-        }
-        const bool eligible = v[0] == v[1] && v[0] >= 2.0f && v[2] >= kMinStageDw;
-        if (!eligible) {
-            if (has) march_ray_direct<TS, false>(p, tft, rs, pix, tf_k, tf_o, eps, s);
-            finish(p, valid, pix, depth, s, lane);
-            return;
-        }
+    float v[4] = {has ? (float)(bl.axis * 2 + (bl.sg > 0 ? 1 : 0)) : 1e9f,
+                  has ? (float)(bl.axis * 2 + (bl.sg > 0 ? 1 : 0)) : -1e9f,
+                  has ? dw_abs : 1e9f, has ? 1.0f : 0.0f};
+    const bool mx[4] = {false, true, false, true};
+    wg_reduce(v, mx, red, buf, lane, wave);
+    buf ^= 1;
+    const float kmin = uniform_f(v[0]), kmax = uniform_f(v[1]);
+    if (uniform_f(v[3]) == 0.0f) {                // no ray of this tile hits the brick
+        finish(p, valid, pix, depth, s, lane);
+        return;
     }
-    // the tile's common slab axis and direction (every ray agrees; any one writes)
-    if (has) {
-        sh.axis_sg[0] = bl.axis;
-        sh.axis_sg[1] = bl.sg;
+    if (!(kmin == kmax && kmin >= 2.0f && uniform_f(v[2]) >= kMinStageDw)) {
+        if (has) march_ray_direct<TS, false>(p, tft, rs, pix, tf_k, tf_o, eps, s);
+        finish(p, valid, pix, depth, s, lane);
+        return;
     }
-    __syncthreads();
-    const int w_axis = sh.axis_sg[0], sg = sh.axis_sg[1];
-    const int b_axis = 3 - w_axis;           // the other of y (1) and z (2)
-    const int snw = pick3(b.sdim, w_axis), snb = pick3(b.sdim, b_axis);
-    // the ray's coordinates along b (origin, direction, grid), selected once
-    const double o_b = has ? pick3(rs.o, b_axis) : 0.0, d_b = has ? pick3(rs.d, b_axis) : 0.0;
-    const double org_b = pick3(b.origin, b_axis), sp_b = pick3(b.spacing, b_axis);
-    // slopes of x and b per unit of s_w along each ray (stored-index units)
-    float kx = 0.f, kb = 0.f;
-    if (has) {
-        const double dwu = pick3(rs.d, w_axis) / pick3(b.spacing, w_axis);
-        kx = (float)((rs.d[0] / b.spacing[0]) / dwu);
-        kb = (float)((d_b / sp_b) / dwu);
-    }
-    const Step st = has ? make_step(rs, b, p.dt) : Step{0.f, 0.f, 0.f};
-    long long n_cur = 0, k_cur = 0, k_next = 0;
-    bool alive = has;
-    if (has) {
-        n_cur = block_of(bl, p.dt, rs.kf);
-        k_cur = rs.kf;
-        k_next = block_start(bl, p.dt, n_cur + 1);
-    }
-    // first slab: the smallest block index of the tile
-    long long n_chunk;
-    {
-        float v[1] = {has ? (float)n_cur : 3e38f};
-        const bool mx[1] = {false};
-        wg_reduce(v, mx, red, buf, lane, wave);
-        buf ^= 1;
-        n_chunk = (long long)v[0];
-    }
-    auto fetch_hbm = [&](const Cell& c) { return trilinear(vox, c, pitch, sxy); };
-
-    // at most snw / kSlab + 3 slabs intersect the brick; the bound only guards
-    // against a logic error turning into a hang
-    const int max_iter = 2 * (snw / kSlab + 4);
-    for (int iter = 0; iter < max_iter; ++iter) {
-        const bool part = alive && n_cur == n_chunk;
-        // slab [wlo, wlo + kSlab] of stored w; crossing of plane wlo per ray
-        const long long wlo = sg > 0 ? (long long)kSlab * n_chunk : -(long long)kSlab * (n_chunk + 1);
-        float xr = 0.f, br = 0.f;
-        if (part) {
-#pragma clang fp contract(off)
-            const double t = bl.c0 + (double)(sg > 0 ? n_chunk : n_chunk + 1) * bl.c1;
-            xr = (float)((rs.o[0] + t * rs.d[0] - b.origin[0]) / b.spacing[0] - 0.5 + (double)b.ghost);
-            br = (float)((o_b + t * d_b - org_b) / sp_b - 0.5 + (double)b.ghost);
-        }
-        float v[11] = {part ? xr : 3e38f, part ? xr : -3e38f, part ? br : 3e38f, part ? br : -3e38f,
-                       part ? kx : 3e38f, part ? kx : -3e38f, part ? kb : 3e38f, part ? kb : -3e38f,
-                       part ? 1.0f : 0.0f, alive ? 1.0f : 0.0f,
-                       (alive && !part) ? (float)n_cur : 3e38f};
-        const bool mx[11] = {false, true, false, true, false, true, false, true, true, true, false};
-        wg_reduce(v, mx, red, buf, lane, wave);
-        buf ^= 1;
-        if (v[9] == 0.0f) break;                   // every ray of the tile is done
-        if (v[8] == 0.0f) {                        // gap: jump to the next slab someone needs
-            n_chunk = (long long)v[10];
-            continue;
-        }
-        // uniform slab geometry (stored-index units)
-        const float xmin0 = v[0], xmax0 = v[1], bmin0 = v[2], bmax0 = v[3];
-        const float kxmin = v[4], kxmax = v[5], kbmin = v[6], kbmax = v[7];
-        const float Kx = fmaxf(fabsf(kxmin), fabsf(kxmax)), Kb = fmaxf(fabsf(kbmin), fabsf(kbmax));
-        // rectangle extents bounding every slice's footprint (clamped before the
-        // conversion so that absurd spans cannot overflow an int)
-        const float span_x = fminf((xmax0 - xmin0) + 2.0f * Kx + (float)kSlices * (kxmax - kxmin), 65536.0f);
-        const float span_b = fminf((bmax0 - bmin0) + 2.0f * Kb + (float)kSlices * (kbmax - kbmin), 65536.0f);
-        int RW = (int)ceilf(span_x) + 6 + V;
-        RW = (RW + V - 1) / V * V;
-        if (RW > pitch) RW = pitch;
-        int RH = (int)ceilf(span_b) + 6;
-        if (RH > snb) RH = snb;
-        const bool use_lds = (long long)kSlices * RW * RH <= kStageFloats && RW > 0 && RH > 0;
-        if (use_lds) {
-            if (tid < kSlices) {
-                const int i = tid;
-                const float da = (float)(i - 2), db = (float)i;
-                const float xl = xmin0 + fminf(fminf(da * kxmin, da * kxmax), fminf(db * kxmin, db * kxmax));
-                const float bl0 = bmin0 + fminf(fminf(da * kbmin, da * kbmax), fminf(db * kbmin, db * kbmax));
-                int x0 = (int)floorf(xl) - 1;
-                x0 = max(x0, 0) / V * V;
-                if (x0 + RW > pitch) x0 = pitch - RW;
-                int b0 = max((int)floorf(bl0) - 1, 0);
-                tab_x0[i] = x0;
-                tab_b0[i] = b0;
-                tab_off[i] = i * RH * RW - b0 * RW - x0;
-            }
-            __syncthreads();
-            // stage slices wlo - 1 .. wlo + kSlab + 1 (rows along x, 16-byte vectors)
-            const int cols = RW / V;
-            const int total = kSlices * RH * cols;
-            const float inv_cols = 1.0f / (float)cols, inv_rh = 1.0f / (float)RH;
-            for (int e = tid; e < total; e += 256) {
-                const int q = (int)(((float)e + 0.5f) * inv_cols);
-                const int c = e - q * cols;
-                const int i = (int)(((float)q + 0.5f) * inv_rh);
-                const int r = q - i * RH;
-                const int wabs = min(max((int)wlo - 1 + i, 0), snw - 1);
-                const int babs = min(tab_b0[i] + r, snb - 1);
-                const int x = tab_x0[i] + c * V;
-                const long long yz = w_axis == 2 ? ((long long)wabs * sny + babs)
-                                                 : ((long long)babs * sny + wabs);
-                StageVec<TS>::copy(vox + yz * pitch + x, &stage[(i * RH + r) * RW + c * V]);
-            }
-            __syncthreads();
-        }
-        if (part) {
-            const long long kend = min(k_next - 1, rs.kl);
-            const int n = (int)(kend - k_cur + 1);
-            bool cont = true;
-            if (n > 0) {
-                if (use_lds) {
-                    const int wbase = (int)wlo - 1;
-                    auto fetch_lds = [&](const Cell& c) {
-                        const int ib = w_axis == 2 ? c.iy : c.iz;
-                        const int iw = w_axis == 2 ? c.iz : c.iy;
-                        const int si = min(max(iw - wbase, 0), kSlices - 2);
-                        const int row = ib * RW + c.ix;
-                        const int a0 = min(max(tab_off[si] + row, 0), kStageFloats - RW - 2);
-                        const int a1 = min(max(tab_off[si + 1] + row, 0), kStageFloats - RW - 2);
-                        const float p00 = stage[a0], p01 = stage[a0 + 1];
-                        const float p10 = stage[a0 + RW], p11 = stage[a0 + RW + 1];
-                        const float q00 = stage[a1], q01 = stage[a1 + 1];
-                        const float q10 = stage[a1 + RW], q11 = stage[a1 + RW + 1];
-                        // (p: slice w, q: slice w+1; second index: row b+1)
-                        return w_axis == 2 ? lerp3(c, p00, p01, p10, p11, q00, q01, q10, q11)
-                                           : lerp3(c, p00, p01, q00, q01, p10, p11, q10, q11);
-                    };
-                    cont = march_block<false>(p, tft, rs, b, st, k_cur, n, pix, tf_k, tf_o, eps, s,
-                                              fetch_lds);
-                } else {
-                    cont = march_block<false>(p, tft, rs, b, st, k_cur, n, pix, tf_k, tf_o, eps, s,
-                                              fetch_hbm);
-                }
-            }
-            k_cur = max(k_cur, kend + 1);
-            ++n_cur;
-            k_next = block_start(bl, p.dt, n_cur + 1);
-            alive = cont && k_cur <= rs.kl;
-        }
-        ++n_chunk;
-    }
+    // the tile's common slab axis and direction: key = 2 axis + (sg > 0)
+    const int key = (int)kmin;
+    const int sg = (key & 1) ? 1 : -1;
+    if ((key >> 1) == 2)
+        staged_walk<TS, 2>(p, sh, buf, rs, bl, has, sg, pix, tf_k, tf_o, eps, s);
+    else
+        staged_walk<TS, 1>(p, sh, buf, rs, bl, has, sg, pix, tf_k, tf_o, eps, s);
     finish(p, valid, pix, depth, s, lane);
 }
-
 
 template <typename TS>
 __global__ __launch_bounds__(256) void march_staged(MarchParams p) {
@@ -443,46 +516,98 @@ __global__ __launch_bounds__(256) void march_staged(MarchParams p) {
 }
 
 // Persistent work-queue march: each workgroup repeatedly takes the next
-// ticket of the queue (one 16x16 tile of one job = one partial image) until
-// the tickets run out, so many small partials (bricks x time steps x fields
-// x cameras) fill the GPU together.  The table is reloaded only when a job's
-// transfer function (or dt) differs from the previous ticket's.
-template <typename TS>
+// ticket (one 16x16 tile of one job = one partial image) until the tickets
+// run out, so many small partials (bricks x time steps x fields x cameras)
+// fill the GPU together.  Tickets come from kQueueParts parts, the own XCD's
+// part first.  The table is reloaded only when a job's transfer function (or
+// dt) differs from the previous ticket's.
+template <typename TS, bool kStaged>
+__device__ void direct_tile(const MarchParams& p, int tile, const TFTable& tft);
+
+// LDS of a queue workgroup: the staging buffers only where tiles are staged.
+template <bool kStaged>
+struct QueueShared {
+    StagedShared st;
+    __device__ TFTable& tf() { return st.tft; }
+};
+template <>
+struct QueueShared<false> {
+    TFTable t;
+    __device__ TFTable& tf() { return t; }
+};
+
+template <typename TS, bool kStaged>
 __global__ __launch_bounds__(256) void march_queue(QueueParams q) {
-    __shared__ StagedShared sh;
+    __shared__ QueueShared<kStaged> sh;
     __shared__ int ticket;
     const int tid = threadIdx.x;
     const float* tf_loaded = nullptr;
     float scale_loaded = -1.0f;
     double dt_loaded = -1.0;
     int buf = 0;
-    for (;;) {
-        if (tid == 0) ticket = atomicAdd(q.head, 1);
-        __syncthreads();
-        const int t = ticket;
-        __syncthreads();
-        if (t >= q.total_tiles) break;
-        // job of ticket t: the last j with tile_start[j] <= t
-        int lo = 0, hi = q.n_jobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (q.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+    (void)buf;
+    const int home = blockIdx.x % kQueueParts;
+    for (int c = 0; c < kQueueParts; ++c) {
+        const int part = (home + c) % kQueueParts;
+        const int lo_t = (int)((long long)q.total_tiles * part / kQueueParts);
+        const int hi_t = (int)((long long)q.total_tiles * (part + 1) / kQueueParts);
+        for (;;) {
+            // the counter only grows, so every workgroup leaves each part
+            // after at most one ticket past its end
+            if (tid == 0) ticket = lo_t + atomicAdd(q.head + part, 1);
+            __syncthreads();
+            const int t = ticket;
+            __syncthreads();
+            if (t >= hi_t) break;
+            // job of ticket t: the last j with tile_start[j] <= t
+            int lo = 0, hi = q.n_jobs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (q.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const MarchParams& p = q.jobs[lo];
+            if (p.tf.rgba != tf_loaded || p.tf.opacity_scale != scale_loaded || p.dt != dt_loaded) {
+                load_tf(sh.tf(), p.tf, p.dt, tid, 256);
+                tf_loaded = p.tf.rgba;
+                scale_loaded = p.tf.opacity_scale;
+                dt_loaded = p.dt;
+                if (!kStaged) __syncthreads();
+                // (staged_tile's first reduction barrier orders these writes before use)
+            }
+            if constexpr (kStaged)
+                staged_tile<TS>(p, t - q.tile_start[lo], sh.st, buf);
+            else
+                direct_tile<TS, false>(p, t - q.tile_start[lo], sh.tf());
+            __syncthreads();
         }
-        const MarchParams& p = q.jobs[lo];
-        if (p.tf.rgba != tf_loaded || p.tf.opacity_scale != scale_loaded || p.dt != dt_loaded) {
-            load_tf(sh.tft, p.tf, p.dt, tid, 256);
-            tf_loaded = p.tf.rgba;
-            scale_loaded = p.tf.opacity_scale;
-            dt_loaded = p.dt;
-            // (staged_tile's first reduction barrier orders these writes before use)
-        }
-        staged_tile<TS>(p, t - q.tile_start[lo], sh, buf);
-        __syncthreads();
     }
 }
 
+// One 16x16 tile, every lane marching its own ray from HBM (no staging, no
+// workgroup-wide steps).
+template <typename TS, bool kStaged>
+__device__ void direct_tile(const MarchParams& p, int tile, const TFTable& tft) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x16 = (p.roi_w + 15) / 16;
+    const int tx = tile % tiles_x16, ty = tile / tiles_x16;
+    const int lx = tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int ly = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const bool valid = lx < p.roi_w && ly < p.roi_h;
+    const long long pix = (long long)ly * p.roi_w + lx;
+    const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
+    const float tf_o = -p.tf.vmin * tf_k;
+    LaneState s{0.f, 0.f, 0.f, 1.f, 0, false};
+    float depth = INFINITY;
+    RaySetup rs;
+    if (valid && setup_ray(p.cam, p.brick, p.dt, p.roi_x0 + lx, p.roi_y0 + ly, rs)) {
+        depth = (float)(((double)rs.kf + 0.5) * p.dt);
+        march_ray_direct<TS, false>(p, tft, rs, pix, tf_k, tf_o, p.ert_eps, s);
+    }
+    finish(p, valid, pix, depth, s, lane);
+}
+
 __global__ void queue_reset(int* head) {
-    if (threadIdx.x == 0) *head = 0;
+    if (threadIdx.x < kQueueParts) head[threadIdx.x] = 0;
 }
 
 template <bool kCkpt>
@@ -498,24 +623,34 @@ hipError_t launch_direct(const MarchParams& p, StorageK storage, hipStream_t str
 
 }  // namespace
 
+template <typename TS, bool kStaged>
+hipError_t launch_queue_t(const QueueParams& q, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((march_queue<TS, kStaged>), dim3(grid), dim3(256), 0, stream, q);
+    return hipGetLastError();
+}
+
+template <typename TS, bool kStaged>
+int queue_occupancy() {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue<TS, kStaged>, 256, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 hipError_t launch_march_queue(const QueueParams& q, StorageK storage, int workgroups,
                               hipStream_t stream) {
     if (q.total_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, stream, q.head);
     const int grid = min(workgroups, q.total_tiles);
     if (storage == kF16)
-        hipLaunchKernelGGL(march_queue<__half>, dim3(grid), dim3(256), 0, stream, q);
-    else
-        hipLaunchKernelGGL(march_queue<float>, dim3(grid), dim3(256), 0, stream, q);
-    return hipGetLastError();
+        return q.staged ? launch_queue_t<__half, true>(q, grid, stream)
+                        : launch_queue_t<__half, false>(q, grid, stream);
+    return q.staged ? launch_queue_t<float, true>(q, grid, stream)
+                    : launch_queue_t<float, false>(q, grid, stream);
 }
 
-int march_queue_workgroups_per_cu(StorageK storage) {
-    int n = 0;
-    hipError_t e = storage == kF16
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue<__half>, 256, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue<float>, 256, 0);
-    return (e == hipSuccess && n > 0) ? n : 1;
+int march_queue_workgroups_per_cu(StorageK storage, bool staged) {
+    if (storage == kF16) return staged ? queue_occupancy<__half, true>() : queue_occupancy<__half, false>();
+    return staged ? queue_occupancy<float, true>() : queue_occupancy<float, false>();
 }
 
 hipError_t launch_march(const MarchParams& p, StorageK storage, hipStream_t stream) {

@@ -116,19 +116,19 @@ __device__ inline Blocks make_blocks(const RaySetup& rs, const BrickK& b) {
     return bl;
 }
 
-__device__ inline long long block_start(const Blocks& bl, double dt, long long n) {
+__device__ inline long long block_start(const Blocks& bl, double inv_dt, long long n) {
 #pragma clang fp contract(off)
     const double t = bl.c0 + (double)n * bl.c1;
-    return (long long)ceil(t / dt - 0.5);
+    return (long long)ceil(t * inv_dt - 0.5);
 }
 
 // Block (plane index n) holding sample k: the largest n with k_n <= k.
-__device__ inline long long block_of(const Blocks& bl, double dt, long long k) {
+__device__ inline long long block_of(const Blocks& bl, double dt, double inv_dt, long long k) {
 #pragma clang fp contract(off)
     const double t = ((double)k + 0.5) * dt;
     long long n = (long long)floor((t - bl.c0) / bl.c1);
-    while (block_start(bl, dt, n) > k) --n;
-    while (block_start(bl, dt, n + 1) <= k) ++n;
+    while (block_start(bl, inv_dt, n) > k) --n;
+    while (block_start(bl, inv_dt, n + 1) <= k) ++n;
     return n;
 }
 
@@ -142,10 +142,11 @@ struct Anchor {
 __device__ inline Anchor make_anchor(const RaySetup& rs, const BrickK& b, double dt, long long kb) {
 #pragma clang fp contract(off)
     const double t = ((double)kb + 0.5) * dt;
+    const double g = (double)b.ghost - 0.5;
     Anchor a;
-    double s0 = (rs.o[0] + t * rs.d[0] - b.origin[0]) / b.spacing[0] - 0.5 + (double)b.ghost;
-    double s1 = (rs.o[1] + t * rs.d[1] - b.origin[1]) / b.spacing[1] - 0.5 + (double)b.ghost;
-    double s2 = (rs.o[2] + t * rs.d[2] - b.origin[2]) / b.spacing[2] - 0.5 + (double)b.ghost;
+    double s0 = (rs.o[0] + t * rs.d[0] - b.origin[0]) * b.inv_spacing[0] + g;
+    double s1 = (rs.o[1] + t * rs.d[1] - b.origin[1]) * b.inv_spacing[1] + g;
+    double s2 = (rs.o[2] + t * rs.d[2] - b.origin[2]) * b.inv_spacing[2] + g;
     double f0 = floor(s0), f1 = floor(s1), f2 = floor(s2);
     a.ia0 = (int)f0; a.ia1 = (int)f1; a.ia2 = (int)f2;
     a.uf0 = (float)(s0 - f0); a.uf1 = (float)(s1 - f1); a.uf2 = (float)(s2 - f2);
@@ -164,25 +165,31 @@ __device__ inline Step make_step(const RaySetup& rs, const BrickK& b, double dt)
     return s;
 }
 
-// Position of sample j after the anchor: base stored index (clamped so that
-// the +1 neighbours stay inside the stored array) and trilinear fractions.
+// floor(x) as an int, and the fraction x - floor(x) (v_fract_f32, which
+// returns the largest float below 1 where that difference would round up
+// to 1).
+__device__ inline int floor_int(float x) { return (int)floorf(x); }
+__device__ inline float fract(float x) { return __builtin_amdgcn_fractf(x); }
+
+// Position of sample j (fj = j as float) after the anchor: base stored index
+// (clamped so that the +1 neighbours stay inside the stored array) and
+// trilinear fractions.  For owned samples the clamp never acts (the ghost
+// layer covers every corner), so paths that skip it read the same voxels.
 struct Cell {
     int ix, iy, iz;
     float fx, fy, fz;
 };
 
-__device__ inline Cell locate(const Anchor& a, const Step& st, int j, int snx, int sny, int snz) {
+__device__ inline Cell locate(const Anchor& a, const Step& st, float fj, int snx, int sny, int snz) {
     // snx = stored extent in x (not the row pitch)
-    const float fj = (float)j;
     const float x = fmaf(fj, st.s0, a.uf0);
     const float y = fmaf(fj, st.s1, a.uf1);
     const float z = fmaf(fj, st.s2, a.uf2);
-    const float flx = floorf(x), fly = floorf(y), flz = floorf(z);
     Cell c;
-    c.fx = x - flx; c.fy = y - fly; c.fz = z - flz;
-    c.ix = min(max(a.ia0 + (int)flx, 0), snx - 2);
-    c.iy = min(max(a.ia1 + (int)fly, 0), sny - 2);
-    c.iz = min(max(a.ia2 + (int)flz, 0), snz - 2);
+    c.fx = fract(x); c.fy = fract(y); c.fz = fract(z);
+    c.ix = min(max(a.ia0 + floor_int(x), 0), snx - 2);
+    c.iy = min(max(a.ia1 + floor_int(y), 0), sny - 2);
+    c.iz = min(max(a.ia2 + floor_int(z), 0), snz - 2);
     return c;
 }
 

@@ -78,6 +78,7 @@ def test_sample_counter_matches_oracle(dp):
         r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange,
                         30.0, sc.step, ert)
         r.set_camera(sc.camera)
+        rois = list(r.rois)
         r.reset_samples()
         r.render()
         got = r.sample_counts()
@@ -90,6 +91,10 @@ def test_sample_counter_matches_oracle(dp):
         if ert == 0.0:
             assert [int(g) for g in got] == [int(c[0]) for c in counts]
         else:
-            for g, c in zip(got, counts):
+            # termination is tested after every second sample, so a ray that
+            # stops may take one sample more than the oracle's first sample
+            # below eps (at most one per ray of the brick's ROI)
+            for g, c, roi in zip(got, counts, rois):
                 assert c[1] < c[0]
-                assert abs(int(g) - int(c[1])) <= 1e-4 * c[1] + 16
+                slack = 1e-4 * c[1] + 16
+                assert -slack <= int(g) - int(c[1]) <= roi[2] * roi[3] + slack
