@@ -132,7 +132,9 @@ vr_status vr_synchronize(vr_context ctx);
 /* Bytes of device workspace a brick of `dims` owned voxels (nx, ny, nz, each
  * >= 1) with `ghost` ghost layers (must be 1) needs at precision `storage`:
  * the ghost-padded voxels with rows padded to a multiple of 8 elements.
- * Host-only; needs no context.  Errors: VR_ERR_INVALID_ARG. */
+ * Host-only; needs no context.  Errors: VR_ERR_INVALID_ARG; VR_ERR_UNSUPPORTED
+ * when the padded brick holds 2^31 or more voxels (kernels use 32-bit
+ * element offsets within a brick). */
 vr_status vr_brick_workspace_size(const int32_t dims[3], int32_t ghost, vr_dtype storage,
                                   size_t* bytes);
 

@@ -219,6 +219,9 @@ vr_status vr_brick_workspace_size(const int32_t dims[3], int32_t ghost, vr_dtype
         if (dims[c] < 1 || dims[c] > (1 << 20))
             return fail(nullptr, VR_ERR_INVALID_ARG, "vr_brick_workspace_size: dims[%d] = %d out of range", c, dims[c]);
     const int64_t n = stored_count(dims, ghost);
+    if (n >= ((int64_t)1 << 31))   // the kernels index a brick with 32-bit element offsets
+        return fail(nullptr, VR_ERR_UNSUPPORTED, "vr_brick_workspace_size: %lld stored voxels (limit 2^31 - 1)",
+                    (long long)n);
     const size_t elt = storage == VR_F16 ? 2 : 4;
     *bytes = ((size_t)n * elt + 255) & ~(size_t)255;
     return VR_OK;

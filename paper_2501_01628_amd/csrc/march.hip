@@ -28,7 +28,8 @@ namespace dpvr {
 namespace {
 
 constexpr int kSlices = kSlab + 3;       // staged slices per slab: [wlo - 1, whi + 1]
-constexpr int kStageFloats = 17408;      // 68 KB of LDS for the staged slab (2 workgroups per CU)
+constexpr int kStageFloats = 16384;      // 64 KB of LDS for the staged slab (2 workgroups per CU)
+constexpr int kMaxRows = 1024;           // staged rows per sub-slab (row start table)
 constexpr float kMinStageDw = 0.25f;     // |d_w| below this: march from HBM
 
 struct LaneState {
@@ -220,7 +221,8 @@ struct StageVec<__half> {
 struct StagedShared {
     TFTable tft;
     __align__(16) float stage[kStageFloats];
-    int tab_off[kSlices], tab_x0[kSlices], tab_b0[kSlices];
+    unsigned row_src[kMaxRows];          // element offset in the brick of each staged row
+    int tab_off[kSlices];
     float red[2][4][kRed];
 };
 
@@ -244,8 +246,7 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
     const TFTable& tft = sh.tft;
     float* stage = sh.stage;
     int* tab_off = sh.tab_off;
-    int* tab_x0 = sh.tab_x0;
-    int* tab_b0 = sh.tab_b0;
+    unsigned* row_src = sh.row_src;
     float (*red)[4][kRed] = sh.red;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const BrickK& b = p.brick;
@@ -279,6 +280,17 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
         n_chunk = (long long)uniform_f(v[0]);
     }
     const double gh = (double)b.ghost - 0.5;
+    // slopes of all rays of the tile (constant along each ray)
+    float kxmin, kxmax, kbmin, kbmax;
+    {
+        float v[4] = {has ? kx : 3e38f, has ? kx : -3e38f, has ? kb : 3e38f, has ? kb : -3e38f};
+        const bool mx[4] = {false, true, false, true};
+        wg_reduce(v, mx, red, buf, lane, wave);
+        buf ^= 1;
+        kxmin = uniform_f(v[0]); kxmax = uniform_f(v[1]);
+        kbmin = uniform_f(v[2]); kbmax = uniform_f(v[3]);
+    }
+    const float Kx = fmaxf(fabsf(kxmin), fabsf(kxmax)), Kb = fmaxf(fabsf(kbmin), fabsf(kbmax));
     // at most snw / kSlab + 3 slabs intersect the brick; the bound only guards
     // against a logic error turning into a hang
     const int max_iter = 2 * (snw / kSlab + 4);
@@ -293,24 +305,22 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
             xr = (float)((rs.o[0] + t * rs.d[0] - b.origin[0]) * b.inv_spacing[0] + gh);
             br = (float)((rs.o[B] + t * rs.d[B] - b.origin[B]) * b.inv_spacing[B] + gh);
         }
-        float v[11] = {part ? xr : 3e38f, part ? xr : -3e38f, part ? br : 3e38f, part ? br : -3e38f,
-                       part ? kx : 3e38f, part ? kx : -3e38f, part ? kb : 3e38f, part ? kb : -3e38f,
-                       part ? 1.0f : 0.0f, alive ? 1.0f : 0.0f,
-                       (alive && !part) ? (float)n_cur : 3e38f};
-        const bool mx[11] = {false, true, false, true, false, true, false, true, true, true, false};
+        // extent of the participating rays at the slab's entry plane, and the
+        // next slab a ray that skips this one needs (none participates: the
+        // max of x stays at -3e38)
+        float v[5] = {part ? xr : 3e38f, part ? xr : -3e38f, part ? br : 3e38f, part ? br : -3e38f,
+                      (alive && !part) ? (float)n_cur : 3e38f};
+        const bool mx[5] = {false, true, false, true, false};
         wg_reduce(v, mx, red, buf, lane, wave);
         buf ^= 1;
-        if (uniform_f(v[9]) == 0.0f) break;        // every ray of the tile is done
-        if (uniform_f(v[8]) == 0.0f) {             // gap: jump to the next slab someone needs
-            n_chunk = (long long)uniform_f(v[10]);
-            continue;
-        }
-        // uniform slab geometry (stored-index units)
         const float xmin0 = uniform_f(v[0]), xmax0 = uniform_f(v[1]);
         const float bmin0 = uniform_f(v[2]), bmax0 = uniform_f(v[3]);
-        const float kxmin = uniform_f(v[4]), kxmax = uniform_f(v[5]);
-        const float kbmin = uniform_f(v[6]), kbmax = uniform_f(v[7]);
-        const float Kx = fmaxf(fabsf(kxmin), fabsf(kxmax)), Kb = fmaxf(fabsf(kbmin), fabsf(kbmax));
+        if (xmax0 < -1e38f) {                      // no ray of the tile in this slab
+            const float nn = uniform_f(v[4]);
+            if (nn > 1e38f) break;                 // every ray of the tile is done
+            n_chunk = (long long)nn;               // gap: jump to the next slab someone needs
+            continue;
+        }
         // a per-slice rectangle of RW x RH bounds every slice's footprint:
         // width <= ceil(span + 2 eps) + 1 (corner column) + 1, plus up to V - 1
         // columns of 16-byte alignment (spans clamped so that they cannot
@@ -327,9 +337,12 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
         RH = uniform_i(RH);
         // split the slab into S sub-slabs of L slices until L + 3 slices fit
         int S = 1;
-        while (S < kSlab && (long long)(kSlab / S + 3) * RW * RH > kStageFloats) S *= 2;
+        auto fits = [&](int sl) {
+            return (long long)sl * RW * RH <= kStageFloats && sl * RH <= kMaxRows;
+        };
+        while (S < kSlab && !fits(kSlab / S + 3)) S *= 2;
         const int L = kSlab / S, nsl = L + 3;
-        const bool use_lds = (long long)nsl * RW * RH <= kStageFloats && RW > 0 && RH > 0;
+        const bool use_lds = fits(nsl) && RW > 0 && RH > 0;
         if (!use_lds) S = 1;
         const long long kend_blk = part ? min(k_next, rs.kl + 1) : 0;   // exclusive
         Anchor an{};
@@ -340,37 +353,46 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
             // lower stored-w plane of sub-slab q (sub-slabs in ray order)
             const int w_a = (int)wlo + (sg > 0 ? q * L : kSlab - (q + 1) * L);
             if (use_lds) {
-                if (tid < nsl) {
-                    // slice w = w_a - 1 + i is touched by samples with s_w in
-                    // [w - 1, w + 1), i.e. s_w - wlo in [d0 + i - 2, d0 + i]
-                    const int i = tid;
+                // slice w = w_a - 1 + i is touched by samples with s_w in
+                // [w - 1, w + 1), i.e. s_w - wlo in [d0 + i - 2, d0 + i]; its
+                // rectangle starts at (x0, b0)
+                auto slice_origin = [&](int i, int& x0, int& b0) {
                     const float da = (float)(w_a - (int)wlo + i - 2), db = da + 2.0f;
                     const float xl = xmin0 + fminf(fminf(da * kxmin, da * kxmax), fminf(db * kxmin, db * kxmax));
                     const float bl0 = bmin0 + fminf(fminf(da * kbmin, da * kbmax), fminf(db * kbmin, db * kbmax));
-                    int x0 = (int)floorf(xl - kEps);
-                    x0 = max(x0, 0) / V * V;
+                    x0 = max((int)floorf(xl - kEps), 0) / V * V;
                     if (x0 + RW > pitch) x0 = pitch - RW;
-                    const int b0 = max((int)floorf(bl0 - kEps), 0);
-                    tab_x0[i] = x0;
-                    tab_b0[i] = b0;
-                    tab_off[i] = (i * RH * RW - b0 * RW - x0) * 4;   // bytes
+                    b0 = max((int)floorf(bl0 - kEps), 0);
+                };
+                const int nrows = nsl * RH;
+                const float inv_rh = 1.0f / (float)RH;
+                if (tid < nsl) {
+                    int x0, b0;
+                    slice_origin(tid, x0, b0);
+                    tab_off[tid] = (tid * RH * RW - b0 * RW - x0) * 4;   // bytes
+                }
+                // source of every staged row (slices w_a - 1 .. w_a + L + 1)
+                for (int qr = tid; qr < nrows; qr += 256) {
+                    const int i = (int)(((float)qr + 0.5f) * inv_rh);
+                    const int r = qr - i * RH;
+                    int x0, b0;
+                    slice_origin(i, x0, b0);
+                    const int wabs = min(max(w_a - 1 + i, 0), snw - 1);
+                    const int babs = min(b0 + r, snb - 1);
+                    const int yz = W == 2 ? wabs * sny + babs : babs * sny + wabs;
+                    row_src[qr] = (unsigned)yz * (unsigned)pitch + (unsigned)x0;
                 }
                 __syncthreads();
-                // stage slices w_a - 1 .. w_a + L + 1 (rows along x, 16-byte vectors)
+                // copy: a fixed 16-byte column per thread, rows strided
                 const int cols = RW / V;
-                const int total = nsl * RH * cols;
-                const float inv_cols = 1.0f / (float)cols, inv_rh = 1.0f / (float)RH;
-                for (int e = tid; e < total; e += 256) {
-                    const int qq = (int)(((float)e + 0.5f) * inv_cols);
-                    const int c = e - qq * cols;
-                    const int i = (int)(((float)qq + 0.5f) * inv_rh);
-                    const int r = qq - i * RH;
-                    const int wabs = min(max(w_a - 1 + i, 0), snw - 1);
-                    const int babs = min(tab_b0[i] + r, snb - 1);
-                    const int x = tab_x0[i] + c * V;
-                    const long long yz = W == 2 ? ((long long)wabs * sny + babs)
-                                                : ((long long)babs * sny + wabs);
-                    StageVec<TS>::copy(vox + yz * pitch + x, &stage[(i * RH + r) * RW + c * V]);
+                const int tpr = min(cols, 256), rpi = 256 / tpr;
+                const int c0 = tid % tpr, r0 = tid / tpr;
+                if (r0 < rpi) {
+                    for (int qr = r0; qr < nrows; qr += rpi) {
+                        const TS* src = vox + row_src[qr];
+                        float* dst = stage + qr * RW;
+                        for (int c = c0; c < cols; c += tpr) StageVec<TS>::copy(src + c * V, dst + c * V);
+                    }
                 }
                 __syncthreads();
             }
