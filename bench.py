@@ -67,15 +67,29 @@ def scene_for(name):
     return sc, desc
 
 
-def traffic_for(kernel_src, workload, storage):
+KERNEL_SOURCES = ("march.hip", "march_common.h", "dpvr_kernels.h")
+
+
+def kernel_sha256():
+    """Hash of the sources the march kernel is built from."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2501_01628_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_path(workload, storage):
+    return os.path.join(ROOT, "profiles", f"march_queue_{workload}_{storage}_traffic.json")
+
+
+def traffic_for(workload, storage):
     """Measured HBM bytes per launch from a committed rocprofv3 --pmc summary,
-    valid only while the kernel source is unchanged."""
-    path = os.path.join(ROOT, "profiles", f"march_{workload}_{storage}_traffic.json")
+    valid only while the kernel sources are unchanged."""
+    path = traffic_path(workload, storage)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if rec.get("kernel_sha256") != h:
+    if rec.get("kernel_sha256") != kernel_sha256():
         return None
     return rec.get("hbm_bytes_per_frame")
 
@@ -115,9 +129,8 @@ def summarize_pmc(args):
                      "march_kib_per_dispatch": sum(march) / len(march),
                      "march_dispatches": len(march),
                      "march_bytes_per_dispatch_scaled": sum(march) / len(march) * 1024.0 * scale}
-    src = os.path.join(ROOT, "paper_2501_01628_amd", "csrc", "march.hip")
     rec = {"kernel": MARCH_KERNEL, "workload": args.workload, "storage": args.storage,
-           "kernel_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+           "kernel_sha256": kernel_sha256(), "kernel_sources": list(KERNEL_SOURCES),
            "hbm_bytes_per_frame": out["FETCH_SIZE"]["march_bytes_per_dispatch_scaled"]
            + out["WRITE_SIZE"]["march_bytes_per_dispatch_scaled"],
            "counters": out,
@@ -126,7 +139,7 @@ def summarize_pmc(args):
            "commands": [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -- python3 bench.py "
                         f"--workload {args.workload} --storage {args.storage} --steps 2 --warmup 1 "
                         f"--no-cpu-baseline --pmc-calibrate" for c in ("FETCH_SIZE", "WRITE_SIZE")]}
-    path = os.path.join(ROOT, "profiles", f"march_{args.workload}_{args.storage}_traffic.json")
+    path = traffic_path(args.workload, args.storage)
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
@@ -344,8 +357,7 @@ def main():
         f"composite {comp_ms:.3f} ms, {samples} samples/frame")
 
     achieved = sum(march_alg) / (march_ms.sum() * 1e-3) / 1e9
-    traffic = traffic_for(os.path.join(ROOT, "paper_2501_01628_amd", "csrc", "march.hip"),
-                          args.workload, args.storage)
+    traffic = traffic_for(args.workload, args.storage)
     out = {
         "metric": "Msamples/s (render+composite, samples evaluated per frame x frames/s)",
         "value": samples / (ms_per_step * 1e-3) / 1e6,
@@ -373,6 +385,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_gbs": traffic / (march_ms.sum() * 1e-3) / 1e9 if traffic else None,
             "launches_per_frame": 1,
             "algorithmic_bytes_per_frame": int(sum(march_alg)),
         },

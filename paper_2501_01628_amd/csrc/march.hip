@@ -28,8 +28,18 @@ namespace dpvr {
 namespace {
 
 constexpr int kSlices = kSlab + 3;       // staged slices per slab: [wlo - 1, whi + 1]
-constexpr int kStageFloats = 16384;      // 64 KB of LDS for the staged slab (2 workgroups per CU)
-constexpr int kMaxRows = 1024;           // staged rows per sub-slab (row start table)
+// Build-time sizes of the staged kernels: LDS floats of the slab stage and
+// rows of the row table.  (64 KB measured best on C2: a 40 KB stage with
+// 3 workgroups per CU ran within 3 %, a 24 KB stage with 4 per CU 20 %
+// slower, from register spills and more sub-slabs.)
+#ifndef DPVR_STAGE_FLOATS
+#define DPVR_STAGE_FLOATS 16384          // 64 KB: 2 workgroups per CU
+#endif
+#ifndef DPVR_STAGE_ROWS
+#define DPVR_STAGE_ROWS 1024
+#endif
+constexpr int kStageFloats = DPVR_STAGE_FLOATS;
+constexpr int kMaxRows = DPVR_STAGE_ROWS;
 constexpr float kMinStageDw = 0.25f;     // |d_w| below this: march from HBM
 
 struct LaneState {
