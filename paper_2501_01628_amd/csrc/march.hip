@@ -53,9 +53,11 @@ struct LaneState {
 // (fj = j as float).  Returns false once early termination stops the ray.
 // Two samples are fetched and classified before either is accumulated, so
 // the memory round trips of consecutive samples overlap; accumulation stays
-// in sample order.  Termination is tested after every second sample (a ray
-// may take one sample past T < eps, which changes its colour by less than
-// eps).
+// in sample order.  Termination is tested after every sample whose offset
+// from the ray's first owned sample is odd (the end of each pair of the ray),
+// wherever the runs of a ray are cut, so every path stops a ray at the same
+// sample; a ray may take one sample past T < eps, which changes its colour by
+// less than eps.
 template <bool kCkpt, typename Sample>
 __device__ inline bool march_run(const MarchParams& p, const TFTable& tft, const RaySetup& rs,
                                  long long kb, int j0, int j1, long long pix, float tf_k,
@@ -79,6 +81,16 @@ __device__ inline bool march_run(const MarchParams& p, const TFTable& tft, const
     };
     int j = j0;
     float fj = (float)j0;
+    if (((kb + j0 - rs.kf) & 1) && j < j1) {   // second sample of a pair begun in the previous run
+        accumulate(classify(tft, sample(fj), tf_k, tf_o), j);
+        ++j;
+        fj += 1.0f;
+        if (s.T < eps) {
+            s.evaluated += 1;
+            s.stopped = true;
+            return false;
+        }
+    }
     for (; j + 1 < j1; j += 2, fj += 2.0f) {
         const float v0 = sample(fj);
         const float v1 = sample(fj + 1.0f);
@@ -92,14 +104,8 @@ __device__ inline bool march_run(const MarchParams& p, const TFTable& tft, const
             return false;
         }
     }
-    if (j < j1) {
-        accumulate(classify(tft, sample(fj), tf_k, tf_o), j);
-        if (s.T < eps) {
-            s.evaluated += j1 - j0;
-            s.stopped = true;
-            return false;
-        }
-    }
+    // first sample of a pair: its test comes after the next sample (next run)
+    if (j < j1) accumulate(classify(tft, sample(fj), tf_k, tf_o), j);
     s.evaluated += j1 - j0;
     return true;
 }

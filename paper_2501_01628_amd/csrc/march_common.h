@@ -13,7 +13,7 @@
 
 namespace dpvr {
 
-constexpr int kSlab = 8;          // anchor block = slab of kSlab slices along the ray's w axis
+constexpr int kSlab = 16;         // anchor block = slab of kSlab slices along the ray's w axis
 constexpr float kLog2e = 1.4426950408889634f;
 
 struct RaySetup {
