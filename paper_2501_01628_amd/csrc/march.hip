@@ -211,20 +211,27 @@ __device__ inline void wg_reduce(float (&v)[N], const bool (&is_max)[N], float (
     }
 }
 
+// 16-byte staging vectors: load() from the brick in HBM (global address
+// space: the loads count only against vmcnt), store() into the float32 stage
+// (float16 decoded here).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
+
 template <typename TS>
 struct StageVec;
 template <>
 struct StageVec<float> {
     static constexpr int V = 4;
-    __device__ static void copy(const float* __restrict__ src, float* dst) {
-        *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(src);
+    __device__ static u32x4 load(const float* src) { return *(gu32x4*)src; }
+    __device__ static void store(const u32x4& raw, float* dst) {
+        *reinterpret_cast<u32x4*>(dst) = raw;
     }
 };
 template <>
 struct StageVec<__half> {
     static constexpr int V = 8;
-    __device__ static void copy(const __half* __restrict__ src, float* dst) {
-        const uint4 raw = *reinterpret_cast<const uint4*>(src);
+    __device__ static u32x4 load(const __half* src) { return *(gu32x4*)src; }
+    __device__ static void store(const u32x4& raw, float* dst) {
         const __half2* h = reinterpret_cast<const __half2*>(&raw);
         const float2 a = __half22float2(h[0]), b = __half22float2(h[1]);
         const float2 c = __half22float2(h[2]), d = __half22float2(h[3]);
@@ -399,15 +406,33 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
                     row_src[qr] = (unsigned)yz * (unsigned)pitch + (unsigned)x0;
                 }
                 __syncthreads();
-                // copy: a fixed 16-byte column per thread, rows strided
+                // copy: a fixed 16-byte column per thread, rows strided; the
+                // loads of kBatch rows are all issued before the first store,
+                // so their HBM latencies overlap
+                constexpr int kBatch = 2;
                 const int cols = RW / V;
                 const int tpr = min(cols, 256), rpi = 256 / tpr;
                 const int c0 = tid % tpr, r0 = tid / tpr;
                 if (r0 < rpi) {
-                    for (int qr = r0; qr < nrows; qr += rpi) {
-                        const TS* src = vox + row_src[qr];
-                        float* dst = stage + qr * RW;
-                        for (int c = c0; c < cols; c += tpr) StageVec<TS>::copy(src + c * V, dst + c * V);
+                    if (cols <= 256) {
+                        for (int qb = r0; qb < nrows; qb += kBatch * rpi) {
+                            u32x4 v[kBatch];
+#pragma unroll
+                            for (int m = 0; m < kBatch; ++m) {
+                                const int qr = qb + m * rpi;
+                                if (qr < nrows) v[m] = StageVec<TS>::load(vox + row_src[qr] + c0 * V);
+                            }
+#pragma unroll
+                            for (int m = 0; m < kBatch; ++m) {
+                                const int qr = qb + m * rpi;
+                                if (qr < nrows) StageVec<TS>::store(v[m], stage + qr * RW + c0 * V);
+                            }
+                        }
+                    } else {
+                        for (int qr = r0; qr < nrows; qr += rpi)
+                            for (int c = c0; c < cols; c += tpr)
+                                StageVec<TS>::store(StageVec<TS>::load(vox + row_src[qr] + c * V),
+                                                    stage + qr * RW + c * V);
                     }
                 }
                 __syncthreads();
