@@ -55,6 +55,15 @@ def test_workspace_size_values():
     assert dp.vr_brick_workspace_size((6, 1, 1), 1, dp.VR_F32) == 512   # 8 x 3 x 3 x 4 B
 
 
+def test_workspace_size_rejects_bricks_beyond_32bit_offsets():
+    # 1026 x 1026 x 2050 stored voxels (pitch 1032) >= 2^31: unsupported
+    with pytest.raises(dp.VRError) as e:
+        dp.vr_brick_workspace_size((1024, 1024, 2048), 1, dp.VR_F16)
+    assert e.value.status == dp.VR_ERR_UNSUPPORTED
+    # just below the limit: 1032 x 1026 x 2028 < 2^31
+    assert dp.vr_brick_workspace_size((1024, 1024, 2026), 1, dp.VR_F16) > 0
+
+
 def test_null_handles_are_rejected():
     for call in (lambda: dp.vr_context_release(None), lambda: dp.vr_synchronize(None),
                  lambda: dp.vr_brick_release(None),
