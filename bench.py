@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c1", "c3"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4"], default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
     ap.add_argument("--path", choices=["staged", "direct"], default="staged",
                     help="march from LDS-staged slabs or straight from HBM (same images)")
@@ -285,6 +285,70 @@ def bench_batch(args):
     return 0
 
 
+def bench_adjoint(args):
+    """Differentiable workload: 128^3 float32 volume, 8 views at 512x512, step
+    0.5; one gradient step = forward with transmittance checkpoints every 64
+    samples + L2 loss against fixed targets + composite backward + adjoint
+    march for all views (gradients for the 256x4 table and all voxels).
+    Targets are seeded random images (timing only; the gradient itself is
+    checked against the oracle and finite differences in the tests)."""
+    import torch
+
+    import paper_2501_01628_amd as dp
+    import synth
+    sc = synth.config_c4()
+    cams = sc.extra["cameras"]
+    n = sc.field.shape[0]
+    dr = dp.DiffRenderer((n, n, n), [((0, 0, 0), (n, n, n))], (0.0, 1.0), 1.0, sc.step, 64)
+    tf = torch.tensor(synth.default_tf(), device="cuda", requires_grad=True)
+    vol = torch.tensor(sc.field, device="cuda", requires_grad=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    w, h = cams[0]["width"], cams[0]["height"]
+    targets = [torch.rand((h, w, 4), device="cuda", generator=g) for _ in cams]
+    bg = (0.1, 0.2, 0.3, 1.0)
+
+    def forward():
+        tot = torch.zeros((), device="cuda")
+        for cam, tgt in zip(cams, targets):
+            tot = tot + ((dr.render(tf, vol, cam, bg) - tgt) ** 2).sum()
+        return tot
+
+    def step():
+        tf.grad = None
+        vol.grad = None
+        forward().backward()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(args.steps):
+        with torch.no_grad():
+            forward()
+    ev[1].record()
+    ev[2].record()
+    for _ in range(args.steps):
+        step()
+    ev[3].record()
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1]) / args.steps
+    step_ms = ev[2].elapsed_time(ev[3]) / args.steps
+    dr.close()
+    out = {"metric": "ms per gradient step (8-view forward with checkpoints + backward)",
+           "value": step_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": step_ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "c4: 128^3 f32 volume (8 blobs), 8 views at 512x512, step 0.5, "
+                                  "64-sample checkpoints, L2 loss, gradients for the 256x4 TF and "
+                                  "all voxels"},
+           "forward_ms": fwd_ms, "backward_ms": step_ms - fwd_ms,
+           "views_per_s": len(cams) * 1e3 / step_ms}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -295,6 +359,8 @@ def main():
         return summarize_pmc(args)
     if args.workload == "c3":
         return bench_batch(args)
+    if args.workload == "c4":
+        return bench_adjoint(args)
     import torch
 
     import paper_2501_01628_amd as dp
