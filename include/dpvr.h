@@ -205,15 +205,18 @@ vr_status vr_set_camera_orthographic(vr_context ctx, const double pos[3], const 
 /* Sample spacing dt along each ray in world units (> 0; the samples sit at
  * (k + 1/2) dt from the ray origin), and the early-termination threshold: a
  * ray stops once its transmittance drops below ert_epsilon (0 disables; the
- * neglected remainder is at most ert_epsilon per channel).  Defaults:
- * dt = 0.5, ert_epsilon = 2^-20. */
+ * neglected remainder is at most ert_epsilon per channel; the test is made
+ * after every second sample of the ray, so a ray may take one sample past the
+ * threshold).  Defaults: dt = 0.5, ert_epsilon = 2^-20. */
 vr_status vr_set_render_params(vr_context ctx, double dt, float ert_epsilon);
 
 /* Launch path of the forward march; every path computes bit-identical
  * images (the sample positions and values do not depend on it):
  *   VR_PATH_STAGED  a workgroup per 16x16 pixel tile stages each slab of
  *                   brick slices its rays cross through LDS (default);
- *   VR_PATH_DIRECT  one wavefront per 8x8 tile reads voxels from HBM. */
+ *   VR_PATH_DIRECT  every lane reads its voxels from HBM (vr_render_partials:
+ *                   the same persistent work queue; vr_render_partial: one
+ *                   wavefront per 8x8 tile). */
 typedef enum { VR_PATH_STAGED = 0, VR_PATH_DIRECT = 1 } vr_path;
 vr_status vr_set_march_path(vr_context ctx, vr_path path);
 
