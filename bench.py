@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="first run one plain copy of known size through the ingest kernel "
                          "(512^3 float32: 512 MiB read, 512 MiB written) for HBM-counter scaling")
+    ap.add_argument("--summarize-sq", metavar="SQ_DIR",
+                    help="turn a rocprofv3 --pmc run with SQ_INSTS_VALU into the per-launch "
+                         "VALU record under profiles/")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs of --pmc-calibrate (FETCH_SIZE, then "
                          "WRITE_SIZE) into the per-frame HBM traffic record under profiles/")
@@ -144,6 +147,49 @@ def summarize_pmc(args):
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
     return 0
+
+
+VALU_LANES_PER_CU_CYCLE = 64        # 4 SIMDs x 16 lanes: one wave64 VALU instruction per 4 cycles
+N_CU, CLOCK_HZ = 256, 2.4e9
+
+
+def valu_path(workload, storage):
+    return os.path.join(ROOT, "profiles", f"march_queue_{workload}_{storage}_valu.json")
+
+
+def summarize_sq(args):
+    """VALU wave instructions per march launch from SQ_INSTS_VALU."""
+    rows = [v for k, v in _pmc_rows(args.summarize_sq, "SQ_INSTS_VALU") if MARCH_KERNEL in k]
+    if not rows:
+        raise SystemExit(f"{args.summarize_sq}: no march dispatch with SQ_INSTS_VALU")
+    rec = {"kernel": MARCH_KERNEL, "workload": args.workload, "storage": args.storage,
+           "kernel_sha256": kernel_sha256(), "kernel_sources": list(KERNEL_SOURCES),
+           "valu_wave_insts_per_launch": sum(rows) / len(rows), "dispatches": len(rows),
+           "command": f"rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU "
+                      f"SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_INSTS_VMEM "
+                      f"--output-format csv -d <dir> -- python3 "
+                      f"bench.py --workload {args.workload} --storage {args.storage} --steps 3 "
+                      f"--warmup 1 --no-cpu-baseline"}
+    with open(valu_path(args.workload, args.storage), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+    return 0
+
+
+def valu_for(workload, storage, march_ms):
+    """Issue time of the launch's VALU instructions at the chip's vector rate
+    (from the committed counter record, while the kernel is unchanged), as a
+    fraction of the measured launch time."""
+    path = valu_path(workload, storage)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_sha256") != kernel_sha256():
+        return None
+    insts = rec["valu_wave_insts_per_launch"]
+    issue_ms = insts * 64 / (VALU_LANES_PER_CU_CYCLE * N_CU * CLOCK_HZ) * 1e3
+    return {"wave_insts_per_launch": insts, "issue_ms": issue_ms, "frac": issue_ms / march_ms,
+            "peak": "64 lanes/CU/cycle x 256 CUs x 2.4 GHz (unpacked fp32)"}
 
 
 def calibration_copy():
@@ -357,6 +403,8 @@ def main():
         return 2
     if args.summarize_pmc:
         return summarize_pmc(args)
+    if args.summarize_sq:
+        return summarize_sq(args)
     if args.workload == "c3":
         return bench_batch(args)
     if args.workload == "c4":
@@ -455,6 +503,7 @@ def main():
             "launches_per_frame": 1,
             "algorithmic_bytes_per_frame": int(sum(march_alg)),
         },
+        "valu": valu_for(args.workload, args.storage, float(march_ms.sum())),
         "composite_roofline": {"achieved": comp_alg / (comp_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "algorithmic_bytes": int(comp_alg)},
     }
