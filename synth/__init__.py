@@ -32,8 +32,8 @@ import numpy as np
 
 __all__ = [
     "Brick", "Scene", "default_tf", "hidden_tf", "orbit_camera", "inside_camera",
-    "draw_blobs", "add_blobs", "add_shock", "kd_split", "extract_brick",
-    "config_c1", "config_c2", "config_c3", "config_c4", "tile_field", "scene_from_field",
+    "draw_blobs", "add_blobs", "add_shock", "add_fractal_noise", "kd_split", "extract_brick",
+    "config_c1", "config_c2", "config_c3", "config_c4", "config_c5", "tile_field", "scene_from_field",
 ]
 
 _THREADS = max(1, min(16, os.cpu_count() or 1))
@@ -327,6 +327,66 @@ def config_c4(n=128, views=8, size=512, seed=4):
     sc.extra["cameras"] = cams
     sc.extra["hidden_tf"] = hidden_tf()
     return sc
+
+
+def add_fractal_noise(acc, rng, amp, octaves=6, base=None):
+    """1/f-like noise: octaves o = 0..octaves-1 of seeded uniform grids with
+    spacing base / 2^o voxels, trilinearly upsampled, amplitude proportional
+    to the spacing (amp at the coarsest octave), zero mean.  Built slab by
+    slab, so large fields need no full-size temporary."""
+    nz, ny, nx = acc.shape
+    if base is None:
+        base = max(8, 2 ** int(math.floor(math.log2(max(nx, ny, nz) / 4))))
+    grids = []
+    for o in range(octaves):
+        sp = base / 2 ** o
+        if sp < 2:
+            break
+        shape = (int(math.ceil(nz / sp)) + 2, int(math.ceil(ny / sp)) + 2, int(math.ceil(nx / sp)) + 2)
+        grids.append((sp, amp * sp / base, rng.uniform(-1.0, 1.0, shape)))
+
+    def lerp_axis(n, sp):
+        u = (np.arange(n, dtype=np.float64) + 0.5) / sp
+        i = np.floor(u).astype(np.int64)
+        return i, u - i
+
+    for sp, a, g in grids:
+        ix, fx = lerp_axis(nx, sp)
+        iy, fy = lerp_axis(ny, sp)
+        for z in range(nz):
+            uz = (z + 0.5) / sp
+            iz = int(math.floor(uz))
+            fz = uz - iz
+            pl = (1 - fz) * g[iz] + fz * g[iz + 1]                    # (gy, gx)
+            rows = (1 - fy)[:, None] * pl[iy] + fy[:, None] * pl[iy + 1]   # (ny, gx)
+            acc[z] += a * ((1 - fx)[None, :] * rows[:, ix] + fx[None, :] * rows[:, ix + 1])
+    return acc
+
+
+def config_c5(dims=(2048, 1024, 1024), n_bricks=64, width=3840, height=2160, seed=5,
+              n_blobs=128):
+    """Large float16 case: blobs + two tanh shock fronts (widths 4 and 8) +
+    1/f-like fractal noise (amplitude 0.05), clamped; kd split into
+    ``n_bricks`` uneven bricks; 3840x2160 orbit view, step 0.25, opacity 0.05.
+    Seed 5; draw order: blobs, shock 1 normal + offset, shock 2 normal +
+    offset, noise grids, kd cuts.  ``dims``/``width``/``height`` may be
+    reduced for parity cases; the recipe is otherwise unchanged."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    acc = np.zeros((nz, ny, nx), dtype=np.float64)
+    add_blobs(acc, *draw_blobs(rng, n_blobs, dims))
+    for amp, w in ((0.6, 4.0), (0.4, 8.0)):
+        n = rng.normal(0.0, 1.0, 3)
+        n /= np.linalg.norm(n)
+        p0 = 0.5 * np.asarray(dims, dtype=np.float64) + rng.uniform(-0.25, 0.25, 3) * np.asarray(dims)
+        add_shock(acc, n, p0, amp, w)
+    add_fractal_noise(acc, rng, 0.05)
+    field = _finish(acc)
+    del acc
+    boxes = kd_split(dims, n_bricks, rng)
+    cam = orbit_camera((0, 0, 0), dims, width, height)
+    return scene_from_field(f"c5_{nx}x{ny}x{nz}_{n_bricks}bricks_{width}x{height}", field, boxes,
+                            default_tf(), cam, 0.25, 0.05)
 
 
 def tile_field(rng, dims, n_blobs=8, noise=0.0, shock=False):

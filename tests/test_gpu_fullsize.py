@@ -98,3 +98,41 @@ def test_sample_counter_matches_oracle(dp):
                 assert c[1] < c[0]
                 slack = 1e-4 * c[1] + 16
                 assert -slack <= int(g) - int(c[1]) <= roi[2] * roi[3] + slack
+
+
+def test_c5_shape_fp16_64_bricks_4k(dp):
+    """The large float16 configuration's shape at a reduced volume: a
+    256x128x128 field (blobs + two shocks + fractal noise) stored as float16
+    in 64 uneven kd bricks, 3840x2160 view, step 0.25, 64-partial composite.
+    Sampled pixels against the oracle on the float16-decoded bricks (kernel
+    error, 1e-5) and on the original float32 field (storage error, 2e-3);
+    depth keys of every partial exact at those pixels."""
+    sc = synth.config_c5(dims=(256, 128, 128))
+    assert len(sc.bricks) == 64
+    r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange, sc.opacity_scale,
+                    sc.step, storage=dp.VR_F16)
+    r.set_camera(sc.camera)
+    bg = (0.1, 0.2, 0.3, 1.0)
+    img = r.render(bg)
+    r.synchronize()
+    W, H = sc.camera["width"], sc.camera["height"]
+    pix = _pixels(W, H, 11, n=2000)
+    got = img.cpu().numpy()[pix[:, 1], pix[:, 0]].astype(np.float64)
+    rois = list(r.rois)
+    depths = [r.partial_arrays(k)[1].cpu().numpy() for k in range(len(r.bricks))]
+    r.close()
+    decoded = [b.voxels.astype(np.float16).astype(np.float32) for b in sc.bricks]
+    ref16, parts16, _ = oracle.render_scene(sc, bg=bg, pixels=pix, field_override=decoded)
+    err16 = float(np.max(np.abs(got - ref16)))
+    ref32, _, cnt = oracle.render_scene(sc, bg=bg, pixels=pix)
+    err32 = float(np.max(np.abs(got - ref32)))
+    print(f"c5 shape: {len(pix)} pixels, {cnt[0]} samples, err vs decoded {err16:.3e}, "
+          f"vs float32 field {err32:.3e}")
+    assert err16 <= 1e-5, err16
+    assert err32 <= 2e-3, err32
+    for (x0, y0, w, h), pd, (_, rd) in zip(rois, depths, parts16):
+        inside = (pix[:, 0] >= x0) & (pix[:, 0] < x0 + w) & (pix[:, 1] >= y0) & (pix[:, 1] < y0 + h)
+        assert np.all(np.isinf(rd[~inside]))
+        q = pix[inside]
+        g_d = pd[q[:, 1] - y0, q[:, 0] - x0]
+        assert np.array_equal(g_d.astype(np.float64), rd[inside].astype(np.float32).astype(np.float64))
