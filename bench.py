@@ -38,8 +38,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4"], default="c2")
-    ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5"], default="c2")
+    ap.add_argument("--storage", choices=["f32", "f16"], default=None,
+                    help="brick storage (default f32; c5 is a float16 workload: f16)")
     ap.add_argument("--path", choices=["staged", "direct"], default="staged",
                     help="march from LDS-staged slabs or straight from HBM (same images)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -54,7 +55,10 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs of --pmc-calibrate (FETCH_SIZE, then "
                          "WRITE_SIZE) into the per-frame HBM traffic record under profiles/")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.storage is None:
+        args.storage = "f16" if args.workload == "c5" else "f32"
+    return args
 
 
 def scene_for(name):
@@ -64,6 +68,11 @@ def scene_for(name):
         desc = ("c2: 1024x1024x512 f32 field (64 blobs + tanh shock), 16 uneven kd bricks with "
                 "1-voxel ghosts, 1920x1080 perspective, step 0.5, opacity 0.05, 16-partial "
                 "sort-last composite")
+    elif name == "c5":
+        sc = synth.config_c5(log=lambda m: log(f"c5 generation: {m}"))
+        desc = ("c5: 2048x1024x1024 field (128 blobs + two tanh shocks + fractal noise) stored "
+                "as f16, 64 uneven kd bricks with 1-voxel ghosts, 3840x2160 perspective, step "
+                "0.25, opacity 0.05, 64-partial sort-last composite")
     else:
         sc = synth.config_c1()
         desc = "c1: 64^3 f32 field (8 blobs + noise), 2 bricks 32x64x64, 256x256, step 0.5"

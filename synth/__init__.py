@@ -329,7 +329,7 @@ def config_c4(n=128, views=8, size=512, seed=4):
     return sc
 
 
-def add_fractal_noise(acc, rng, amp, octaves=6, base=None):
+def add_fractal_noise(acc, rng, amp, octaves=6, base=None, log=None):
     """1/f-like noise: octaves o = 0..octaves-1 of seeded uniform grids with
     spacing base / 2^o voxels, trilinearly upsampled, amplitude proportional
     to the spacing (amp at the coarsest octave), zero mean.  Built slab by
@@ -351,6 +351,8 @@ def add_fractal_noise(acc, rng, amp, octaves=6, base=None):
         return i, u - i
 
     for sp, a, g in grids:
+        if log:
+            log(f"fractal noise octave, spacing {sp:g}")
         ix, fx = lerp_axis(nx, sp)
         iy, fy = lerp_axis(ny, sp)
         for z in range(nz):
@@ -364,25 +366,30 @@ def add_fractal_noise(acc, rng, amp, octaves=6, base=None):
 
 
 def config_c5(dims=(2048, 1024, 1024), n_bricks=64, width=3840, height=2160, seed=5,
-              n_blobs=128):
+              n_blobs=128, log=None):
     """Large float16 case: blobs + two tanh shock fronts (widths 4 and 8) +
     1/f-like fractal noise (amplitude 0.05), clamped; kd split into
     ``n_bricks`` uneven bricks; 3840x2160 orbit view, step 0.25, opacity 0.05.
     Seed 5; draw order: blobs, shock 1 normal + offset, shock 2 normal +
     offset, noise grids, kd cuts.  ``dims``/``width``/``height`` may be
-    reduced for parity cases; the recipe is otherwise unchanged."""
+    reduced for parity cases; the recipe is otherwise unchanged.  ``log``
+    (optional) is called with a message after each generation step."""
+    say = log or (lambda msg: None)
     rng = np.random.default_rng(seed)
     nx, ny, nz = dims
     acc = np.zeros((nz, ny, nx), dtype=np.float64)
     add_blobs(acc, *draw_blobs(rng, n_blobs, dims))
+    say("blobs")
     for amp, w in ((0.6, 4.0), (0.4, 8.0)):
         n = rng.normal(0.0, 1.0, 3)
         n /= np.linalg.norm(n)
         p0 = 0.5 * np.asarray(dims, dtype=np.float64) + rng.uniform(-0.25, 0.25, 3) * np.asarray(dims)
         add_shock(acc, n, p0, amp, w)
-    add_fractal_noise(acc, rng, 0.05)
+        say(f"shock front, width {w:g}")
+    add_fractal_noise(acc, rng, 0.05, log=log)
     field = _finish(acc)
     del acc
+    say("clamped to float32")
     boxes = kd_split(dims, n_bricks, rng)
     cam = orbit_camera((0, 0, 0), dims, width, height)
     return scene_from_field(f"c5_{nx}x{ny}x{nz}_{n_bricks}bricks_{width}x{height}", field, boxes,
