@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint"], default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default=None,
                     help="brick storage (default f32; c5 is a float16 workload: f16)")
     ap.add_argument("--path", choices=["staged", "direct"], default="staged",
@@ -57,7 +57,7 @@ def parse():
                          "WRITE_SIZE) into the per-frame HBM traffic record under profiles/")
     args = ap.parse_args()
     if args.storage is None:
-        args.storage = "f16" if args.workload == "c5" else "f32"
+        args.storage = "f16" if args.workload.startswith("c5") else "f32"
     return args
 
 
@@ -340,28 +340,9 @@ def bench_batch(args):
     return 0
 
 
-def bench_adjoint(args):
-    """Differentiable workload: 128^3 float32 volume, 8 views at 512x512, step
-    0.5; one gradient step = forward with transmittance checkpoints every 64
-    samples + L2 loss against fixed targets + composite backward + adjoint
-    march for all views (gradients for the 256x4 table and all voxels).
-    Targets are seeded random images (timing only; the gradient itself is
-    checked against the oracle and finite differences in the tests)."""
+def _time_gradient_steps(args, dr, tf, vol, cams, targets, bg):
+    """Mean ms of a forward pass (no grad) and of a gradient step."""
     import torch
-
-    import paper_2501_01628_amd as dp
-    import synth
-    sc = synth.config_c4()
-    cams = sc.extra["cameras"]
-    n = sc.field.shape[0]
-    dr = dp.DiffRenderer((n, n, n), [((0, 0, 0), (n, n, n))], (0.0, 1.0), 1.0, sc.step, 64)
-    tf = torch.tensor(synth.default_tf(), device="cuda", requires_grad=True)
-    vol = torch.tensor(sc.field, device="cuda", requires_grad=True)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(0)
-    w, h = cams[0]["width"], cams[0]["height"]
-    targets = [torch.rand((h, w, 4), device="cuda", generator=g) for _ in cams]
-    bg = (0.1, 0.2, 0.3, 1.0)
 
     def forward():
         tot = torch.zeros((), device="cuda")
@@ -377,6 +358,7 @@ def bench_adjoint(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log("warmup done")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
     for _ in range(args.steps):
@@ -388,16 +370,58 @@ def bench_adjoint(args):
         step()
     ev[3].record()
     torch.cuda.synchronize()
-    fwd_ms = ev[0].elapsed_time(ev[1]) / args.steps
-    step_ms = ev[2].elapsed_time(ev[3]) / args.steps
+    return ev[0].elapsed_time(ev[1]) / args.steps, ev[2].elapsed_time(ev[3]) / args.steps
+
+
+def bench_adjoint(args):
+    """Differentiable workloads.  c4: 128^3 float32 volume, 8 views at
+    512x512, step 0.5.  c5-adjoint: the c5 volume (2048x1024x1024, 64 float16
+    bricks, step 0.25) seen through the central 512x512 crop of its 3840x2160
+    view (same pixel rays: the crop camera narrows the field of view).  One
+    gradient step = forward with transmittance checkpoints every 64 samples
+    + L2 loss against fixed targets + composite backward + adjoint march
+    (gradients for the 256x4 table and all voxels).  Targets are seeded random
+    images (timing only; the gradient itself is checked against the oracle
+    and finite differences in the tests)."""
+    import math
+
+    import torch
+
+    import paper_2501_01628_amd as dp
+    import synth
+    if args.workload == "c4":
+        sc = synth.config_c4()
+        cams = sc.extra["cameras"]
+        n = sc.field.shape[0]
+        dims, boxes, storage = (n, n, n), [((0, 0, 0), (n, n, n))], dp.VR_F32
+        desc = ("c4: 128^3 f32 volume (8 blobs), 8 views at 512x512, step 0.5, 64-sample "
+                "checkpoints, L2 loss, gradients for the 256x4 TF and all voxels")
+    else:
+        sc = synth.config_c5(log=lambda m: log(f"c5 generation: {m}"))
+        cam = dict(sc.camera)
+        crop = 512
+        half = math.tan(math.radians(cam["fovy_deg"]) / 2.0) * crop / cam["height"]
+        cam.update(width=crop, height=crop, fovy_deg=math.degrees(2.0 * math.atan(half)))
+        cams = [cam]
+        dims = sc.dims
+        boxes = [(b.lo, b.hi) for b in sc.bricks]
+        storage = dp.VR_F16
+        desc = ("c5-adjoint: 2048x1024x1024 field in 64 f16 bricks, central 512x512 crop of the "
+                "3840x2160 view, step 0.25, 64-sample checkpoints, L2 loss, gradients for the "
+                "256x4 TF and all voxels")
+    dr = dp.DiffRenderer(dims, boxes, sc.vrange, sc.opacity_scale, sc.step, 64, storage=storage)
+    tf = torch.tensor(synth.default_tf(), device="cuda", requires_grad=True)
+    vol = torch.tensor(sc.field, device="cuda", requires_grad=True)
+    log(f"volume on the device: {tuple(vol.shape)}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    targets = [torch.rand((c["height"], c["width"], 4), device="cuda", generator=g) for c in cams]
+    fwd_ms, step_ms = _time_gradient_steps(args, dr, tf, vol, cams, targets, (0.1, 0.2, 0.3, 1.0))
     dr.close()
-    out = {"metric": "ms per gradient step (8-view forward with checkpoints + backward)",
+    out = {"metric": f"ms per gradient step ({len(cams)}-view forward with checkpoints + backward)",
            "value": step_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": step_ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "c4: 128^3 f32 volume (8 blobs), 8 views at 512x512, step 0.5, "
-                                  "64-sample checkpoints, L2 loss, gradients for the 256x4 TF and "
-                                  "all voxels"},
+           "dtype": "f32", "data": "synthetic", "config": {"workload": desc},
            "forward_ms": fwd_ms, "backward_ms": step_ms - fwd_ms,
            "views_per_s": len(cams) * 1e3 / step_ms}
     print(json.dumps(out), flush=True)
@@ -416,7 +440,7 @@ def main():
         return summarize_sq(args)
     if args.workload == "c3":
         return bench_batch(args)
-    if args.workload == "c4":
+    if args.workload in ("c4", "c5-adjoint"):
         return bench_adjoint(args)
     import torch
 
