@@ -16,7 +16,8 @@
 // table gradients are accumulated per workgroup in LDS (ds_add_f32) and
 // flushed with one global atomic per touched entry; voxel gradients are
 // scattered with the 8 trilinear weights to the global voxels that the stored
-// (ghost-padded) voxels copy, so ghost contributions fold back to their source.
+// (ghost-padded) voxels copy, so ghost contributions fold back to their source
+// (summed per lane while consecutive samples stay in one cell, then 8 atomics).
 #include "march_common.h"
 
 namespace dpvr {
@@ -81,6 +82,32 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
             const Cell c = locate(an, st, (float)(k - kA), snx, sny, snz);
             return c;
         };
+        // voxel-gradient contributions of the current cell, not yet added
+        int pend_key = -1, pend_ix = 0, pend_iy = 0, pend_iz = 0;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        auto flush = [&]() {
+            if (pend_key < 0) return;
+            // stored index s -> global index clamp(lo + s - ghost)
+            const long long gx0 = min(max((long long)bp.lo[0] + pend_ix - b.ghost, 0LL), gnx - 1);
+            const long long gx1 = min(max((long long)bp.lo[0] + pend_ix + 1 - b.ghost, 0LL), gnx - 1);
+            const long long gy0 = min(max((long long)bp.lo[1] + pend_iy - b.ghost, 0LL), gny - 1);
+            const long long gy1 = min(max((long long)bp.lo[1] + pend_iy + 1 - b.ghost, 0LL), gny - 1);
+            const long long gz0 = min(max((long long)bp.lo[2] + pend_iz - b.ghost, 0LL), gnz - 1);
+            const long long gz1 = min(max((long long)bp.lo[2] + pend_iz + 1 - b.ghost, 0LL), gnz - 1);
+            float* G = bp.grad_vox;
+            const long long r00 = (gz0 * gny + gy0) * gnx, r10 = (gz0 * gny + gy1) * gnx;
+            const long long r01 = (gz1 * gny + gy0) * gnx, r11 = (gz1 * gny + gy1) * gnx;
+            atomicAdd(G + r00 + gx0, acc[0]);
+            atomicAdd(G + r00 + gx1, acc[1]);
+            atomicAdd(G + r10 + gx0, acc[2]);
+            atomicAdd(G + r10 + gx1, acc[3]);
+            atomicAdd(G + r01 + gx0, acc[4]);
+            atomicAdd(G + r01 + gx1, acc[5]);
+            atomicAdd(G + r11 + gx0, acc[6]);
+            atomicAdd(G + r11 + gx1, acc[7]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+        };
         for (int s = nseg - 1; s >= 0; --s) {
             const long long k0 = rs.kf + (long long)s * I;
             const int n = (int)min((long long)I, rs.kl - k0 + 1);
@@ -120,25 +147,23 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
                     const float4 D = tft.diff[e.seg];
                     const float dv = tf_k * (d_r * D.x + d_g * D.y + d_b * D.z + d_ap * D.w);
                     if (dv != 0.0f) {
-                        // stored index s -> global index clamp(lo + s - ghost)
-                        const long long gx0 = min(max((long long)bp.lo[0] + c.ix - b.ghost, 0LL), gnx - 1);
-                        const long long gx1 = min(max((long long)bp.lo[0] + c.ix + 1 - b.ghost, 0LL), gnx - 1);
-                        const long long gy0 = min(max((long long)bp.lo[1] + c.iy - b.ghost, 0LL), gny - 1);
-                        const long long gy1 = min(max((long long)bp.lo[1] + c.iy + 1 - b.ghost, 0LL), gny - 1);
-                        const long long gz0 = min(max((long long)bp.lo[2] + c.iz - b.ghost, 0LL), gnz - 1);
-                        const long long gz1 = min(max((long long)bp.lo[2] + c.iz + 1 - b.ghost, 0LL), gnz - 1);
+                        // consecutive samples mostly share a cell: sum their
+                        // corner weights here, one set of atomics per cell
+                        const int key = (c.iz * sny + c.iy) * snx + c.ix;
+                        if (key != pend_key) {
+                            flush();
+                            pend_key = key;
+                            pend_ix = c.ix; pend_iy = c.iy; pend_iz = c.iz;
+                        }
                         const float ux = 1.0f - c.fx, uy = 1.0f - c.fy, uz = 1.0f - c.fz;
-                        float* G = bp.grad_vox;
-                        const long long r00 = (gz0 * gny + gy0) * gnx, r10 = (gz0 * gny + gy1) * gnx;
-                        const long long r01 = (gz1 * gny + gy0) * gnx, r11 = (gz1 * gny + gy1) * gnx;
-                        atomicAdd(G + r00 + gx0, dv * ux * uy * uz);
-                        atomicAdd(G + r00 + gx1, dv * c.fx * uy * uz);
-                        atomicAdd(G + r10 + gx0, dv * ux * c.fy * uz);
-                        atomicAdd(G + r10 + gx1, dv * c.fx * c.fy * uz);
-                        atomicAdd(G + r01 + gx0, dv * ux * uy * c.fz);
-                        atomicAdd(G + r01 + gx1, dv * c.fx * uy * c.fz);
-                        atomicAdd(G + r11 + gx0, dv * ux * c.fy * c.fz);
-                        atomicAdd(G + r11 + gx1, dv * c.fx * c.fy * c.fz);
+                        acc[0] += dv * ux * uy * uz;
+                        acc[1] += dv * c.fx * uy * uz;
+                        acc[2] += dv * ux * c.fy * uz;
+                        acc[3] += dv * c.fx * c.fy * uz;
+                        acc[4] += dv * ux * uy * c.fz;
+                        acc[5] += dv * c.fx * uy * c.fz;
+                        acc[6] += dv * ux * c.fy * c.fz;
+                        acc[7] += dv * c.fx * c.fy * c.fz;
                     }
                 }
                 R0 = fmaf(al, e.r, om * R0);
@@ -147,6 +172,7 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
                 Q = om * Q;
             }
         }
+        flush();
     }
     __syncthreads();
     for (int e = lane; e < 1024; e += 64) {
