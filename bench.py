@@ -233,7 +233,7 @@ def cpu_baseline(sc, target_s, frame=None):
     t, _, _, _ = run(20000)
     npix = int(min(W * H, max(20000, 20000 * target_s / max(t, 1e-3))))
     t, samples, pix, img = run(npix)
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    cores = oracle.threads()
     out = {"value": samples / t / 1e6, "unit": "Msamples/s", "cores": cores, "kind": "oracle",
            "sample": f"{npix} random pixels of the same frame, all {len(sc.bricks)} bricks + "
                      f"composite, {samples} samples (no early termination) in {t:.1f} s"}

@@ -85,6 +85,7 @@ def _load():
             lib.oc_render_brick_grad.argtypes = [C.POINTER(_Camera), C.POINTER(_Brick),
                                                  C.POINTER(_TF), C.c_double, _dp, _dp, _dp]
             lib.oc_render_brick_grad.restype = C.c_int
+            lib.oc_threads.restype = C.c_int
             _lib = lib
     return _lib
 
@@ -138,6 +139,11 @@ class _TFRef:
         s.vmin, s.vmax = float(vrange[0]), float(vrange[1])
         s.opacity_scale = float(opacity_scale)
         self.s = s
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().oc_threads())
 
 
 def ray(cam: dict, i: int, j: int):

@@ -42,6 +42,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t kind;          /* 0 = perspective, 1 = orthographic */
@@ -464,4 +467,13 @@ int oc_render_brick_grad(const oc_camera* cam, const oc_brick* b, const oc_tf* t
         free(smp);
     }
     return status;
+}
+
+/* Threads the parallel loops above use (reported with timings). */
+int oc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
