@@ -219,6 +219,61 @@ def test_axis_orientation_in_image():
     np.testing.assert_allclose(a[0], a[1], rtol=0, atol=0)
 
 
+def _ortho_ramp(axis, n_axis, eye, up, width, height, view_height, scale, dt):
+    """Alpha of every pixel of an orthographic view down -z through an
+    n_axis x n_axis x 4 field that is a linear ramp along `axis` (x or y;
+    voxel i holds (i + 1/2) / n_axis, so the trilinear interpolant is
+    v = position / n_axis away from the edges), with the identity alpha
+    table a = v.  Returns (alpha image, lattice count
+    m of the 4-voxel thick slab)."""
+    nx, ny, nz = n_axis, n_axis, 4
+    vol = np.empty((nz, ny, nx), dtype=np.float32)
+    idx = np.indices((nz, ny, nx))[2 - axis]
+    vol[:] = ((idx + 0.5) / n_axis).astype(np.float32)
+    tf = _ramp_tf()
+    cam = dict(kind="ortho", eye=eye, dir=(0.0, 0.0, -1.0), up=up, width=width, height=height,
+               view_height=view_height)
+    rgba, _, cnt = oracle.render_brick(cam, vol, (nx, ny, nz), 0, (0, 0, 0), (1, 1, 1), tf,
+                                       (0, 1), scale, dt)
+    # rays start at z = eye_z = 10 and cross z in [0, 4): t in (6, 10]
+    m = _slab_count(-eye[2], -4.0, 0.0, dt)
+    assert cnt[0] == m * width * height
+    return rgba[..., 3], m
+
+
+def test_orthographic_pixel_mapping():
+    """Orthographic pixel centres at hand-computed world positions.  Image
+    10 x 4 pixels, 2 world units tall, centred at (8, 2): the pixel pitch is
+    2 / 4 = 0.5 in both directions, so the columns sit at x = 8 + 0.5 (i - 4.5)
+    = 5.75, 6.25, ..., 10.25 and the rows (row 0 on top, up = +y) at
+    y = 2 + 0.5 (1.5 - j) = 2.75, 2.25, 1.75, 1.25.  A ramp along x (then
+    along y) turns each pixel's alpha into the coordinate its ray travels
+    at: v = -ln(1 - A) / (scale m dt) = coordinate / 16."""
+    scale, dt = 1.0, 0.5
+    cols = np.array([5.75, 6.25, 6.75, 7.25, 7.75, 8.25, 8.75, 9.25, 9.75, 10.25])
+    rows = np.array([2.75, 2.25, 1.75, 1.25])
+    a, m = _ortho_ramp(0, 16, (8.0, 2.0, 10.0), (0.0, 1.0, 0.0), 10, 4, 2.0, scale, dt)
+    assert m == 8
+    v = -np.log1p(-a) / (scale * m * dt)
+    np.testing.assert_allclose(v, np.broadcast_to(cols / 16.0, v.shape), rtol=0, atol=1e-12)
+    # ramp along y, the image centred at (8, 8): rows at y = 8 + 0.5 (1.5 - j)
+    a, m = _ortho_ramp(1, 16, (8.0, 8.0, 10.0), (0.0, 1.0, 0.0), 10, 4, 2.0, scale, dt)
+    v = -np.log1p(-a) / (scale * m * dt)
+    np.testing.assert_allclose(v, np.broadcast_to(((rows + 6.0) / 16.0)[:, None], v.shape),
+                               rtol=0, atol=1e-12)
+    # a tall image (3 x 10, 5 units tall): pitch 0.5, columns at x = 7.5, 8, 8.5,
+    # rows at y = 10.25 - 0.5 j
+    a, m = _ortho_ramp(0, 16, (8.0, 8.0, 10.0), (0.0, 1.0, 0.0), 3, 10, 5.0, scale, dt)
+    v = -np.log1p(-a) / (scale * m * dt)
+    np.testing.assert_allclose(v, np.broadcast_to(np.array([7.5, 8.0, 8.5]) / 16.0, v.shape),
+                               rtol=0, atol=1e-12)
+    a, m = _ortho_ramp(1, 16, (8.0, 8.0, 10.0), (0.0, 1.0, 0.0), 3, 10, 5.0, scale, dt)
+    v = -np.log1p(-a) / (scale * m * dt)
+    ys = 10.25 - 0.5 * np.arange(10)
+    np.testing.assert_allclose(v, np.broadcast_to((ys / 16.0)[:, None], v.shape), rtol=0,
+                               atol=1e-12)
+
+
 def test_camera_matches_projection_matrix():
     """Camera pin: project points along the oracle's pixel rays with an
     independent look-at + perspective matrix (OpenGL convention) and recover
@@ -336,8 +391,29 @@ def test_ert_counter_and_bound():
     rgba, _, cnt = oracle.render_brick(cam, field, dims, 0, (0, 0, 0), (1, 1, 1), tf, (0, 1), 30.0,
                                        0.5, eps)
     assert cnt[1] < cnt[0]     # some rays saturate at this opacity scale
-    # emulate the stop on the recorded transmittance: the remainder is <= T_stop
     assert np.all(rgba[..., 3] <= 1.0) and np.all(rgba >= 0)
+
+
+@pytest.mark.parametrize("sigma,dt,eps", [(0.8, 0.5, 2.0 ** -20), (0.3, 0.25, 1e-3),
+                                          (2.5, 0.5, 2.0 ** -20), (0.01, 0.5, 2.0 ** -20)])
+def test_ert_stop_index_closed_form(sigma, dt, eps):
+    """Constant slab: after n samples T = exp(-sigma n dt), so a renderer that
+    stops once T < eps evaluates n* = floor(ln(1/eps) / (sigma dt)) + 1
+    samples (the stopping one included), or all m owned samples if T never
+    drops below eps."""
+    vol = np.full((32, 2, 2), 0.5, dtype=np.float32)
+    tf = np.zeros((256, 4)); tf[:] = (1.0, 1.0, 1.0, sigma)
+    cam = dict(kind="ortho", eye=(1.0, 1.0, -0.3), dir=(0, 0, 1.0), up=(0, 1.0, 0), width=2,
+               height=2, view_height=1.0)
+    rgba, _, cnt = oracle.render_brick(cam, vol, (2, 2, 32), 0, (0, 0, 0), (1, 1, 1), tf, (0, 1),
+                                       1.0, dt, eps)
+    m = _slab_count(-0.3, 0.0, 32.0, dt)
+    x = math.log(1.0 / eps) / (sigma * dt)
+    assert abs(x - round(x)) > 1e-6          # no tie at the threshold
+    n_stop = min(math.floor(x) + 1, m)
+    assert cnt[0] == 4 * m
+    assert cnt[1] == 4 * n_stop
+    np.testing.assert_allclose(rgba[..., 3], 1.0 - math.exp(-sigma * m * dt), rtol=1e-12)
 
 
 # ------------------------------------------------------------- brute force
