@@ -41,7 +41,9 @@ def _small_case(seed=31, dims=(24, 20, 16), nb=3, w=40, h=32, views=2, scale=3.0
     return field, boxes, cams, tf, targets, scale
 
 
-def _oracle_grads(field, boxes, cams, tf, targets, scale, dt=0.5):
+def _oracle_grads(field, boxes, cams, tf, targets, scale, dt=0.5, storage=0):
+    if storage == 1:      # float16 storage: the oracle sees the decoded voxels
+        field = field.astype(np.float16).astype(np.float32)
     gtf = np.zeros((256, 4))
     gvol = np.zeros(field.shape)
     L = 0.0
@@ -63,9 +65,9 @@ def _oracle_grads(field, boxes, cams, tf, targets, scale, dt=0.5):
     return L, gtf, gvol
 
 
-def _gpu_grads(dp, field, boxes, cams, tf, targets, scale, interval=64, dt=0.5):
+def _gpu_grads(dp, field, boxes, cams, tf, targets, scale, interval=64, dt=0.5, storage=0):
     nx, ny, nz = field.shape[2], field.shape[1], field.shape[0]
-    dr = dp.DiffRenderer((nx, ny, nz), boxes, (0.0, 1.0), scale, dt, interval)
+    dr = dp.DiffRenderer((nx, ny, nz), boxes, (0.0, 1.0), scale, dt, interval, storage=storage)
     tft = torch.tensor(tf, dtype=torch.float32, device="cuda", requires_grad=True)
     vol = torch.tensor(field, dtype=torch.float32, device="cuda", requires_grad=True)
     L = 0.0
@@ -83,16 +85,50 @@ def _gpu_grads(dp, field, boxes, cams, tf, targets, scale, interval=64, dt=0.5):
     return out
 
 
-def test_gradients_match_oracle(dp):
+@pytest.mark.parametrize("storage", [0, 1], ids=["f32", "f16"])
+def test_gradients_match_oracle(dp, storage):
+    """float32 storage, and float16 storage against the oracle on the decoded
+    field (the gradient is taken with respect to the stored values)."""
     case = _small_case()
-    L_ref, gtf_ref, gvol_ref = _oracle_grads(*case)
-    L, gtf, gvol, _ = _gpu_grads(dp, *case)
+    L_ref, gtf_ref, gvol_ref = _oracle_grads(*case, storage=storage)
+    L, gtf, gvol, _ = _gpu_grads(dp, *case, storage=storage)
     assert abs(L - L_ref) <= 1e-5 * abs(L_ref) + 1e-6
     for got, ref in ((gtf, gtf_ref), (gvol, gvol_ref)):
         scale = np.max(np.abs(ref))
         assert scale > 0
         err = np.max(np.abs(got - ref))
         assert err <= 1e-4 * scale, (err, scale)
+
+
+def test_f16_table_gradient_central_differences(dp):
+    """float16 storage: table gradients against central differences of the
+    GPU loss (the table stays float32, so a perturbation of it is exact)."""
+    field, boxes, cams, tf, targets, scale = _small_case(seed=34)
+    nx, ny, nz = field.shape[2], field.shape[1], field.shape[0]
+    dr = dp.DiffRenderer((nx, ny, nz), boxes, (0.0, 1.0), scale, 0.5, 64, storage=1)
+    tft = torch.tensor(tf, dtype=torch.float32, device="cuda", requires_grad=True)
+    vol = torch.tensor(field, dtype=torch.float32, device="cuda")
+    tg = [torch.tensor(t, device="cuda") for t in targets]
+
+    def loss_of(t_):
+        tot = torch.zeros((), dtype=torch.float64, device="cuda")
+        for cam, tgt in zip(cams, tg):
+            tot = tot + ((dr.render(t_, vol, cam, BG).double() - tgt) ** 2).sum()
+        return tot
+
+    loss_of(tft).backward()
+    g = tft.grad.double().cpu().numpy()
+    cand = np.flatnonzero(np.abs(g).reshape(-1) > 1e-2 * np.abs(g).max())
+    h = 1e-3
+    with torch.no_grad():
+        for idx in np.random.default_rng(35).choice(cand, 8, replace=False):
+            e, c = divmod(int(idx), 4)
+            tp, tm = tft.detach().clone(), tft.detach().clone()
+            tp[e, c] += h
+            tm[e, c] -= h
+            fd = (float(loss_of(tp)) - float(loss_of(tm))) / (2 * h)
+            assert abs(fd - g[e, c]) <= 1e-2 * abs(fd) + 1e-3 * np.abs(g).max(), (e, c, fd, g[e, c])
+    dr.close()
 
 
 def test_checkpoint_interval_invariance(dp):
