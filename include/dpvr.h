@@ -18,7 +18,9 @@
  *   - Device memory is always owned by the caller.  The library allocates no
  *     device memory: bricks live in caller-provided workspaces, partial and
  *     final images in caller-provided buffers.  Pointers are borrowed for the
- *     duration of the work the call enqueues.
+ *     duration of the work the call enqueues.  (One exception:
+ *     vr_render_partials_static keeps its tables in a small static device
+ *     array of the library.)
  *   - Work is enqueued asynchronously on the context's HIP stream; nothing
  *     returns to the host until the caller synchronises (vr_synchronize or
  *     its own stream/device synchronisation).
@@ -253,6 +255,25 @@ vr_status vr_frame_workspace_size(int32_t n, size_t* bytes);
  * work has run.  Errors: as vr_render_partial, and VR_ERR_WORKSPACE. */
 vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
                              const vr_partial* parts, void* workspace, size_t workspace_bytes);
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc -- and so
+ * cannot provide vr_render_partials' workspace: the same call (same results,
+ * bit for bit) with the job table, tile prefix and work-queue counters kept
+ * in a fixed device array the library owns (about 26 KB, one copy per GPU,
+ * held until the process ends; its address is taken once per context at
+ * vr_context_create, which also allocates two pinned host staging buffers of
+ * the same size).  This call allocates nothing: the tables are staged through the
+ * context's pinned buffers and copied into the array on the context stream.
+ * n <= DPVR_STATIC_MAX_PARTIALS (VR_ERR_INVALID_ARG otherwise).  Every call on
+ * one GPU, from any context, uses the same array: calls whose work overlaps
+ * on one GPU (different streams, or several contexts) race and give wrong
+ * images; calls ordered on one stream are safe.  The host may block until
+ * the table copy of the call before the previous one has run.
+ * Errors: as vr_render_partials (except VR_ERR_WORKSPACE). */
+#define DPVR_STATIC_MAX_PARTIALS 64
+vr_status vr_render_partials_static(vr_context ctx, int32_t n, const vr_brick* bricks,
+                                    const vr_partial* parts);
 
 /* Sort-last composite (paper Sec. 3: the framebuffer ends up on the main
  * rank): for every pixel of the frame, the n partials (0 <= n <=

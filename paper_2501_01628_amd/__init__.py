@@ -39,6 +39,7 @@ VR_F32, VR_F16 = 0, 1
 VR_PATH_STAGED, VR_PATH_DIRECT = 0, 1
 TF_ENTRIES = 256
 MAX_PARTIALS = 64
+STATIC_MAX_PARTIALS = 64
 
 
 class vr_partial(C.Structure):
@@ -108,6 +109,8 @@ _SIGS = {
     "vr_batch_release": ([C.c_void_p], _st),
     "vr_render_partials": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_partial),
                             C.c_void_p, C.c_size_t], _st),
+    "vr_render_partials_static": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
+                                   C.POINTER(vr_partial)], _st),
     "vr_checkpoint_size": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
                             C.POINTER(C.c_size_t)], _st),
     "vr_render_partial_checkpointed": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
@@ -262,6 +265,13 @@ def vr_render_partials(ctx, bricks, parts, workspace, workspace_bytes):
     hb = (C.c_void_p * max(n, 1))(*bricks)
     hp = (vr_partial * max(n, 1))(*parts)
     _check(_lib.vr_render_partials(ctx, n, hb, hp, _ptr(workspace), int(workspace_bytes)), ctx)
+
+
+def vr_render_partials_static(ctx, bricks, parts):
+    n = len(bricks)
+    hb = (C.c_void_p * max(n, 1))(*bricks)
+    hp = (vr_partial * max(n, 1))(*parts)
+    _check(_lib.vr_render_partials_static(ctx, n, hb, hp), ctx)
 
 
 def camera_desc(cam: dict) -> vr_camera_desc:

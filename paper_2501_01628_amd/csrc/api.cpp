@@ -34,6 +34,14 @@ struct vr_context_s {
     int32_t path = kPathStaged;
     int32_t live_bricks = 0;
     std::string err;
+    // vr_render_partials_static: this device's library-owned scratch array
+    // (address from hipGetSymbolAddress at context creation) and two pinned
+    // host staging slots for its job table, each guarded by an event that
+    // completes when the copy out of it has run
+    void* scratch = nullptr;
+    void* pinned[2] = {nullptr, nullptr};
+    hipEvent_t pinned_done[2] = {nullptr, nullptr};
+    int32_t pinned_next = 0;
 };
 
 struct vr_brick_s {
@@ -132,6 +140,22 @@ vr_status make_frame(vr_context ctx, const double fwd[3], const double up[3], Ca
     return VR_OK;
 }
 
+// Pinned staging of vr_render_partials_static (waits for copies still
+// reading it).
+void release_static_staging(vr_context c) {
+    for (int i = 0; i < 2; ++i) {
+        if (c->pinned_done[i]) {
+            (void)hipEventSynchronize(c->pinned_done[i]);
+            (void)hipEventDestroy(c->pinned_done[i]);
+            c->pinned_done[i] = nullptr;
+        }
+        if (c->pinned[i]) {
+            (void)hipHostFree(c->pinned[i]);
+            c->pinned[i] = nullptr;
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,6 +198,23 @@ vr_status vr_context_create(int32_t device, void* stream, vr_context* out) {
     c->cus = cus;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     {
+        // set-up of vr_render_partials_static, with the context's device current
+        DeviceGuard g(device);
+        hipError_t e = g.ok ? hipSuccess : hipErrorInvalidDevice;
+        if (e == hipSuccess) e = static_scratch_address(&c->scratch);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+            e = hipHostMalloc(&c->pinned[i], kStaticScratchBytes, hipHostMallocDefault);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->pinned_done[i], hipEventDisableTiming);
+        }
+        if (e == hipSuccess && !c->scratch) e = hipErrorInvalidSymbol;
+        if (e != hipSuccess) {
+            release_static_staging(c);
+            delete c;
+            return fail(nullptr, VR_ERR_DEVICE, "vr_context_create: static scratch set-up on device %d: %s",
+                        device, hipGetErrorString(e));
+        }
+    }
+    {
         std::lock_guard<std::mutex> lk(g_mu);
         g_live.insert(c);
     }
@@ -188,6 +229,10 @@ vr_status vr_context_release(vr_context ctx) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_live.erase(ctx);
+    }
+    {
+        DeviceGuard g(ctx->device);
+        release_static_staging(ctx);
     }
     delete ctx;
     return VR_OK;
@@ -558,22 +603,15 @@ static int queue_workgroups(vr_context ctx, StorageK st, bool staged) {
     return n;
 }
 
-vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
-                             const vr_partial* parts, void* workspace, size_t workspace_bytes) {
-    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_render_partials: invalid context");
-    if (n < 0 || (n > 0 && (!bricks || !parts)))
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_render_partials: bad n or NULL arrays");
-    if (n == 0) return ok(ctx);
-    size_t off_t = 0, off_j = 0;
-    const size_t need = frame_ws_bytes(n, &off_t, &off_j);
-    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
-        return fail(ctx, VR_ERR_WORKSPACE, "vr_render_partials: workspace of %zu bytes (256-aligned), need %zu",
-                    workspace_bytes, need);
-    // job table grouped by storage precision (float32 jobs first): each group
-    // is one queue with its own exclusive tile prefix and counter
-    std::vector<MarchParams> jobs;
+// Job table and tile prefix of a frame of n partials, grouped by storage
+// precision (float32 jobs first): each group is one queue with its own
+// exclusive tile prefix (prefix[0 .. n32] and prefix[n32 + 1 .. n + 1]).
+static vr_status frame_tables(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_partial* parts,
+                              const char* who, std::vector<MarchParams>& jobs, std::vector<int32_t>& prefix,
+                              int* n32_out) {
+    jobs.clear();
     jobs.reserve(n);
-    std::vector<int32_t> prefix(n + 2, 0);
+    prefix.assign(n + 2, 0);
     int n32 = 0;
     for (int pass = 0; pass < 2; ++pass) {
         int32_t acc = 0;
@@ -581,10 +619,10 @@ vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
         int cnt = 0;
         for (int i = 0; i < n; ++i) {
             if (!live(bricks[i]) || bricks[i]->ctx != ctx)
-                return fail(ctx, VR_ERR_INVALID_HANDLE, "vr_render_partials: invalid brick %d", i);
+                return fail(ctx, VR_ERR_INVALID_HANDLE, "%s: invalid brick %d", who, i);
             if ((bricks[i]->storage == VR_F16) != (pass == 1)) continue;
             MarchParams p;
-            vr_status st = prepare_march(ctx, bricks[i], &parts[i], "vr_render_partials", p);
+            vr_status st = prepare_march(ctx, bricks[i], &parts[i], who, p);
             if (st != VR_OK) return st;
             p.tiles_x = (parts[i].w + 15) / 16;
             p.tiles_y = (parts[i].h + 15) / 16;
@@ -596,6 +634,46 @@ vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
         prefix[base + cnt] = acc;
         if (pass == 0) n32 = cnt;
     }
+    *n32_out = n32;
+    return VR_OK;
+}
+
+// The frame's queue launches over tables already in (or enqueued into)
+// device memory at ws (frame workspace layout).
+static hipError_t launch_frame(vr_context ctx, char* ws, size_t off_t, size_t off_j, int32_t n, int n32,
+                               const std::vector<int32_t>& prefix) {
+    const MarchParams* djobs = reinterpret_cast<const MarchParams*>(ws + off_j);
+    const int32_t* dtiles = reinterpret_cast<const int32_t*>(ws + off_t);
+    int32_t* heads = reinterpret_cast<int32_t*>(ws);
+    const int staged = ctx->path == kPathDirect ? 0 : 1;
+    hipError_t e = hipSuccess;
+    if (n32 > 0) {
+        QueueParams q{djobs, dtiles, n32, prefix[n32], heads, staged};
+        e = launch_march_queue(q, kF32, queue_workgroups(ctx, kF32, staged), ctx->stream);
+    }
+    if (e == hipSuccess && n - n32 > 0) {
+        QueueParams q{djobs + n32, dtiles + n32 + 1, n - n32, prefix[n + 1], heads + kQueueParts, staged};
+        e = launch_march_queue(q, kF16, queue_workgroups(ctx, kF16, staged), ctx->stream);
+    }
+    return e;
+}
+
+vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
+                             const vr_partial* parts, void* workspace, size_t workspace_bytes) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_render_partials: invalid context");
+    if (n < 0 || (n > 0 && (!bricks || !parts)))
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_render_partials: bad n or NULL arrays");
+    if (n == 0) return ok(ctx);
+    size_t off_t = 0, off_j = 0;
+    const size_t need = frame_ws_bytes(n, &off_t, &off_j);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(ctx, VR_ERR_WORKSPACE, "vr_render_partials: workspace of %zu bytes (256-aligned), need %zu",
+                    workspace_bytes, need);
+    std::vector<MarchParams> jobs;
+    std::vector<int32_t> prefix;
+    int n32 = 0;
+    vr_status st = frame_tables(ctx, n, bricks, parts, "vr_render_partials", jobs, prefix, &n32);
+    if (st != VR_OK) return st;
     char* ws = reinterpret_cast<char*>(workspace);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: cannot select device %d", ctx->device);
@@ -605,20 +683,48 @@ vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws + off_j, jobs.data(), (size_t)n * sizeof(MarchParams), hipMemcpyHostToDevice,
                            ctx->stream);
+    if (e == hipSuccess) e = launch_frame(ctx, ws, off_t, off_j, n, n32, prefix);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: %s", hipGetErrorString(e));
-    const MarchParams* djobs = reinterpret_cast<const MarchParams*>(ws + off_j);
-    const int32_t* dtiles = reinterpret_cast<const int32_t*>(ws + off_t);
-    int32_t* heads = reinterpret_cast<int32_t*>(ws);
-    const int staged = ctx->path == kPathDirect ? 0 : 1;
-    if (n32 > 0) {
-        QueueParams q{djobs, dtiles, n32, prefix[n32], heads, staged};
-        e = launch_march_queue(q, kF32, queue_workgroups(ctx, kF32, staged), ctx->stream);
+    return ok(ctx);
+}
+
+vr_status vr_render_partials_static(vr_context ctx, int32_t n, const vr_brick* bricks,
+                                    const vr_partial* parts) {
+    static const char* who = "vr_render_partials_static";
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (n < 0 || (n > 0 && (!bricks || !parts)))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: bad n or NULL arrays", who);
+    if (n > kStaticMaxPartials)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: %d partials exceed the static scratch limit of %d "
+                    "(use vr_render_partials with a workspace)", who, n, kStaticMaxPartials);
+    if (n == 0) return ok(ctx);
+    size_t off_t = 0, off_j = 0;
+    const size_t need = frame_ws_bytes(n, &off_t, &off_j);
+    if (need > kStaticScratchBytes)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: tables of %zu bytes exceed the %zu-byte scratch", who, need,
+                    kStaticScratchBytes);
+    std::vector<MarchParams> jobs;
+    std::vector<int32_t> prefix;
+    int n32 = 0;
+    vr_status st = frame_tables(ctx, n, bricks, parts, who, jobs, prefix, &n32);
+    if (st != VR_OK) return st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+    // stage the tables in the next pinned slot (once the copy that last read
+    // it has run), then one stream-ordered copy into the scratch array
+    const int slot = ctx->pinned_next;
+    ctx->pinned_next ^= 1;
+    hipError_t e = hipEventSynchronize(ctx->pinned_done[slot]);
+    char* host = reinterpret_cast<char*>(ctx->pinned[slot]);
+    if (e == hipSuccess) {
+        std::memcpy(host + off_t, prefix.data(), prefix.size() * sizeof(int32_t));
+        std::memcpy(host + off_j, jobs.data(), (size_t)n * sizeof(MarchParams));
+        e = hipMemcpyAsync(reinterpret_cast<char*>(ctx->scratch) + off_t, host + off_t, need - off_t,
+                           hipMemcpyHostToDevice, ctx->stream);
     }
-    if (e == hipSuccess && n - n32 > 0) {
-        QueueParams q{djobs + n32, dtiles + n32 + 1, n - n32, prefix[n + 1], heads + kQueueParts, staged};
-        e = launch_march_queue(q, kF16, queue_workgroups(ctx, kF16, staged), ctx->stream);
-    }
-    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: %s", hipGetErrorString(e));
+    if (e == hipSuccess) e = hipEventRecord(ctx->pinned_done[slot], ctx->stream);
+    if (e == hipSuccess) e = launch_frame(ctx, reinterpret_cast<char*>(ctx->scratch), off_t, off_j, n, n32, prefix);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
     return ok(ctx);
 }
 

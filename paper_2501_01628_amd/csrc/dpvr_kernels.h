@@ -124,6 +124,17 @@ struct GatherParams {
 
 enum StorageK : int32_t { kF32 = 0, kF16 = 1 };
 
+// Library-owned scratch of vr_render_partials_static (static_scratch.hip):
+// the frame workspace layout of vr_render_partials for up to
+// kStaticMaxPartials partials -- queue counters (256 B), tile prefix
+// (n + 2 int32, 256-aligned), job table (n MarchParams, 256-aligned).
+constexpr int kStaticMaxPartials = 64;
+constexpr size_t kStaticScratchBytes =
+    256 + (((size_t)(kStaticMaxPartials + 2) * sizeof(int32_t) + 255) / 256) * 256 +
+    (((size_t)kStaticMaxPartials * sizeof(MarchParams) + 255) / 256) * 256;
+// Device address of this GPU's scratch array (call with the device current).
+hipError_t static_scratch_address(void** out);
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_ingest(const float* src, void* dst, const int32_t sdim[3], StorageK storage,
                          hipStream_t stream);
