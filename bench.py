@@ -42,7 +42,15 @@ def parse():
     ap.add_argument("--storage", choices=["f32", "f16"], default=None,
                     help="brick storage (default f32; c5 is a float16 workload: f16)")
     ap.add_argument("--path", choices=["staged", "direct"], default="staged",
-                    help="march from LDS-staged slabs or straight from HBM (same images)")
+                    help="march from LDS-staged slices or straight from HBM (same images)")
+    ap.add_argument("--staging", choices=["slab", "ring"], default=None,
+                    help="staged march family: all waves stage a slab then march it, or a producer "
+                         "wave streams slices into an LDS ring ahead of the marching waves "
+                         "(default: the library's choice for the storage, f32 ring, f16 slab)")
+    ap.add_argument("--tile-width", type=int, choices=[16, 32], default=32,
+                    help="staged march: tile width in pixels (tiles are 16 rows high; slab: 16)")
+    ap.add_argument("--chunk", type=int, choices=[4, 8], default=4,
+                    help="staged march: slices per chunk between producer/consumer synchronisations")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -293,9 +301,11 @@ def bench_batch(args):
         torch.cuda.synchronize()
         batch_ms = e0.elapsed_time(e1) / args.steps
         samples = int(br.samples.sum().item()) // args.steps
-        wg, order = br.config()
-        # plain path on the same bricks: per frame, one march launch per brick + a composite
+        wg, order, staging, tile_w, chunk = br.config()
+        # plain path on the same bricks: per frame, one march launch per brick + a composite,
+        # with the launch shape the batch was tuned to
         ctx = br.ctx
+        dp.vr_set_march_config(ctx, st, staging, tile_w, chunk)
         dp.vr_set_transfer_function(ctx, br._tf_keep[0], 256, 0.0, 1.0, d["opacity_scale"])
         frame_parts = []
         fi = 0
@@ -324,6 +334,8 @@ def bench_batch(args):
         plain_ms = e0.elapsed_time(e1) / plain_steps
         results[storage] = {"batch_ms": batch_ms, "plain_ms": plain_ms, "samples": samples,
                             "autotune": {"wg_per_cu": wg, "order": ["as given", "by brick"][order],
+                                         "staging": ["slab", "ring"][staging],
+                                         "tile_width": tile_w, "chunk_slices": chunk,
                                          "tuned_ms": tuned_ms},
                             "msamples_per_s": samples / (batch_ms * 1e-3) / 1e6,
                             "speedup_vs_plain": plain_ms / batch_ms}
@@ -452,9 +464,13 @@ def main():
     sc, desc = scene_for(args.workload)
     log(f"generated {sc.name} in {time.perf_counter() - t0:.1f} s")
     storage = dp.VR_F16 if args.storage == "f16" else dp.VR_F32
+    if args.staging is None:
+        args.staging = "slab" if args.storage == "f16" else "ring"
     r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange, sc.opacity_scale,
                     sc.step, storage=storage, device=0,
-                    path=dp.VR_PATH_DIRECT if args.path == "direct" else dp.VR_PATH_STAGED)
+                    path=dp.VR_PATH_DIRECT if args.path == "direct" else dp.VR_PATH_STAGED,
+                    march_config=(0 if args.staging == "slab" else 1,
+                                  16 if args.staging == "slab" else args.tile_width, args.chunk))
     r.set_camera(sc.camera)
     r.synchronize()
     # drop the float32 upload copies: only the workspaces stay resident
@@ -520,7 +536,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "bricks": nb, "width": W, "height": H,
-                   "storage": args.storage, "step_voxels": sc.step, "path": args.path},
+                   "storage": args.storage, "step_voxels": sc.step, "path": args.path,
+                   "staging": args.staging,
+                   "tile_width": 16 if args.staging == "slab" else args.tile_width,
+                   "chunk_slices": None if args.staging == "slab" else args.chunk},
         "samples_per_frame": samples,
         "march_ms_per_frame": float(march_ms.sum()),
         "composite_ms_per_frame": comp_ms,

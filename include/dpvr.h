@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define DPVR_ABI_VERSION 1
+#define DPVR_ABI_VERSION 2
 #define DPVR_TF_ENTRIES 256          /* transfer-function table size */
 #define DPVR_MAX_PARTIALS 64         /* partials per vr_composite call */
 
@@ -76,7 +76,8 @@ typedef enum {
     VR_ERR_WORKSPACE = -3,       /* caller workspace too small or misaligned */
     VR_ERR_UNSUPPORTED = -4,     /* valid request this build does not implement */
     VR_ERR_DEVICE = -5,          /* HIP runtime error (launch or asynchronous fault) */
-    VR_ERR_STATE = -6            /* required state (camera, transfer function) not set */
+    VR_ERR_STATE = -6,           /* required state (camera, transfer function) not set */
+    VR_ERR_OUT_OF_MEMORY = -7    /* a host (or pinned host) allocation of the library failed */
 } vr_status;
 
 /* Storage precision of a brick's internal copy.  VR_F16 stores IEEE
@@ -127,7 +128,12 @@ vr_status vr_context_release(vr_context ctx);
 vr_status vr_context_set_stream(vr_context ctx, void* stream);
 
 /* Block until all work enqueued on the context's stream has finished and
- * report any asynchronous device error (VR_ERR_DEVICE). */
+ * report any asynchronous device error (VR_ERR_DEVICE).  This includes the
+ * device's error word: the staged march bounds every wait between the
+ * wavefronts of a workgroup, and a wait that times out (which only a logic
+ * error could cause) ends the launch early and sets the word instead of
+ * hanging the GPU; the word is per device, so the next vr_synchronize of any
+ * context on that device reports it (and clears it). */
 vr_status vr_synchronize(vr_context ctx);
 
 /* ---------------------------------------------------------------- bricks */
@@ -222,6 +228,28 @@ vr_status vr_set_render_params(vr_context ctx, double dt, float ert_epsilon);
 typedef enum { VR_PATH_STAGED = 0, VR_PATH_DIRECT = 1 } vr_path;
 vr_status vr_set_march_path(vr_context ctx, vr_path path);
 
+/* Launch shape of the staged path for bricks of one storage precision
+ * (results are bit-identical for every choice).  Two families stage brick
+ * data in LDS:
+ *   VR_STAGING_SLAB  a 16x16-pixel tile per 256-thread workgroup; per slab of
+ *                    16 brick slices every wavefront first stages its share of
+ *                    the slab, then marches (two workgroups per CU overlap);
+ *                    tile_width must be 16, chunk_slices is ignored;
+ *   VR_STAGING_RING  a tile_width x 16 tile (16 or 32) per workgroup with one
+ *                    marching wavefront per 8x8 quarter and one wavefront that
+ *                    streams brick slices into an LDS ring ahead of them
+ *                    (direct LDS loads); chunk_slices = 4 or 8 slices marched
+ *                    between two synchronisations of a wavefront with the
+ *                    streaming wavefront (about 2.9 samples per slice at step
+ *                    0.5 along the slab axis).
+ * Defaults: VR_F32 bricks ring, 32, 4; VR_F16 bricks slab (the fastest
+ * measured for each on a 1920x1080 frame of 16 bricks).  A batch takes the
+ * configuration of the storage most of its jobs use until it is tuned.
+ * Errors: VR_ERR_INVALID_ARG. */
+typedef enum { VR_STAGING_SLAB = 0, VR_STAGING_RING = 1 } vr_staging;
+vr_status vr_set_march_config(vr_context ctx, vr_dtype storage, vr_staging staging, int32_t tile_width,
+                              int32_t chunk_slices);
+
 /* --------------------------------------------------------------- render */
 /* Host-only: the smallest pixel rectangle of the current camera's frame that
  * holds every pixel whose ray can own a sample of `brick` (its owned box
@@ -245,14 +273,18 @@ vr_status vr_render_partial(vr_context ctx, vr_brick brick, const vr_partial* pa
 vr_status vr_frame_workspace_size(int32_t n, size_t* bytes);
 
 /* Render the partial images of n bricks in one persistent launch (per
- * storage precision): the 16x16 tiles of all n ROIs form one device work
+ * storage precision): the tiles (16 rows by 16 or 32 pixels) of all n ROIs form one device work
  * queue, so bricks that are small on screen still fill the GPU.  Results are
  * bit-identical to n calls of vr_render_partial.  bricks and parts are host
  * arrays of n entries; workspace is caller device memory of at least
  * vr_frame_workspace_size(n) bytes, 256-byte aligned, written by this call
- * (the job table is copied from host memory, so the call is not meant for
- * stream capture; the batch API below is) and borrowed until the enqueued
- * work has run.  Errors: as vr_render_partial, and VR_ERR_WORKSPACE. */
+ * and borrowed until the enqueued work has run.  The job table is built on
+ * the host and copied in stream order from one of two pinned host slots the
+ * context owns (the call waits until the copy that used that slot two calls
+ * earlier has run; a slot grows, once, for frames of more than 64 partials),
+ * so the call is not meant for stream capture; the batch API below keeps its
+ * tables resident and is.  Errors: as vr_render_partial, VR_ERR_WORKSPACE,
+ * VR_ERR_OUT_OF_MEMORY. */
 vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
                              const vr_partial* parts, void* workspace, size_t workspace_bytes);
 
@@ -354,18 +386,24 @@ vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_des
  * produce, bit for bit, whatever launch configuration the batch uses. */
 vr_status vr_batch_launch(vr_batch batch);
 
-/* Launch-configuration search: time each candidate configuration (persistent
- * workgroups per CU x job order: as given, or grouped by brick so that the
- * cameras of one brick run together and share L2) over `reps` replays, keep
- * the fastest and report its average time per launch in *best_ms.  When the
+/* Launch-configuration search: time each candidate configuration -- staged
+ * family and tile shape (slab 16x16; ring 16 or 32 pixels wide) x chunk
+ * length (ring: 4 or 8 slices, i.e. the samples a marching wavefront takes
+ * between synchronisations) x job order (as given, or grouped by brick so
+ * that the cameras of one brick run together and share L2) x persistent
+ * workgroups per CU -- over `reps` replays, keep the
+ * fastest and report its average time per launch in *best_ms.  When the
  * environment variable DPVR_AUTOTUNE_CACHE names a file, a configuration
  * found earlier for the same batch shape and device is reused from it (and
  * new results are appended).  Synchronises the context stream. */
 vr_status vr_batch_autotune(vr_batch batch, int32_t reps, double* best_ms);
 
-/* The batch's current configuration: workgroups per CU and job order
- * (0 = as given, 1 = grouped by brick). */
-vr_status vr_batch_config(vr_batch batch, int32_t* wg_per_cu, int32_t* order);
+/* The batch's current configuration: workgroups per CU, job order
+ * (0 = as given, 1 = grouped by brick), staged family (vr_staging), tile
+ * width and chunk length.  Any pointer may be NULL.  A new batch starts with
+ * the context's march configuration and the most workgroups per CU that fit. */
+vr_status vr_batch_config(vr_batch batch, int32_t* wg_per_cu, int32_t* order, int32_t* staging,
+                          int32_t* tile_width, int32_t* chunk_slices);
 
 vr_status vr_batch_release(vr_batch batch);
 

@@ -34,9 +34,10 @@ import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB_PATH)
 
 VR_OK, VR_ERR_INVALID_ARG, VR_ERR_INVALID_HANDLE, VR_ERR_WORKSPACE = 0, -1, -2, -3
-VR_ERR_UNSUPPORTED, VR_ERR_DEVICE, VR_ERR_STATE = -4, -5, -6
+VR_ERR_UNSUPPORTED, VR_ERR_DEVICE, VR_ERR_STATE, VR_ERR_OUT_OF_MEMORY = -4, -5, -6, -7
 VR_F32, VR_F16 = 0, 1
 VR_PATH_STAGED, VR_PATH_DIRECT = 0, 1
+VR_STAGING_SLAB, VR_STAGING_RING = 0, 1
 TF_ENTRIES = 256
 MAX_PARTIALS = 64
 STATIC_MAX_PARTIALS = 64
@@ -105,7 +106,9 @@ _SIGS = {
                          C.POINTER(vr_batch_frame), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)], _st),
     "vr_batch_launch": ([C.c_void_p], _st),
     "vr_batch_autotune": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double)], _st),
-    "vr_batch_config": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], _st),
+    "vr_batch_config": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)], _st),
+    "vr_set_march_config": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32], _st),
     "vr_batch_release": ([C.c_void_p], _st),
     "vr_render_partials": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_partial),
                             C.c_void_p, C.c_size_t], _st),
@@ -254,6 +257,10 @@ def vr_set_march_path(ctx, path):
     _check(_lib.vr_set_march_path(ctx, int(path)), ctx)
 
 
+def vr_set_march_config(ctx, storage, staging, tile_width, chunk_slices=4):
+    _check(_lib.vr_set_march_config(ctx, int(storage), int(staging), int(tile_width), int(chunk_slices)), ctx)
+
+
 def vr_frame_workspace_size(n):
     b = C.c_size_t()
     _check(_lib.vr_frame_workspace_size(int(n), C.byref(b)))
@@ -321,9 +328,10 @@ def vr_batch_autotune(batch, reps=3, ctx=None):
 
 
 def vr_batch_config(batch, ctx=None):
-    w, o = C.c_int32(), C.c_int32()
-    _check(_lib.vr_batch_config(batch, C.byref(w), C.byref(o)), ctx)
-    return w.value, o.value
+    """(workgroups per CU, job order, staging, tile width, chunk slices)."""
+    w, o, g, t, c = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.vr_batch_config(batch, C.byref(w), C.byref(o), C.byref(g), C.byref(t), C.byref(c)), ctx)
+    return w.value, o.value, g.value, t.value, c.value
 
 
 def vr_batch_release(batch):
@@ -379,7 +387,7 @@ class Renderer:
 
     def __init__(self, bricks, tf, vrange=(0.0, 1.0), opacity_scale=1.0, dt=0.5,
                  ert_eps=2.0 ** -20, storage=VR_F32, device=0, stream=None, spacing=(1.0, 1.0, 1.0),
-                 path=VR_PATH_STAGED):
+                 path=VR_PATH_STAGED, march_config=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -391,6 +399,9 @@ class Renderer:
         vr_set_transfer_function(self.ctx, self.tf, TF_ENTRIES, vrange[0], vrange[1], opacity_scale)
         vr_set_render_params(self.ctx, dt, ert_eps)
         vr_set_march_path(self.ctx, path)
+        if march_config is not None:     # (staging, tile_width, chunk_slices) for both storages
+            for st in (VR_F32, VR_F16):
+                vr_set_march_config(self.ctx, st, *march_config)
         for vox, lo in bricks:
             self.add_brick(vox, lo, spacing)
         self._parts = {}

@@ -21,10 +21,21 @@
 
 using namespace dpvr;
 
+// Staged-march launch shape (see vr_set_march_config).
+struct MarchCfg {
+    int32_t staging, tile_w, chunk;
+};
+
 struct vr_context_s {
     int32_t device = 0;
     int32_t cus = 0;               // compute units of the device
-    int32_t queue_wg[2][2] = {{0, 0}, {0, 0}};  // persistent march workgroups [F32/F16][direct/staged], 0 = not yet queried
+    // persistent march workgroups per CU [F32/F16][direct, slab, ring tile 16/32 x chunk 4/8];
+    // 0 = not yet queried
+    int32_t queue_wg[2][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
+    // staged march configuration per storage precision [F32, F16]: the
+    // fastest measured on the 1920x1080 frame of 16 bricks -- float32: ring,
+    // 32-pixel tiles, 4-slice chunks; float16: slab
+    MarchCfg cfg[2] = {{kStagingRing, 32, 4}, {kStagingSlab, 16, 4}};
     hipStream_t stream = nullptr;
     bool has_camera = false, has_tf = false;
     CameraK cam{};
@@ -40,8 +51,14 @@ struct vr_context_s {
     // completes when the copy out of it has run
     void* scratch = nullptr;
     void* pinned[2] = {nullptr, nullptr};
+    size_t pinned_bytes[2] = {0, 0};
     hipEvent_t pinned_done[2] = {nullptr, nullptr};
     int32_t pinned_next = 0;
+    // host copies of the current frame's job table and tile prefix (capacity
+    // for kStaticMaxPartials reserved at creation, so that a frame of at most
+    // that many partials allocates nothing)
+    std::vector<MarchParams> fjobs;
+    std::vector<int32_t> fprefix;
 };
 
 struct vr_brick_s {
@@ -156,6 +173,12 @@ void release_static_staging(vr_context c) {
     }
 }
 
+// Device error word of a context's device: kernels OR error bits into it
+// (the word lives in the library's static scratch array of that device).
+int32_t* err_word(vr_context c) {
+    return reinterpret_cast<int32_t*>(reinterpret_cast<char*>(c->scratch) + kErrWordOffset);
+}
+
 }  // namespace
 
 extern "C" {
@@ -193,7 +216,7 @@ vr_status vr_context_create(int32_t device, void* stream, vr_context* out) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         return fail(nullptr, VR_ERR_DEVICE, "vr_context_create: cannot query device %d", device);
     vr_context c = new (std::nothrow) vr_context_s;
-    if (!c) return fail(nullptr, VR_ERR_INVALID_ARG, "vr_context_create: out of host memory");
+    if (!c) return fail(nullptr, VR_ERR_OUT_OF_MEMORY, "vr_context_create: out of host memory");
     c->device = device;
     c->cus = cus;
     c->stream = reinterpret_cast<hipStream_t>(stream);
@@ -204,7 +227,16 @@ vr_status vr_context_create(int32_t device, void* stream, vr_context* out) {
         if (e == hipSuccess) e = static_scratch_address(&c->scratch);
         for (int i = 0; i < 2 && e == hipSuccess; ++i) {
             e = hipHostMalloc(&c->pinned[i], kStaticScratchBytes, hipHostMallocDefault);
+            if (e == hipSuccess) c->pinned_bytes[i] = kStaticScratchBytes;
             if (e == hipSuccess) e = hipEventCreateWithFlags(&c->pinned_done[i], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) {
+            try {
+                c->fjobs.reserve(kStaticMaxPartials);
+                c->fprefix.reserve(kStaticMaxPartials + 2);
+            } catch (const std::bad_alloc&) {
+                e = hipErrorOutOfMemory;
+            }
         }
         if (e == hipSuccess && !c->scratch) e = hipErrorInvalidSymbol;
         if (e != hipSuccess) {
@@ -214,9 +246,13 @@ vr_status vr_context_create(int32_t device, void* stream, vr_context* out) {
                         device, hipGetErrorString(e));
         }
     }
-    {
+    try {
         std::lock_guard<std::mutex> lk(g_mu);
         g_live.insert(c);
+    } catch (const std::bad_alloc&) {
+        release_static_staging(c);
+        delete c;
+        return fail(nullptr, VR_ERR_OUT_OF_MEMORY, "vr_context_create: out of host memory");
     }
     *out = c;
     return VR_OK;
@@ -251,6 +287,17 @@ vr_status vr_synchronize(vr_context ctx) {
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_synchronize: %s", hipGetErrorString(e));
     e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_synchronize: %s", hipGetErrorString(e));
+    // kernel guards (bounded waits) report through the device error word
+    int32_t word = 0;
+    e = hipMemcpy(&word, err_word(ctx), sizeof word, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_synchronize: %s", hipGetErrorString(e));
+    if (word != 0) {
+        const int32_t zero = 0;
+        (void)hipMemcpy(err_word(ctx), &zero, sizeof zero, hipMemcpyHostToDevice);
+        return fail(ctx, VR_ERR_DEVICE,
+                    "vr_synchronize: a march kernel gave up a bounded wait (device error bits 0x%x); "
+                    "images rendered since the last synchronisation are unreliable", (unsigned)word);
+    }
     return ok(ctx);
 }
 
@@ -292,7 +339,7 @@ vr_status vr_brick_create(vr_context ctx, const int32_t dims[3], int32_t ghost,
         return fail(ctx, VR_ERR_WORKSPACE, "vr_brick_create: workspace holds %zu bytes, need %zu",
                     workspace_bytes, need);
     vr_brick b = new (std::nothrow) vr_brick_s;
-    if (!b) return fail(ctx, VR_ERR_INVALID_ARG, "vr_brick_create: out of host memory");
+    if (!b) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "vr_brick_create: out of host memory");
     b->ctx = ctx;
     for (int c = 0; c < 3; ++c) {
         b->dims[c] = dims[c];
@@ -303,9 +350,12 @@ vr_status vr_brick_create(vr_context ctx, const int32_t dims[3], int32_t ghost,
     b->storage = storage;
     b->ws = workspace;
     b->ws_bytes = workspace_bytes;
-    {
+    try {
         std::lock_guard<std::mutex> lk(g_mu);
         g_live.insert(b);
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "vr_brick_create: out of host memory");
     }
     ctx->live_bricks++;
     *out = b;
@@ -442,6 +492,20 @@ vr_status vr_set_march_path(vr_context ctx, vr_path path) {
     return ok(ctx);
 }
 
+vr_status vr_set_march_config(vr_context ctx, vr_dtype storage, vr_staging staging, int32_t tile_width,
+                              int32_t chunk_slices) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_set_march_config: invalid context");
+    if (storage != VR_F32 && storage != VR_F16)
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_march_config: unknown storage %d", (int)storage);
+    const int st = staging == VR_STAGING_SLAB ? kStagingSlab : kStagingRing;
+    if ((staging != VR_STAGING_SLAB && staging != VR_STAGING_RING) ||
+        !valid_march_config(st, tile_width, st == kStagingSlab ? 4 : chunk_slices))
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_march_config: slab staging takes 16-pixel tiles, ring staging "
+                    "16 or 32 with chunks of 4 or 8 slices (got %d, %d, %d)", (int)staging, tile_width, chunk_slices);
+    ctx->cfg[storage == VR_F16 ? 1 : 0] = MarchCfg{st, tile_width, st == kStagingSlab ? 4 : chunk_slices};
+    return ok(ctx);
+}
+
 // Pixel rectangle of the frame of `cam` whose rays can own samples of brick b:
 // the owned box's corners projected to the image plus one pixel of margin,
 // the whole frame when a corner lies at or behind the eye plane.
@@ -567,6 +631,11 @@ static vr_status prepare_march_with(vr_context ctx, vr_brick b, const vr_partial
     p.out_depth = part->depth;
     p.samples = part->samples;
     p.path = ctx->path;
+    const MarchCfg& mc = ctx->cfg[b->storage == VR_F16 ? 1 : 0];
+    p.staging = mc.staging;
+    p.tile_w = mc.tile_w;
+    p.chunk = mc.chunk;
+    p.err = err_word(ctx);
     return VR_OK;
 }
 
@@ -597,21 +666,33 @@ vr_status vr_frame_workspace_size(int32_t n, size_t* bytes) {
     return VR_OK;
 }
 
-static int queue_workgroups(vr_context ctx, StorageK st, bool staged) {
-    int& n = ctx->queue_wg[st == kF16 ? 1 : 0][staged ? 1 : 0];
-    if (n == 0) n = march_queue_workgroups_per_cu(st, staged) * ctx->cus;
+static int queue_workgroups(vr_context ctx, StorageK st, bool staged, int staging, int tile_w, int chunk) {
+    const int cfg = !staged ? 0 : staging == kStagingSlab ? 1 : 2 + (tile_w == 32 ? 2 : 0) + (chunk == 8 ? 1 : 0);
+    int& n = ctx->queue_wg[st == kF16 ? 1 : 0][cfg];
+    if (n == 0) n = march_queue_workgroups_per_cu(st, staged, staging, tile_w, chunk) * ctx->cus;
     return n;
+}
+
+// Tile width of the frame queue of storage group g (0 float32, 1 float16)
+// with the context's current path.
+static int frame_tile_w(vr_context ctx, int g) {
+    return ctx->path == kPathDirect || ctx->cfg[g].staging == kStagingSlab ? 16 : ctx->cfg[g].tile_w;
 }
 
 // Job table and tile prefix of a frame of n partials, grouped by storage
 // precision (float32 jobs first): each group is one queue with its own
 // exclusive tile prefix (prefix[0 .. n32] and prefix[n32 + 1 .. n + 1]).
 static vr_status frame_tables(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_partial* parts,
-                              const char* who, std::vector<MarchParams>& jobs, std::vector<int32_t>& prefix,
-                              int* n32_out) {
+                              const char* who, int* n32_out) {
+    std::vector<MarchParams>& jobs = ctx->fjobs;
+    std::vector<int32_t>& prefix = ctx->fprefix;
     jobs.clear();
-    jobs.reserve(n);
-    prefix.assign(n + 2, 0);
+    try {
+        jobs.reserve(n);
+        prefix.assign(n + 2, 0);
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory for the tables of %d partials", who, n);
+    }
     int n32 = 0;
     for (int pass = 0; pass < 2; ++pass) {
         int32_t acc = 0;
@@ -624,10 +705,8 @@ static vr_status frame_tables(vr_context ctx, int32_t n, const vr_brick* bricks,
             MarchParams p;
             vr_status st = prepare_march(ctx, bricks[i], &parts[i], who, p);
             if (st != VR_OK) return st;
-            p.tiles_x = (parts[i].w + 15) / 16;
-            p.tiles_y = (parts[i].h + 15) / 16;
             prefix[base + cnt] = acc;
-            acc += staged_tiles(parts[i].w, parts[i].h);
+            acc += queue_tiles(parts[i].w, parts[i].h, frame_tile_w(ctx, pass));
             jobs.push_back(p);
             ++cnt;
         }
@@ -636,6 +715,32 @@ static vr_status frame_tables(vr_context ctx, int32_t n, const vr_brick* bricks,
     }
     *n32_out = n32;
     return VR_OK;
+}
+
+// Stream-ordered copy of the frame tables (ctx->fprefix at off_t, ctx->fjobs
+// at off_j; `need` bytes of frame workspace layout) to device memory at ws,
+// through the next of the context's two pinned host slots (once the copy
+// that last read that slot has run).  A slot smaller than `need` is
+// reallocated, which never happens for kStaticMaxPartials or fewer partials.
+static hipError_t stage_frame_tables(vr_context ctx, char* ws, size_t off_t, size_t off_j, size_t need) {
+    const int slot = ctx->pinned_next;
+    ctx->pinned_next ^= 1;
+    hipError_t e = hipEventSynchronize(ctx->pinned_done[slot]);
+    if (e != hipSuccess) return e;
+    if (ctx->pinned_bytes[slot] < need) {
+        (void)hipHostFree(ctx->pinned[slot]);
+        ctx->pinned[slot] = nullptr;
+        ctx->pinned_bytes[slot] = 0;
+        e = hipHostMalloc(&ctx->pinned[slot], need, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        ctx->pinned_bytes[slot] = need;
+    }
+    char* host = reinterpret_cast<char*>(ctx->pinned[slot]);
+    std::memcpy(host + off_t, ctx->fprefix.data(), ctx->fprefix.size() * sizeof(int32_t));
+    std::memcpy(host + off_j, ctx->fjobs.data(), ctx->fjobs.size() * sizeof(MarchParams));
+    e = hipMemcpyAsync(ws + off_t, host + off_t, need - off_t, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->pinned_done[slot], ctx->stream);
+    return e;
 }
 
 // The frame's queue launches over tables already in (or enqueued into)
@@ -648,12 +753,15 @@ static hipError_t launch_frame(vr_context ctx, char* ws, size_t off_t, size_t of
     const int staged = ctx->path == kPathDirect ? 0 : 1;
     hipError_t e = hipSuccess;
     if (n32 > 0) {
-        QueueParams q{djobs, dtiles, n32, prefix[n32], heads, staged};
-        e = launch_march_queue(q, kF32, queue_workgroups(ctx, kF32, staged), ctx->stream);
+        const int tw = frame_tile_w(ctx, 0), ch = ctx->cfg[0].chunk, sk = ctx->cfg[0].staging;
+        QueueParams q{djobs, dtiles, n32, prefix[n32], heads, staged, sk, tw, ch, err_word(ctx)};
+        e = launch_march_queue(q, kF32, queue_workgroups(ctx, kF32, staged, sk, tw, ch), ctx->stream);
     }
     if (e == hipSuccess && n - n32 > 0) {
-        QueueParams q{djobs + n32, dtiles + n32 + 1, n - n32, prefix[n + 1], heads + kQueueParts, staged};
-        e = launch_march_queue(q, kF16, queue_workgroups(ctx, kF16, staged), ctx->stream);
+        const int tw = frame_tile_w(ctx, 1), ch = ctx->cfg[1].chunk, sk = ctx->cfg[1].staging;
+        QueueParams q{djobs + n32, dtiles + n32 + 1, n - n32, prefix[n + 1], heads + kQueueParts, staged, sk, tw,
+                      ch, err_word(ctx)};
+        e = launch_march_queue(q, kF16, queue_workgroups(ctx, kF16, staged, sk, tw, ch), ctx->stream);
     }
     return e;
 }
@@ -669,21 +777,16 @@ vr_status vr_render_partials(vr_context ctx, int32_t n, const vr_brick* bricks,
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(ctx, VR_ERR_WORKSPACE, "vr_render_partials: workspace of %zu bytes (256-aligned), need %zu",
                     workspace_bytes, need);
-    std::vector<MarchParams> jobs;
-    std::vector<int32_t> prefix;
     int n32 = 0;
-    vr_status st = frame_tables(ctx, n, bricks, parts, "vr_render_partials", jobs, prefix, &n32);
+    vr_status st = frame_tables(ctx, n, bricks, parts, "vr_render_partials", &n32);
     if (st != VR_OK) return st;
     char* ws = reinterpret_cast<char*>(workspace);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: cannot select device %d", ctx->device);
-    // pageable host source: the runtime stages the data before returning
-    hipError_t e = hipMemcpyAsync(ws + off_t, prefix.data(), prefix.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(ws + off_j, jobs.data(), (size_t)n * sizeof(MarchParams), hipMemcpyHostToDevice,
-                           ctx->stream);
-    if (e == hipSuccess) e = launch_frame(ctx, ws, off_t, off_j, n, n32, prefix);
+    hipError_t e = stage_frame_tables(ctx, ws, off_t, off_j, need);
+    if (e == hipErrorOutOfMemory)
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "vr_render_partials: pinned staging of %zu bytes", need);
+    if (e == hipSuccess) e = launch_frame(ctx, ws, off_t, off_j, n, n32, ctx->fprefix);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partials: %s", hipGetErrorString(e));
     return ok(ctx);
 }
@@ -703,27 +806,15 @@ vr_status vr_render_partials_static(vr_context ctx, int32_t n, const vr_brick* b
     if (need > kStaticScratchBytes)
         return fail(ctx, VR_ERR_INVALID_ARG, "%s: tables of %zu bytes exceed the %zu-byte scratch", who, need,
                     kStaticScratchBytes);
-    std::vector<MarchParams> jobs;
-    std::vector<int32_t> prefix;
     int n32 = 0;
-    vr_status st = frame_tables(ctx, n, bricks, parts, who, jobs, prefix, &n32);
+    vr_status st = frame_tables(ctx, n, bricks, parts, who, &n32);
     if (st != VR_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
-    // stage the tables in the next pinned slot (once the copy that last read
-    // it has run), then one stream-ordered copy into the scratch array
-    const int slot = ctx->pinned_next;
-    ctx->pinned_next ^= 1;
-    hipError_t e = hipEventSynchronize(ctx->pinned_done[slot]);
-    char* host = reinterpret_cast<char*>(ctx->pinned[slot]);
-    if (e == hipSuccess) {
-        std::memcpy(host + off_t, prefix.data(), prefix.size() * sizeof(int32_t));
-        std::memcpy(host + off_j, jobs.data(), (size_t)n * sizeof(MarchParams));
-        e = hipMemcpyAsync(reinterpret_cast<char*>(ctx->scratch) + off_t, host + off_t, need - off_t,
-                           hipMemcpyHostToDevice, ctx->stream);
-    }
-    if (e == hipSuccess) e = hipEventRecord(ctx->pinned_done[slot], ctx->stream);
-    if (e == hipSuccess) e = launch_frame(ctx, reinterpret_cast<char*>(ctx->scratch), off_t, off_j, n, n32, prefix);
+    // the pinned slots hold kStaticScratchBytes from creation: nothing is allocated
+    char* scratch = reinterpret_cast<char*>(ctx->scratch);
+    hipError_t e = stage_frame_tables(ctx, scratch, off_t, off_j, need);
+    if (e == hipSuccess) e = launch_frame(ctx, scratch, off_t, off_j, n, n32, ctx->fprefix);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
     return ok(ctx);
 }
@@ -942,6 +1033,7 @@ struct vr_batch_s {
     size_t off_mprefix = 0, off_mjobs = 0, off_cprefix = 0, off_cframes = 0;
     int32_t n32 = 0, total32 = 0, total16 = 0, ctotal = 0;
     int32_t wg_per_cu = 0, order = 0;
+    int32_t staging = kStagingRing, tile_w = 32, chunk = 4;   // staged configuration of the tables
     uint64_t shape_key = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -968,9 +1060,13 @@ void fnv(uint64_t& h, const void* p, size_t n) {
     for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
 }
 
-// Upload the job table in the given order (float32 jobs first, then float16).
-vr_status batch_upload(vr_batch b, int order) {
+// Upload the job table in the given order (float32 jobs first, then float16)
+// with tickets of tile_w x 16 pixels.  Work already enqueued on the context
+// stream (an earlier launch of this batch reads the tables) finishes first.
+vr_status batch_upload_tables(vr_batch b, int order, int staging, int tile_w, int chunk) {
     const int n = (int)b->jobs.size();
+    hipError_t se = hipStreamSynchronize(b->ctx->stream);
+    if (se != hipSuccess) return fail(b->ctx, VR_ERR_DEVICE, "batch upload: %s", hipGetErrorString(se));
     std::vector<int> idx(n);
     for (int i = 0; i < n; ++i) idx[i] = i;
     if (order == 1) {   // group the jobs of each brick, bricks in order of first appearance
@@ -994,7 +1090,7 @@ vr_status batch_upload(vr_batch b, int order) {
             const int i = idx[k];
             if (b->f16[i] != pass) continue;
             prefix[base + cnt] = acc;
-            acc += staged_tiles(b->jobs[i].roi_w, b->jobs[i].roi_h);
+            acc += queue_tiles(b->jobs[i].roi_w, b->jobs[i].roi_h, tile_w);
             table.push_back(b->jobs[i]);
             ++cnt;
         }
@@ -1008,7 +1104,23 @@ vr_status batch_upload(vr_batch b, int order) {
         e = hipMemcpy(b->ws + b->off_mjobs, table.data(), (size_t)n * sizeof(MarchParams), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(b->ctx, VR_ERR_DEVICE, "batch upload: %s", hipGetErrorString(e));
     b->order = order;
+    b->staging = staging;
+    b->tile_w = tile_w;
+    b->chunk = chunk;
+    for (MarchParams& jp : b->jobs) {      // (single-partial fields; the queue passes its own)
+        jp.staging = staging;
+        jp.tile_w = tile_w;
+        jp.chunk = chunk;
+    }
     return VR_OK;
+}
+
+vr_status batch_upload(vr_batch b, int order, int staging, int tile_w, int chunk) {
+    try {
+        return batch_upload_tables(b, order, staging, tile_w, chunk);
+    } catch (const std::bad_alloc&) {
+        return fail(b->ctx, VR_ERR_OUT_OF_MEMORY, "batch upload: out of host memory");
+    }
 }
 
 void batch_drop_graph(vr_batch b) {
@@ -1031,11 +1143,12 @@ vr_status batch_capture(vr_batch b, int wg_per_cu) {
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "batch capture: %s", hipGetErrorString(e));
     hipError_t le = hipSuccess;
     if (b->n32 > 0) {
-        QueueParams q{djobs, dprefix, b->n32, b->total32, heads, 1};
+        QueueParams q{djobs, dprefix, b->n32, b->total32, heads, 1, b->staging, b->tile_w, b->chunk, err_word(ctx)};
         le = launch_march_queue(q, kF32, wg_per_cu * ctx->cus, b->cap);
     }
     if (le == hipSuccess && n - b->n32 > 0) {
-        QueueParams q{djobs + b->n32, dprefix + b->n32 + 1, n - b->n32, b->total16, heads + kQueueParts, 1};
+        QueueParams q{djobs + b->n32, dprefix + b->n32 + 1, n - b->n32, b->total16, heads + kQueueParts, 1,
+                      b->staging, b->tile_w, b->chunk, err_word(ctx)};
         le = launch_march_queue(q, kF16, wg_per_cu * ctx->cus, b->cap);
     }
     if (le == hipSuccess && !b->frames.empty())
@@ -1056,11 +1169,11 @@ vr_status batch_capture(vr_batch b, int wg_per_cu) {
     return VR_OK;
 }
 
-int max_wg_per_cu(vr_context ctx, const vr_batch b) {
+int max_wg_per_cu(const vr_batch b, int staging, int tile_w, int chunk) {
     int m = 0;
-    if (b->n32 > 0) m = std::max(m, march_queue_workgroups_per_cu(kF32, true));
-    if ((int)b->jobs.size() > b->n32) m = std::max(m, march_queue_workgroups_per_cu(kF16, true));
-    (void)ctx;
+    if (b->n32 > 0) m = std::max(m, march_queue_workgroups_per_cu(kF32, true, staging, tile_w, chunk));
+    if ((int)b->jobs.size() > b->n32)
+        m = std::max(m, march_queue_workgroups_per_cu(kF16, true, staging, tile_w, chunk));
     return std::max(m, 1);
 }
 
@@ -1074,10 +1187,10 @@ vr_status vr_batch_workspace_size(int32_t n_jobs, int32_t n_frames, size_t* byte
     return VR_OK;
 }
 
-vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_desc* cameras,
-                          int32_t n_tfs, const vr_tf_desc* tfs, int32_t n_jobs,
-                          const vr_batch_job* jobs, int32_t n_frames, const vr_batch_frame* frames,
-                          void* workspace, size_t workspace_bytes, vr_batch* out) {
+static vr_status batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_desc* cameras,
+                              int32_t n_tfs, const vr_tf_desc* tfs, int32_t n_jobs,
+                              const vr_batch_job* jobs, int32_t n_frames, const vr_batch_frame* frames,
+                              void* workspace, size_t workspace_bytes, vr_batch* out) {
     static const char* who = "vr_batch_create";
     if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
     if (!out) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out is NULL", who);
@@ -1105,7 +1218,7 @@ vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_des
         tfk[i] = TFK{t.rgba, t.vmin, t.vmax, t.opacity_scale, DPVR_TF_ENTRIES};
     }
     std::unique_ptr<vr_batch_s> b(new (std::nothrow) vr_batch_s);
-    if (!b) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out of host memory", who);
+    if (!b) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
     b->ctx = ctx;
     uint64_t key = 1469598103934665603ull;
     for (int i = 0; i < n_jobs; ++i) {
@@ -1147,7 +1260,7 @@ vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_des
         if (st != VR_OK) return st;
         cpar.out = fr.out;
         b->frames.push_back(cpar);
-        cprefix[f + 1] = cprefix[f] + composite_tiles(cams[fr.camera].width, cams[fr.camera].height);
+        cprefix[f + 1] = cprefix[f] + composite_blocks(cams[fr.camera].width, cams[fr.camera].height);
         fnv(key, &cams[fr.camera].width, 2 * sizeof(int32_t));
     }
     b->ctotal = cprefix[n_frames];
@@ -1168,8 +1281,10 @@ vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_des
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
-    vr_status st = batch_upload(b.get(), 0);
-    if (st == VR_OK) st = batch_capture(b.get(), max_wg_per_cu(ctx, b.get()));
+    // until tuned, the context's configuration of the storage with more jobs
+    const MarchCfg& mc = ctx->cfg[(int32_t)b->jobs.size() - b->n32 > b->n32 ? 1 : 0];
+    vr_status st = batch_upload(b.get(), 0, mc.staging, mc.tile_w, mc.chunk);
+    if (st == VR_OK) st = batch_capture(b.get(), max_wg_per_cu(b.get(), mc.staging, mc.tile_w, mc.chunk));
     if (st != VR_OK) {
         batch_drop_graph(b.get());
         (void)hipStreamDestroy(b->cap);
@@ -1184,6 +1299,18 @@ vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_des
     return ok(ctx);
 }
 
+vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_desc* cameras,
+                          int32_t n_tfs, const vr_tf_desc* tfs, int32_t n_jobs,
+                          const vr_batch_job* jobs, int32_t n_frames, const vr_batch_frame* frames,
+                          void* workspace, size_t workspace_bytes, vr_batch* out) {
+    try {
+        return batch_create(ctx, n_cameras, cameras, n_tfs, tfs, n_jobs, jobs, n_frames, frames, workspace,
+                            workspace_bytes, out);
+    } catch (const std::bad_alloc&) {
+        return fail(live(ctx) ? ctx : nullptr, VR_ERR_OUT_OF_MEMORY, "vr_batch_create: out of host memory");
+    }
+}
+
 vr_status vr_batch_launch(vr_batch b) {
     if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_launch: invalid batch");
     vr_context ctx = b->ctx;
@@ -1194,34 +1321,72 @@ vr_status vr_batch_launch(vr_batch b) {
     return ok(ctx);
 }
 
-vr_status vr_batch_config(vr_batch b, int32_t* wg_per_cu, int32_t* order) {
+vr_status vr_batch_config(vr_batch b, int32_t* wg_per_cu, int32_t* order, int32_t* staging,
+                          int32_t* tile_width, int32_t* chunk_slices) {
     if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_config: invalid batch");
     if (wg_per_cu) *wg_per_cu = b->wg_per_cu;
     if (order) *order = b->order;
+    if (staging) *staging = b->staging == kStagingSlab ? VR_STAGING_SLAB : VR_STAGING_RING;
+    if (tile_width) *tile_width = b->tile_w;
+    if (chunk_slices) *chunk_slices = b->chunk;
     return ok(b->ctx);
 }
 
-static bool cache_lookup(const char* path, uint64_t key, int* wg, int* order) {
+namespace {
+
+struct TuneChoice {
+    int wg, order, staging, tile_w, chunk;
+};
+
+// Staged configurations the autotuner times: slab, and ring with 16- or
+// 32-pixel tiles and 4- or 8-slice chunks.
+constexpr int kTuneConfigs[5][3] = {
+    {kStagingSlab, 16, 4}, {kStagingRing, 16, 4}, {kStagingRing, 16, 8}, {kStagingRing, 32, 4}, {kStagingRing, 32, 8}};
+
+// Autotuner cache: one line per tuned batch shape,
+// "key wg order staging tile chunk ms".
+bool cache_lookup(const char* path, uint64_t key, TuneChoice* c) {
     if (!path) return false;
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
-    unsigned long long k;
-    int w, o;
-    double ms;
+    char line[256];
     bool found = false;
-    while (std::fscanf(f, "%llx %d %d %lf", &k, &w, &o, &ms) == 4)
-        if (k == key) { *wg = w; *order = o; found = true; }
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned long long k;
+        TuneChoice t;
+        double ms;
+        if (std::sscanf(line, "%llx %d %d %d %d %d %lf", &k, &t.wg, &t.order, &t.staging, &t.tile_w, &t.chunk,
+                        &ms) == 7 &&
+            k == key) {
+            *c = t;
+            found = true;
+        }
+    }
     std::fclose(f);
     return found;
 }
 
-static void cache_store(const char* path, uint64_t key, int wg, int order, double ms) {
+void cache_store(const char* path, uint64_t key, const TuneChoice& c, double ms) {
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%llx %d %d %.6f\n", (unsigned long long)key, wg, order, ms);
+    std::fprintf(f, "%llx %d %d %d %d %d %.6f\n", (unsigned long long)key, c.wg, c.order, c.staging, c.tile_w,
+                 c.chunk, ms);
     std::fclose(f);
 }
+
+bool choice_valid(const vr_batch b, const TuneChoice& c) {
+    return valid_march_config(c.staging, c.tile_w, c.chunk) && (c.order == 0 || c.order == 1) && c.wg >= 1 &&
+           c.wg <= max_wg_per_cu(b, c.staging, c.tile_w, c.chunk);
+}
+
+vr_status apply_choice(vr_batch b, const TuneChoice& c) {
+    vr_status st = batch_upload(b, c.order, c.staging, c.tile_w, c.chunk);
+    if (st == VR_OK) st = batch_capture(b, c.wg);
+    return st;
+}
+
+}  // namespace
 
 vr_status vr_batch_autotune(vr_batch b, int32_t reps, double* best_ms) {
     if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_autotune: invalid batch");
@@ -1230,11 +1395,9 @@ vr_status vr_batch_autotune(vr_batch b, int32_t reps, double* best_ms) {
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_batch_autotune: cannot select device %d", ctx->device);
     const char* path = std::getenv("DPVR_AUTOTUNE_CACHE");
-    int cwg = 0, cord = 0;
-    const int maxwg = max_wg_per_cu(ctx, b);
-    if (cache_lookup(path, b->shape_key, &cwg, &cord) && cwg >= 1 && cwg <= maxwg && (cord == 0 || cord == 1)) {
-        vr_status st = batch_upload(b, cord);
-        if (st == VR_OK) st = batch_capture(b, cwg);
+    TuneChoice cached{};
+    if (cache_lookup(path, b->shape_key, &cached) && choice_valid(b, cached)) {
+        vr_status st = apply_choice(b, cached);
         if (best_ms) *best_ms = -1.0;   // taken from the cache, not timed
         return st == VR_OK ? ok(ctx) : st;
     }
@@ -1242,32 +1405,41 @@ vr_status vr_batch_autotune(vr_batch b, int32_t reps, double* best_ms) {
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(ctx, VR_ERR_DEVICE, "vr_batch_autotune: cannot create events");
     double best = 1e300;
-    int bw = b->wg_per_cu, bo = b->order;
+    TuneChoice bc{b->wg_per_cu, b->order, b->staging, b->tile_w, b->chunk};
     vr_status st = VR_OK;
-    for (int order = 0; order < 2 && st == VR_OK; ++order) {
-        st = batch_upload(b, order);
-        for (int wg = 1; wg <= maxwg && st == VR_OK; ++wg) {
-            st = batch_capture(b, wg);
-            if (st != VR_OK) break;
-            hipError_t e = hipGraphLaunch(b->exec, ctx->stream);   // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
-            for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, ctx->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) { st = fail(ctx, VR_ERR_DEVICE, "vr_batch_autotune: %s", hipGetErrorString(e)); break; }
-            const double per = ms / reps;
-            if (per < best) { best = per; bw = wg; bo = order; }
+    // candidates: staged configuration x job order x persistent workgroups per CU
+    for (const auto& cfg : kTuneConfigs) {
+        for (int order = 0; order < 2 && st == VR_OK; ++order) {
+            st = batch_upload(b, order, cfg[0], cfg[1], cfg[2]);
+            const int maxwg = max_wg_per_cu(b, cfg[0], cfg[1], cfg[2]);
+            for (int wg = 1; wg <= maxwg && st == VR_OK; ++wg) {
+                st = batch_capture(b, wg);
+                if (st != VR_OK) break;
+                hipError_t e = hipGraphLaunch(b->exec, ctx->stream);   // warm-up
+                if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    st = fail(ctx, VR_ERR_DEVICE, "vr_batch_autotune: %s", hipGetErrorString(e));
+                    break;
+                }
+                const double per = ms / reps;
+                if (per < best) {
+                    best = per;
+                    bc = TuneChoice{wg, order, cfg[0], cfg[1], cfg[2]};
+                }
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != VR_OK) return st;
-    st = batch_upload(b, bo);
-    if (st == VR_OK) st = batch_capture(b, bw);
+    st = apply_choice(b, bc);
     if (st != VR_OK) return st;
-    cache_store(path, b->shape_key, bw, bo, best);
+    cache_store(path, b->shape_key, bc, best);
     if (best_ms) *best_ms = best;
     return ok(ctx);
 }

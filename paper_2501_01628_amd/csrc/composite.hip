@@ -1,19 +1,197 @@
 // Sort-last compositing of partial images for gfx950.
 //
-// One wavefront per 8x8 pixel tile, one lane per pixel.  The wave first
-// tests every partial's region of interest against the tile (wave-uniform
-// scalar work) and skips partials whose ROI misses it; a ballot then skips
-// partials that are empty (depth +inf) on every lane of the tile.  Each lane
-// inserts the finite depth keys of its pixel into a sorted list held in LDS
-// (stable: equal keys keep the lower partial index first), then composites
-// front to back with "over" and finally over the background.
+// Forward: a 256-thread workgroup composites a 64 x 4 pixel block, one
+// wavefront per 64 consecutive pixels of a row, so that every partial's row
+// segment is one contiguous run (256 B of depth keys, 1 KB of colour).
+// Partials whose ROI misses the wave's row segment are skipped by a
+// wave-uniform test.  A pass reads the depth key and the colour of every
+// covering partial together (kBatch partials' loads in flight at once) and
+// keeps, in registers, the kList smallest entries in (key, partial index)
+// order that come after the last entry already composited; those are
+// composited front to back with "over".  A pixel with more than kList finite
+// keys takes further passes; the frame pixel is finally "over" the
+// background.  Ties between equal keys go to the lower partial index first.
+//
+// Backward: one wavefront per 8x8 tile with the key lists in LDS.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stddef.h>
 
 #include "dpvr_kernels.h"
 
 namespace dpvr {
 namespace {
+
+constexpr int kList = 4;
+constexpr int kBatch = 2;
+
+// Word 3 of a raw (untyped, unswizzled) buffer resource on gfx9-family
+// chips: 32-bit data format; with stride 0 an access at or past the
+// resource's byte size returns zero and reads nothing.
+constexpr int kRawBuffer = 0x00020000;
+
+static_assert(kMaxPartials <= 64, "one lane per partial in the overlap vote");
+static_assert(offsetof(PartialK, x0) == 0 && offsetof(PartialK, h) == 12, "ROI read as one int4: x0, y0, w, h");
+
+// One 64-pixel row segment (this wave's) of one frame.
+__device__ inline void composite_row(const CompositeParams& p, int bx, int by) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sx0 = bx * 64;
+    const int px = sx0 + lane, py = by * 4 + wave;
+    if (py >= p.height) return;                 // (wave-uniform)
+    const bool valid = px < p.width;
+    // lane c reads partial c's ROI (one 16-byte load per lane) and votes for
+    // it when the ROI holds part of this row segment; a pass then reads the
+    // descriptors of the partials it visits with scalar loads
+    int4 roi = make_int4(0, 0, 0, 0);
+    if (lane < p.n) roi = *reinterpret_cast<const int4*>(&p.parts[lane]);
+    const bool hit = (roi.z > 0) & (roi.w > 0) & (py >= roi.y) & (py < roi.y + roi.w) & (roi.x < sx0 + 64) &
+                     (roi.x + roi.z > sx0);
+    const unsigned long long covering = __ballot(hit);
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+    float lk = -INFINITY;                       // (key, index) of the last composited entry
+    int li = -1;
+    bool active = valid;
+    while (__ballot(active) != 0) {
+        float key[kList];
+        int idx[kList];
+        float4 val[kList];
+#pragma unroll
+        for (int s = 0; s < kList; ++s) {
+            key[s] = INFINITY;
+            idx[s] = 0;
+            val[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        int cnt = 0;   // entries after (lk, li) at this pixel
+        unsigned long long rest = covering;
+        while (rest != 0) {
+            // the next kBatch covering partials in index order; slots past
+            // the last repeat the first and are masked (use[u] false), so
+            // that every load of the batch is issued without a branch
+            int cs[kBatch];
+            bool use[kBatch];
+            const int first = __builtin_ctzll(rest);
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                use[u] = rest != 0;
+                cs[u] = use[u] ? __builtin_ctzll(rest) : first;
+                rest &= rest - 1;
+            }
+            float z[kBatch];
+            float4 v[kBatch];
+            unsigned zraw[kBatch];
+            bool inside[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int c = cs[u];
+                const PartialK q = p.parts[c];
+                const int qx0 = q.x0;
+                const int qw = q.w;
+                const float4* rgba = reinterpret_cast<const float4*>(q.rgba);
+                const float* depth = q.depth;
+                const int lx = px - qx0;
+                const bool in = use[u] & active & (lx >= 0) & (lx < qw);
+                // the row lies inside the ROI (the partial covers this row
+                // segment): buffer loads over that one row, addressed by the
+                // lane's column; lanes off the ROI (and inactive lanes) ask
+                // for column -1, which the buffer's range check turns into
+                // zeros without a read
+                const long long row = (long long)(py - q.y0) * qw;
+                const int col = in ? lx : -1;
+                const __amdgpu_buffer_rsrc_t rd =
+                    __builtin_amdgcn_make_buffer_rsrc((void*)(depth + row), 0, qw * 4, kRawBuffer);
+                const __amdgpu_buffer_rsrc_t rc =
+                    __builtin_amdgcn_make_buffer_rsrc((void*)(rgba + row), 0, qw * 16, kRawBuffer);
+                zraw[u] = __builtin_amdgcn_raw_buffer_load_b32(rd, col * 4, 0, 0);
+                const auto vv = __builtin_amdgcn_raw_buffer_load_b128(rc, col * 16, 0, 0);
+                v[u] = make_float4(__uint_as_float(vv[0]), __uint_as_float(vv[1]), __uint_as_float(vv[2]),
+                                   __uint_as_float(vv[3]));
+                inside[u] = in;
+            }
+            // off the ROI the load returned 0, which or-ing turns into the
+            // bits of +inf (an unconditional use of every load, so that none
+            // is deferred behind a branch)
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) z[u] = __uint_as_float(zraw[u] | (inside[u] ? 0u : 0x7f800000u));
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int c = cs[u];
+                const bool take = z[u] < INFINITY && (z[u] > lk || (z[u] == lk && c > li));
+                if (__ballot(take) == 0) continue;     // no lane takes it (wave-uniform)
+                cnt += take;
+                // insert (branch-free; an entry not taken enters as +inf and
+                // moves nothing): entries compare by (key, index), so that an
+                // entry displaced from its slot lands before equal keys of
+                // higher index; the largest drops out
+                float nk = take ? z[u] : INFINITY;
+                int ni = c;
+                float4 nv = v[u];
+#pragma unroll
+                for (int s = 0; s < kList; ++s) {
+                    const bool before = nk < key[s] || (nk == key[s] && ni < idx[s]);
+                    const float tk = key[s];
+                    const int ti = idx[s];
+                    const float4 tv = val[s];
+                    key[s] = before ? nk : tk;
+                    idx[s] = before ? ni : ti;
+                    val[s].x = before ? nv.x : tv.x;
+                    val[s].y = before ? nv.y : tv.y;
+                    val[s].z = before ? nv.z : tv.z;
+                    val[s].w = before ? nv.w : tv.w;
+                    nk = before ? tk : nk;
+                    ni = before ? ti : ni;
+                    nv.x = before ? tv.x : nv.x;
+                    nv.y = before ? tv.y : nv.y;
+                    nv.z = before ? tv.z : nv.z;
+                    nv.w = before ? tv.w : nv.w;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kList; ++s) {
+            if (s < cnt) {
+                const float w = 1.0f - A;
+                C0 = fmaf(w, val[s].x, C0);
+                C1 = fmaf(w, val[s].y, C1);
+                C2 = fmaf(w, val[s].z, C2);
+                A = fmaf(w, val[s].w, A);
+            }
+        }
+        if (cnt > kList) {
+            lk = key[kList - 1];
+            li = idx[kList - 1];
+        } else {
+            active = false;
+        }
+    }
+    if (!valid) return;
+    const float w = 1.0f - A;
+    reinterpret_cast<float4*>(p.out)[(long long)py * p.width + px] =
+        make_float4(fmaf(w, p.bg[0], C0), fmaf(w, p.bg[1], C1), fmaf(w, p.bg[2], C2), fmaf(w, p.bg[3], A));
+}
+
+__global__ __launch_bounds__(256) void composite_kernel(CompositeParams p) {
+    const int bxs = (p.width + 63) / 64;
+    composite_row(p, blockIdx.x % bxs, blockIdx.x / bxs);
+}
+
+// Many frames in one launch: workgroup b composites block b - block_start[i]
+// of frame i (the last i with block_start[i] <= b); frame descriptors in
+// device memory.
+__global__ __launch_bounds__(256) void composite_many_kernel(const CompositeParams* __restrict__ frames,
+                                                            const int32_t* __restrict__ block_start,
+                                                            int32_t n_frames) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = n_frames - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (block_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const CompositeParams& p = frames[lo];
+    const int local = b - block_start[lo];
+    const int bxs = (p.width + 63) / 64;
+    composite_row(p, local % bxs, local / bxs);
+}
 
 // Sorted list of the finite depth keys of this lane's pixel, in LDS
 // (column `lane` of key_s / idx_s); returns its length.  Every lane of the
@@ -45,56 +223,6 @@ __device__ int sort_keys(const CompositeParams& p, int t0x, int t0y, int px, int
         }
     }
     return m;
-}
-
-// One 8x8 tile of one frame (one wavefront).
-__device__ inline void composite_tile(const CompositeParams& p, int tile, float* key_s,
-                                      unsigned char* idx_s) {
-    const int lane = threadIdx.x;
-    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-    const int t0x = tx * 8, t0y = ty * 8;
-    const int px = t0x + (lane & 7), py = t0y + (lane >> 3);
-    const bool valid = px < p.width && py < p.height;
-    const int m = sort_keys(p, t0x, t0y, px, py, valid, lane, key_s, idx_s);
-    if (!valid) return;
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
-    for (int k = 0; k < m; ++k) {
-        const PartialK& q = p.parts[idx_s[k * 64 + lane]];
-        const long long o = (long long)(py - q.y0) * q.w + (px - q.x0);
-        const float4 s = reinterpret_cast<const float4*>(q.rgba)[o];
-        const float w = 1.0f - A;
-        C0 = fmaf(w, s.x, C0);
-        C1 = fmaf(w, s.y, C1);
-        C2 = fmaf(w, s.z, C2);
-        A = fmaf(w, s.w, A);
-    }
-    const float w = 1.0f - A;
-    reinterpret_cast<float4*>(p.out)[(long long)py * p.width + px] =
-        make_float4(fmaf(w, p.bg[0], C0), fmaf(w, p.bg[1], C1), fmaf(w, p.bg[2], C2),
-                    fmaf(w, p.bg[3], A));
-}
-
-__global__ __launch_bounds__(64) void composite_kernel(CompositeParams p) {
-    __shared__ float key_s[kMaxPartials * 64];
-    __shared__ unsigned char idx_s[kMaxPartials * 64];
-    composite_tile(p, blockIdx.x, key_s, idx_s);
-}
-
-// Many frames in one launch: workgroup b composites tile b - tile_start[i]
-// of frame i (the last i with tile_start[i] <= b); frame descriptors in
-// device memory.
-__global__ __launch_bounds__(64) void composite_many_kernel(const CompositeParams* __restrict__ frames,
-                                                            const int32_t* __restrict__ tile_start,
-                                                            int32_t n_frames) {
-    __shared__ float key_s[kMaxPartials * 64];
-    __shared__ unsigned char idx_s[kMaxPartials * 64];
-    const int b = blockIdx.x;
-    int lo = 0, hi = n_frames - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    composite_tile(frames[lo], b - tile_start[lo], key_s, idx_s);
 }
 
 // Backward of the composite.  With the partials of a pixel in visibility
@@ -160,19 +288,18 @@ hipError_t launch_composite_backward(const CompositeParams& p, const CompositeBa
     return hipGetLastError();
 }
 
-hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* tile_start,
-                                 int32_t n_frames, int32_t total_tiles, hipStream_t stream) {
-    if (total_tiles <= 0 || n_frames <= 0) return hipSuccess;
-    hipLaunchKernelGGL(composite_many_kernel, dim3(total_tiles), dim3(64), 0, stream, frames,
-                       tile_start, n_frames);
+hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* block_start,
+                                 int32_t n_frames, int32_t total_blocks, hipStream_t stream) {
+    if (total_blocks <= 0 || n_frames <= 0) return hipSuccess;
+    hipLaunchKernelGGL(composite_many_kernel, dim3(total_blocks), dim3(256), 0, stream, frames,
+                       block_start, n_frames);
     return hipGetLastError();
 }
 
 hipError_t launch_composite(const CompositeParams& p, hipStream_t stream) {
-    const int tiles_y = (p.height + 7) / 8;
-    const int blocks = p.tiles_x * tiles_y;
+    const int blocks = composite_blocks(p.width, p.height);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(64), 0, stream, p);
+    hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 

@@ -55,12 +55,20 @@ struct MarchParams {
     int32_t ckpt_interval;
     int32_t ckpt_nseg;
     int32_t path;          // kPathStaged or kPathDirect (bit-identical results)
+    int32_t staging;       // staged path: kStagingSlab or kStagingRing
+    int32_t tile_w;        // staged path: tile width in pixels (slab: 16; ring: 16 or 32; 16 rows)
+    int32_t chunk;         // staged ring: slices per chunk of the walk (4 or 8)
+    int32_t* err;          // device error word: a kernel guard that trips ORs a bit in (may be NULL)
 };
 
 enum : int32_t { kPathStaged = 0, kPathDirect = 1 };
+// Staged-march families: slab (all waves stage a slab, then all march it)
+// and ring (a producer wave streams slices ahead of the marching waves).
+enum : int32_t { kStagingSlab = 0, kStagingRing = 1 };
 
 // A device work queue of march jobs (partial images): tickets
-// tile_start[j] .. tile_start[j + 1] - 1 are the 16x16 tiles of job j.
+// tile_start[j] .. tile_start[j + 1] - 1 are the tiles of job j (tile_w x 16
+// pixels when staged, 16 x 16 when direct).
 struct QueueParams {
     const MarchParams* jobs;   // device, n_jobs entries
     const int32_t* tile_start; // device, n_jobs + 1 entries (exclusive prefix of tiles)
@@ -68,7 +76,20 @@ struct QueueParams {
     int32_t total_tiles;
     int32_t* head;             // device, kQueueParts ticket counters (reset by the launcher)
     int32_t staged;            // 1: LDS-staged tiles, 0: every lane marches from HBM
+    int32_t staging;           // kStagingSlab or kStagingRing
+    int32_t tile_w;            // staged tile width (16, or 32 for the ring)
+    int32_t chunk;             // staged chunk length in slices (4 or 8)
+    int32_t* err;              // device error word (see MarchParams::err)
 };
+
+// Error bits of the device error word, which sits at byte kErrWordOffset of
+// the library's static scratch array of each device (zero at load).
+enum : int32_t { kErrSpin = 1 };
+constexpr size_t kErrWordOffset = 128;
+
+// Launch-configuration knobs of the staged march.
+constexpr int kTileWidths[2] = {16, 32};
+constexpr int kChunks[2] = {4, 8};
 
 // The tickets are split into kQueueParts contiguous parts, one per XCD
 // (workgroup i runs on XCD i mod 8): a workgroup drains its own XCD's part
@@ -76,7 +97,10 @@ struct QueueParams {
 // helps with the other parts in turn.
 constexpr int kQueueParts = 8;
 
-inline int32_t staged_tiles(int32_t w, int32_t h) { return ((w + 15) / 16) * ((h + 15) / 16); }
+// Tickets of a w x h ROI with tiles tile_w pixels wide and 16 rows high.
+inline int32_t queue_tiles(int32_t w, int32_t h, int32_t tile_w) {
+    return ((w + tile_w - 1) / tile_w) * ((h + 15) / 16);
+}
 
 constexpr int kMaxCkptInterval = 64;
 
@@ -141,11 +165,19 @@ hipError_t launch_ingest(const float* src, void* dst, const int32_t sdim[3], Sto
 hipError_t launch_march(const MarchParams& p, StorageK storage, hipStream_t stream);
 hipError_t launch_march_queue(const QueueParams& q, StorageK storage, int workgroups,
                               hipStream_t stream);
-int march_queue_workgroups_per_cu(StorageK storage, bool staged);
+// Resident workgroups per CU of the persistent march for this configuration.
+int march_queue_workgroups_per_cu(StorageK storage, bool staged, int staging, int tile_w, int chunk);
+// A valid staged configuration: slab with 16-pixel tiles, or ring with 16- or
+// 32-pixel tiles and chunks of 4 or 8 slices.
+inline bool valid_march_config(int staging, int tile_w, int chunk) {
+    if (staging == kStagingSlab) return tile_w == 16;
+    return staging == kStagingRing && (tile_w == 16 || tile_w == 32) && (chunk == 4 || chunk == 8);
+}
 hipError_t launch_composite(const CompositeParams& p, hipStream_t stream);
-hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* tile_start,
-                                 int32_t n_frames, int32_t total_tiles, hipStream_t stream);
-inline int32_t composite_tiles(int32_t w, int32_t h) { return ((w + 7) / 8) * ((h + 7) / 8); }
+hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* block_start,
+                                 int32_t n_frames, int32_t total_blocks, hipStream_t stream);
+// Workgroups of the forward composite of a w x h frame (64 x 4 pixel blocks).
+inline int32_t composite_blocks(int32_t w, int32_t h) { return ((w + 63) / 64) * ((h + 3) / 4); }
 hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp, StorageK storage,
                                  hipStream_t stream);
 hipError_t launch_composite_backward(const CompositeParams& p, const CompositeBackParams& bp,

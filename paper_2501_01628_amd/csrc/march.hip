@@ -11,36 +11,21 @@
 // from an LDS table, emission-absorption update, early termination once
 // T < eps.
 //
-// Two kernels compute bit-identical images:
-//  * march_staged (default): a 256-thread workgroup owns a 16x16 pixel tile,
-//    one wavefront per 8x8 quarter.  The workgroup walks the slabs of the
-//    tile's common slab axis w (y or z; rows along x stay contiguous in HBM)
-//    in ray order; for each slab it stages, per slice, the sheared rectangle
-//    the tile's rays cross (16-byte loads, converted to float32) into LDS,
-//    then every lane marches its samples of that slab out of LDS.  Tiles
-//    whose rays do not share a slab axis and direction, or whose slab does
-//    not fit in LDS, march from HBM directly.
-//  * march_direct: one wavefront per 8x8 tile, corner values straight from
-//    HBM; also writes transmittance checkpoints for the adjoint.
+// Two families of kernels compute bit-identical images:
+//  * staged (default): a workgroup owns a TW x 16 pixel tile (TW = 16 or 32),
+//    one consumer wavefront per 8x8 quarter plus one producer wavefront that
+//    streams, with the LDS DMA, the slices of brick data the tile's rays
+//    cross into a ring of LDS slots ahead of the consumers, which march
+//    their rays chunk by chunk out of LDS.  Tiles whose rays do not share a
+//    slab axis and direction, or whose slice footprint does not fit the
+//    ring, march from HBM directly.
+//  * direct: every lane reads its voxels straight from HBM (one wavefront per
+//    8x8 tile, or a 16x16 tile per workgroup in the work queue); the
+//    checkpointing forward of the adjoint uses it.
 #include "march_common.h"
 
 namespace dpvr {
 namespace {
-
-constexpr int kSlices = kSlab + 3;       // staged slices per slab: [wlo - 1, whi + 1]
-// Build-time sizes of the staged kernels: LDS floats of the slab stage and
-// rows of the row table.  (64 KB measured best on C2: a 40 KB stage with
-// 3 workgroups per CU ran within 3 %, a 24 KB stage with 4 per CU 20 %
-// slower, from register spills and more sub-slabs.)
-#ifndef DPVR_STAGE_FLOATS
-#define DPVR_STAGE_FLOATS 16384          // 64 KB: 2 workgroups per CU
-#endif
-#ifndef DPVR_STAGE_ROWS
-#define DPVR_STAGE_ROWS 1024
-#endif
-constexpr int kStageFloats = DPVR_STAGE_FLOATS;
-constexpr int kMaxRows = DPVR_STAGE_ROWS;
-constexpr float kMinStageDw = 0.25f;     // |d_w| below this: march from HBM
 
 struct LaneState {
     float C0, C1, C2, T;
@@ -106,6 +91,163 @@ __device__ inline bool march_run(const MarchParams& p, const TFTable& tft, const
     }
     // first sample of a pair: its test comes after the next sample (next run)
     if (j < j1) accumulate(classify(tft, sample(fj), tf_k, tf_o), j);
+    s.evaluated += j1 - j0;
+    return true;
+}
+
+// march_run for a sampler in three stages -- pre(fj) locates sample j and
+// issues its first dependent reads, gather(P) issues its voxel reads,
+// value(G) interpolates -- with the two samples of a pair interleaved stage
+// by stage (scheduling barriers keep both samples' reads of a stage in
+// flight together): three memory round trips per pair instead of six.  The
+// arithmetic of every sample, and the order of accumulation, are those of
+// march_run, so results are bit-identical.
+template <typename Pre, typename Gather, typename Value>
+__device__ inline bool march_run_pipe(const TFTable& tft, const RaySetup& rs, long long kb, int j0,
+                                      int j1, float tf_k, float tf_o, float eps, LaneState& s,
+                                      Pre pre, Gather gather, Value value) {
+    auto accumulate = [&](const Classified& e) {
+#pragma clang fp contract(off)
+        const float Tn = s.T * trans_exp2(-e.a);
+        const float w = s.T - Tn;
+        s.C0 = fmaf(w, e.r, s.C0);
+        s.C1 = fmaf(w, e.g, s.C1);
+        s.C2 = fmaf(w, e.b, s.C2);
+        s.T = Tn;
+    };
+    auto one = [&](float fj) { return classify(tft, value(gather(pre(fj))), tf_k, tf_o); };
+    int j = j0;
+    float fj = (float)j0;
+    if (((kb + j0 - rs.kf) & 1) && j < j1) {   // second sample of a pair begun in the previous run
+        accumulate(one(fj));
+        ++j;
+        fj += 1.0f;
+        if (s.T < eps) {
+            s.evaluated += 1;
+            s.stopped = true;
+            return false;
+        }
+    }
+    for (; j + 1 < j1; j += 2, fj += 2.0f) {
+        const auto pa = pre(fj);
+        const auto pb = pre(fj + 1.0f);
+        __builtin_amdgcn_sched_barrier(0);
+        const auto ga = gather(pa);
+        const auto gb = gather(pb);
+        __builtin_amdgcn_sched_barrier(0);
+        const float v0 = value(ga), v1 = value(gb);
+        // classification in two stages (table index, then both table reads)
+        const float sr0 = fmaf(v0, tf_k, tf_o), sr1 = fmaf(v1, tf_k, tf_o);
+        const float s0 = fminf(fmaxf(sr0, 0.0f), 255.0f), s1 = fminf(fmaxf(sr1, 0.0f), 255.0f);
+        const int g0 = min((int)s0, 254), g1 = min((int)s1, 254);
+        const float4 b0 = tft.base[g0], d0 = tft.diff[g0], b1 = tft.base[g1], d1 = tft.diff[g1];
+        __builtin_amdgcn_sched_barrier(0);
+        const float ph0 = s0 - (float)g0, ph1 = s1 - (float)g1;
+        Classified e0, e1;
+        e0.r = fmaf(ph0, d0.x, b0.x); e0.g = fmaf(ph0, d0.y, b0.y);
+        e0.b = fmaf(ph0, d0.z, b0.z); e0.a = fmaf(ph0, d0.w, b0.w);
+        e1.r = fmaf(ph1, d1.x, b1.x); e1.g = fmaf(ph1, d1.y, b1.y);
+        e1.b = fmaf(ph1, d1.z, b1.z); e1.a = fmaf(ph1, d1.w, b1.w);
+        accumulate(e0);
+        accumulate(e1);
+        if (s.T < eps) {
+            s.evaluated += j - j0 + 2;
+            s.stopped = true;
+            return false;
+        }
+    }
+    // first sample of a pair: its test comes after the next sample (next run)
+    if (j < j1) accumulate(one(fj));
+    s.evaluated += j1 - j0;
+    return true;
+}
+
+// march_run_pipe with the pairs software-pipelined four deep: iteration i
+// issues the first reads of pair i + 3, the voxel reads of pair i + 2 and the
+// table reads of pair i + 1, then accumulates pair i, so every read has a
+// whole iteration to arrive.  Pairs past the run's end are located and read
+// (from clamped addresses) but never accumulated.  Same arithmetic and
+// accumulation order as march_run_pipe: bit-identical results.
+template <typename Pre, typename Gather, typename Value>
+__device__ inline bool march_run_deep(const TFTable& tft, const RaySetup& rs, long long kb, int j0,
+                                      int j1, float tf_k, float tf_o, float eps, LaneState& s,
+                                      Pre pre, Gather gather, Value value) {
+    auto accumulate = [&](const Classified& e) {
+#pragma clang fp contract(off)
+        const float Tn = s.T * trans_exp2(-e.a);
+        const float w = s.T - Tn;
+        s.C0 = fmaf(w, e.r, s.C0);
+        s.C1 = fmaf(w, e.g, s.C1);
+        s.C2 = fmaf(w, e.b, s.C2);
+        s.T = Tn;
+    };
+    auto one = [&](float fj) { return classify(tft, value(gather(pre(fj))), tf_k, tf_o); };
+    using P = decltype(pre(0.0f));
+    using G = decltype(gather(pre(0.0f)));
+    struct P2 { P a, b; };
+    struct G2 { G a, b; };
+    struct T2 { float ph0, ph1; float4 b0, d0, b1, d1; };
+    auto pre2 = [&](float f) { return P2{pre(f), pre(f + 1.0f)}; };
+    auto gather2 = [&](const P2& x) { return G2{gather(x.a), gather(x.b)}; };
+    auto table2 = [&](const G2& x) {
+        const float v0 = value(x.a), v1 = value(x.b);
+        const float s0 = fminf(fmaxf(fmaf(v0, tf_k, tf_o), 0.0f), 255.0f);
+        const float s1 = fminf(fmaxf(fmaf(v1, tf_k, tf_o), 0.0f), 255.0f);
+        const int g0 = min((int)s0, 254), g1 = min((int)s1, 254);
+        return T2{s0 - (float)g0, s1 - (float)g1, tft.base[g0], tft.diff[g0], tft.base[g1], tft.diff[g1]};
+    };
+    auto finish2 = [&](const T2& t) {
+        Classified e0, e1;
+        e0.r = fmaf(t.ph0, t.d0.x, t.b0.x); e0.g = fmaf(t.ph0, t.d0.y, t.b0.y);
+        e0.b = fmaf(t.ph0, t.d0.z, t.b0.z); e0.a = fmaf(t.ph0, t.d0.w, t.b0.w);
+        e1.r = fmaf(t.ph1, t.d1.x, t.b1.x); e1.g = fmaf(t.ph1, t.d1.y, t.b1.y);
+        e1.b = fmaf(t.ph1, t.d1.z, t.b1.z); e1.a = fmaf(t.ph1, t.d1.w, t.b1.w);
+        accumulate(e0);
+        accumulate(e1);
+    };
+    int j = j0;
+    float fj = (float)j0;
+    if (((kb + j0 - rs.kf) & 1) && j < j1) {   // second sample of a pair begun in the previous run
+        accumulate(one(fj));
+        ++j;
+        fj += 1.0f;
+        if (s.T < eps) {
+            s.evaluated += 1;
+            s.stopped = true;
+            return false;
+        }
+    }
+    const int npairs = (j1 - j) >> 1;
+    if (npairs > 0) {
+        P2 p2 = pre2(fj + 4.0f);
+        const P2 p1 = pre2(fj + 2.0f);
+        const P2 p0 = pre2(fj);
+        __builtin_amdgcn_sched_barrier(0);
+        G2 g1 = gather2(p1);
+        const G2 g0 = gather2(p0);
+        __builtin_amdgcn_sched_barrier(0);
+        T2 t0 = table2(g0);
+        __builtin_amdgcn_sched_barrier(0);
+        for (int i = 0; i < npairs; ++i) {
+            const P2 p3 = pre2(fj + (float)(2 * i + 6));
+            const G2 g2 = gather2(p2);
+            const T2 t1 = table2(g1);
+            __builtin_amdgcn_sched_barrier(0);
+            finish2(t0);
+            if (s.T < eps) {
+                s.evaluated += j - j0 + 2 * i + 2;
+                s.stopped = true;
+                return false;
+            }
+            t0 = t1;
+            g1 = g2;
+            p2 = p3;
+        }
+        j += 2 * npairs;
+        fj += (float)(2 * npairs);
+    }
+    // first sample of a pair: its test comes after the next sample (next run)
+    if (j < j1) accumulate(one(fj));
     s.evaluated += j1 - j0;
     return true;
 }
@@ -181,13 +323,14 @@ __global__ __launch_bounds__(64) void march_direct(MarchParams p) {
     finish(p, valid, pix, depth, s, lane);
 }
 
-// ------------------------------------------------------------ staged kernel
-// Workgroup-wide reduction of kRed values: wave reduction by shuffles, one
-// LDS round trip (double-buffered by `buf`, so one barrier per call).
-constexpr int kRed = 12;
+// ------------------------------------------------- shared by the staged kernels
+constexpr int kRed = 8;                  // values per workgroup reduction (at most)
+constexpr float kMinStageDw = 0.25f;     // |d_w| below this: march from HBM
 
-template <int N>
-__device__ inline void wg_reduce(float (&v)[N], const bool (&is_max)[N], float (*red)[4][kRed],
+// Workgroup-wide reduction of N values over NW waves: shuffles within each
+// wave, one LDS round trip (double-buffered by `buf`: one barrier per call).
+template <int N, int NW>
+__device__ inline void wg_reduce(float (&v)[N], const bool (&is_max)[N], float (*red)[NW][kRed],
                                  int buf, int lane, int wave) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -206,10 +349,25 @@ __device__ inline void wg_reduce(float (&v)[N], const bool (&is_max)[N], float (
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         float x = red[buf][0][i];
-        for (int w = 1; w < 4; ++w) x = is_max[i] ? fmaxf(x, red[buf][w][i]) : fminf(x, red[buf][w][i]);
-        v[i] = x;
+        for (int w = 1; w < NW; ++w) x = is_max[i] ? fmaxf(x, red[buf][w][i]) : fminf(x, red[buf][w][i]);
+        v[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
     }
 }
+
+__device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------- staged kernel (slabs)
+// A 256-thread workgroup owns a 16x16 pixel tile (one wavefront per 8x8
+// quarter) and walks the slabs of the tile's common slab axis w (y or z;
+// rows along x stay contiguous in HBM) in ray order, all four waves in step:
+// per slab (one 16-slice anchor block), a workgroup reduction gives the
+// extent of the tile's rays in the slab; the slab (or each of its sub-slabs,
+// when it does not fit) is staged into LDS slice by slice as sheared
+// rectangles, then every lane marches its samples of it from LDS.  Two
+// workgroups share a CU, so one stages while the other marches.
+constexpr int kSlices = kSlab + 3;       // staged slices per slab: [wlo - 1, whi + 1]
+constexpr int kStageFloats = 16384;      // 64 KB stage: 2 workgroups per CU
+constexpr int kMaxRows = 1024;
 
 // 16-byte staging vectors: load() from the brick in HBM (global address
 // space: the loads count only against vmcnt), store() into the float32 stage
@@ -240,19 +398,19 @@ struct StageVec<__half> {
     }
 };
 
-// LDS of a staged-march workgroup.
+// LDS of a slab-march workgroup.
 struct StagedShared {
     TFTable tft;
     __align__(16) float stage[kStageFloats];
     unsigned row_src[kMaxRows];          // element offset in the brick of each staged row
     int tab_off[kSlices];
     float red[2][4][kRed];
+    int ticket;
 };
 
 __device__ inline float uniform_f(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
-__device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Walk of one eligible tile through the slabs of its common slab axis W
 // (2: z, rows along y; 1: y, rows along z) in ray order.  Per slab, a
@@ -261,7 +419,7 @@ __device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v
 // slice by slice as sheared rectangles, then every lane marches its samples
 // of it from LDS.
 template <typename TS, int W>
-__device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, const RaySetup& rs,
+__device__ void slab_walk(const MarchParams& p, StagedShared& sh, int& buf, const RaySetup& rs,
                             const Blocks& bl, bool has, int sg, long long pix, float tf_k,
                             float tf_o, float eps, LaneState& s) {
     constexpr int B = 3 - W;                 // the other of y (1) and z (2)
@@ -298,7 +456,7 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
     {
         float v[1] = {has ? (float)n_cur : 3e38f};
         const bool mx[1] = {false};
-        wg_reduce(v, mx, red, buf, lane, wave);
+        wg_reduce<sizeof(v) / sizeof(v[0]), 4>(v, mx, red, buf, lane, wave);
         buf ^= 1;
         n_chunk = (long long)uniform_f(v[0]);
     }
@@ -308,7 +466,7 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
     {
         float v[4] = {has ? kx : 3e38f, has ? kx : -3e38f, has ? kb : 3e38f, has ? kb : -3e38f};
         const bool mx[4] = {false, true, false, true};
-        wg_reduce(v, mx, red, buf, lane, wave);
+        wg_reduce<sizeof(v) / sizeof(v[0]), 4>(v, mx, red, buf, lane, wave);
         buf ^= 1;
         kxmin = uniform_f(v[0]); kxmax = uniform_f(v[1]);
         kbmin = uniform_f(v[2]); kbmax = uniform_f(v[3]);
@@ -334,7 +492,7 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
         float v[5] = {part ? xr : 3e38f, part ? xr : -3e38f, part ? br : 3e38f, part ? br : -3e38f,
                       (alive && !part) ? (float)n_cur : 3e38f};
         const bool mx[5] = {false, true, false, true, false};
-        wg_reduce(v, mx, red, buf, lane, wave);
+        wg_reduce<sizeof(v) / sizeof(v[0]), 4>(v, mx, red, buf, lane, wave);
         buf ^= 1;
         const float xmin0 = uniform_f(v[0]), xmax0 = uniform_f(v[1]);
         const float bmin0 = uniform_f(v[2]), bmax0 = uniform_f(v[3]);
@@ -456,34 +614,56 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
                         const int base4 = ia_b * RW4 + an.ia0 * 4;
                         const int sio = ia_w - (w_a - 1);
                         const char* S8 = reinterpret_cast<const char*>(stage);
-                        auto sample_lds = [&](float fj) {
+                        struct SlabPre {
+                            Cell c;
+                            int row4, t0, t1;
+                        };
+                        struct SlabGather {
+                            Cell c;
+                            float v[8];
+                        };
+                        auto pre = [&](float fj) {
                             const float x = fmaf(fj, st.s0, an.uf0);
                             const float y = fmaf(fj, st.s1, an.uf1);
                             const float z = fmaf(fj, st.s2, an.uf2);
-                            Cell c;
-                            c.fx = fract(x); c.fy = fract(y); c.fz = fract(z);
+                            SlabPre r;
+                            r.c.fx = fract(x); r.c.fy = fract(y); r.c.fz = fract(z);
                             const int fx_i = floor_int(x);
                             const int fb = floor_int(W == 2 ? y : z), fw = floor_int(W == 2 ? z : y);
                             // (unsigned clamps keep every read inside the stage;
                             // the slab bounds make them inactive)
                             const unsigned si = min((unsigned)(fw + sio), (unsigned)(nsl - 2));
-                            const int row4 = __mul24(fb, RW4) + fx_i * 4 + base4;
-                            const unsigned a0 = min((unsigned)(tab_off[si] + row4), (unsigned)lim4);
-                            const unsigned a1 = min((unsigned)(tab_off[si + 1] + row4), (unsigned)lim4);
-                            const float p00 = *reinterpret_cast<const float*>(S8 + a0);
-                            const float p01 = *reinterpret_cast<const float*>(S8 + a0 + 4);
-                            const float p10 = *reinterpret_cast<const float*>(S8 + a0 + RW4);
-                            const float p11 = *reinterpret_cast<const float*>(S8 + a0 + RW4 + 4);
-                            const float q00 = *reinterpret_cast<const float*>(S8 + a1);
-                            const float q01 = *reinterpret_cast<const float*>(S8 + a1 + 4);
-                            const float q10 = *reinterpret_cast<const float*>(S8 + a1 + RW4);
-                            const float q11 = *reinterpret_cast<const float*>(S8 + a1 + RW4 + 4);
-                            // (p: slice w, q: slice w+1; second index: row b+1)
-                            return W == 2 ? lerp3(c, p00, p01, p10, p11, q00, q01, q10, q11)
-                                          : lerp3(c, p00, p01, q00, q01, p10, p11, q10, q11);
+                            r.row4 = __mul24(fb, RW4) + fx_i * 4 + base4;
+                            r.t0 = tab_off[si];
+                            r.t1 = tab_off[si + 1];
+                            return r;
                         };
-                        cont = march_run<false>(p, tft, rs, k_cur, j0, j1, pix, tf_k, tf_o, eps, s,
-                                                sample_lds);
+                        auto gather = [&](const SlabPre& r) {
+                            const unsigned a0 = min((unsigned)(r.t0 + r.row4), (unsigned)lim4);
+                            const unsigned a1 = min((unsigned)(r.t1 + r.row4), (unsigned)lim4);
+                            SlabGather g;
+                            g.c = r.c;
+                            g.v[0] = *reinterpret_cast<const float*>(S8 + a0);
+                            g.v[1] = *reinterpret_cast<const float*>(S8 + a0 + 4);
+                            g.v[2] = *reinterpret_cast<const float*>(S8 + a0 + RW4);
+                            g.v[3] = *reinterpret_cast<const float*>(S8 + a0 + RW4 + 4);
+                            g.v[4] = *reinterpret_cast<const float*>(S8 + a1);
+                            g.v[5] = *reinterpret_cast<const float*>(S8 + a1 + 4);
+                            g.v[6] = *reinterpret_cast<const float*>(S8 + a1 + RW4);
+                            g.v[7] = *reinterpret_cast<const float*>(S8 + a1 + RW4 + 4);
+                            return g;
+                        };
+                        // (v[0..3]: slice w, v[4..7]: slice w + 1; odd: x + 1;
+                        // 2, 3, 6, 7: row b + 1)
+                        auto value = [&](const SlabGather& g) {
+                            return W == 2 ? lerp3(g.c, g.v[0], g.v[1], g.v[2], g.v[3], g.v[4], g.v[5], g.v[6], g.v[7])
+                                          : lerp3(g.c, g.v[0], g.v[1], g.v[4], g.v[5], g.v[2], g.v[3], g.v[6], g.v[7]);
+                        };
+                        // (the plain two-sample loop: measured faster here than the
+                        // staged loop, whose scheduling barriers the slab's lock-step
+                        // waves cannot hide)
+                        auto sample_lds = [&](float fj) { return value(gather(pre(fj))); };
+                        cont = march_run<false>(p, tft, rs, k_cur, j0, j1, pix, tf_k, tf_o, eps, s, sample_lds);
                     } else {
                         auto sample_hbm = [&](float fj) {
                             return trilinear(vox, locate(an, st, fj, snx, sny, snz), pitch, sxy);
@@ -511,7 +691,7 @@ __device__ void staged_walk(const MarchParams& p, StagedShared& sh, int& buf, co
 // reduction buffer and is carried between calls.  Every thread of the
 // workgroup must call it with the same arguments.
 template <typename TS>
-__device__ void staged_tile(const MarchParams& p, int tile, StagedShared& sh, int& buf) {
+__device__ void slab_tile(const MarchParams& p, int tile, StagedShared& sh, int& buf) {
     const TFTable& tft = sh.tft;
     float (*red)[4][kRed] = sh.red;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -542,7 +722,7 @@ __device__ void staged_tile(const MarchParams& p, int tile, StagedShared& sh, in
                   has ? (float)(bl.axis * 2 + (bl.sg > 0 ? 1 : 0)) : -1e9f,
                   has ? dw_abs : 1e9f, has ? 1.0f : 0.0f};
     const bool mx[4] = {false, true, false, true};
-    wg_reduce(v, mx, red, buf, lane, wave);
+    wg_reduce<sizeof(v) / sizeof(v[0]), 4>(v, mx, red, buf, lane, wave);
     buf ^= 1;
     const float kmin = uniform_f(v[0]), kmax = uniform_f(v[1]);
     if (uniform_f(v[3]) == 0.0f) {                // no ray of this tile hits the brick
@@ -558,57 +738,702 @@ __device__ void staged_tile(const MarchParams& p, int tile, StagedShared& sh, in
     const int key = (int)kmin;
     const int sg = (key & 1) ? 1 : -1;
     if ((key >> 1) == 2)
-        staged_walk<TS, 2>(p, sh, buf, rs, bl, has, sg, pix, tf_k, tf_o, eps, s);
+        slab_walk<TS, 2>(p, sh, buf, rs, bl, has, sg, pix, tf_k, tf_o, eps, s);
     else
-        staged_walk<TS, 1>(p, sh, buf, rs, bl, has, sg, pix, tf_k, tf_o, eps, s);
+        slab_walk<TS, 1>(p, sh, buf, rs, bl, has, sg, pix, tf_k, tf_o, eps, s);
     finish(p, valid, pix, depth, s, lane);
 }
 
 template <typename TS>
-__global__ __launch_bounds__(256) void march_staged(MarchParams p) {
+__global__ __launch_bounds__(256) void march_slab_single(MarchParams p) {
     __shared__ StagedShared sh;
     load_tf(sh.tft, p.tf, p.dt, threadIdx.x, 256);
-    // XCD-aware order: workgroup i runs on XCD i mod 8, so give each XCD a
-    // contiguous run of tiles (neighbouring tiles share L2 lines); the map is
-    // a bijection on [0, gridDim.x)
+    // XCD-aware order (see march_staged)
     const int nb = gridDim.x, bid = blockIdx.x;
     const int per = nb / 8, rem = nb % 8, xcd = bid % 8;
     const int tile = xcd * per + min(xcd, rem) + bid / 8;
     int buf = 0;
-    staged_tile<TS>(p, tile, sh, buf);
+    slab_tile<TS>(p, tile, sh, buf);
+}
+
+// ------------------------------------------------------- staged kernel (slice ring)
+// A workgroup owns a TW x 16 pixel tile: NCW = TW / 4 consumer wavefronts
+// march the 8 x 8 quarters, one producer wavefront streams the brick slices
+// the tile's rays cross into a ring of LDS slots with the gfx950 LDS DMA
+// (global_load_lds_dwordx4: no registers, up to 63 KB in flight per wave).
+// The tile walks the slices of its common slab axis w in ray order, in
+// chunks of CH slices (CH divides the 16-slice anchor block); a chunk's
+// samples touch the CH + 3 slices [CH k, CH k + CH + 2] of the walk (one
+// slice of margin each side for float32 rounding across a chunk plane).
+// Producer and consumers synchronise through LDS words only: `ready` (walk
+// slices published so far) and one `done` word per consumer wave (the lowest
+// walk slice it may still read); a slot is refilled once every consumer wave
+// has moved past its slice.  No workgroup barrier is taken during the walk.
+// Every wait is bounded: a wait that times out sets `abort` (all later waits
+// of the workgroup return at once) and the kErrSpin bit of the device error
+// word, so a logic error ends the launch with an error instead of a hang.
+constexpr int kTabSize = 512;            // walk slices per tile (a deeper walk marches from HBM)
+constexpr int kTabMask = kTabSize - 1;
+constexpr int kMaxSlots = 64;
+constexpr int kAllDone = 1 << 30;
+constexpr int kSpinLimit = 1 << 22;      // polls of ~64 cycles: ~0.1 s per wait at most
+constexpr double kMargin = 0.01;         // voxels of slack around a slice's footprint
+constexpr long long kNoBlock = -(1LL << 62);
+
+template <int NCW>
+constexpr int ring_bytes() { return 144 * 1024; }
+
+template <int NCW>
+struct RingShared {
+    __align__(1024) unsigned char ring[ring_bytes<NCW>()];
+    TFTable tft;
+    int tab[kTabSize];   // walk slice q: byte offset of its slot minus its rectangle's origin
+    __align__(16) int src[kTabSize];   // walk slice q: element offset of its rectangle's origin in the brick
+    int ready;           // walk slices published by the producer
+    __align__(16) int done[NCW];   // per consumer wave: walk slices below this are no longer read
+    int abort;
+    int ticket;
+    float red[2][NCW + 1][kRed];
+};
+
+// LDS words accessed as volatile through LDS-qualified pointers (a volatile
+// access through a generic pointer becomes a FLAT access, which counts
+// against the vector-memory counter and so waits behind the LDS DMA).
+typedef __attribute__((address_space(3))) volatile int lds_vint;
+__device__ inline int ld_volatile(const int& w) { return uniform_i(*(lds_vint*)&w); }
+// The same read, written as inline asm that waits for its own result: the
+// producer wave uses it while its LDS DMA is in flight, where the compiler
+// would otherwise wait for every outstanding DMA (vmcnt(0)) before any LDS
+// read, since it cannot tell that the read does not touch the ring.
+__device__ inline int ld_lds_nowait_dma(const int& w) {
+    typedef __attribute__((address_space(3))) const int lds_int;
+    const unsigned a = (unsigned)(uintptr_t)((lds_int*)&w);
+    int v;
+    __asm__ volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(a) : "memory");
+    return uniform_i(v);
+}
+__device__ inline void st_volatile(int& w, int v) { *(lds_vint*)&w = v; }
+__device__ inline void compiler_fence() { __asm__ volatile("" ::: "memory"); }
+
+// s_waitcnt with only the vector-memory counter (gfx9 encoding: vmcnt in
+// bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 at their no-wait maxima).
+template <int N>
+__device__ inline void wait_vmcnt() {
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+// Wait until at most n vector-memory operations of this wave are pending
+// (rounded down to a listed count: waiting for more is always safe).
+__device__ inline void wait_vmcnt_le(int n) {
+    if (n >= 48) wait_vmcnt<48>();
+    else if (n >= 32) wait_vmcnt<32>();
+    else if (n >= 24) wait_vmcnt<24>();
+    else if (n >= 16) wait_vmcnt<16>();
+    else if (n >= 12) wait_vmcnt<12>();
+    else if (n >= 8) wait_vmcnt<8>();
+    else if (n >= 4) wait_vmcnt<4>();
+    else wait_vmcnt<0>();
+}
+
+// Minimum of the NCW done words (16-byte aligned), read with one or two
+// 16-byte LDS reads in an asm block that waits for its own results (see
+// ld_lds_nowait_dma).
+template <int NCW>
+__device__ inline int min_done(const int (&done)[NCW]) {
+    typedef __attribute__((address_space(3))) const int lds_int;
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    const unsigned a = (unsigned)(uintptr_t)((lds_int*)&done[0]);
+    i32x4 v0, v1;
+    if constexpr (NCW == 4) {
+        __asm__ volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v0) : "v"(a) : "memory");
+        v1 = v0;
+    } else {
+        static_assert(NCW == 8, "4 or 8 consumer waves");
+        __asm__ volatile("ds_read_b128 %0, %2\n\tds_read_b128 %1, %2 offset:16\n\ts_waitcnt lgkmcnt(0)"
+                         : "=&v"(v0), "=&v"(v1) : "v"(a) : "memory");
+    }
+    const int m = min(min(min(v0.x, v0.y), min(v0.z, v0.w)), min(min(v1.x, v1.y), min(v1.z, v1.w)));
+    return uniform_i(m);
+}
+
+template <int NCW>
+__device__ inline void trip(RingShared<NCW>& sh, int* err) {
+    st_volatile(sh.abort, 1);
+    if (err && (threadIdx.x & 63) == 0) atomicOr(err, kErrSpin);
+}
+
+// Bounded wait until word >= target; false on abort or time-out.
+template <int NCW>
+__device__ inline bool wait_ge(RingShared<NCW>& sh, const int& word, int target, int* err) {
+    for (int it = 0; it < kSpinLimit; ++it) {
+        if (ld_volatile(word) >= target) {
+            compiler_fence();
+            return true;
+        }
+        if (ld_volatile(sh.abort)) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    trip(sh, err);
+    return false;
+}
+
+// Uniform geometry of a tile's walk.  The rays of the tile cross the plane
+// s_w = s (stored-index coordinate of the slab axis) at x = xa + xb s,
+// b = ba + bb s; on a plane, x and b are ratios of affine functions of the
+// pixel coordinates (pinhole) or affine (orthographic), monotone along rows
+// and columns, so over the tile's pixel rectangle they are bounded by the
+// four corner rays.  A slice w is read by samples with s_w in [w - 1, w + 1).
+struct Lines {
+    double xa[4], xb[4], ba[4], bb[4];
+};
+
+template <int W>
+__device__ inline void corner_lines(const MarchParams& p, int px0, int px1, int py0, int py1, Lines& L) {
+#pragma clang fp contract(off)
+    constexpr int B = 3 - W;
+    const BrickK& b = p.brick;
+    const double g = (double)b.ghost - 0.5;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const CamRay r = camera_ray(p.cam, (c & 1) ? px1 : px0, (c & 2) ? py1 : py0);
+        const double t0 = ((0.5 - (double)b.ghost) * b.spacing[W] + b.origin[W] - r.o[W]) / r.d[W];
+        const double dt_ds = b.spacing[W] / r.d[W];    // dt per unit of s_w
+        L.xa[c] = (r.o[0] + t0 * r.d[0] - b.origin[0]) * b.inv_spacing[0] + g;
+        L.xb[c] = r.d[0] * dt_ds * b.inv_spacing[0];
+        L.ba[c] = (r.o[B] + t0 * r.d[B] - b.origin[B]) * b.inv_spacing[B] + g;
+        L.bb[c] = r.d[B] * dt_ds * b.inv_spacing[B];
+    }
+}
+
+// Footprint of slice w: x in [xlo, xhi], b in [blo, bhi] (before margins).
+__device__ inline void slice_bounds(const Lines& L, double w, double& xlo, double& xhi, double& blo,
+                                    double& bhi) {
+    xlo = blo = INFINITY;
+    xhi = bhi = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double xm = L.xa[c] + L.xb[c] * w, xr = fabs(L.xb[c]);
+        const double bm = L.ba[c] + L.bb[c] * w, br = fabs(L.bb[c]);
+        xlo = fmin(xlo, xm - xr); xhi = fmax(xhi, xm + xr);
+        blo = fmin(blo, bm - br); bhi = fmax(bhi, bm + br);
+    }
+}
+
+// First sample of chunk kap of a ray: chunks cut the anchor blocks into
+// 16 / CH parts, at the planes n = kap CH / 16 of the block numbering (a
+// chunk plane with kap CH a multiple of 16 is a block plane, computed with
+// the same expression as block_start).
+__device__ inline long long chunk_start(const Blocks& bl, double inv_dt, long long kap, int ch) {
+#pragma clang fp contract(off)
+    const double n = (double)(kap * ch) * 0.0625;
+    const double t = bl.c0 + n * bl.c1;
+    return (long long)ceil(t * inv_dt - 0.5);
+}
+
+__device__ inline long long chunk_of(const Blocks& bl, double dt, double inv_dt, long long k, int ch) {
+#pragma clang fp contract(off)
+    const double t = ((double)k + 0.5) * dt;
+    long long kap = (long long)floor(((t - bl.c0) / bl.c1) * (16.0 / (double)ch));
+    while (chunk_start(bl, inv_dt, kap, ch) > k) --kap;
+    while (chunk_start(bl, inv_dt, kap + 1, ch) <= k) ++kap;
+    return kap;
+}
+
+struct RingGeom {
+    int ok;
+    int RW, RH;     // slot rectangle (elements x rows)
+    int SB;         // slot stride in bytes (multiple of 1 KB)
+    int R;          // slots in the ring
+    int NI;         // DMA instructions per slice (SB / 1 KB)
+    int D;          // slices the producer keeps in flight before publishing
+    int Q;          // walk slices
+    int K;          // chunks
+    int w_start;    // stored slice of walk slice 0
+    long long klo;  // first chunk
+};
+
+template <typename TS, int NCW, int CH, int W>
+__device__ inline RingGeom ring_geometry(const MarchParams& p, const Lines& L, int sg, long long klo,
+                                         long long khi) {
+    constexpr int ESZ = sizeof(TS);
+    constexpr int V = 16 / ESZ;                  // elements per 16-byte vector
+    constexpr int B = 3 - W;
+    const BrickK& b = p.brick;
+    const int pitch = row_pitch(b.sdim[0]);
+    const int snb = b.sdim[B];
+    RingGeom G{};
+    G.klo = klo;
+    G.K = (int)(khi - klo + 1);
+    G.Q = CH * G.K + 3;
+    G.w_start = sg > 0 ? (int)(CH * klo - 1) : (int)(-CH * klo + 1);
+    // the footprint width is convex in w: its maximum is at an end of the walk
+    double sx = 0.0, sb = 0.0;
+    for (int e = 0; e < 2; ++e) {
+        const double w = (double)(G.w_start + (e ? sg * (G.Q - 1) : 0));
+        double xlo, xhi, blo, bhi;
+        slice_bounds(L, w, xlo, xhi, blo, bhi);
+        sx = fmax(sx, xhi - xlo);
+        sb = fmax(sb, bhi - blo);
+    }
+    const double cap = 65536.0;
+    int RW = (int)ceil(fmin(sx, cap) + 2.0 * kMargin) + 2 + V - 1;
+    RW = (RW + V - 1) / V * V;
+    if (RW > pitch) RW = pitch;
+    int RH = (int)ceil(fmin(sb, cap) + 2.0 * kMargin) + 2;
+    if (RH > snb) RH = snb;
+    G.RW = RW;
+    G.RH = RH;
+    // slots hold float32 (float16 slices are copied raw into a slot's upper
+    // half and decoded in place, see ring_produce)
+    const long long bytes = (long long)RW * RH * 4;
+    const long long align = ESZ == 2 ? 2048 : 1024;
+    G.SB = (int)(((bytes + align - 1) / align) * align);
+    G.R = bytes > 0 ? (int)min((long long)kMaxSlots, (long long)ring_bytes<NCW>() / G.SB) : 0;
+    G.NI = (int)(((long long)RW * RH * ESZ + 1023) / 1024);
+    // the producer addresses a slice's rows with 32-bit byte offsets
+    const long long b_stride = W == 2 ? (long long)pitch : (long long)b.sdim[1] * pitch;
+    const bool offsets32 = ((long long)(RH - 1) * b_stride + RW) * ESZ < (1LL << 32);
+    G.ok = G.R >= CH + 4 && G.K >= 1 && G.Q <= kTabSize && offsets32;
+    int D = G.R - (CH + 3);
+    D = min(D, 8);
+    if (G.NI * (D - 1) > 48) D = 48 / G.NI + 1;
+    G.D = max(D, 1);
+    return G;
+}
+
+// The walk's slice tables, filled by every thread of the workgroup at tile
+// set-up: walk slice q (stored slice w = w_start + sg q) is staged in slot
+// q mod R as the RW x RH rectangle at (x0, b0) that bounds the footprint of
+// the tile's rays on it; consumers address a voxel (b, x) of the slice at
+// byte tab[q] + 4 (b RW + x) (float32 in LDS), the producer copies from element src[q] of
+// the brick.
+template <typename TS, int NCW, int CH, int W>
+__device__ void ring_tables(const MarchParams& p, RingShared<NCW>& sh, const Lines& L, const RingGeom& G,
+                            int sg) {
+    constexpr int ESZ = sizeof(TS);
+    constexpr int V = 16 / ESZ;
+    constexpr int B = 3 - W;
+    const BrickK& b = p.brick;
+    const int snx = b.sdim[0], sny = b.sdim[1];
+    const int snw = b.sdim[W], snb = b.sdim[B];
+    const int pitch = row_pitch(snx);
+    const int w_stride = W == 2 ? sny * pitch : pitch;   // elements (a brick holds < 2^31)
+    const int b_stride = W == 2 ? pitch : sny * pitch;
+    const int RW = G.RW, RH = G.RH, RWB = RW * 4;   // LDS rows hold float32
+    for (int q = threadIdx.x; q < G.Q; q += (NCW + 1) * 64) {
+        const int w = G.w_start + sg * q;
+        double xlo, xhi, blo, bhi;
+        slice_bounds(L, (double)w, xlo, xhi, blo, bhi);
+        const double xf = fmin(fmax(floor(xlo - kMargin), 0.0), 65536.0);
+        const double bf = fmin(fmax(floor(blo - kMargin), 0.0), 65536.0);
+        int x0 = ((int)xf) / V * V;
+        if (x0 + RW > pitch) x0 = pitch - RW;
+        int b0 = (int)bf;
+        if (b0 + RH > snb) b0 = snb - RH;
+        const int wl = min(max(w, 0), snw - 1);         // slices outside the brick: never sampled
+        sh.tab[q] = (q % G.R) * G.SB - b0 * RWB - x0 * 4;
+        sh.src[q] = wl * w_stride + b0 * b_stride + x0;
+    }
+}
+
+// DMA instructions per slice the producer can issue (a slot of at most
+// ring_bytes / 8: the ring holds at least CH + 4 >= 8 slots).
+template <int NCW>
+constexpr int max_ni() { return ring_bytes<NCW>() / (8 * 1024); }
+
+// Producer wavefront: stream the walk's slices into the ring.  It runs at a
+// raised wave priority, so that the issue of its few instructions per slice
+// is not held back by the marching wavefronts on its SIMD.  float16 slices
+// land raw in the upper half of their slot and are decoded to float32 in
+// place (front to back in 512-element chunks: chunk c writes bytes
+// [2048 c, 2048 c + 2048), which lie below every byte of the halves still to
+// be read) before the slice is published.
+template <typename TS, int NCW, int CH, int W>
+__device__ void ring_produce(const MarchParams& p, RingShared<NCW>& sh, const RingGeom& G, int* err) {
+    constexpr int ESZ = sizeof(TS);
+    constexpr int V = 16 / ESZ;
+    constexpr int B = 3 - W;
+    constexpr int EPI = 1024 / ESZ;              // elements per DMA instruction (64 lanes x 16 B)
+    constexpr int MNI = max_ni<NCW>();
+    typedef __attribute__((address_space(1))) void gvoid_t;
+    typedef __attribute__((address_space(3))) void lvoid_t;
+    __builtin_amdgcn_s_setprio(2);
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) const int lds_int;
+    const int lane = threadIdx.x & 63;
+    const BrickK& b = p.brick;
+    const unsigned char* vox = reinterpret_cast<const unsigned char*>(b.data);
+    const int sny = b.sdim[1];
+    const int pitch = row_pitch(b.sdim[0]);
+    const long long b_stride = W == 2 ? (long long)pitch : (long long)sny * pitch;
+    const int RW = uniform_i(G.RW), RH = uniform_i(G.RH);
+    const int NI = uniform_i(G.NI), SB = uniform_i(G.SB), R = uniform_i(G.R), D = uniform_i(G.D);
+    const int Q = uniform_i(G.Q);
+    const unsigned bstr = (unsigned)(b_stride * ESZ);
+    const unsigned src_addr = (unsigned)(uintptr_t)((lds_int*)&sh.src[0]);
+    const unsigned ring_addr = (unsigned)(uintptr_t)((lds_int*)(const void*)sh.ring);
+    const int dma_base = ESZ == 2 ? SB / 2 : 0;         // float16: raw halves in the slot's upper half
+    i32x4 src4 = {0, 0, 0, 0};
+    // the LDS reads and writes of the decoding are inline asm for the reason
+    // given at ld_lds_nowait_dma (other slices' DMA is still in flight)
+    auto decode = [&](int sl) {
+        if constexpr (ESZ == 2) {
+            const unsigned base = ring_addr + (unsigned)(sl * SB);
+            const int nch = (RW * RH + 511) >> 9;
+            auto convert_store = [&](const i32x4& raw, int c) {
+                const __half2* h = reinterpret_cast<const __half2*>(&raw);
+                const float2 f0 = __half22float2(h[0]), f1 = __half22float2(h[1]);
+                const float2 f2 = __half22float2(h[2]), f3 = __half22float2(h[3]);
+                const i32x4 lo = {__float_as_int(f0.x), __float_as_int(f0.y), __float_as_int(f1.x),
+                                  __float_as_int(f1.y)};
+                const i32x4 hi = {__float_as_int(f2.x), __float_as_int(f2.y), __float_as_int(f3.x),
+                                  __float_as_int(f3.y)};
+                __asm__ volatile("ds_write_b128 %0, %1\n\tds_write_b128 %0, %2 offset:16"
+                                 :: "v"(base + (unsigned)(2048 * c + 32 * lane)), "v"(lo), "v"(hi) : "memory");
+            };
+            // eight chunks per round trip: all read before any is written;
+            // reads past the slice's last chunk stay inside the workgroup's LDS
+            // (the slot's neighbour, or the tables after the ring) and their
+            // results are dropped
+            for (int c = 0; c < nch; c += 8) {
+                i32x4 r0, r1, r2, r3, r4, r5, r6, r7;
+                __asm__ volatile("ds_read_b128 %0, %8\n\tds_read_b128 %1, %8 offset:1024\n\t"
+                                 "ds_read_b128 %2, %8 offset:2048\n\tds_read_b128 %3, %8 offset:3072\n\t"
+                                 "ds_read_b128 %4, %8 offset:4096\n\tds_read_b128 %5, %8 offset:5120\n\t"
+                                 "ds_read_b128 %6, %8 offset:6144\n\tds_read_b128 %7, %8 offset:7168\n\t"
+                                 "s_waitcnt lgkmcnt(0)"
+                                 : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(r6),
+                                   "=&v"(r7)
+                                 : "v"(base + (unsigned)(dma_base + 1024 * c + 16 * lane)) : "memory");
+                convert_store(r0, c);
+                if (c + 1 < nch) convert_store(r1, c + 1);
+                if (c + 2 < nch) convert_store(r2, c + 2);
+                if (c + 3 < nch) convert_store(r3, c + 3);
+                if (c + 4 < nch) convert_store(r4, c + 4);
+                if (c + 5 < nch) convert_store(r5, c + 5);
+                if (c + 6 < nch) convert_store(r6, c + 6);
+                if (c + 7 < nch) convert_store(r7, c + 7);
+            }
+            __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        }
+        (void)sl;
+    };
+    int pub = 0, pslot = 0;                              // slices published; slot of slice `pub`
+    auto publish = [&](int n) {                          // slices < n have landed: decode, publish
+        for (; pub < n; ++pub) {
+            decode(pslot);
+            pslot = pslot + 1 == R ? 0 : pslot + 1;
+        }
+        compiler_fence();
+        st_volatile(sh.ready, n);
+    };
+    // byte offset, within a slice's rectangle, of this lane's 16 bytes of each
+    // DMA instruction (the same for every slice of the tile; lanes past the
+    // rectangle's last row fetch its first bytes into the slot's padding)
+    unsigned off[MNI];
+#pragma unroll
+    for (int i = 0; i < MNI; ++i) {
+        const int e = i * EPI + lane * V;
+        const int r = e / RW, c = e - r * RW;
+        off[i] = r < RH ? (unsigned)r * bstr + (unsigned)(c * ESZ) : 0u;
+    }
+    int slot = 0, inflight = 0;
+    int q = 0;
+    int md = 0;                                          // last seen minimum of the done words
+    for (; q < Q; ++q) {
+        // wait for the slot of walk slice q: every consumer past slice q - R
+        bool go = q < md + R;
+        for (int it = 0; !go && it < kSpinLimit; ++it) {
+            md = min_done<NCW>(sh.done);
+            if (md >= kAllDone) break;                   // every consumer has finished
+            if (q < md + R) {
+                go = true;
+                break;
+            }
+            if (inflight) {                               // publish before blocking
+                wait_vmcnt<0>();
+                publish(q);
+                inflight = 0;
+            }
+            if (ld_lds_nowait_dma(sh.abort)) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (it == kSpinLimit - 1) trip(sh, err);
+        }
+        compiler_fence();
+        if (!go) break;
+        // source offsets of four slices at a time (one 16-byte LDS read that
+        // waits for itself; see ld_lds_nowait_dma)
+        if ((q & 3) == 0) {
+            __asm__ volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(src4)
+                             : "v"(src_addr + (unsigned)q * 4u) : "memory");
+        }
+        const int qi = q & 3;
+        const int el = uniform_i(qi == 0 ? src4.x : qi == 1 ? src4.y : qi == 2 ? src4.z : src4.w);
+        const unsigned char* sbase = vox + (long long)el * ESZ;
+        unsigned char* dst = sh.ring + slot * SB;
+#pragma unroll
+        for (int i = 0; i < MNI; ++i)
+            if (i < NI)
+                __builtin_amdgcn_global_load_lds((gvoid_t*)(sbase + off[i]),
+                                                 (lvoid_t*)(dst + dma_base + i * 1024), 16, 0, 0);
+        slot = slot + 1 == R ? 0 : slot + 1;
+        if (++inflight == D) {
+            wait_vmcnt_le(NI * (D - 1));                 // slice q - D + 1 has landed
+            publish(q - D + 2);
+            --inflight;
+        }
+    }
+    wait_vmcnt<0>();
+    publish(q);
+    __builtin_amdgcn_s_setprio(0);
+}
+
+template <typename TS>
+__device__ inline float ring_ld(const unsigned char* p);
+template <>
+__device__ inline float ring_ld<float>(const unsigned char* p) {
+    return *reinterpret_cast<const float*>(p);
+}
+
+// Consumer wavefront: march every lane's ray chunk by chunk from the ring.
+template <typename TS, int NCW, int CH, int W>
+__device__ void ring_consume(const MarchParams& p, RingShared<NCW>& sh, const RingGeom& G, int sg,
+                             const RaySetup& rs, const Blocks& bl, bool has, long long pix, float tf_k,
+                             float tf_o, float eps, LaneState& s, int* err) {
+    constexpr int ESZ = 4;                       // the ring holds float32 for both storages
+    constexpr int B = 3 - W;
+    const int wave = threadIdx.x >> 6;
+    const BrickK& b = p.brick;
+    const TFTable& tft = sh.tft;
+    const int RWB = G.RW * ESZ;
+    const unsigned lim = (unsigned)(ring_bytes<NCW>() - RWB - 2 * ESZ);
+    const unsigned char* R8 = sh.ring;
+    const Step st = has ? make_step(rs, b, p.dt) : Step{0.f, 0.f, 0.f};
+    long long k_cur = has ? rs.kf : 0;
+    bool alive = has;
+    long long an_blk = kNoBlock, k_anchor = 0;
+    Anchor an{};
+    int qoff = 0, rbase = 0;
+    int seen = 0;                                        // last seen value of the ready word
+    for (int kk = 0; kk < G.K; ++kk) {
+        const long long kap = G.klo + kk;
+        long long ke = 0;
+        if (alive) ke = min(chunk_start(bl, p.inv_dt, kap + 1, CH), rs.kl + 1);
+        const bool work = alive && k_cur < ke;
+        if (__ballot(work)) {
+            const int need = CH * kk + CH + 3;
+            if (seen < need) {
+                if (!wait_ge(sh, sh.ready, need, err)) break;
+                seen = ld_volatile(sh.ready);
+                compiler_fence();
+            }
+            if (work) {
+                const long long blk = (kap * CH) >> 4;   // floor(kap CH / 16)
+                if (blk != an_blk) {
+                    an = make_anchor(rs, b, p.dt, k_cur);
+                    an_blk = blk;
+                    k_anchor = k_cur;
+                    const int ia_w = W == 2 ? an.ia2 : an.ia1, ia_b = W == 2 ? an.ia1 : an.ia2;
+                    qoff = sg * (ia_w - G.w_start);
+                    rbase = ia_b * RWB + an.ia0 * ESZ;
+                }
+                // stage 1: position, cell, and the two slices' table entries
+                struct RingPre {
+                    Cell c;
+                    int row, t0, t1;
+                };
+                struct RingGather {
+                    Cell c;
+                    float v[8];
+                };
+                auto pre = [&](float fj) {
+                    const float x = fmaf(fj, st.s0, an.uf0);
+                    const float y = fmaf(fj, st.s1, an.uf1);
+                    const float z = fmaf(fj, st.s2, an.uf2);
+                    RingPre r;
+                    r.c.fx = fract(x); r.c.fy = fract(y); r.c.fz = fract(z);
+                    const int fx_i = floor_int(x);
+                    const int fb = floor_int(W == 2 ? y : z), fw = floor_int(W == 2 ? z : y);
+                    const int q = fw * sg + qoff;
+                    r.row = __mul24(fb, RWB) + fx_i * ESZ + rbase;
+                    r.t0 = sh.tab[q & kTabMask];
+                    r.t1 = sh.tab[(q + sg) & kTabMask];
+                    return r;
+                };
+                // stage 2: the 8 corner reads (unsigned clamps keep every read
+                // inside the ring; for owned samples they never act)
+                auto gather = [&](const RingPre& r) {
+                    const unsigned a0 = min((unsigned)(r.t0 + r.row), lim);
+                    const unsigned a1 = min((unsigned)(r.t1 + r.row), lim);
+                    RingGather g;
+                    g.c = r.c;
+                    g.v[0] = ring_ld<float>(R8 + a0);       g.v[1] = ring_ld<float>(R8 + a0 + ESZ);
+                    g.v[2] = ring_ld<float>(R8 + a0 + RWB); g.v[3] = ring_ld<float>(R8 + a0 + RWB + ESZ);
+                    g.v[4] = ring_ld<float>(R8 + a1);       g.v[5] = ring_ld<float>(R8 + a1 + ESZ);
+                    g.v[6] = ring_ld<float>(R8 + a1 + RWB); g.v[7] = ring_ld<float>(R8 + a1 + RWB + ESZ);
+                    return g;
+                };
+                // stage 3: trilinear (v[0..3]: slice w, v[4..7]: slice w + 1;
+                // odd index: x + 1; 2, 3, 6, 7: row b + 1)
+                auto value = [&](const RingGather& g) {
+                    return W == 2 ? lerp3(g.c, g.v[0], g.v[1], g.v[2], g.v[3], g.v[4], g.v[5], g.v[6], g.v[7])
+                                  : lerp3(g.c, g.v[0], g.v[1], g.v[4], g.v[5], g.v[2], g.v[3], g.v[6], g.v[7]);
+                };
+                // 16-wide tiles (five waves, two per SIMD: 256 registers)
+                // take the four-deep pipeline; 32-wide tiles (nine waves,
+                // three per SIMD: 168 registers) the two-sample one
+                bool cont;
+                if constexpr (NCW == 4)
+                    cont = march_run_deep(tft, rs, k_anchor, (int)(k_cur - k_anchor), (int)(ke - k_anchor),
+                                          tf_k, tf_o, eps, s, pre, gather, value);
+                else
+                    cont = march_run_pipe(tft, rs, k_anchor, (int)(k_cur - k_anchor), (int)(ke - k_anchor),
+                                          tf_k, tf_o, eps, s, pre, gather, value);
+                k_cur = ke;
+                alive = cont && k_cur <= rs.kl;
+            }
+        }
+        compiler_fence();
+        if ((threadIdx.x & 63) == 0) st_volatile(sh.done[wave], CH * (kk + 1));
+        if (!__ballot(alive)) break;
+    }
+    compiler_fence();
+    if ((threadIdx.x & 63) == 0) st_volatile(sh.done[wave], kAllDone);
+}
+
+// One TW x 16 tile of one partial image, by the whole workgroup (NCW + 1
+// waves).  The classification table must already be in sh.tft (ordered by
+// the first reduction's barrier); every thread must call it.
+template <typename TS, int NCW, int CH>
+__device__ void ring_tile(const MarchParams& p, int tile, RingShared<NCW>& sh, int& buf, int* err) {
+    constexpr int NW = NCW + 1, TW = NCW * 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool producer = wave == NCW;
+    const int tiles_x = (p.roi_w + TW - 1) / TW;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int wx = wave % (TW / 8), wy = wave / (TW / 8);
+    const int lx = tx * TW + wx * 8 + (lane & 7), ly = ty * 16 + wy * 8 + (lane >> 3);
+    const bool valid = !producer && lx < p.roi_w && ly < p.roi_h;
+    const long long pix = (long long)ly * p.roi_w + lx;
+    const BrickK& b = p.brick;
+    const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
+    const float tf_o = -p.tf.vmin * tf_k;
+    const float eps = p.ert_eps;
+
+    LaneState s{0.f, 0.f, 0.f, 1.f, 0, false};
+    float depth = INFINITY;
+    RaySetup rs;
+    const bool has = valid && setup_ray(p.cam, b, p.dt, p.roi_x0 + lx, p.roi_y0 + ly, rs);
+    Blocks bl{0.0, 1.0, 0, 1};
+    float dw_abs = 1.0f;
+    long long kf_chunk = 0, kl_chunk = 0;
+    if (has) {
+        depth = (float)(((double)rs.kf + 0.5) * p.dt);
+        bl = make_blocks(rs, b);
+        dw_abs = (float)fabs(pick3(rs.d, bl.axis));
+        kf_chunk = chunk_of(bl, p.dt, p.inv_dt, rs.kf, CH);
+        kl_chunk = chunk_of(bl, p.dt, p.inv_dt, rs.kl, CH);
+    }
+    // the previous tile ended with a barrier: nobody reads the words now
+    if (tid == 0) st_volatile(sh.ready, 0);
+    if (lane == 0 && !producer) st_volatile(sh.done[wave], 0);
+    // eligibility: every ray shares slab axis (y or z) and direction; the walk's chunk range
+    const float key = (float)(bl.axis * 2 + (bl.sg > 0 ? 1 : 0));
+    float v[6] = {has ? key : 1e9f, has ? key : -1e9f, has ? dw_abs : 1e9f, has ? 1.0f : 0.0f,
+                  has ? (float)kf_chunk : 3e38f, has ? (float)kl_chunk : -3e38f};
+    const bool mx[6] = {false, true, false, true, false, true};
+    wg_reduce<6, NW>(v, mx, sh.red, buf, lane, wave);
+    buf ^= 1;
+    if (v[3] == 0.0f) {                      // no ray of this tile hits the brick
+        finish(p, valid, pix, depth, s, lane);
+        return;
+    }
+    bool ok = v[0] == v[1] && v[0] >= 2.0f && v[2] >= kMinStageDw;
+    const int ukey = (int)v[0];
+    const int W = ukey >> 1, sg = (ukey & 1) ? 1 : -1;
+    const long long klo = (long long)v[4], khi = (long long)v[5];
+    RingGeom G{};
+    Lines L;
+    if (ok) {
+        const int px0 = p.roi_x0 + tx * TW, px1 = p.roi_x0 + min(tx * TW + TW - 1, p.roi_w - 1);
+        const int py0 = p.roi_y0 + ty * 16, py1 = p.roi_y0 + min(ty * 16 + 15, p.roi_h - 1);
+        if (W == 2) {
+            corner_lines<2>(p, px0, px1, py0, py1, L);
+            G = ring_geometry<TS, NCW, CH, 2>(p, L, sg, klo, khi);
+        } else {
+            corner_lines<1>(p, px0, px1, py0, py1, L);
+            G = ring_geometry<TS, NCW, CH, 1>(p, L, sg, klo, khi);
+        }
+        ok = G.ok;
+    }
+    if (!ok) {                               // march this tile from HBM
+        if (has) march_ray_direct<TS, false>(p, sh.tft, rs, pix, tf_k, tf_o, eps, s);
+        finish(p, valid, pix, depth, s, lane);
+        return;
+    }
+    if (W == 2) ring_tables<TS, NCW, CH, 2>(p, sh, L, G, sg);
+    else ring_tables<TS, NCW, CH, 1>(p, sh, L, G, sg);
+    __syncthreads();
+    if (producer) {
+        if (W == 2) ring_produce<TS, NCW, CH, 2>(p, sh, G, err);
+        else ring_produce<TS, NCW, CH, 1>(p, sh, G, err);
+    } else {
+        if (W == 2) ring_consume<TS, NCW, CH, 2>(p, sh, G, sg, rs, bl, has, pix, tf_k, tf_o, eps, s, err);
+        else ring_consume<TS, NCW, CH, 1>(p, sh, G, sg, rs, bl, has, pix, tf_k, tf_o, eps, s, err);
+    }
+    finish(p, valid, pix, depth, s, lane);
+}
+
+// One partial, one workgroup per tile (tiles in an XCD-aware order:
+// workgroup i runs on XCD i mod 8, each XCD takes a contiguous run of tiles,
+// a bijection on [0, gridDim.x)).
+template <typename TS, int NCW, int CH>
+__global__ __launch_bounds__((NCW + 1) * 64, 2) void march_staged(MarchParams p) {
+    __shared__ RingShared<NCW> sh;
+    load_tf(sh.tft, p.tf, p.dt, threadIdx.x, (NCW + 1) * 64);
+    if (threadIdx.x == 0) sh.abort = 0;
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int per = nb / 8, rem = nb % 8, xcd = bid % 8;
+    const int tile = xcd * per + min(xcd, rem) + bid / 8;
+    int buf = 0;
+    ring_tile<TS, NCW, CH>(p, tile, sh, buf, p.err);
+}
+
+// One 16x16 tile, every lane marching its own ray from HBM (no staging, no
+// workgroup-wide steps).
+template <typename TS>
+__device__ void direct_tile(const MarchParams& p, int tile, const TFTable& tft) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x16 = (p.roi_w + 15) / 16;
+    const int tx = tile % tiles_x16, ty = tile / tiles_x16;
+    const int lx = tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int ly = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const bool valid = lx < p.roi_w && ly < p.roi_h;
+    const long long pix = (long long)ly * p.roi_w + lx;
+    const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
+    const float tf_o = -p.tf.vmin * tf_k;
+    LaneState s{0.f, 0.f, 0.f, 1.f, 0, false};
+    float depth = INFINITY;
+    RaySetup rs;
+    if (valid && setup_ray(p.cam, p.brick, p.dt, p.roi_x0 + lx, p.roi_y0 + ly, rs)) {
+        depth = (float)(((double)rs.kf + 0.5) * p.dt);
+        march_ray_direct<TS, false>(p, tft, rs, pix, tf_k, tf_o, p.ert_eps, s);
+    }
+    finish(p, valid, pix, depth, s, lane);
 }
 
 // Persistent work-queue march: each workgroup repeatedly takes the next
-// ticket (one 16x16 tile of one job = one partial image) until the tickets
-// run out, so many small partials (bricks x time steps x fields x cameras)
-// fill the GPU together.  Tickets come from kQueueParts parts, the own XCD's
-// part first.  The table is reloaded only when a job's transfer function (or
-// dt) differs from the previous ticket's.
-template <typename TS, bool kStaged>
-__device__ void direct_tile(const MarchParams& p, int tile, const TFTable& tft);
-
-// LDS of a queue workgroup: the staging buffers only where tiles are staged.
-template <bool kStaged>
-struct QueueShared {
-    StagedShared st;
-    __device__ TFTable& tf() { return st.tft; }
-};
-template <>
-struct QueueShared<false> {
-    TFTable t;
-    __device__ TFTable& tf() { return t; }
-};
-
-template <typename TS, bool kStaged>
-__global__ __launch_bounds__(256) void march_queue(QueueParams q) {
-    __shared__ QueueShared<kStaged> sh;
-    __shared__ int ticket;
+// ticket (one tile of one job = one partial image) until the tickets run
+// out, so many small partials (bricks x time steps x fields x cameras) fill
+// the GPU together.  Tickets come from kQueueParts parts, the own XCD's part
+// first.  The table is reloaded only when a job's transfer function (or dt)
+// differs from the previous ticket's.
+template <typename TS, typename Shared, typename TileFn>
+__device__ inline void queue_loop(const QueueParams& q, Shared& sh, TFTable& tft, int& ticket, bool sync_tf,
+                                  TileFn tile_fn) {
     const int tid = threadIdx.x;
     const float* tf_loaded = nullptr;
     float scale_loaded = -1.0f;
     double dt_loaded = -1.0;
-    int buf = 0;
-    (void)buf;
     const int home = blockIdx.x % kQueueParts;
     for (int c = 0; c < kQueueParts; ++c) {
         const int part = (home + c) % kQueueParts;
@@ -630,43 +1455,48 @@ __global__ __launch_bounds__(256) void march_queue(QueueParams q) {
             }
             const MarchParams& p = q.jobs[lo];
             if (p.tf.rgba != tf_loaded || p.tf.opacity_scale != scale_loaded || p.dt != dt_loaded) {
-                load_tf(sh.tf(), p.tf, p.dt, tid, 256);
+                load_tf(tft, p.tf, p.dt, tid, blockDim.x);
                 tf_loaded = p.tf.rgba;
                 scale_loaded = p.tf.opacity_scale;
                 dt_loaded = p.dt;
-                if (!kStaged) __syncthreads();
-                // (staged_tile's first reduction barrier orders these writes before use)
+                if (sync_tf) __syncthreads();
             }
-            if constexpr (kStaged)
-                staged_tile<TS>(p, t - q.tile_start[lo], sh.st, buf);
-            else
-                direct_tile<TS, false>(p, t - q.tile_start[lo], sh.tf());
+            tile_fn(p, t - q.tile_start[lo]);
             __syncthreads();
         }
     }
 }
 
-// One 16x16 tile, every lane marching its own ray from HBM (no staging, no
-// workgroup-wide steps).
-template <typename TS, bool kStaged>
-__device__ void direct_tile(const MarchParams& p, int tile, const TFTable& tft) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tiles_x16 = (p.roi_w + 15) / 16;
-    const int tx = tile % tiles_x16, ty = tile / tiles_x16;
-    const int lx = tx * 16 + (wave & 1) * 8 + (lane & 7);
-    const int ly = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
-    const bool valid = lx < p.roi_w && ly < p.roi_h;
-    const long long pix = (long long)ly * p.roi_w + lx;
-    const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
-    const float tf_o = -p.tf.vmin * tf_k;
-    LaneState s{0.f, 0.f, 0.f, 1.f, 0, false};
-    float depth = INFINITY;
-    RaySetup rs;
-    if (valid && setup_ray(p.cam, p.brick, p.dt, p.roi_x0 + lx, p.roi_y0 + ly, rs)) {
-        depth = (float)(((double)rs.kf + 0.5) * p.dt);
-        march_ray_direct<TS, false>(p, tft, rs, pix, tf_k, tf_o, p.ert_eps, s);
-    }
-    finish(p, valid, pix, depth, s, lane);
+template <typename TS, int NCW, int CH>
+__global__ __launch_bounds__((NCW + 1) * 64, 2) void march_queue_ring(QueueParams q) {
+    __shared__ RingShared<NCW> sh;
+    if (threadIdx.x == 0) sh.abort = 0;
+    int buf = 0;
+    // (ring_tile's first reduction barrier orders table writes before use)
+    queue_loop<TS>(q, sh, sh.tft, sh.ticket, false, [&](const MarchParams& p, int tile) {
+        ring_tile<TS, NCW, CH>(p, tile, sh, buf, q.err);
+    });
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void march_queue_slab(QueueParams q) {
+    __shared__ StagedShared sh;
+    int buf = 0;
+    // (slab_tile's first reduction barrier orders table writes before use)
+    queue_loop<TS>(q, sh, sh.tft, sh.ticket, false,
+                   [&](const MarchParams& p, int tile) { slab_tile<TS>(p, tile, sh, buf); });
+}
+
+struct DirectShared {
+    TFTable tft;
+    int ticket;
+};
+
+template <typename TS>
+__global__ __launch_bounds__(256) void march_queue_direct(QueueParams q) {
+    __shared__ DirectShared sh;
+    queue_loop<TS>(q, sh, sh.tft, sh.ticket, true,
+                   [&](const MarchParams& p, int tile) { direct_tile<TS>(p, tile, sh.tft); });
 }
 
 __global__ void queue_reset(int* head) {
@@ -684,52 +1514,111 @@ hipError_t launch_direct(const MarchParams& p, StorageK storage, hipStream_t str
     return hipGetLastError();
 }
 
-}  // namespace
-
-template <typename TS, bool kStaged>
-hipError_t launch_queue_t(const QueueParams& q, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL((march_queue<TS, kStaged>), dim3(grid), dim3(256), 0, stream, q);
-    return hipGetLastError();
+// Dispatch over the compiled staged configurations (tile width 16 or 32,
+// chunk 4 or 8 slices) and storage precisions.
+template <template <typename, int, int> class Fn, typename... A>
+auto staged_dispatch(StorageK storage, int tile_w, int chunk, A&&... a) {
+    const bool wide = tile_w == 32, long_chunk = chunk == 8;
+    if (storage == kF16) {
+        if (wide) return long_chunk ? Fn<__half, 8, 8>::run(a...) : Fn<__half, 8, 4>::run(a...);
+        return long_chunk ? Fn<__half, 4, 8>::run(a...) : Fn<__half, 4, 4>::run(a...);
+    }
+    if (wide) return long_chunk ? Fn<float, 8, 8>::run(a...) : Fn<float, 8, 4>::run(a...);
+    return long_chunk ? Fn<float, 4, 8>::run(a...) : Fn<float, 4, 4>::run(a...);
 }
 
-template <typename TS, bool kStaged>
-int queue_occupancy() {
+template <typename TS, int NCW, int CH>
+struct LaunchQueueRing {
+    static hipError_t run(const QueueParams& q, int grid, hipStream_t stream) {
+        hipLaunchKernelGGL((march_queue_ring<TS, NCW, CH>), dim3(grid), dim3((NCW + 1) * 64), 0, stream, q);
+        return hipGetLastError();
+    }
+};
+
+template <typename TS, int NCW, int CH>
+struct OccupancyRing {
+    static int run() {
+        int n = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue_ring<TS, NCW, CH>,
+                                                                    (NCW + 1) * 64, 0);
+        return (e == hipSuccess && n > 0) ? n : 1;
+    }
+};
+
+template <typename TS, int NCW, int CH>
+struct LaunchStaged {
+    static hipError_t run(const MarchParams& p, int blocks, hipStream_t stream) {
+        hipLaunchKernelGGL((march_staged<TS, NCW, CH>), dim3(blocks), dim3((NCW + 1) * 64), 0, stream, p);
+        return hipGetLastError();
+    }
+};
+
+template <typename TS>
+int occupancy_direct() {
     int n = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue<TS, kStaged>, 256, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue_direct<TS>, 256, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
+
+template <typename TS>
+int occupancy_slab() {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_queue_slab<TS>, 256, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace
 
 hipError_t launch_march_queue(const QueueParams& q, StorageK storage, int workgroups,
                               hipStream_t stream) {
     if (q.total_tiles <= 0) return hipSuccess;
+    if (q.staged && !valid_march_config(q.staging, q.tile_w, q.chunk)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, stream, q.head);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int grid = min(workgroups, q.total_tiles);
-    if (storage == kF16)
-        return q.staged ? launch_queue_t<__half, true>(q, grid, stream)
-                        : launch_queue_t<__half, false>(q, grid, stream);
-    return q.staged ? launch_queue_t<float, true>(q, grid, stream)
-                    : launch_queue_t<float, false>(q, grid, stream);
+    if (!q.staged) {
+        if (storage == kF16)
+            hipLaunchKernelGGL(march_queue_direct<__half>, dim3(grid), dim3(256), 0, stream, q);
+        else
+            hipLaunchKernelGGL(march_queue_direct<float>, dim3(grid), dim3(256), 0, stream, q);
+        return hipGetLastError();
+    }
+    if (q.staging == kStagingSlab) {
+        if (storage == kF16)
+            hipLaunchKernelGGL(march_queue_slab<__half>, dim3(grid), dim3(256), 0, stream, q);
+        else
+            hipLaunchKernelGGL(march_queue_slab<float>, dim3(grid), dim3(256), 0, stream, q);
+        return hipGetLastError();
+    }
+    return staged_dispatch<LaunchQueueRing>(storage, q.tile_w, q.chunk, q, grid, stream);
 }
 
-int march_queue_workgroups_per_cu(StorageK storage, bool staged) {
-    if (storage == kF16) return staged ? queue_occupancy<__half, true>() : queue_occupancy<__half, false>();
-    return staged ? queue_occupancy<float, true>() : queue_occupancy<float, false>();
+int march_queue_workgroups_per_cu(StorageK storage, bool staged, int staging, int tile_w, int chunk) {
+    if (!staged) return storage == kF16 ? occupancy_direct<__half>() : occupancy_direct<float>();
+    if (!valid_march_config(staging, tile_w, chunk)) return 1;
+    if (staging == kStagingSlab) return storage == kF16 ? occupancy_slab<__half>() : occupancy_slab<float>();
+    return staged_dispatch<OccupancyRing>(storage, tile_w, chunk);
 }
 
 hipError_t launch_march(const MarchParams& p, StorageK storage, hipStream_t stream) {
     if (p.ckpt) return launch_direct<true>(p, storage, stream);
     if (p.path == kPathDirect) return launch_direct<false>(p, storage, stream);
-    // staged: one workgroup per 16x16 tile; tiles_x/tiles_y count 16x16 tiles
-    MarchParams q = p;
-    q.tiles_x = (p.roi_w + 15) / 16;
-    q.tiles_y = (p.roi_h + 15) / 16;
-    const int blocks = q.tiles_x * q.tiles_y;
+    if (!valid_march_config(p.staging, p.tile_w, p.chunk)) return hipErrorInvalidValue;
+    // staged: one workgroup per tile_w x 16 tile
+    const int blocks = queue_tiles(p.roi_w, p.roi_h, p.tile_w);
     if (blocks == 0) return hipSuccess;
-    if (storage == kF16)
-        hipLaunchKernelGGL(march_staged<__half>, dim3(blocks), dim3(256), 0, stream, q);
-    else
-        hipLaunchKernelGGL(march_staged<float>, dim3(blocks), dim3(256), 0, stream, q);
-    return hipGetLastError();
+    if (p.staging == kStagingSlab) {
+        MarchParams q = p;
+        q.tiles_x = (p.roi_w + 15) / 16;
+        q.tiles_y = (p.roi_h + 15) / 16;
+        if (storage == kF16)
+            hipLaunchKernelGGL(march_slab_single<__half>, dim3(blocks), dim3(256), 0, stream, q);
+        else
+            hipLaunchKernelGGL(march_slab_single<float>, dim3(blocks), dim3(256), 0, stream, q);
+        return hipGetLastError();
+    }
+    return staged_dispatch<LaunchStaged>(storage, p.tile_w, p.chunk, p, blocks, stream);
 }
 
 }  // namespace dpvr

@@ -28,9 +28,40 @@ __device__ inline bool owned(const double o[3], const double d[3], double t, con
     return p0 >= lo[0] && p0 < hi[0] && p1 >= lo[1] && p1 < hi[1] && p2 >= lo[2] && p2 < hi[2];
 }
 
+// Camera ray (origin o, unit direction d) through the centre of pixel
+// (px, py).  float64, no contraction, in the operation order of the
+// documented formulas (the same expressions as setup_ray).
+struct CamRay {
+    double o[3], d[3];
+};
+
+__device__ inline CamRay camera_ray(const CameraK& cam, int px, int py) {
+#pragma clang fp contract(off)
+    const double W = (double)cam.width, H = (double)cam.height;
+    const double sx = (2.0 * ((double)px + 0.5)) / W - 1.0;
+    const double sy = 1.0 - (2.0 * ((double)py + 0.5)) / H;
+    const double x = sx * cam.ax, y = sy * cam.ay;
+    CamRay r;
+    if (cam.kind == 0) {
+        double d0 = (cam.f[0] + x * cam.r[0]) + y * cam.u[0];
+        double d1 = (cam.f[1] + x * cam.r[1]) + y * cam.u[1];
+        double d2 = (cam.f[2] + x * cam.r[2]) + y * cam.u[2];
+        double n = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        r.d[0] = d0 / n; r.d[1] = d1 / n; r.d[2] = d2 / n;
+        r.o[0] = cam.eye[0]; r.o[1] = cam.eye[1]; r.o[2] = cam.eye[2];
+    } else {
+        r.o[0] = (cam.eye[0] + x * cam.r[0]) + y * cam.u[0];
+        r.o[1] = (cam.eye[1] + x * cam.r[1]) + y * cam.u[1];
+        r.o[2] = (cam.eye[2] + x * cam.r[2]) + y * cam.u[2];
+        r.d[0] = cam.f[0]; r.d[1] = cam.f[1]; r.d[2] = cam.f[2];
+    }
+    return r;
+}
+
 // Camera ray through pixel (px, py) and the brick's owned run [kf, kl] of the
-// global lattice t_k = (k + 1/2) dt.  float64, no contraction, in the
-// operation order of the documented formulas.
+// global lattice t_k = (k + 1/2) dt.  float64, no contraction; the same
+// expressions as camera_ray (written out: storing through array pointers
+// there would keep the ray in scratch memory).
 __device__ inline bool setup_ray(const CameraK& cam, const BrickK& b, double dt, int px, int py,
                                  RaySetup& rs) {
 #pragma clang fp contract(off)

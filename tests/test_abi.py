@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_status_strings():
-    assert dp.vr_abi_version() == 1
+    assert dp.vr_abi_version() == 2
     assert dp.vr_status_string(dp.VR_ERR_WORKSPACE) == "VR_ERR_WORKSPACE"
     assert dp.vr_status_string(12345) == "VR_ERR_UNKNOWN"
 

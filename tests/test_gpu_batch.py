@@ -99,8 +99,8 @@ def test_autotune_keeps_bits_and_replays_are_stable(dp, c3_small, tmp_path, monk
     monkeypatch.setenv("DPVR_AUTOTUNE_CACHE", str(cache))
     ms = br.autotune(reps=2)
     assert ms > 0 and cache.exists()
-    wg, order = br.config()
-    assert wg >= 1 and order in (0, 1)
+    wg, order, staging, tile_w, chunk = br.config()
+    assert wg >= 1 and order in (0, 1) and staging in (0, 1) and tile_w in (16, 32) and chunk in (4, 8)
     for rep in range(4):
         # eager work and a synchronisation between replays
         for fr in br.frames:

@@ -214,12 +214,16 @@ def test_fp16_storage(dp):
 
 
 # --------------------------------------------------------------- composite
-@pytest.mark.parametrize("n,seed", [(1, 1), (7, 2), (64, 3)])
-def test_composite_kernel_random_partials(dp, n, seed):
+@pytest.mark.parametrize("n,seed,ties", [(1, 1, False), (7, 2, False), (64, 3, False), (7, 4, True),
+                                         (64, 5, True)])
+def test_composite_kernel_random_partials(dp, n, seed, ties):
     """Random ROIs (ragged, overlapping, some empty pixels, +inf keys) and
-    random premultiplied values: the GPU composite equals the oracle's."""
+    random premultiplied values: the GPU composite equals the oracle's.  With
+    ``ties`` the keys take three values only, so most pixels hold equal keys
+    of several partials (taken in partial-index order) and more than four
+    finite keys."""
     rng = np.random.default_rng(seed)
-    W, H = 77, 45
+    W, H = (150, 37) if ties else (77, 45)
     ctx = dp.vr_context_create(0, torch.cuda.current_stream())
     dp.vr_set_camera_perspective(ctx, (0, 0, 10.0), (0, 0, 0), (0, 1.0, 0), 45.0, W, H)
     parts, bufs, ref_parts = [], [], []
@@ -229,7 +233,10 @@ def test_composite_kernel_random_partials(dp, n, seed):
         A = rng.uniform(0, 1, (h, w)).astype(np.float32)
         rgb = (A[..., None] * rng.uniform(0, 1, (h, w, 3))).astype(np.float32)
         rgba = np.concatenate([rgb, A[..., None]], -1)
-        depth = rng.uniform(0.0, 1000.0, (h, w)).astype(np.float32)
+        if ties:
+            depth = rng.integers(0, 3, (h, w)).astype(np.float32)
+        else:
+            depth = rng.uniform(0.0, 1000.0, (h, w)).astype(np.float32)
         depth[rng.uniform(0, 1, (h, w)) < 0.2] = np.inf
         rgba[np.isinf(depth)] = 0
         tr = torch.from_numpy(rgba).cuda().contiguous()
@@ -278,15 +285,20 @@ def test_state_errors(dp):
     (203, (40, 40, 40), 4, 72, 64, 90.0, 0.0, 2.0, 0.5),      # view along -x: HBM fallback
     (204, (60, 40, 30), 7, 64, 64, 200.0, -50.0, 1.3, 0.25),  # y slabs, negative direction
 ])
-def test_staged_equals_direct_bitwise(dp, seed, dims, nb, w, h, az, el, radius, step):
-    """The LDS-staged march and the direct march evaluate every sample at the
-    same float32 position from the same voxel values, so partial images and
-    sample counts are bit-identical; both match the oracle."""
+@pytest.mark.parametrize("config", [(0, 16, 4), (1, 16, 4), (1, 16, 8), (1, 32, 4), (1, 32, 8)],
+                         ids=["slab", "ring16x4", "ring16x8", "ring32x4", "ring32x8"])
+def test_staged_equals_direct_bitwise(dp, seed, dims, nb, w, h, az, el, radius, step, config):
+    """The LDS-staged march (slab staging, and ring staging with every tile
+    width x chunk length) and the direct
+    march evaluate every sample at the same float32 position from the same
+    voxel values, so partial images and sample counts are bit-identical; both
+    match the oracle."""
     sc = _scene_small(seed, dims, nb, w, h, az, el, radius, scale=3.0, step=step)
     out = []
     for path in (dp.VR_PATH_STAGED, dp.VR_PATH_DIRECT):
         bricks = [(b.voxels, b.lo) for b in sc.bricks]
-        r = dp.Renderer(bricks, sc.tf, sc.vrange, sc.opacity_scale, sc.step, path=path)
+        r = dp.Renderer(bricks, sc.tf, sc.vrange, sc.opacity_scale, sc.step, path=path,
+                        march_config=config)
         r.reset_samples()
         img, parts = _gpu_frame(r, sc.camera, BG)
         counts = r.sample_counts()
@@ -302,15 +314,18 @@ def test_staged_equals_direct_bitwise(dp, seed, dims, nb, w, h, az, el, radius, 
     assert np.max(np.abs(ia - ref)) <= TOL32
 
 
-def test_staged_fp16_and_inside_camera(dp):
-    """FP16 storage (staged as float32) and a camera inside the volume (large
-    per-slab footprints that may exceed LDS and fall back)."""
+@pytest.mark.parametrize("config", [(0, 16, 4), (1, 16, 4), (1, 32, 8)],
+                         ids=["slab", "ring16x4", "ring32x8"])
+def test_staged_fp16_and_inside_camera(dp, config):
+    """FP16 storage (staged raw, decoded at read) and a camera inside the
+    volume (large per-slice footprints that may exceed the ring and fall
+    back)."""
     sc = _scene_small(205, (48, 40, 36), 6, 64, 56, scale=3.0)
     cam = synth.inside_camera((0, 0, 0), (48, 40, 36), 64, 56, fovy_deg=80.0)
     outs = []
     for path in (dp.VR_PATH_STAGED, dp.VR_PATH_DIRECT):
         r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange, sc.opacity_scale,
-                        sc.step, storage=dp.VR_F16, path=path)
+                        sc.step, storage=dp.VR_F16, path=path, march_config=config)
         outs.append(_gpu_frame(r, cam, BG)[0])
         r.close()
     assert np.array_equal(outs[0], outs[1])
