@@ -224,6 +224,65 @@ def calibration_copy():
     log(f"calibration copy: {CALIB_BYTES} B read + written by the ingest kernel")
 
 
+def host_info():
+    """Host the oracle runs on: logical CPUs, the CPUs this process may use,
+    and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def copy_bandwidth_gbs(nbytes=1 << 30, reps=10):
+    """Streaming-copy bandwidth of this GPU (a 1 GiB device-to-device copy,
+    read + write bytes per second), measured live for the HBM fractions."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / t / 1e9
+
+
+def _oracle_rates(run, target_s, unit_scale, first=2000, cap=None):
+    """Time ``run(n) -> (seconds, work, payload)`` on a sample sized for
+    about target_s seconds (at most cap) with all of the oracle's threads,
+    then on a smaller sample with one thread.  Rates are work / s *
+    unit_scale."""
+    import oracle
+    t, _, _ = run(first)
+    n = max(first, int(first * target_s / max(t, 1e-3)))
+    if cap is not None:
+        n = min(n, cap)
+    t, work, payload = run(n)
+    cores = oracle.threads()
+    n1 = max(first // 4, int(n * min(1.0, (target_s / 4) / max(t * cores, 1e-3))))
+    oracle.set_threads(1)
+    try:
+        t1, work1, _ = run(n1)
+    finally:
+        oracle.set_threads(cores)
+    return {"value": work / t * unit_scale, "cores": cores, "n": n, "seconds": t, "work": work,
+            "one_core_value": work1 / t1 * unit_scale, "one_core_n": n1, "one_core_seconds": t1,
+            "payload": payload}
+
+
 def cpu_baseline(sc, target_s, frame=None):
     """The oracle timed on a random pixel sample of the frame; with the GPU
     frame given, also its max error against the oracle at those pixels."""
@@ -231,25 +290,100 @@ def cpu_baseline(sc, target_s, frame=None):
     import oracle
     W, H = sc.camera["width"], sc.camera["height"]
     rng = np.random.default_rng(0)
-    # calibrate on a sample of ~1 s, then size the measured sample
+
     def run(npix):
-        idx = rng.choice(W * H, npix, replace=False)
+        idx = rng.choice(W * H, min(npix, W * H), replace=False)
         pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
         t0 = time.perf_counter()
         img, _, cnt = oracle.render_scene(sc, pixels=pix)
-        return time.perf_counter() - t0, int(cnt[0]), pix, img
-    t, _, _, _ = run(20000)
-    npix = int(min(W * H, max(20000, 20000 * target_s / max(t, 1e-3))))
-    t, samples, pix, img = run(npix)
-    cores = oracle.threads()
-    out = {"value": samples / t / 1e6, "unit": "Msamples/s", "cores": cores, "kind": "oracle",
-           "sample": f"{npix} random pixels of the same frame, all {len(sc.bricks)} bricks + "
-                     f"composite, {samples} samples (no early termination) in {t:.1f} s"}
+        return time.perf_counter() - t0, int(cnt[0]), (pix, img)
+    r = _oracle_rates(run, target_s, 1e-6, first=20000, cap=W * H)
+    pix, img = r["payload"]
+    out = {"value": r["value"], "unit": "Msamples/s", "cores": r["cores"], "kind": "oracle",
+           "sample": f"{len(pix)} random pixels of the same frame, all {len(sc.bricks)} bricks + "
+                     f"composite, {r['work']} samples (no early termination) in {r['seconds']:.1f} s",
+           "one_core_value": r["one_core_value"],
+           "one_core_sample": f"{min(r['one_core_n'], W * H)} random pixels, one thread, "
+                              f"{r['one_core_seconds']:.1f} s",
+           **host_info()}
     err = None
     if frame is not None:
         got = frame[pix[:, 1], pix[:, 0]].astype(np.float64)
         err = float(np.max(np.abs(got - img)))
     return out, err
+
+
+def _c3_oracle_frame(d, frame, pix):
+    """Oracle image of one C3 frame at pixels pix, and its owned samples."""
+    import oracle
+    t, f, c, ids = frame
+    cam = d["cameras"][c]
+    parts, samples = [], 0
+    for i in ids:
+        _, _, _, lo, vox = d["bricks"][i]
+        nz, ny, nx = (s - 2 for s in vox.shape)
+        rgba, depth, cnt = oracle.render_brick(cam, vox, (nx, ny, nz), 1, lo, (1, 1, 1), d["tf"], (0, 1),
+                                               d["opacity_scale"], d["step"], 0.0, pix)
+        parts.append((rgba, depth))
+        samples += int(cnt[0])
+    return oracle.composite(parts, (0.0, 0.0, 0.0, 0.0)), samples
+
+
+def c3_pixel_sets(d, frame_list, target_s):
+    """A seeded random pixel sample of every frame, sized so that the oracle
+    renders all of them in about target_s seconds."""
+    rng = np.random.default_rng(11)
+    probe = frame_list[:: max(1, len(frame_list) // 4)]
+    t0 = time.perf_counter()
+    for fr in probe:
+        cam = d["cameras"][fr[2]]
+        idx = rng.choice(cam["width"] * cam["height"], 8000, replace=False)
+        _c3_oracle_frame(d, fr, np.stack([idx % cam["width"], idx // cam["width"]], 1).astype(np.int32))
+    per_px = (time.perf_counter() - t0) / (8000 * len(probe))
+    W, H = d["cameras"][0]["width"], d["cameras"][0]["height"]
+    n = int(min(W * H, max(500, target_s / (len(frame_list) * per_px))))
+    sets = []
+    for t, f, c, ids in frame_list:
+        W, H = d["cameras"][c]["width"], d["cameras"][c]["height"]
+        idx = rng.choice(W * H, min(n, W * H), replace=False)
+        sets.append(np.stack([idx % W, idx // W], 1).astype(np.int32))
+    return sets
+
+
+def c3_oracle(d, frame_list, pix_sets, gpu_px, target_s):
+    """The oracle on the pixel sample of all 72 frames (timed with all
+    threads, then a part of it with one), and the per-frame max error of the
+    float32 and float16 batches against it (float16 against the oracle on
+    the original float32 field)."""
+    import oracle
+    errs = {k: [] for k in gpu_px}
+    t0 = time.perf_counter()
+    samples = 0
+    for fi, (frame, pix) in enumerate(zip(frame_list, pix_sets)):
+        ref, n = _c3_oracle_frame(d, frame, pix)
+        samples += n
+        for k in gpu_px:
+            errs[k].append(float(np.max(np.abs(gpu_px[k][fi] - ref))))
+    t = time.perf_counter() - t0
+    cores = oracle.threads()
+    # one thread on the first frames' samples, about target_s / 4 seconds
+    n1 = max(1, int(len(frame_list) * min(1.0, (target_s / 4) / max(t * cores, 1e-3))))
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        s1 = sum(_c3_oracle_frame(d, frame_list[i], pix_sets[i])[1] for i in range(n1))
+        t1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
+    npx = sum(len(p) for p in pix_sets)
+    out = {"value": samples / t / 1e6, "unit": "Msamples/s", "cores": cores, "kind": "oracle",
+           "sample": f"{npx} seeded random pixels over all {len(frame_list)} frames "
+                     f"({len(pix_sets[0])} per frame), 14 bricks each + composite, {samples} samples "
+                     f"(no early termination) in {t:.1f} s",
+           "one_core_value": s1 / t1 / 1e6,
+           "one_core_sample": f"the first {n1} frames' pixel samples, one thread, {t1:.1f} s",
+           **host_info()}
+    return out, errs
 
 
 def bench_batch(args):
@@ -274,6 +408,17 @@ def bench_batch(args):
            "config": {"workload": "c3: 14 uneven bricks (U{64..320}^3) x 6 time steps x 3 fields x "
                                   "4 cameras at 1024x1024, step 0.5, opacity 0.1; 1008 partials, "
                                   "72 frames of 14-partial sort-last composites"}}
+    # frames in add_frame order, and a seeded pixel sample of each for the
+    # oracle (per-image errors of both storages + the CPU baseline)
+    frame_list = []
+    for (t, f) in keys:
+        ids = [i for i, (tt, ff, _, _, _) in enumerate(d["bricks"]) if (tt, ff) == (t, f)]
+        for c in range(len(d["cameras"])):
+            frame_list.append((t, f, c, ids))
+    pix_sets = None
+    if not args.no_cpu_baseline:
+        pix_sets = c3_pixel_sets(d, frame_list, args.cpu_seconds)
+    gpu_px = {}
     results = {}
     for storage in ("f32", "f16"):
         st = dp.VR_F16 if storage == "f16" else dp.VR_F32
@@ -302,6 +447,15 @@ def bench_batch(args):
         batch_ms = e0.elapsed_time(e1) / args.steps
         samples = int(br.samples.sum().item()) // args.steps
         wg, order, staging, tile_w, chunk = br.config()
+        if pix_sets is not None:
+            gpu_px[storage] = [br.frames[fi][torch.from_numpy(px[:, 1]).long().cuda(),
+                                             torch.from_numpy(px[:, 0]).long().cuda()].double().cpu().numpy()
+                               for fi, px in enumerate(pix_sets)]
+        elt = 2 if storage == "f16" else 4
+        roi_px = sum(w * h for (_, _, w, h), _, _ in br.parts)
+        vol_bytes = sum(int(np.prod(vox.shape)) * elt for (_, _, _, _, vox) in d["bricks"])
+        frame_px = sum(d["cameras"][c]["width"] * d["cameras"][c]["height"] for _, _, c, _ in frame_list)
+        batch_alg = vol_bytes + roi_px * 40 + frame_px * 16
         # plain path on the same bricks: per frame, one march launch per brick + a composite,
         # with the launch shape the batch was tuned to
         ctx = br.ctx
@@ -332,7 +486,13 @@ def bench_batch(args):
         e1.record(br.stream)
         torch.cuda.synchronize()
         plain_ms = e0.elapsed_time(e1) / plain_steps
+        achieved = batch_alg / (batch_ms * 1e-3) / 1e9
         results[storage] = {"batch_ms": batch_ms, "plain_ms": plain_ms, "samples": samples,
+                            "roofline": {"kernel": "batch graph (march_queue over all 1008 partials "
+                                                   "+ composite_many over all 72 frames)",
+                                         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                         "traffic": None, "algorithmic_bytes_per_batch": int(batch_alg)},
                             "autotune": {"wg_per_cu": wg, "order": ["as given", "by brick"][order],
                                          "staging": ["slab", "ring"][staging],
                                          "tile_width": tile_w, "chunk_slices": chunk,
@@ -346,6 +506,20 @@ def bench_batch(args):
     out["value"] = results["f32"]["msamples_per_s"]
     out["ms_per_step"] = results["f32"]["batch_ms"]
     out["storage"] = results
+    copy_gbs = copy_bandwidth_gbs()
+    r32 = results["f32"]["roofline"]
+    out["roofline"] = {**r32, "copy_gbs": copy_gbs, "frac_of_copy": r32["achieved"] / copy_gbs}
+    if pix_sets is not None:
+        log("c3 oracle on the pixel sample of every frame ...")
+        out["cpu_baseline"], errs = c3_oracle(d, frame_list, pix_sets, gpu_px, args.cpu_seconds)
+        out["per_image_max_abs_err_vs_oracle"] = {
+            "pixels": "a seeded random sample of every frame (count in cpu_baseline.sample)",
+            "f32": [float("%.3g" % e) for e in errs["f32"]],
+            "f16": [float("%.3g" % e) for e in errs["f16"]],
+            "max_f32": max(errs["f32"]), "max_f16": max(errs["f16"]),
+            "bars": {"f32": 1e-5, "f16 (vs the float32 field)": 2e-3}}
+    else:
+        out["cpu_baseline"] = None
     out["f16_vs_f32_batch_speedup"] = results["f32"]["batch_ms"] / results["f16"]["batch_ms"]
     out["f16_batch_vs_f32_plain_speedup"] = results["f32"]["plain_ms"] / results["f16"]["batch_ms"]
     print(json.dumps(out), flush=True)
@@ -430,14 +604,99 @@ def bench_adjoint(args):
     targets = [torch.rand((c["height"], c["width"], 4), device="cuda", generator=g) for c in cams]
     fwd_ms, step_ms = _time_gradient_steps(args, dr, tf, vol, cams, targets, (0.1, 0.2, 0.3, 1.0))
     dr.close()
+    del vol, targets
+    torch.cuda.empty_cache()
+    # owned samples of all views (the forward march's counter, early
+    # termination off): the nominal sample count of one gradient step
+    r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], synth.default_tf(), sc.vrange, sc.opacity_scale,
+                    sc.step, ert_eps=0.0, storage=storage, device=0)
+    samples = 0
+    for cam in cams:
+        r.set_camera(cam)
+        r.reset_samples()
+        r.render()
+        samples += int(r.sample_counts().sum())
+    r.close()
+    del r
+    torch.cuda.empty_cache()
+    evals = 3     # checkpointed forward, segment re-march, adjoint walk
+    lane_ops = samples * evals * VALU_LANE_OPS_PER_SAMPLE
+    achieved = lane_ops / (step_ms * 1e-3)
+    peak = VALU_LANES_PER_CU_CYCLE * N_CU * CLOCK_HZ
     out = {"metric": f"ms per gradient step ({len(cams)}-view forward with checkpoints + backward)",
            "value": step_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": step_ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic", "config": {"workload": desc},
            "forward_ms": fwd_ms, "backward_ms": step_ms - fwd_ms,
-           "views_per_s": len(cams) * 1e3 / step_ms}
+           "backward_over_forward": (step_ms - fwd_ms) / fwd_ms,
+           "views_per_s": len(cams) * 1e3 / step_ms, "samples_per_step": samples,
+           "roofline": {"kernel": "march_checkpointed + march_backward (+ composite and its backward)",
+                        "bound": "alu", "achieved": achieved, "peak": peak, "unit": "lane-op/s",
+                        "frac": achieved / peak, "traffic": None,
+                        "model": f"{VALU_LANE_OPS_PER_SAMPLE} VALU lane-ops per sample evaluation, "
+                                 f"{evals} evaluations per owned sample per step (checkpointed forward, "
+                                 f"segment re-march, adjoint walk); peak = 64 lanes/CU/cycle x 256 CUs "
+                                 f"x 2.4 GHz, unpacked fp32"}}
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle gradient on a central crop) ...")
+        out["cpu_baseline"] = adjoint_cpu_baseline(sc, cams, args.cpu_seconds, samples)
     print(json.dumps(out), flush=True)
     return 0
+
+
+VALU_LANE_OPS_PER_SAMPLE = 48
+
+
+def _crop_camera(cam, side):
+    """The central side x side pixels of a perspective view as a camera of
+    its own (same pixel rays)."""
+    import math
+    c = dict(cam)
+    half = math.tan(math.radians(cam["fovy_deg"]) / 2.0) * side / cam["height"]
+    c.update(width=side, height=side, fovy_deg=math.degrees(2.0 * math.atan(half)))
+    return c
+
+
+def adjoint_cpu_baseline(sc, cams, target_s, samples_per_step):
+    """The oracle's reverse-mode gradient (forward + adjoint for the table
+    and the voxels, every brick) on a central crop of the first view with a
+    seeded upstream gradient, scaled by owned samples (the crop's, counted by
+    the oracle, against the step's) to ms per gradient step over all views
+    (the composite backward is not included)."""
+    import oracle
+    rng = np.random.default_rng(5)
+
+    def run(side):
+        cam = _crop_camera(cams[0], side)
+        g = rng.uniform(-1.0, 1.0, (side, side, 4))
+        t0 = time.perf_counter()
+        for b in sc.bricks:
+            oracle.render_brick_grad(cam, b.voxels, b.dims, b.ghost, b.origin, (1.0, 1.0, 1.0), sc.tf,
+                                     sc.vrange, sc.opacity_scale, sc.step, g)
+        t = time.perf_counter() - t0
+        n = sum(int(oracle.render_brick(cam, b.voxels, b.dims, b.ghost, b.origin, (1.0, 1.0, 1.0), sc.tf,
+                                        sc.vrange, sc.opacity_scale, sc.step)[2][0]) for b in sc.bricks)
+        return t, max(n, 1)
+
+    side = 16
+    t, _ = run(side)
+    side = int(min(cams[0]["height"], max(16, side * (target_s / max(t, 1e-3)) ** 0.5)))
+    t, n = run(side)
+    cores = oracle.threads()
+    side1 = max(8, int(side * min(1.0, (target_s / 4 / max(t * cores, 1e-3))) ** 0.5))
+    oracle.set_threads(1)
+    try:
+        t1, n1 = run(side1)
+    finally:
+        oracle.set_threads(cores)
+    return {"value": t * samples_per_step / n * 1e3, "unit": "ms", "cores": cores, "kind": "oracle",
+            "sample": f"central {side}x{side} crop of view 0 ({n} owned samples), all {len(sc.bricks)} "
+                      f"bricks' table and voxel gradients in {t:.1f} s, scaled to the step's "
+                      f"{samples_per_step} owned samples",
+            "one_core_value": t1 * samples_per_step / n1 * 1e3,
+            "one_core_sample": f"central {side1}x{side1} crop ({n1} owned samples), one thread, {t1:.1f} s",
+            **host_info()}
 
 
 def main():
@@ -563,6 +822,11 @@ def main():
     r.close()
     del r
     torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth_gbs()
+    out["roofline"]["copy_gbs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = achieved / copy_gbs
+    out["composite_roofline"]["frac"] = out["composite_roofline"]["achieved"] / HBM_PEAK_GBS
+    out["composite_roofline"]["frac_of_copy"] = out["composite_roofline"]["achieved"] / copy_gbs
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"], err = cpu_baseline(sc, args.cpu_seconds, frame)

@@ -86,6 +86,8 @@ def _load():
                                                  C.POINTER(_TF), C.c_double, _dp, _dp, _dp]
             lib.oc_render_brick_grad.restype = C.c_int
             lib.oc_threads.restype = C.c_int
+            lib.oc_set_threads.argtypes = [C.c_int]
+            lib.oc_set_threads.restype = None
             _lib = lib
     return _lib
 
@@ -144,6 +146,11 @@ class _TFRef:
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().oc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops from now on."""
+    _load().oc_set_threads(int(n))
 
 
 def ray(cam: dict, i: int, j: int):

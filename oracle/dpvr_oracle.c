@@ -477,3 +477,12 @@ int oc_threads(void) {
     return 1;
 #endif
 }
+
+/* Set the thread count of the parallel loops (for a one-core timing). */
+void oc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -1,0 +1,250 @@
+// Drives the library's host code (linked with the host-memory HIP stand-in)
+// through valid calls and every kind of rejected argument, under
+// AddressSanitizer / UndefinedBehaviorSanitizer.  Prints one line per
+// failed expectation and exits non-zero if there was any.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "dpvr.h"
+
+static int g_fail = 0;
+#define EXPECT(cond)                                                             \
+    do {                                                                         \
+        if (!(cond)) {                                                           \
+            std::printf("FAILED line %d: %s\n", __LINE__, #cond);               \
+            ++g_fail;                                                            \
+        }                                                                        \
+    } while (0)
+
+static void* aligned_buf(size_t bytes) {
+    void* p = nullptr;
+    if (posix_memalign(&p, 256, bytes ? bytes : 256) != 0) std::abort();
+    std::memset(p, 0, bytes ? bytes : 256);
+    return p;
+}
+
+int main() {
+    EXPECT(vr_abi_version() == DPVR_ABI_VERSION);
+    for (int s = -8; s <= 1; ++s) EXPECT(vr_status_string((vr_status)s) != nullptr);
+
+    // workspace sizes: valid, degenerate, overflowing
+    size_t bytes = 0;
+    const int32_t d_ok[3] = {30, 20, 10}, d_zero[3] = {0, 4, 4}, d_huge[3] = {2048, 2048, 2048};
+    EXPECT(vr_brick_workspace_size(d_ok, 1, VR_F32, &bytes) == VR_OK && bytes > 0);
+    EXPECT(vr_brick_workspace_size(d_zero, 1, VR_F32, &bytes) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_brick_workspace_size(d_ok, 2, VR_F32, &bytes) != VR_OK);
+    EXPECT(vr_brick_workspace_size(d_huge, 1, VR_F16, &bytes) == VR_ERR_UNSUPPORTED);
+    EXPECT(vr_brick_workspace_size(nullptr, 1, VR_F32, &bytes) != VR_OK);
+    EXPECT(vr_frame_workspace_size(-1, &bytes) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_frame_workspace_size(64, &bytes) == VR_OK && bytes > 0);
+    EXPECT(vr_batch_workspace_size(-1, 1, &bytes) != VR_OK);
+
+    // context
+    vr_context ctx = nullptr;
+    EXPECT(vr_context_create(5, nullptr, &ctx) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_context_create(0, nullptr, &ctx) == VR_OK && ctx);
+    EXPECT(vr_last_error(ctx) != nullptr);
+    EXPECT(vr_set_render_params(ctx, -1.0, 0.0f) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_render_params(ctx, NAN, 0.0f) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_render_params(ctx, 0.5, 1.5f) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_render_params(ctx, 0.5, 0.0f) == VR_OK);
+    EXPECT(vr_set_march_path(ctx, (vr_path)7) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_march_config(ctx, VR_F32, VR_STAGING_SLAB, 32, 4) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_march_config(ctx, VR_F32, VR_STAGING_RING, 24, 4) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_march_config(ctx, (vr_dtype)3, VR_STAGING_RING, 32, 4) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_march_config(ctx, VR_F16, VR_STAGING_RING, 16, 8) == VR_OK);
+
+    // transfer function
+    std::vector<float> tf(256 * 4, 0.5f);
+    EXPECT(vr_set_transfer_function(ctx, tf.data(), 255, 0.f, 1.f, 1.f) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_transfer_function(ctx, tf.data(), 256, 1.f, 0.f, 1.f) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_transfer_function(ctx, tf.data(), 256, 0.f, 1.f, -1.f) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_transfer_function(ctx, tf.data(), 256, 0.f, 1.f, 1.f) == VR_OK);
+
+    // bricks: two float32, one float16
+    const int32_t dims[3][3] = {{30, 20, 10}, {17, 20, 10}, {8, 8, 33}};
+    const double origins[3][3] = {{0, 0, 0}, {30, 0, 0}, {0, 20, 0}};
+    const double spacing[3] = {1, 1, 1};
+    vr_brick bricks[3];
+    void* ws[3];
+    for (int i = 0; i < 3; ++i) {
+        const vr_dtype st = i == 2 ? VR_F16 : VR_F32;
+        EXPECT(vr_brick_workspace_size(dims[i], 1, st, &bytes) == VR_OK);
+        ws[i] = aligned_buf(bytes);
+        vr_brick b = nullptr;
+        EXPECT(vr_brick_create(ctx, dims[i], 1, origins[i], spacing, st, ws[i], bytes - 1, &b) ==
+               VR_ERR_WORKSPACE);
+        EXPECT(vr_brick_create(ctx, dims[i], 1, origins[i], spacing, st,
+                               static_cast<char*>(ws[i]) + 4, bytes, &b) == VR_ERR_WORKSPACE);
+        const double bad_sp[3] = {1, 0, 1};
+        EXPECT(vr_brick_create(ctx, dims[i], 1, origins[i], bad_sp, st, ws[i], bytes, &b) ==
+               VR_ERR_INVALID_ARG);
+        EXPECT(vr_brick_create(ctx, dims[i], 1, origins[i], spacing, st, ws[i], bytes, &bricks[i]) == VR_OK);
+        std::vector<float> vox((size_t)(dims[i][0] + 2) * (dims[i][1] + 2) * (dims[i][2] + 2), 0.25f);
+        EXPECT(vr_brick_set_data(bricks[i], vox.data()) == VR_OK);
+    }
+    const int32_t vol[3] = {47, 40, 33}, lo_ok[3] = {0, 0, 0}, lo_bad[3] = {40, 0, 0};
+    std::vector<float> volume((size_t)vol[0] * vol[1] * vol[2], 0.5f);
+    EXPECT(vr_brick_set_data_global(bricks[0], volume.data(), vol, lo_ok) == VR_OK);
+    EXPECT(vr_brick_set_data_global(bricks[0], volume.data(), vol, lo_bad) == VR_ERR_INVALID_ARG);
+
+    // no camera yet
+    int32_t roi[4];
+    EXPECT(vr_partial_roi(ctx, bricks[0], roi) == VR_ERR_STATE);
+    const double eye[3] = {23, 20, -80}, tgt[3] = {23, 20, 16}, up[3] = {0, 1, 0}, up_bad[3] = {0, 0, 1};
+    EXPECT(vr_set_camera_perspective(ctx, eye, eye, up, 45, 64, 48) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_camera_perspective(ctx, eye, tgt, up_bad, 45, 64, 48) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_camera_perspective(ctx, eye, tgt, up, 180, 64, 48) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_camera_perspective(ctx, eye, tgt, up, 45, 0, 48) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_set_camera_perspective(ctx, eye, tgt, up, 45, 64, 48) == VR_OK);
+
+    // partials of the frame
+    vr_partial parts[3];
+    std::vector<void*> bufs;
+    for (int i = 0; i < 3; ++i) {
+        EXPECT(vr_partial_roi(ctx, bricks[i], roi) == VR_OK);
+        EXPECT(roi[0] >= 0 && roi[1] >= 0 && roi[0] + roi[2] <= 64 && roi[1] + roi[3] <= 48);
+        const size_t px = (size_t)(roi[2] > 0 ? roi[2] : 1) * (roi[3] > 0 ? roi[3] : 1);
+        float* rgba = static_cast<float*>(aligned_buf(px * 16));
+        float* depth = static_cast<float*>(aligned_buf(px * 4));
+        bufs.push_back(rgba);
+        bufs.push_back(depth);
+        parts[i] = vr_partial{roi[0], roi[1], roi[2], roi[3], rgba, depth, nullptr};
+        EXPECT(vr_render_partial(ctx, bricks[i], &parts[i]) == VR_OK);
+    }
+    vr_partial bad = parts[0];
+    bad.x0 = 60;
+    bad.w = 10;                                     // past the frame's right edge
+    EXPECT(vr_render_partial(ctx, bricks[0], &bad) == VR_ERR_INVALID_ARG);
+    bad = parts[0];
+    bad.rgba = reinterpret_cast<float*>(reinterpret_cast<char*>(bad.rgba) + 4);   // misaligned
+    EXPECT(vr_render_partial(ctx, bricks[0], &bad) == VR_ERR_INVALID_ARG);
+
+    // the frame queue with a workspace, then without
+    EXPECT(vr_frame_workspace_size(3, &bytes) == VR_OK);
+    void* fws = aligned_buf(bytes);
+    EXPECT(vr_render_partials(ctx, 3, bricks, parts, fws, bytes - 1) == VR_ERR_WORKSPACE);
+    EXPECT(vr_render_partials(ctx, 3, bricks, parts, fws, bytes) == VR_OK);
+    EXPECT(vr_render_partials(ctx, 3, bricks, parts, fws, bytes) == VR_OK);   // both pinned slots
+    EXPECT(vr_render_partials(ctx, 0, nullptr, nullptr, nullptr, 0) == VR_OK);
+    EXPECT(vr_render_partials_static(ctx, 3, bricks, parts) == VR_OK);
+    EXPECT(vr_render_partials_static(ctx, 65, bricks, parts) == VR_ERR_INVALID_ARG);
+    // a frame of more partials than the pinned slots hold at first (they grow)
+    {
+        const int n = 200;
+        std::vector<vr_brick> bb(n, bricks[1]);
+        std::vector<vr_partial> pp(n, parts[1]);
+        EXPECT(vr_frame_workspace_size(n, &bytes) == VR_OK);
+        void* big = aligned_buf(bytes);
+        EXPECT(vr_render_partials(ctx, n, bb.data(), pp.data(), big, bytes) == VR_OK);
+        EXPECT(vr_synchronize(ctx) == VR_OK);
+        std::free(big);
+    }
+
+    // composite and its backward
+    float* out = static_cast<float*>(aligned_buf(64 * 48 * 16));
+    const float bg[4] = {0.1f, 0.2f, 0.3f, 1.f}, bg_bad[4] = {NAN, 0, 0, 0};
+    EXPECT(vr_composite(ctx, parts, 3, bg, out) == VR_OK);
+    EXPECT(vr_composite(ctx, parts, 3, bg_bad, out) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_composite(ctx, parts, DPVR_MAX_PARTIALS + 1, bg, out) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_composite(ctx, parts, 0, bg, out) == VR_OK);
+    float* d_parts[3];
+    for (int i = 0; i < 3; ++i) {
+        d_parts[i] = static_cast<float*>(aligned_buf((size_t)parts[i].w * parts[i].h * 16 + 16));
+        bufs.push_back(d_parts[i]);
+    }
+    EXPECT(vr_composite_backward(ctx, parts, 3, bg, out, d_parts) == VR_OK);
+
+    // checkpointed forward and adjoint of one partial
+    size_t ck = 0;
+    EXPECT(vr_checkpoint_size(ctx, bricks[0], &parts[0], 0, &ck) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_checkpoint_size(ctx, bricks[0], &parts[0], 65, &ck) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_checkpoint_size(ctx, bricks[0], &parts[0], 16, &ck) == VR_OK && ck > 0);
+    float* ckpt = static_cast<float*>(aligned_buf(ck));
+    EXPECT(vr_render_partial_checkpointed(ctx, bricks[0], &parts[0], 16, ckpt, ck - 4) == VR_ERR_WORKSPACE);
+    EXPECT(vr_render_partial_checkpointed(ctx, bricks[0], &parts[0], 16, ckpt, ck) == VR_OK);
+    float* gtf = static_cast<float*>(aligned_buf(256 * 16));
+    float* gvol = static_cast<float*>(aligned_buf(volume.size() * 4));
+    EXPECT(vr_render_partial_backward(ctx, bricks[0], &parts[0], 16, ckpt, ck, d_parts[0], gtf, gvol, vol,
+                                      lo_ok) == VR_OK);
+    EXPECT(vr_render_partial_backward(ctx, bricks[0], &parts[0], 16, ckpt, ck, d_parts[0], gtf, gvol, vol,
+                                      lo_bad) == VR_ERR_INVALID_ARG);
+
+    // a batch of two frames (two cameras), its launch, tuning and release
+    vr_camera_desc cams[2] = {};
+    for (int c = 0; c < 2; ++c) {
+        cams[c].kind = c;
+        cams[c].width = 40 + 8 * c;
+        cams[c].height = 32;
+        std::memcpy(cams[c].eye, c == 0 ? eye : tgt, sizeof eye);
+        const double dir[3] = {0, 0, 1};
+        std::memcpy(cams[c].target, c == 0 ? tgt : dir, sizeof tgt);
+        std::memcpy(cams[c].up, up, sizeof up);
+        cams[c].fovy_deg = c == 0 ? 40.0 : 50.0;
+    }
+    vr_tf_desc tfs[1] = {{tf.data(), 0.f, 1.f, 1.f, 0}};
+    std::vector<vr_batch_job> jobs;
+    std::vector<vr_batch_frame> frames;
+    for (int c = 0; c < 2; ++c) {
+        vr_batch_frame f{};
+        f.camera = c;
+        f.first_job = (int32_t)jobs.size();
+        f.n_jobs = 3;
+        f.out = static_cast<float*>(aligned_buf((size_t)cams[c].width * cams[c].height * 16));
+        bufs.push_back(f.out);
+        for (int i = 0; i < 3; ++i) {
+            int32_t r[4];
+            EXPECT(vr_camera_roi(ctx, bricks[i], &cams[c], r) == VR_OK);
+            const size_t px = (size_t)(r[2] > 0 ? r[2] : 1) * (r[3] > 0 ? r[3] : 1);
+            float* rgba = static_cast<float*>(aligned_buf(px * 16));
+            float* depth = static_cast<float*>(aligned_buf(px * 4));
+            bufs.push_back(rgba);
+            bufs.push_back(depth);
+            jobs.push_back(vr_batch_job{bricks[i], c, 0, vr_partial{r[0], r[1], r[2], r[3], rgba, depth, nullptr}});
+        }
+        frames.push_back(f);
+    }
+    EXPECT(vr_batch_workspace_size((int32_t)jobs.size(), (int32_t)frames.size(), &bytes) == VR_OK);
+    void* bws = aligned_buf(bytes);
+    vr_batch batch = nullptr;
+    std::vector<vr_batch_job> bad_jobs = jobs;
+    bad_jobs[1].camera = 7;
+    EXPECT(vr_batch_create(ctx, 2, cams, 1, tfs, (int32_t)bad_jobs.size(), bad_jobs.data(), 2, frames.data(), bws,
+                           bytes, &batch) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_batch_create(ctx, 2, cams, 1, tfs, (int32_t)jobs.size(), jobs.data(), 2, frames.data(), bws,
+                           bytes - 1, &batch) == VR_ERR_WORKSPACE);
+    EXPECT(vr_batch_create(ctx, 2, cams, 1, tfs, (int32_t)jobs.size(), jobs.data(), 2, frames.data(), bws,
+                           bytes, &batch) == VR_OK);
+    EXPECT(vr_batch_launch(batch) == VR_OK);
+    double best = 0;
+    EXPECT(vr_batch_autotune(batch, 0, &best) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_batch_autotune(batch, 1, &best) == VR_OK);
+    int32_t wg, order, staging, tile, chunk;
+    EXPECT(vr_batch_config(batch, &wg, &order, &staging, &tile, &chunk) == VR_OK);
+    EXPECT(wg >= 1 && (order == 0 || order == 1) && (tile == 16 || tile == 32) && (chunk == 4 || chunk == 8));
+    EXPECT(vr_context_release(ctx) == VR_ERR_STATE);     // bricks and the batch still live
+    EXPECT(vr_batch_release(batch) == VR_OK);
+    EXPECT(vr_batch_release(batch) == VR_ERR_INVALID_HANDLE);
+
+    // release, then use of released handles
+    for (int i = 0; i < 3; ++i) EXPECT(vr_brick_release(bricks[i]) == VR_OK);
+    EXPECT(vr_brick_release(bricks[0]) == VR_ERR_INVALID_HANDLE);
+    EXPECT(vr_synchronize(ctx) == VR_OK);
+    EXPECT(vr_context_release(ctx) == VR_OK);
+    EXPECT(vr_context_release(ctx) == VR_ERR_INVALID_HANDLE);
+    EXPECT(vr_set_render_params(ctx, 0.5, 0.0f) == VR_ERR_INVALID_HANDLE);
+
+    for (void* p : bufs) std::free(p);
+    for (void* p : ws) std::free(p);
+    std::free(fws);
+    std::free(out);
+    std::free(ckpt);
+    std::free(gtf);
+    std::free(gvol);
+    std::free(bws);
+    std::printf("%s: %d failed expectations\n", g_fail ? "FAIL" : "OK", g_fail);
+    return g_fail ? 1 : 0;
+}

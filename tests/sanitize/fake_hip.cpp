@@ -1,0 +1,79 @@
+// Host-memory stand-in for the HIP runtime calls and kernel launchers that
+// the library's host code (api.cpp) makes, so that its argument checks,
+// table building, staging and handle bookkeeping can run under
+// AddressSanitizer / UndefinedBehaviorSanitizer on a machine without a GPU.
+// "Device" memory is host memory here; copies are memcpy; streams, events
+// and graphs are small heap objects (so leaks of them are reported); every
+// kernel launcher validates nothing and returns success.
+#include <hip/hip_runtime_api.h>
+
+#include <cstdlib>
+#include <cstring>
+
+#include "dpvr_kernels.h"
+
+namespace {
+int g_device = 0;
+template <typename T>
+T fresh() { return reinterpret_cast<T>(std::malloc(16)); }
+alignas(256) unsigned char g_scratch[dpvr::kStaticScratchBytes];
+}  // namespace
+
+extern "C" {
+const char* hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "fake HIP error"; }
+hipError_t hipGetLastError(void) { return hipSuccess; }
+hipError_t hipGetDeviceCount(int* count) { *count = 1; return hipSuccess; }
+hipError_t hipGetDevice(int* d) { *d = g_device; return hipSuccess; }
+hipError_t hipSetDevice(int d) { if (d != 0) return hipErrorInvalidDevice; g_device = d; return hipSuccess; }
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
+    *v = a == hipDeviceAttributeMultiprocessorCount ? 256 : 0;
+    return hipSuccess;
+}
+hipError_t hipMemcpy(void* dst, const void* src, size_t n, hipMemcpyKind) { std::memmove(dst, src, n); return hipSuccess; }
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind, hipStream_t) {
+    std::memmove(dst, src, n);
+    return hipSuccess;
+}
+hipError_t hipHostMalloc(void** p, size_t n, unsigned int) {
+    *p = std::malloc(n ? n : 1);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned int) { *s = fresh<hipStream_t>(); return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t s) { std::free(s); return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipEventCreate(hipEvent_t* e) { *e = fresh<hipEvent_t>(); return hipSuccess; }
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = fresh<hipEvent_t>(); return hipSuccess; }
+hipError_t hipEventDestroy(hipEvent_t e) { std::free(e); return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 1.0f; return hipSuccess; }
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) { *g = fresh<hipGraph_t>(); return hipSuccess; }
+hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t, hipGraphNode_t*, char*, size_t) {
+    *x = fresh<hipGraphExec_t>();
+    return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipSuccess; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t x) { std::free(x); return hipSuccess; }
+hipError_t hipGraphDestroy(hipGraph_t g) { std::free(g); return hipSuccess; }
+}
+
+namespace dpvr {
+hipError_t static_scratch_address(void** out) { *out = g_scratch; return hipSuccess; }
+hipError_t launch_ingest(const float*, void*, const int32_t*, StorageK, hipStream_t) { return hipSuccess; }
+hipError_t launch_march(const MarchParams&, StorageK, hipStream_t) { return hipSuccess; }
+hipError_t launch_march_queue(const QueueParams&, StorageK, int, hipStream_t) { return hipSuccess; }
+int march_queue_workgroups_per_cu(StorageK, bool, int, int, int) { return 2; }
+hipError_t launch_composite(const CompositeParams&, hipStream_t) { return hipSuccess; }
+hipError_t launch_composite_many(const CompositeParams*, const int32_t*, int32_t, int32_t, hipStream_t) {
+    return hipSuccess;
+}
+hipError_t launch_march_backward(const MarchParams&, const BackwardParams&, StorageK, hipStream_t) {
+    return hipSuccess;
+}
+hipError_t launch_composite_backward(const CompositeParams&, const CompositeBackParams&, hipStream_t) {
+    return hipSuccess;
+}
+hipError_t launch_gather(const GatherParams&, void*, StorageK, hipStream_t) { return hipSuccess; }
+}  // namespace dpvr
