@@ -4,7 +4,8 @@
 // pixel) and the transmittance checkpoints written by the checkpointing
 // forward march.
 //
-// One wavefront per 8x8 tile, one lane per ray, as in the forward.  A ray's
+// One wavefront per 8x8 tile, one lane per ray, four tiles per workgroup
+// (sharing the table and its gradient in LDS).  A ray's
 // owned samples are cut into segments of ckpt_interval (<= 64) samples.
 // Segments are processed last to first: the segment is re-marched forward
 // from its checkpoint, storing the transmittance T_k in front of each sample
@@ -13,8 +14,9 @@
 // (R = colour, Q = transmittance of what lies behind sample k in the brick),
 //   dC/drgb_k = T_k a_k,  dC/da_k = T_k (rgb_k - R_{k+1}),  dA/da_k = T_k Q_{k+1}.
 // The opacity a_k = 1 - exp2(-a'_k) with a' the pre-scaled table opacity;
-// table gradients are accumulated per workgroup in LDS (ds_add_f32) and
-// flushed with one global atomic per touched entry; voxel gradients are
+// table gradients are summed per lane while consecutive samples use one
+// table segment, accumulated per workgroup in LDS (ds_add_f32) and flushed
+// with one global atomic per touched entry; voxel gradients are
 // scattered with the 8 trilinear weights to the global voxels that the stored
 // (ghost-padded) voxels copy, so ghost contributions fold back to their source
 // (summed per lane while consecutive samples stay in one cell, then 8 atomics).
@@ -24,22 +26,26 @@ namespace dpvr {
 namespace {
 
 constexpr int kTile = 8;
+// Wavefronts per workgroup, one 8x8 tile each: they share the table and its
+// gradient in LDS, so that the per-wave transmittance buffers set occupancy.
+constexpr int kWaves = 4;
 constexpr float kLn2 = 0.6931471805599453f;
 
 template <typename TS>
-__global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardParams bp) {
+__global__ __launch_bounds__(kWaves * 64) void march_backward(MarchParams p, BackwardParams bp) {
     __shared__ TFTable tft;
     __shared__ float gtf[256 * 4];
-    __shared__ float tbuf[kMaxCkptInterval * 64];
-    const int lane = threadIdx.x;
-    load_tf(tft, p.tf, p.dt, lane, 64);
-    for (int e = lane; e < 1024; e += 64) gtf[e] = 0.0f;
+    __shared__ float tbuf_all[kWaves][kMaxCkptInterval * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float* tbuf = tbuf_all[wave];
+    load_tf(tft, p.tf, p.dt, threadIdx.x, kWaves * 64);
+    for (int e = threadIdx.x; e < 1024; e += kWaves * 64) gtf[e] = 0.0f;
     __syncthreads();
 
-    const int tile = blockIdx.x;
+    const int tile = blockIdx.x * kWaves + wave;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int lx = tx * kTile + (lane & 7), ly = ty * kTile + (lane >> 3);
-    const bool valid = lx < p.roi_w && ly < p.roi_h;
+    const bool valid = tile < p.tiles_x * p.tiles_y && lx < p.roi_w && ly < p.roi_h;
     const int px = p.roi_x0 + lx, py = p.roi_y0 + ly;
     const long long pix = (long long)ly * p.roi_w + lx;
 
@@ -108,6 +114,20 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
 #pragma unroll
             for (int i = 0; i < 8; ++i) acc[i] = 0.f;
         };
+        // table-gradient contributions of the current segment index, not
+        // yet added (entries seg and seg + 1): consecutive samples mostly
+        // use one segment, so LDS atomics happen once per change
+        int tseg = -1;
+        float tacc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        auto tflush = [&]() {
+            if (tseg < 0) return;
+            float* g0 = &gtf[4 * tseg];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (tacc[i] != 0.0f) atomicAdd(g0 + i, tacc[i]);
+                tacc[i] = 0.f;
+            }
+        };
         for (int s = nseg - 1; s >= 0; --s) {
             const long long k0 = rs.kf + (long long)s * I;
             const int n = (int)min((long long)I, rs.kl - k0 + 1);
@@ -132,17 +152,18 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
                                          g.w * Q);
                 const float d_ap = d_al * kLn2 * om;   // dL/da'
                 const float w1 = e.phi, w0 = 1.0f - e.phi;
-                float* g0 = &gtf[4 * e.seg];
-                atomicAdd(g0 + 0, w0 * d_r);
-                atomicAdd(g0 + 1, w0 * d_g);
-                atomicAdd(g0 + 2, w0 * d_b);
-                atomicAdd(g0 + 3, w0 * d_ap * a_scale);
-                if (w1 != 0.0f) {
-                    atomicAdd(g0 + 4, w1 * d_r);
-                    atomicAdd(g0 + 5, w1 * d_g);
-                    atomicAdd(g0 + 6, w1 * d_b);
-                    atomicAdd(g0 + 7, w1 * d_ap * a_scale);
+                if (e.seg != tseg) {
+                    tflush();
+                    tseg = e.seg;
                 }
+                tacc[0] += w0 * d_r;
+                tacc[1] += w0 * d_g;
+                tacc[2] += w0 * d_b;
+                tacc[3] += w0 * d_ap * a_scale;
+                tacc[4] += w1 * d_r;
+                tacc[5] += w1 * d_g;
+                tacc[6] += w1 * d_b;
+                tacc[7] += w1 * d_ap * a_scale;
                 if (e.inside) {
                     const float4 D = tft.diff[e.seg];
                     const float dv = tf_k * (d_r * D.x + d_g * D.y + d_b * D.z + d_ap * D.w);
@@ -173,9 +194,10 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
             }
         }
         flush();
+        tflush();
     }
     __syncthreads();
-    for (int e = lane; e < 1024; e += 64) {
+    for (int e = threadIdx.x; e < 1024; e += kWaves * 64) {
         const float v = gtf[e];
         if (v != 0.0f) atomicAdd(bp.grad_tf + e, v);
     }
@@ -185,12 +207,13 @@ __global__ __launch_bounds__(64) void march_backward(MarchParams p, BackwardPara
 
 hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp, StorageK storage,
                                  hipStream_t stream) {
-    const int blocks = p.tiles_x * p.tiles_y;
-    if (blocks == 0) return hipSuccess;
+    const int tiles = p.tiles_x * p.tiles_y;
+    if (tiles == 0) return hipSuccess;
+    const int blocks = (tiles + kWaves - 1) / kWaves;
     if (storage == kF16)
-        hipLaunchKernelGGL(march_backward<__half>, dim3(blocks), dim3(64), 0, stream, p, bp);
+        hipLaunchKernelGGL(march_backward<__half>, dim3(blocks), dim3(kWaves * 64), 0, stream, p, bp);
     else
-        hipLaunchKernelGGL(march_backward<float>, dim3(blocks), dim3(64), 0, stream, p, bp);
+        hipLaunchKernelGGL(march_backward<float>, dim3(blocks), dim3(kWaves * 64), 0, stream, p, bp);
     return hipGetLastError();
 }
 
