@@ -86,6 +86,12 @@ def _load():
                                                  C.POINTER(_TF), C.c_double, _dp, _dp, _dp]
             lib.oc_render_brick_grad.restype = C.c_int
             lib.oc_threads.restype = C.c_int
+            lib.oc_render_brick_shadowed.argtypes = [C.POINTER(_Camera), C.POINTER(_Brick), C.c_int32,
+                                                     C.POINTER(C.POINTER(_Brick)), C.POINTER(_TF),
+                                                     C.c_double, C.c_double, _dp, C.c_double,
+                                                     C.POINTER(C.c_int32), C.c_int64, _dp, _dp,
+                                                     C.POINTER(C.c_int64)]
+            lib.oc_render_brick_shadowed.restype = C.c_int
             lib.oc_set_threads.argtypes = [C.c_int]
             lib.oc_set_threads.restype = None
             _lib = lib
@@ -269,6 +275,57 @@ def fold_ghost_grad(gvox_stored, lo, global_shape, ghost=1):
     out = np.zeros(global_shape)
     np.add.at(out, np.ix_(iz, iy, ix), gvox_stored)
     return out
+
+
+# ---------------------------------------------------------------- shadows
+def render_brick_shadowed(cam, brick, bricks, tf, vrange, opacity_scale, dt, light_dir, ambient,
+                          ert_eps=0.0, pixels=None):
+    """Partial image of one brick with one directional light (R-shadow): the
+    colour of each owned sample is scaled by ambient + (1 - ambient) S, S the
+    transmittance of its shadow ray toward the light through all ``bricks``.
+    ``brick`` and every entry of ``bricks`` are (vox, dims, ghost, origin,
+    spacing).  Returns (rgba, depth, counters) as :func:`render_brick`."""
+    lib = _load()
+    c = _camera(cam)
+    refs = [_BrickRef(*bb) for bb in bricks]
+    me = _BrickRef(*brick)
+    arr = (C.POINTER(_Brick) * max(len(refs), 1))(*[C.pointer(r.s) for r in refs])
+    t = _TFRef(tf, vrange, opacity_scale)
+    l = np.ascontiguousarray(light_dir, dtype=np.float64)
+    if pixels is None:
+        n = c.width * c.height
+        pix_p = None
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        n = pix.shape[0]
+        pix_p = _ptr(pix, C.c_int32)
+    rgba = np.zeros(n * 4)
+    depth = np.zeros(n)
+    cnt = np.zeros(2, dtype=np.int64)
+    st = lib.oc_render_brick_shadowed(C.byref(c), C.byref(me.s), len(refs), arr, C.byref(t.s), float(dt),
+                                      float(ert_eps), _ptr(l, C.c_double), float(ambient), pix_p, n,
+                                      _ptr(rgba, C.c_double), _ptr(depth, C.c_double),
+                                      _ptr(cnt, C.c_int64))
+    if st != 0:
+        raise ValueError("bad light direction or ambient fraction")
+    if pixels is None:
+        return rgba.reshape(c.height, c.width, 4), depth.reshape(c.height, c.width), cnt
+    return rgba.reshape(n, 4), depth, cnt
+
+
+def render_scene_shadowed(scene, light_dir, ambient, camera=None, bg=(0.0, 0.0, 0.0, 0.0), pixels=None,
+                          ert_eps=0.0):
+    """Final image of a :class:`synth.Scene` with R-shadow: every brick's
+    shadowed partial, composited over bg.  Returns (image, partials, counters)."""
+    cam = camera or scene.camera
+    desc = [(b.voxels, b.dims, b.ghost, b.origin, (1.0, 1.0, 1.0)) for b in scene.bricks]
+    parts, counters = [], np.zeros(2, dtype=np.int64)
+    for d in desc:
+        rgba, depth, cnt = render_brick_shadowed(cam, d, desc, scene.tf, scene.vrange, scene.opacity_scale,
+                                                 scene.step, light_dir, ambient, ert_eps, pixels)
+        parts.append((rgba, depth))
+        counters += cnt
+    return composite(parts, bg), parts, counters
 
 
 # ---------------------------------------------------------------- scenes

@@ -15,6 +15,10 @@
  *   - sort-last compositing of partial images over a background oc_composite
  *   - gradients of a sum-of-squares image loss with respect to the
  *     transfer-function table and the stored voxels             oc_render_brick_grad
+ *   - a brick's partial image with one directional light whose shadow
+ *     rays run through every brick (the secondary rays that data-parallel
+ *     ray tracing must send to the ranks holding the occluders)
+ *                                                  oc_render_brick_shadowed
  *
  * The paper (Zellmann, "Data Parallel Visualization and Rendering on the
  * RAMSES Supercomputer with ANARI") describes data-parallel ray tracing over
@@ -33,6 +37,12 @@
  *   R-depth  depth key = t of the first sample the brick owns (+inf if none)
  *   R-over   composite partials by ascending key with "over", then the
  *            background
+ *   R-shadow one directional light (unit direction l toward the light) and
+ *            an ambient fraction a0: sample k's emitted colour is scaled by
+ *            a0 + (1 - a0) S(p_k), S = transmittance of the shadow ray from
+ *            p_k toward the light (samples p_k + (j + 1/2) dt l, j >= 0, each
+ *            evaluated in the brick whose half-open box holds it, none
+ *            outside every brick); a0 = 1: no shadows
  * No early ray termination: every owned sample is evaluated.  The counters
  * report how many samples a renderer that stops once T < eps would evaluate.
  *
@@ -280,6 +290,111 @@ void oc_render_brick(const oc_camera* cam, const oc_brick* b, const oc_tf* tf, d
         ev += cnt[1];
     }
     if (counters) { counters[0] += nom; counters[1] += ev; }
+}
+
+/* ---------------------------------------------------------------- shadows */
+/* R-shadow: transmittance from point p toward the light along unit l through
+ * the nb bricks.  The shadow ray's samples are q_j = p + (j + 1/2) dt l for
+ * j >= 0; each q_j inside some brick's half-open owned box is evaluated in
+ * that brick exactly as a primary sample (trilinear value, table, extinction)
+ * and multiplies S by 1 - alpha(q_j).  Candidates are the lattice points the
+ * ray can have inside the bricks' common bounding box. */
+static double shadow_transmittance(int32_t nb, const oc_brick* const* bricks, const oc_tf* tf,
+                                   double dt, const double p[3], const double l[3]) {
+    double LO[3] = {INFINITY, INFINITY, INFINITY}, HI[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t b = 0; b < nb; ++b) {
+        double lo[3], hi[3];
+        brick_box(bricks[b], lo, hi);
+        for (int c = 0; c < 3; ++c) {
+            if (lo[c] < LO[c]) LO[c] = lo[c];
+            if (hi[c] > HI[c]) HI[c] = hi[c];
+        }
+    }
+    int64_t j0, j1;
+    if (nb == 0 || !sample_range(p, l, LO, HI, dt, &j0, &j1)) return 1.0;
+    double S = 1.0;
+    for (int64_t j = j0; j <= j1; ++j) {
+        double t = ((double)j + 0.5) * dt;
+        double q[3] = {p[0] + t * l[0], p[1] + t * l[1], p[2] + t * l[2]};
+        for (int32_t b = 0; b < nb; ++b) {
+            double lo[3], hi[3];
+            brick_box(bricks[b], lo, hi);
+            if (!in_box(q, lo, hi)) continue;
+            int64_t base[3]; double fr[3], e[4], phi; int32_t seg; int inside;
+            double v = sample_value(bricks[b], q, base, fr);
+            classify(tf, v, e, &seg, &phi, &inside);
+            double alpha = 1.0 - exp(-tf->opacity_scale * e[3] * dt);
+            S = S * (1.0 - alpha);
+            break;
+        }
+    }
+    return S;
+}
+
+/* render_pixel with R-shadow: the colour of every owned sample p_k of brick b
+ * is scaled by a0 + (1 - a0) S(p_k), S through all nb bricks (b among them);
+ * alpha, T and the depth key are those of render_pixel. */
+static void render_pixel_shadowed(const oc_camera* cam, const oc_brick* b, int32_t nb,
+                                  const oc_brick* const* bricks, const oc_tf* tf, double dt,
+                                  double ert_eps, const double l[3], double a0, int32_t i, int32_t j,
+                                  double out[4], double* depth, int64_t* counters) {
+    double o[3], d[3], lo[3], hi[3];
+    oc_ray(cam, i, j, o, d);
+    brick_box(b, lo, hi);
+    double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
+    double key = INFINITY;
+    int64_t nominal = 0, evaluated = 0;
+    int stopped = 0;
+    int64_t k0, k1;
+    if (sample_range(o, d, lo, hi, dt, &k0, &k1)) {
+        for (int64_t k = k0; k <= k1; ++k) {
+            double t = ((double)k + 0.5) * dt;
+            double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+            if (!in_box(p, lo, hi)) continue;
+            if (key == INFINITY) key = t;
+            int64_t base[3]; double fr[3], e[4], phi; int32_t seg; int inside;
+            double v = sample_value(b, p, base, fr);
+            classify(tf, v, e, &seg, &phi, &inside);
+            double sigma = tf->opacity_scale * e[3];
+            double alpha = 1.0 - exp(-sigma * dt);
+            double f = a0 + (1.0 - a0) * shadow_transmittance(nb, bricks, tf, dt, p, l);
+            for (int c = 0; c < 3; ++c) C[c] += T * alpha * e[c] * f;
+            T = T * (1.0 - alpha);
+            ++nominal;
+            if (!stopped) { ++evaluated; if (T < ert_eps) stopped = 1; }
+        }
+    }
+    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
+    *depth = key;
+    if (counters) { counters[0] += nominal; counters[1] += evaluated; }
+}
+
+/* Partial images of brick b with R-shadow (light direction l, normalised
+ * here; ambient a0 in [0, 1]), shadow rays through all nb bricks; pixels,
+ * outputs and counters as for oc_render_brick.  Returns -1 on bad input. */
+int oc_render_brick_shadowed(const oc_camera* cam, const oc_brick* b, int32_t nb,
+                             const oc_brick* const* bricks, const oc_tf* tf, double dt,
+                             double ert_eps, const double light_dir[3], double a0,
+                             const int32_t* pix, int64_t npix, double* rgba, double* depth,
+                             int64_t* counters) {
+    double l[3] = {light_dir[0], light_dir[1], light_dir[2]};
+    double nl = sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+    if (!(nl > 0.0) || !(a0 >= 0.0 && a0 <= 1.0)) return -1;
+    l[0] = l[0] / nl; l[1] = l[1] / nl; l[2] = l[2] / nl;
+    int64_t n = pix ? npix : (int64_t)cam->width * cam->height;
+    int64_t nom = 0, ev = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : nom, ev)
+    for (int64_t q = 0; q < n; ++q) {
+        int32_t i = pix ? pix[2 * q] : (int32_t)(q % cam->width);
+        int32_t j = pix ? pix[2 * q + 1] : (int32_t)(q / cam->width);
+        int64_t cnt[2] = {0, 0};
+        render_pixel_shadowed(cam, b, nb, bricks, tf, dt, ert_eps, l, a0, i, j, rgba + 4 * q,
+                              depth + q, cnt);
+        nom += cnt[0];
+        ev += cnt[1];
+    }
+    if (counters) { counters[0] += nom; counters[1] += ev; }
+    return 0;
 }
 
 /* -------------------------------------------------------------- composite */

@@ -531,3 +531,86 @@ def test_gradient_against_central_differences():
             vals.append(_loss_parts(cam, _bricks64(fp, boxes), tf, scale, dt, bg, target)[0])
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - gvox[z, y, x]) <= 1e-5 * max(1.0, abs(fd)), (z, y, x, fd, gvox[z, y, x])
+
+
+# ------------------------------------------------------------------- shadows
+def _lattice_count(o, lo, hi, dt):
+    """Number of j >= 0 with lo <= o + (j + 1/2) dt < hi (a 1-D count)."""
+    return sum(1 for j in range(100000) if lo <= o + (j + 0.5) * dt < hi)
+
+
+@pytest.mark.parametrize("a0,dt,x,light_sign", [(0.0, 0.5, 4.3, 1), (0.3, 0.5, 1.7, 1), (0.0, 0.25, 6.9, 1),
+                                                (0.0, 0.5, 4.3, -1), (1.0, 0.5, 4.3, 1)])
+def test_shadow_constant_slab_closed_form(a0, dt, x, light_sign):
+    """A constant emitter brick A (x in [0, 8)) seen along -z, a constant
+    occluder slab B (x in [10, 14)) beyond a gap, light along +x (or -x, where
+    nothing but A itself lies).  Every sample of the pixel's ray has the same
+    shadow ray up to a shift along z, so the pixel is the unshadowed closed
+    form rgb (1 - (1 - aA)^m) times a0 + (1 - a0) (1 - aA)^nA (1 - aB)^nB, with
+    m, nA, nB lattice counts and a = 1 - exp(-scale v dt)."""
+    vA, vB, scale, rgb = 0.375, 0.75, 1.5, np.array([1.0, 0.5, 0.25])   # exact in float32
+    tf = _ramp_tf(lambda s: (1.0 + 0 * s, 0.5 + 0 * s, 0.25 + 0 * s))
+    A = (np.full((6, 10, 10), vA, np.float32), (8, 8, 4), 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    B = (np.full((6, 10, 6), vB, np.float32), (4, 8, 4), 1, (10.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    y, zeye = 3.7, 20.0
+    cam = dict(kind="ortho", eye=(x, y, zeye), dir=(0.0, 0.0, -1.0), up=(0.0, 1.0, 0.0), width=1, height=1,
+               view_height=1.0)
+    light = (float(light_sign), 0.0, 0.0)
+    rgba, depth, cnt = oracle.render_brick_shadowed(cam, A, [A, B], tf, (0, 1), scale, dt, light, a0)
+    aA, aB = 1.0 - math.exp(-scale * vA * dt), 1.0 - math.exp(-scale * vB * dt)
+    m = _lattice_count(-zeye, -4.0, 0.0, dt)             # t along -z: z = zeye - t in [0, 4)
+    if light_sign > 0:
+        nA, nB = _lattice_count(x, x, 8.0, dt), _lattice_count(x, 10.0, 14.0, dt)
+    else:
+        nA, nB = _lattice_count(-x, -x, 0.0, dt), 0       # along -x: x - (j + 1/2) dt in [0, x)
+    S = (1.0 - aA) ** nA * (1.0 - aB) ** nB
+    f = a0 + (1.0 - a0) * S
+    np.testing.assert_allclose(rgba[0, 0, :3], rgb * (1.0 - (1.0 - aA) ** m) * f, rtol=0, atol=1e-12)
+    assert abs(rgba[0, 0, 3] - (1.0 - (1.0 - aA) ** m)) < 1e-12
+    assert depth[0, 0] == min((k + 0.5) * dt for k in range(1000) if 0.0 <= zeye - (k + 0.5) * dt < 4.0)
+    assert cnt[0] == m
+    # the occluder itself, seen by a ray that misses A, is lit by nothing in front of it
+    cam_b = dict(cam, eye=(12.2, y, zeye))
+    rgba_b, _, _ = oracle.render_brick_shadowed(cam_b, B, [A, B], tf, (0, 1), scale, dt, light, a0)
+    mb = m
+    if light_sign > 0:
+        Sb = (1.0 - aB) ** _lattice_count(12.2, 12.2, 14.0, dt)
+    else:
+        Sb = (1.0 - aB) ** _lattice_count(-12.2, -12.2, -10.0, dt) * (1.0 - aA) ** _lattice_count(-12.2, -8.0, 0.0, dt)
+    np.testing.assert_allclose(rgba_b[0, 0, :3], rgb * (1.0 - (1.0 - aB) ** mb) * (a0 + (1.0 - a0) * Sb),
+                               rtol=0, atol=1e-12)
+
+
+def test_shadow_ambient_one_equals_unshadowed_bitwise():
+    """a0 = 1 turns shadows off: the shadowed partial equals the plain one."""
+    rng = np.random.default_rng(21)
+    dims = (14, 12, 10)
+    field = synth.tile_field(rng, dims, n_blobs=4, noise=0.02, shock=False)
+    boxes = synth.kd_split(dims, 3, rng)
+    cam = synth.orbit_camera((0, 0, 0), dims, 24, 20, az_deg=35.0, el_deg=25.0, radius_factor=1.7)
+    sc = synth.scene_from_field("sh1", field, boxes, synth.default_tf(), cam, 0.5, 2.0)
+    desc = [(b.voxels, b.dims, b.ghost, b.origin, (1.0, 1.0, 1.0)) for b in sc.bricks]
+    for d in desc:
+        a = oracle.render_brick(cam, *d, sc.tf, (0, 1), 2.0, 0.5)
+        b = oracle.render_brick_shadowed(cam, d, desc, sc.tf, (0, 1), 2.0, 0.5, (0.3, 1.0, -0.2), 1.0)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and list(a[2]) == list(b[2])
+
+
+@pytest.mark.parametrize("seed,n_bricks,light", [(31, 2, (1.0, 0.4, 0.2)), (32, 5, (-0.3, 1.0, 0.6))])
+def test_shadow_split_invariance(seed, n_bricks, light):
+    """Shadow rays see the same samples whatever the decomposition: one
+    brick and kd bricks (with ghosts) give the same shadowed image."""
+    rng = np.random.default_rng(seed)
+    dims = (16, 14, 12)
+    field = synth.tile_field(rng, dims, n_blobs=5, noise=0.02, shock=True)
+    cam = synth.orbit_camera((0, 0, 0), dims, 20, 16, az_deg=25.0, el_deg=20.0, radius_factor=1.6)
+    tf = synth.default_tf()
+    bg = (0.1, 0.2, 0.3, 1.0)
+    one = synth.scene_from_field("one", field, [((0, 0, 0), dims)], tf, cam, 0.5, 2.0)
+    many = synth.scene_from_field("many", field, synth.kd_split(dims, n_bricks, rng), tf, cam, 0.5, 2.0)
+    a, _, ca = oracle.render_scene_shadowed(one, light, 0.2, bg=bg)
+    b, _, cb = oracle.render_scene_shadowed(many, light, 0.2, bg=bg)
+    assert np.max(np.abs(a - b)) < 1e-12
+    assert ca[0] == cb[0]
+    plain, _, _ = oracle.render_scene(many, bg=bg)
+    assert np.max(np.abs(plain - b)) > 1e-3          # the light does darken the image
