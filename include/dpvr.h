@@ -452,6 +452,53 @@ vr_status vr_render_partial_backward(vr_context ctx, vr_brick brick, const vr_pa
                                      const float* d_part, float* grad_tf, float* grad_volume,
                                      const int32_t vol_dims[3], const int32_t lo[3]);
 
+/* ---------------------------------------------------- ray-queue cycling */
+/* Data-parallel ray tracing by ray-queue cycling (paper Sec. 2.2 and Fig. 2:
+ * rays are queued and batched, every ray is cycled through every rank's
+ * data, and a shadow ray must visit the rank that holds its occluder; Sec. 3:
+ * the DP-ANARI conventions assume this, so the data need not be
+ * redistributed).  Here the n bricks play the ranks on one GPU.  One
+ * directional light: every owned primary sample's emitted colour is scaled
+ * by ambient + (1 - ambient) S, S the transmittance toward the light of a
+ * shadow ray from the sample (samples at p + (j + 1/2) dt l, j >= 0, each
+ * evaluated in the brick that owns it; alpha, depth keys and the primary
+ * transmittance are unchanged).  ambient = 1: no shadow rays; the image then
+ * equals the sort-last image of the same bricks (vr_render_partials +
+ * vr_composite) exactly. */
+typedef struct {
+    double direction[3];   /* toward the light, world units, non-zero (normalised here) */
+    float ambient;         /* in [0, 1] */
+    int32_t pad_;
+} vr_light;
+
+/* Host-only: bytes of the workspace vr_rqc_plan and vr_render_rqc use for
+ * these n bricks (1 <= n <= DPVR_MAX_PARTIALS, no brick twice) and the
+ * context camera: the brick table, one plan entry per (brick, ROI pixel), the
+ * per-pixel segment slots of every brick.  Errors: VR_ERR_INVALID_HANDLE,
+ * VR_ERR_INVALID_ARG, VR_ERR_STATE (no camera). */
+vr_status vr_rqc_workspace_size(vr_context ctx, int32_t n, const vr_brick* bricks, size_t* bytes);
+
+/* Plan a frame: counts every (brick, ROI pixel)'s owned primary samples and
+ * gives each a slot (device scan), then synchronises the context stream and
+ * returns the number of slots, which sizes the shade buffer of
+ * vr_render_rqc (total_samples * 4 bytes).  workspace: device memory of
+ * vr_rqc_workspace_size bytes, 256-byte aligned, kept by the caller for the
+ * renders of this plan.  Depends on the bricks' geometry, the camera and dt
+ * only.  Errors: as vr_rqc_workspace_size, VR_ERR_WORKSPACE, VR_ERR_DEVICE. */
+vr_status vr_rqc_plan(vr_context ctx, int32_t n, const vr_brick* bricks, void* workspace, size_t workspace_bytes,
+                      int64_t* total_samples);
+
+/* Render the frame of the last vr_rqc_plan (same workspace, bricks, camera
+ * and dt, or VR_ERR_STATE) with the current transfer function and data:
+ * n cycle steps of the shadow-ray queues (skipped when ambient = 1), n cycle
+ * steps of the primary-ray queues, then per pixel the bricks' segments in
+ * depth order over bg.  shade: device, total_samples floats (ignored when
+ * ambient = 1); out: device, height x width x 4 floats, 16-byte aligned.
+ * Enqueued on the context stream.  Errors: VR_ERR_INVALID_HANDLE,
+ * VR_ERR_INVALID_ARG, VR_ERR_STATE, VR_ERR_WORKSPACE, VR_ERR_DEVICE. */
+vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_light* light, const float bg[4],
+                        void* workspace, size_t workspace_bytes, float* shade, size_t shade_bytes, float* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,10 @@ class vr_batch_frame(C.Structure):
                 ("pad_", C.c_int32), ("bg", C.c_float * 4), ("out", C.c_void_p)]
 
 
+class vr_light(C.Structure):
+    _fields_ = [("direction", C.c_double * 3), ("ambient", C.c_float), ("pad_", C.c_int32)]
+
+
 _i3 = C.c_int32 * 3
 _d3 = C.c_double * 3
 _f4 = C.c_float * 4
@@ -123,6 +127,11 @@ _SIGS = {
     "vr_render_partial_backward": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
                                     C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                     _i3, _i3], _st),
+    "vr_rqc_workspace_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)], _st),
+    "vr_rqc_plan": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t,
+                     C.POINTER(C.c_int64)], _st),
+    "vr_render_rqc": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_light), _f4, C.c_void_p,
+                       C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p], _st),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -251,6 +260,27 @@ def vr_composite(ctx, parts, bg, out):
     n = len(parts)
     arr = (vr_partial * max(n, 1))(*parts)
     _check(_lib.vr_composite(ctx, arr, n, _f4(*bg), _ptr(out)), ctx)
+
+
+def vr_rqc_workspace_size(ctx, bricks):
+    arr = (C.c_void_p * len(bricks))(*bricks)
+    b = C.c_size_t()
+    _check(_lib.vr_rqc_workspace_size(ctx, len(bricks), arr, C.byref(b)), ctx)
+    return b.value
+
+
+def vr_rqc_plan(ctx, bricks, ws, nbytes):
+    arr = (C.c_void_p * len(bricks))(*bricks)
+    total = C.c_int64()
+    _check(_lib.vr_rqc_plan(ctx, len(bricks), arr, _ptr(ws), nbytes, C.byref(total)), ctx)
+    return total.value
+
+
+def vr_render_rqc(ctx, bricks, light_dir, ambient, bg, ws, nbytes, shade, shade_bytes, out):
+    arr = (C.c_void_p * len(bricks))(*bricks)
+    lt = vr_light((C.c_double * 3)(*[float(v) for v in light_dir]), float(ambient), 0)
+    _check(_lib.vr_render_rqc(ctx, len(bricks), arr, C.byref(lt), _f4(*bg), _ptr(ws), nbytes,
+                              _ptr(shade) if shade is not None else None, shade_bytes, _ptr(out)), ctx)
 
 
 def vr_set_march_path(ctx, path):
@@ -479,6 +509,26 @@ class Renderer:
     def render(self, bg=(0.0, 0.0, 0.0, 0.0)):
         self.render_partials()
         return self.composite(bg)
+
+    def rqc_plan(self):
+        """Plan the ray-queue-cycling frame of the current camera (workspace
+        and shade buffer allocated here; synchronises)."""
+        torch = self.torch
+        nbytes = vr_rqc_workspace_size(self.ctx, self.bricks)
+        ws = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=self.device)
+        base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+        total = vr_rqc_plan(self.ctx, self.bricks, base, nbytes)
+        shade = torch.empty(max(total, 1), dtype=torch.float32, device=self.device)
+        self._rqc = (ws, base, nbytes, shade, total)
+        return total
+
+    def render_rqc(self, light_dir, ambient, bg=(0.0, 0.0, 0.0, 0.0)):
+        """The frame by ray-queue cycling with one directional light (plan
+        first with :meth:`rqc_plan`); returns the (H, W, 4) frame tensor."""
+        _, base, nbytes, shade, total = self._rqc
+        vr_render_rqc(self.ctx, self.bricks, light_dir, ambient, bg, base, nbytes, shade, shade.numel() * 4,
+                      self.frame)
+        return self.frame
 
     def partial_arrays(self, k):
         """(rgba (h, w, 4), depth (h, w)) torch views of partial k."""

@@ -5,7 +5,8 @@
 // forward march.
 //
 // One wavefront per 8x8 tile, one lane per ray, four tiles per workgroup
-// (sharing the table and its gradient in LDS).  A ray's
+// (sharing the table and its gradient in LDS) when the partial has many
+// tiles, one otherwise.  A ray's
 // owned samples are cut into segments of ckpt_interval (<= 64) samples.
 // Segments are processed last to first: the segment is re-marched forward
 // from its checkpoint, storing the transmittance T_k in front of each sample
@@ -26,12 +27,15 @@ namespace dpvr {
 namespace {
 
 constexpr int kTile = 8;
-// Wavefronts per workgroup, one 8x8 tile each: they share the table and its
-// gradient in LDS, so that the per-wave transmittance buffers set occupancy.
-constexpr int kWaves = 4;
+// Wavefronts per workgroup, one 8x8 tile each: four share the table and its
+// gradient in LDS, so that the per-wave transmittance buffers set occupancy;
+// a partial of few tiles takes one per workgroup, so that its tiles still
+// spread over the compute units.
+constexpr int kWavesWide = 4;
+constexpr int kWideMinTiles = 2048;
 constexpr float kLn2 = 0.6931471805599453f;
 
-template <typename TS>
+template <typename TS, int kWaves>
 __global__ __launch_bounds__(kWaves * 64) void march_backward(MarchParams p, BackwardParams bp) {
     __shared__ TFTable tft;
     __shared__ float gtf[256 * 4];
@@ -209,11 +213,19 @@ hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp,
                                  hipStream_t stream) {
     const int tiles = p.tiles_x * p.tiles_y;
     if (tiles == 0) return hipSuccess;
-    const int blocks = (tiles + kWaves - 1) / kWaves;
-    if (storage == kF16)
-        hipLaunchKernelGGL(march_backward<__half>, dim3(blocks), dim3(kWaves * 64), 0, stream, p, bp);
-    else
-        hipLaunchKernelGGL(march_backward<float>, dim3(blocks), dim3(kWaves * 64), 0, stream, p, bp);
+    if (tiles >= kWideMinTiles) {
+        const int blocks = (tiles + kWavesWide - 1) / kWavesWide;
+        if (storage == kF16)
+            hipLaunchKernelGGL((march_backward<__half, kWavesWide>), dim3(blocks), dim3(kWavesWide * 64), 0,
+                               stream, p, bp);
+        else
+            hipLaunchKernelGGL((march_backward<float, kWavesWide>), dim3(blocks), dim3(kWavesWide * 64), 0,
+                               stream, p, bp);
+    } else if (storage == kF16) {
+        hipLaunchKernelGGL((march_backward<__half, 1>), dim3(tiles), dim3(64), 0, stream, p, bp);
+    } else {
+        hipLaunchKernelGGL((march_backward<float, 1>), dim3(tiles), dim3(64), 0, stream, p, bp);
+    }
     return hipGetLastError();
 }
 

@@ -59,6 +59,15 @@ struct vr_context_s {
     // that many partials allocates nothing)
     std::vector<MarchParams> fjobs;
     std::vector<int32_t> fprefix;
+    // the last vr_rqc_plan: its workspace, bricks, camera and spacing, plan
+    // entries and owned primary samples (vr_render_rqc must match it)
+    struct {
+        const void* ws = nullptr;
+        std::vector<const void*> bricks;
+        CameraK cam{};
+        double dt = 0.0;
+        long long entries = 0, total = -1;
+    } rqc;
 };
 
 struct vr_brick_s {
@@ -1019,6 +1028,195 @@ vr_status vr_render_partial_backward(vr_context ctx, vr_brick b, const vr_partia
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_render_partial_backward: cannot select device %d", ctx->device);
     hipError_t e = launch_march_backward(p, bp, b->storage == VR_F16 ? kF16 : kF32, ctx->stream);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partial_backward: %s", hipGetErrorString(e));
+    return ok(ctx);
+}
+
+// ------------------------------------------------------- ray-queue cycling
+// Workspace of vr_rqc_plan / vr_render_rqc: [RqcBrick x n][kf int32 x E]
+// [offsets int64 x (E + 1)][scan block sums int64][segments float x W H n 5],
+// each part 256-byte aligned.
+static size_t rqc_layout(int32_t n, long long E, int W, int H, size_t off[5]) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    size_t o = 0;
+    off[0] = o; o += up((size_t)n * sizeof(RqcBrick));
+    off[1] = o; o += up((size_t)E * sizeof(int32_t));
+    off[2] = o; o += up((size_t)(E + 1) * sizeof(long long));
+    off[3] = o; o += up((size_t)(rqc_scan_blocks(E) + 1) * sizeof(long long));
+    off[4] = o; o += up((size_t)W * H * (size_t)n * 5 * sizeof(float));
+    return o;
+}
+
+// The bricks' ROIs and RqcBrick table for the context camera; E = ROI pixels.
+static vr_status rqc_bricks(vr_context ctx, int32_t n, const vr_brick* bricks, const char* who, bool need_data,
+                            std::vector<RqcBrick>& tab, long long* E) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (n < 1 || n > DPVR_MAX_PARTIALS || !bricks)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: n = %d outside [1, %d] or NULL bricks", who, n, DPVR_MAX_PARTIALS);
+    if (!ctx->has_camera) return fail(ctx, VR_ERR_STATE, "%s: no camera set", who);
+    tab.assign(n, RqcBrick{});
+    long long e = 0;
+    for (int i = 0; i < n; ++i) {
+        vr_brick b = bricks[i];
+        if (!live(b) || b->ctx != ctx) return fail(ctx, VR_ERR_INVALID_HANDLE, "%s: invalid brick %d", who, i);
+        if (need_data && !b->has_data) return fail(ctx, VR_ERR_STATE, "%s: brick %d has no voxel data", who, i);
+        for (int j = 0; j < i; ++j)
+            if (bricks[j] == b) return fail(ctx, VR_ERR_INVALID_ARG, "%s: brick %d repeats brick %d", who, i, j);
+        RqcBrick& r = tab[i];
+        r.brick.data = b->ws;
+        for (int c = 0; c < 3; ++c) {
+            r.brick.sdim[c] = b->dims[c] + 2 * b->ghost;
+            r.brick.lo[c] = b->origin[c];
+            r.brick.hi[c] = b->origin[c] + (double)b->dims[c] * b->spacing[c];
+            r.brick.origin[c] = b->origin[c];
+            r.brick.spacing[c] = b->spacing[c];
+            r.brick.inv_spacing[c] = 1.0 / b->spacing[c];
+        }
+        r.brick.ghost = b->ghost;
+        int32_t roi[4];
+        roi_for(ctx->cam, b, roi);
+        r.roi_x0 = roi[0];
+        r.roi_y0 = roi[1];
+        r.roi_w = roi[2];
+        r.roi_h = roi[3];
+        r.entry0 = e;
+        r.storage = b->storage == VR_F16 ? kF16 : kF32;
+        e += (long long)roi[2] * roi[3];
+    }
+    *E = e;
+    return VR_OK;
+}
+
+vr_status vr_rqc_workspace_size(vr_context ctx, int32_t n, const vr_brick* bricks, size_t* bytes) {
+    static const char* who = "vr_rqc_workspace_size";
+    if (!bytes) return fail(live(ctx) ? ctx : nullptr, VR_ERR_INVALID_ARG, "%s: bytes is NULL", who);
+    std::vector<RqcBrick> tab;
+    long long E = 0;
+    try {
+        vr_status st = rqc_bricks(ctx, n, bricks, who, false, tab, &E);
+        if (st != VR_OK) return st;
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
+    size_t off[5];
+    *bytes = rqc_layout(n, E, ctx->cam.width, ctx->cam.height, off);
+    return ok(ctx);
+}
+
+vr_status vr_rqc_plan(vr_context ctx, int32_t n, const vr_brick* bricks, void* workspace, size_t workspace_bytes,
+                      int64_t* total_samples) {
+    static const char* who = "vr_rqc_plan";
+    std::vector<RqcBrick> tab;
+    long long E = 0;
+    try {
+        vr_status st = rqc_bricks(ctx, n, bricks, who, false, tab, &E);
+        if (st != VR_OK) return st;
+        if (!total_samples) return fail(ctx, VR_ERR_INVALID_ARG, "%s: total_samples is NULL", who);
+        size_t off[5];
+        const size_t need = rqc_layout(n, E, ctx->cam.width, ctx->cam.height, off);
+        if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+            return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes (256-aligned), need %zu", who,
+                        workspace_bytes, need);
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+        char* ws = reinterpret_cast<char*>(workspace);
+        RqcParams p{};
+        p.cam = ctx->cam;
+        p.dt = ctx->dt;
+        p.inv_dt = 1.0 / ctx->dt;
+        p.n = n;
+        p.width = ctx->cam.width;
+        p.height = ctx->cam.height;
+        p.bricks = reinterpret_cast<const RqcBrick*>(ws + off[0]);
+        p.n_entries = E;
+        p.kf = reinterpret_cast<int32_t*>(ws + off[1]);
+        p.offsets = reinterpret_cast<long long*>(ws + off[2]);
+        p.err = err_word(ctx);
+        long long total = 0;
+        hipError_t e = hipMemcpyAsync(ws + off[0], tab.data(), tab.size() * sizeof(RqcBrick), hipMemcpyHostToDevice,
+                                      ctx->stream);
+        if (e == hipSuccess)
+            e = launch_rqc_plan(p, reinterpret_cast<long long*>(ws + off[3]), p.offsets + E, ctx->stream);
+        if (e == hipSuccess && E > 0)
+            e = hipMemcpyAsync(&total, p.offsets + E, sizeof(long long), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+        ctx->rqc.ws = workspace;
+        ctx->rqc.bricks.assign(bricks, bricks + n);
+        ctx->rqc.cam = ctx->cam;
+        ctx->rqc.dt = ctx->dt;
+        ctx->rqc.entries = E;
+        ctx->rqc.total = total;
+        *total_samples = total;
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
+    return ok(ctx);
+}
+
+vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_light* light, const float bg[4],
+                        void* workspace, size_t workspace_bytes, float* shade, size_t shade_bytes, float* out) {
+    static const char* who = "vr_render_rqc";
+    std::vector<RqcBrick> tab;
+    long long E = 0;
+    try {
+        vr_status st = rqc_bricks(ctx, n, bricks, who, true, tab, &E);
+        if (st != VR_OK) return st;
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
+    if (!ctx->has_tf) return fail(ctx, VR_ERR_STATE, "%s: no transfer function set", who);
+    const auto& pl = ctx->rqc;
+    if (pl.ws != workspace || pl.total < 0 || (int32_t)pl.bricks.size() != n ||
+        !std::equal(pl.bricks.begin(), pl.bricks.end(), bricks) || std::memcmp(&pl.cam, &ctx->cam, sizeof(CameraK)) != 0 ||
+        pl.dt != ctx->dt || pl.entries != E)
+        return fail(ctx, VR_ERR_STATE, "%s: no vr_rqc_plan of this workspace for these bricks, camera and spacing",
+                    who);
+    if (!light || !bg || !out) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
+    const double ln = std::sqrt(light->direction[0] * light->direction[0] + light->direction[1] * light->direction[1] +
+                                light->direction[2] * light->direction[2]);
+    if (!finite3(light->direction) || !(ln > 0.0) || !(light->ambient >= 0.0f && light->ambient <= 1.0f))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: light direction must be finite and non-zero, ambient in [0, 1]",
+                    who);
+    for (int c = 0; c < 4; ++c)
+        if (!std::isfinite(bg[c])) return fail(ctx, VR_ERR_INVALID_ARG, "%s: background not finite", who);
+    if ((reinterpret_cast<uintptr_t>(out) & 15) != 0) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out must be 16-byte aligned", who);
+    const bool shadows = light->ambient < 1.0f;
+    if (shadows && (size_t)pl.total * sizeof(float) > shade_bytes)
+        return fail(ctx, VR_ERR_WORKSPACE, "%s: shade buffer of %zu bytes, need %lld", who, shade_bytes,
+                    pl.total * (long long)sizeof(float));
+    if (shadows && pl.total > 0 && (!shade || (reinterpret_cast<uintptr_t>(shade) & 3) != 0))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: shade buffer NULL or misaligned", who);
+    size_t off[5];
+    const size_t need = rqc_layout(n, E, ctx->cam.width, ctx->cam.height, off);
+    if (workspace_bytes < need) return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes, need %zu", who,
+                                            workspace_bytes, need);
+    char* ws = reinterpret_cast<char*>(workspace);
+    RqcParams p{};
+    p.cam = ctx->cam;
+    p.tf = ctx->tf;
+    p.dt = ctx->dt;
+    p.inv_dt = 1.0 / ctx->dt;
+    for (int c = 0; c < 3; ++c) p.light[c] = light->direction[c] / ln;
+    p.ert_eps = ctx->ert_eps;
+    p.ambient = light->ambient;
+    p.shadows = shadows ? 1 : 0;
+    p.n = n;
+    p.width = ctx->cam.width;
+    p.height = ctx->cam.height;
+    p.bricks = reinterpret_cast<const RqcBrick*>(ws + off[0]);
+    p.n_entries = E;
+    p.kf = reinterpret_cast<int32_t*>(ws + off[1]);
+    p.offsets = reinterpret_cast<long long*>(ws + off[2]);
+    p.total = pl.total;
+    p.shade = shade;
+    p.segs = reinterpret_cast<float*>(ws + off[4]);
+    p.out = out;
+    for (int c = 0; c < 4; ++c) p.bg[c] = bg[c];
+    p.err = err_word(ctx);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+    const hipError_t e = launch_rqc_frame(p, ctx->cus, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
     return ok(ctx);
 }
 

@@ -84,7 +84,7 @@ struct QueueParams {
 
 // Error bits of the device error word, which sits at byte kErrWordOffset of
 // the library's static scratch array of each device (zero at load).
-enum : int32_t { kErrSpin = 1 };
+enum : int32_t { kErrSpin = 1, kErrRange = 2 };
 constexpr size_t kErrWordOffset = 128;
 
 // Launch-configuration knobs of the staged march.
@@ -183,5 +183,41 @@ hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp,
 hipError_t launch_composite_backward(const CompositeParams& p, const CompositeBackParams& bp,
                                      hipStream_t stream);
 hipError_t launch_gather(const GatherParams& g, void* dst, StorageK storage, hipStream_t stream);
+
+// Ray-queue cycling (rqc.hip): bricks as ranks, one directional light.
+struct RqcBrick {
+    BrickK brick;
+    int32_t roi_x0, roi_y0, roi_w, roi_h;   // pixels whose rays can own samples of the brick
+    long long entry0;                       // first plan entry of the brick (its ROI pixels, row-major)
+    int32_t storage;                        // kF32 / kF16
+    int32_t pad_;
+};
+
+struct RqcParams {
+    CameraK cam;
+    TFK tf;
+    double dt, inv_dt;
+    double light[3];            // unit direction toward the light
+    float ert_eps;
+    float ambient;              // a0: emission scaled by a0 + (1 - a0) S
+    int32_t shadows;            // 0: a0 = 1, no shadow rays traced
+    int32_t n;                  // bricks (ranks)
+    int32_t step;               // cycle step of a step launch
+    int32_t width, height;
+    const RqcBrick* bricks;     // device, n
+    long long n_entries;        // sum of ROI pixels over the bricks
+    int32_t* kf;                // per entry: first owned sample index (-1: none)
+    long long* offsets;         // per entry: first sample slot; offsets[n_entries] = total
+    long long total;            // owned primary samples (shadow rays)
+    float* shade;               // per slot: shadow transmittance
+    float* segs;                // per pixel: n x (key, C_r, C_g, C_b, alpha)
+    float* out;                 // height x width x 4
+    float bg[4];
+    int32_t* err;               // device error word
+};
+
+hipError_t launch_rqc_plan(const RqcParams& p, long long* scan_sums, long long* total, hipStream_t stream);
+long long rqc_scan_blocks(long long n_entries);
+hipError_t launch_rqc_frame(RqcParams p, int cus, hipStream_t stream);
 
 }  // namespace dpvr

@@ -109,6 +109,39 @@ __device__ inline bool setup_ray(const CameraK& cam, const BrickK& b, double dt,
     return true;
 }
 
+// Any ray (origin o, unit direction d, float64) and its owned run [kf, kl] of
+// the lattice t_k = (k + 1/2) dt in brick b, by the ownership scan of
+// setup_ray (shadow rays start at a primary sample and head for the light).
+__device__ inline bool setup_ray_from(double o0, double o1, double o2, double d0, double d1, double d2,
+                                      const BrickK& b, double dt, RaySetup& rs) {
+#pragma clang fp contract(off)
+    rs.o[0] = o0; rs.o[1] = o1; rs.o[2] = o2;
+    rs.d[0] = d0; rs.d[1] = d1; rs.d[2] = d2;
+    double tin = 0.0, tout = INFINITY;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (rs.d[c] == 0.0) {
+            if (rs.o[c] < b.lo[c] || rs.o[c] >= b.hi[c]) return false;
+            continue;
+        }
+        double ta = (b.lo[c] - rs.o[c]) / rs.d[c], tb = (b.hi[c] - rs.o[c]) / rs.d[c];
+        tin = fmax(tin, fmin(ta, tb));
+        tout = fmin(tout, fmax(ta, tb));
+    }
+    if (!(tout >= tin - 2.0 * dt)) return false;
+    long long k0 = (long long)fmax(floor(tin / dt - 0.5) - 2.0, 0.0);
+    long long k1 = (long long)(ceil(tout / dt - 0.5) + 2.0);
+    if (k1 < k0) return false;
+    long long kf = k0;
+    while (kf <= k1 && !owned(rs.o, rs.d, ((double)kf + 0.5) * dt, b.lo, b.hi)) ++kf;
+    if (kf > k1) return false;
+    long long kl = k1;
+    while (kl > kf && !owned(rs.o, rs.d, ((double)kl + 0.5) * dt, b.lo, b.hi)) --kl;
+    rs.kf = kf;
+    rs.kl = kl;
+    return true;
+}
+
 // Anchor blocks.  Every ray picks a slab axis w (z or y, whichever has the
 // larger direction component; x only if both are below 1/16) and cuts its
 // owned samples at the planes s_w = kSlab * m of the brick's stored-index

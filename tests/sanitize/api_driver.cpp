@@ -158,6 +158,37 @@ int main() {
     }
     EXPECT(vr_composite_backward(ctx, parts, 3, bg, out, d_parts) == VR_OK);
 
+    // ray-queue cycling: sizes, plan, renders with and without shadows
+    {
+        size_t rb = 0;
+        EXPECT(vr_rqc_workspace_size(ctx, 0, bricks, &rb) == VR_ERR_INVALID_ARG);
+        vr_brick twice[2] = {bricks[0], bricks[0]};
+        EXPECT(vr_rqc_workspace_size(ctx, 2, twice, &rb) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_rqc_workspace_size(ctx, 3, bricks, &rb) == VR_OK && rb > 0);
+        void* rws = aligned_buf(rb);
+        int64_t total = -1;
+        vr_light light = {{1.0, 0.5, -0.25}, 0.3f, 0};
+        float* frame = static_cast<float*>(aligned_buf(64 * 48 * 16));
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, nullptr, 0, frame) == VR_ERR_STATE);  // no plan
+        EXPECT(vr_rqc_plan(ctx, 3, bricks, rws, rb - 1, &total) == VR_ERR_WORKSPACE);
+        EXPECT(vr_rqc_plan(ctx, 3, bricks, rws, rb, &total) == VR_OK && total >= 0);
+        float* shade = static_cast<float*>(aligned_buf((size_t)(total > 0 ? total : 1) * 4));
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, 0, frame) ==
+               (total > 0 ? VR_ERR_WORKSPACE : VR_OK));
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, (size_t)total * 4, frame) == VR_OK);
+        vr_light off = {{0.0, 0.0, 0.0}, 1.0f, 0};
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &off, bg, rws, rb, nullptr, 0, frame) == VR_ERR_INVALID_ARG);
+        off.direction[1] = 1.0;
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &off, bg, rws, rb, nullptr, 0, frame) == VR_OK);
+        light.ambient = 1.5f;
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, (size_t)total * 4, frame) ==
+               VR_ERR_INVALID_ARG);
+        EXPECT(vr_render_rqc(ctx, 2, bricks, &off, bg, rws, rb, nullptr, 0, frame) == VR_ERR_STATE);  // other bricks
+        std::free(shade);
+        std::free(frame);
+        std::free(rws);
+    }
+
     // checkpointed forward and adjoint of one partial
     size_t ck = 0;
     EXPECT(vr_checkpoint_size(ctx, bricks[0], &parts[0], 0, &ck) == VR_ERR_INVALID_ARG);

@@ -76,4 +76,12 @@ hipError_t launch_composite_backward(const CompositeParams&, const CompositeBack
     return hipSuccess;
 }
 hipError_t launch_gather(const GatherParams&, void*, StorageK, hipStream_t) { return hipSuccess; }
+hipError_t launch_rqc_plan(const RqcParams& p, long long*, long long* total, hipStream_t) {
+    // every plan entry one sample, so the total is known on the host side
+    for (long long e = 0; e < p.n_entries; ++e) { p.kf[e] = 0; p.offsets[e] = e; }
+    *total = p.n_entries;
+    return hipSuccess;
+}
+long long rqc_scan_blocks(long long n_entries) { return (n_entries + 1023) / 1024; }
+hipError_t launch_rqc_frame(RqcParams, int, hipStream_t) { return hipSuccess; }
 }  // namespace dpvr
