@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint", "rqc"], default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default=None,
                     help="brick storage (default f32; c5 is a float16 workload: f16)")
     ap.add_argument("--path", choices=["staged", "direct"], default="staged",
@@ -699,6 +699,102 @@ def adjoint_cpu_baseline(sc, cams, target_s, samples_per_step):
             **host_info()}
 
 
+def rqc_scene():
+    """Ray-queue-cycling workload: 96^3 field (8 blobs + a tanh shock), 6 kd
+    bricks as ranks, 384x384 orbit view, step 0.5, one
+    directional light at ambient 0.3 (opacity scale 0.25)."""
+    import synth
+    rng = np.random.default_rng(6)
+    dims = (96, 96, 96)
+    field = synth.tile_field(rng, dims, n_blobs=8, noise=0.0, shock=True)
+    boxes = synth.kd_split(dims, 6, rng)
+    cam = synth.orbit_camera((0, 0, 0), dims, 384, 384)
+    sc = synth.scene_from_field("rqc_96cube_6bricks", field, boxes, synth.default_tf(), cam, 0.5, 0.25)
+    return sc, (0.8, 1.0, -0.4), 0.3
+
+
+def bench_rqc(args):
+    """Ray-queue cycling with shadow rays (bricks as ranks): the frame with
+    the light, the same frame without shadow rays, and the sort-last frame of
+    the same bricks for comparison."""
+    import torch
+
+    import oracle
+    import paper_2501_01628_amd as dp
+    sc, light, ambient = rqc_scene()
+    r = dp.Renderer([(b.voxels, b.lo) for b in sc.bricks], sc.tf, sc.vrange, sc.opacity_scale, sc.step, 0.0,
+                    storage=dp.VR_F32, device=0)
+    r.set_camera(sc.camera)
+    total = r.rqc_plan()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    bg = (0.0, 0.0, 0.0, 0.0)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(r.stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(r.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ms_shadow = timed(lambda: r.render_rqc(light, ambient, bg))
+    cnt.zero_()
+    r.render_rqc(light, ambient, bg, samples=cnt)
+    torch.cuda.synchronize()
+    samples = int(cnt.item())
+    frame = r.frame.cpu().numpy().astype(np.float64)
+    ms_plain = timed(lambda: r.render_rqc(light, 1.0, bg))
+    ms_sortlast = timed(lambda: r.render(bg))
+    r.close()
+    W, H = sc.camera["width"], sc.camera["height"]
+    peak = VALU_LANES_PER_CU_CYCLE * N_CU * CLOCK_HZ
+    achieved = samples * VALU_LANE_OPS_PER_SAMPLE / (ms_shadow * 1e-3)
+    out = {"metric": "Msamples/s (ray-queue-cycled frame with shadow rays: primary + shadow samples "
+                     "evaluated per frame x frames/s)",
+           "value": samples / (ms_shadow * 1e-3) / 1e6, "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_shadow, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"rqc: 96^3 f32 field (8 blobs + tanh shock), 6 kd bricks as ranks, "
+                                  f"{W}x{H} perspective, step 0.5, opacity 0.25, light {light}, ambient {ambient}"},
+           "samples_per_frame": samples, "primary_samples_per_frame": total,
+           "ms_without_shadows": ms_plain, "ms_sort_last": ms_sortlast,
+           "roofline": {"kernel": "rqc_shadow_step x 6 + rqc_primary_step x 6 + rqc_resolve", "bound": "alu",
+                        "achieved": achieved, "peak": peak, "unit": "lane-op/s", "frac": achieved / peak,
+                        "traffic": None,
+                        "model": f"{VALU_LANE_OPS_PER_SAMPLE} VALU lane-ops per evaluated sample; peak = 64 "
+                                 f"lanes/CU/cycle x 256 CUs x 2.4 GHz, unpacked fp32"}}
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle with shadow rays on a pixel sample) ...")
+        rng = np.random.default_rng(3)
+
+        def run(npix):
+            idx = rng.choice(W * H, min(npix, W * H), replace=False)
+            pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
+            t0 = time.perf_counter()
+            img, _, _ = oracle.render_scene_shadowed(sc, light, ambient, pixels=pix)
+            return time.perf_counter() - t0, len(pix), (pix, img)
+        spp = samples / (W * H)       # primary + shadow samples per pixel, counted on the GPU
+        rr = _oracle_rates(run, args.cpu_seconds, spp * 1e-6, first=200, cap=W * H)
+        pix, img = rr["payload"]
+        got = frame[pix[:, 1], pix[:, 0]]
+        out["cpu_baseline"] = {
+            "value": rr["value"], "unit": "Msamples/s", "cores": rr["cores"], "kind": "oracle",
+            "sample": f"{len(pix)} random pixels with shadow rays in {rr['seconds']:.1f} s, pixels/s times "
+                      f"the frame's {spp:.0f} primary + shadow samples per pixel",
+            "one_core_value": rr["one_core_value"],
+            "one_core_sample": f"{min(rr['one_core_n'], W * H)} random pixels, one thread, "
+                               f"{rr['one_core_seconds']:.1f} s", **host_info()}
+        out["max_abs_err_vs_oracle"] = {"value": float(np.max(np.abs(got - img))),
+                                        "pixels": "the cpu_baseline sample", "bar": 1e-5}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -713,6 +809,8 @@ def main():
         return bench_batch(args)
     if args.workload in ("c4", "c5-adjoint"):
         return bench_adjoint(args)
+    if args.workload == "rqc":
+        return bench_rqc(args)
     import torch
 
     import paper_2501_01628_amd as dp

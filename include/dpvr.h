@@ -493,11 +493,14 @@ vr_status vr_rqc_plan(vr_context ctx, int32_t n, const vr_brick* bricks, void* w
  * n cycle steps of the shadow-ray queues (skipped when ambient = 1), n cycle
  * steps of the primary-ray queues, then per pixel the bricks' segments in
  * depth order over bg.  shade: device, total_samples floats (ignored when
- * ambient = 1); out: device, height x width x 4 floats, 16-byte aligned.
- * Enqueued on the context stream.  Errors: VR_ERR_INVALID_HANDLE,
- * VR_ERR_INVALID_ARG, VR_ERR_STATE, VR_ERR_WORKSPACE, VR_ERR_DEVICE. */
+ * ambient = 1); out: device, height x width x 4 floats, 16-byte aligned;
+ * samples: optional device counter (8-byte aligned) to which the primary and
+ * shadow samples evaluated are added.  Enqueued on the context stream.
+ * Errors: VR_ERR_INVALID_HANDLE, VR_ERR_INVALID_ARG, VR_ERR_STATE,
+ * VR_ERR_WORKSPACE, VR_ERR_DEVICE. */
 vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_light* light, const float bg[4],
-                        void* workspace, size_t workspace_bytes, float* shade, size_t shade_bytes, float* out);
+                        void* workspace, size_t workspace_bytes, float* shade, size_t shade_bytes, float* out,
+                        unsigned long long* samples);
 
 #ifdef __cplusplus
 }

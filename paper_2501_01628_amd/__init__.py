@@ -131,7 +131,7 @@ _SIGS = {
     "vr_rqc_plan": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t,
                      C.POINTER(C.c_int64)], _st),
     "vr_render_rqc": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_light), _f4, C.c_void_p,
-                       C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p], _st),
+                       C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], _st),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -276,11 +276,12 @@ def vr_rqc_plan(ctx, bricks, ws, nbytes):
     return total.value
 
 
-def vr_render_rqc(ctx, bricks, light_dir, ambient, bg, ws, nbytes, shade, shade_bytes, out):
+def vr_render_rqc(ctx, bricks, light_dir, ambient, bg, ws, nbytes, shade, shade_bytes, out, samples=None):
     arr = (C.c_void_p * len(bricks))(*bricks)
     lt = vr_light((C.c_double * 3)(*[float(v) for v in light_dir]), float(ambient), 0)
     _check(_lib.vr_render_rqc(ctx, len(bricks), arr, C.byref(lt), _f4(*bg), _ptr(ws), nbytes,
-                              _ptr(shade) if shade is not None else None, shade_bytes, _ptr(out)), ctx)
+                              _ptr(shade) if shade is not None else None, shade_bytes, _ptr(out),
+                              _ptr(samples)), ctx)
 
 
 def vr_set_march_path(ctx, path):
@@ -522,12 +523,14 @@ class Renderer:
         self._rqc = (ws, base, nbytes, shade, total)
         return total
 
-    def render_rqc(self, light_dir, ambient, bg=(0.0, 0.0, 0.0, 0.0)):
+    def render_rqc(self, light_dir, ambient, bg=(0.0, 0.0, 0.0, 0.0), samples=None):
         """The frame by ray-queue cycling with one directional light (plan
-        first with :meth:`rqc_plan`); returns the (H, W, 4) frame tensor."""
+        first with :meth:`rqc_plan`); returns the (H, W, 4) frame tensor.
+        ``samples``: optional int64 device tensor that counts the primary and
+        shadow samples evaluated."""
         _, base, nbytes, shade, total = self._rqc
         vr_render_rqc(self.ctx, self.bricks, light_dir, ambient, bg, base, nbytes, shade, shade.numel() * 4,
-                      self.frame)
+                      self.frame, samples)
         return self.frame
 
     def partial_arrays(self, k):

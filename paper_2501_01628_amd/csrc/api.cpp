@@ -1154,7 +1154,8 @@ vr_status vr_rqc_plan(vr_context ctx, int32_t n, const vr_brick* bricks, void* w
 }
 
 vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_light* light, const float bg[4],
-                        void* workspace, size_t workspace_bytes, float* shade, size_t shade_bytes, float* out) {
+                        void* workspace, size_t workspace_bytes, float* shade, size_t shade_bytes, float* out,
+                        unsigned long long* samples) {
     static const char* who = "vr_render_rqc";
     std::vector<RqcBrick> tab;
     long long E = 0;
@@ -1179,7 +1180,8 @@ vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const
                     who);
     for (int c = 0; c < 4; ++c)
         if (!std::isfinite(bg[c])) return fail(ctx, VR_ERR_INVALID_ARG, "%s: background not finite", who);
-    if ((reinterpret_cast<uintptr_t>(out) & 15) != 0) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out must be 16-byte aligned", who);
+    if ((reinterpret_cast<uintptr_t>(out) & 15) != 0 || (reinterpret_cast<uintptr_t>(samples) & 7) != 0)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: out must be 16-, samples 8-byte aligned", who);
     const bool shadows = light->ambient < 1.0f;
     if (shadows && (size_t)pl.total * sizeof(float) > shade_bytes)
         return fail(ctx, VR_ERR_WORKSPACE, "%s: shade buffer of %zu bytes, need %lld", who, shade_bytes,
@@ -1212,6 +1214,7 @@ vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const
     p.segs = reinterpret_cast<float*>(ws + off[4]);
     p.out = out;
     for (int c = 0; c < 4; ++c) p.bg[c] = bg[c];
+    p.samples = samples;
     p.err = err_word(ctx);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);

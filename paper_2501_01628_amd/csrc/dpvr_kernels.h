@@ -213,6 +213,7 @@ struct RqcParams {
     float* segs;                // per pixel: n x (key, C_r, C_g, C_b, alpha)
     float* out;                 // height x width x 4
     float bg[4];
+    unsigned long long* samples;  // optional: += primary and shadow samples evaluated
     int32_t* err;               // device error word
 };
 

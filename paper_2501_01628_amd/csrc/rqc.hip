@@ -54,6 +54,14 @@ __device__ inline long long entry_of_slot(const RqcParams& p, long long q) {
     return lo;
 }
 
+// Adds every lane's n to *counter (one atomic per wavefront); all lanes of
+// the wavefront must call it.
+__device__ inline void count_samples(unsigned long long* counter, unsigned long long n) {
+    if (!counter) return;
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off);
+    if ((threadIdx.x & 63) == 0 && n) atomicAdd(counter, n);
+}
+
 // ----------------------------------------------------------------- plan
 __global__ __launch_bounds__(256) void rqc_count(RqcParams p) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,6 +184,7 @@ __global__ __launch_bounds__(256) void rqc_shadow_step(RqcParams p) {
     __syncthreads();
     const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
     const float tf_o = -p.tf.vmin * tf_k;
+    unsigned long long evaluated = 0;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < p.total;
          q += (long long)gridDim.x * blockDim.x) {
         const long long e = entry_of_slot(p, q);
@@ -199,6 +208,7 @@ __global__ __launch_bounds__(256) void rqc_shadow_step(RqcParams p) {
         if (setup_ray_from(x0, x1, x2, p.light[0], p.light[1], p.light[2], at.brick, p.dt, rs)) {
             auto absorb = [&](long long, float v) {
                 T = T * trans_exp2(-classify(tft, v, tf_k, tf_o).a);
+                ++evaluated;
                 return true;
             };
             if (at.storage == kF16)
@@ -208,6 +218,7 @@ __global__ __launch_bounds__(256) void rqc_shadow_step(RqcParams p) {
         }
         p.shade[q] = p.step == 0 ? T : p.shade[q] * T;
     }
+    count_samples(p.samples, evaluated);
 }
 
 // --------------------------------------------------------------- primary
@@ -220,17 +231,20 @@ __global__ __launch_bounds__(256) void rqc_primary_step(RqcParams p) {
     __shared__ TFTable tft;
     load_tf(tft, p.tf, p.dt, threadIdx.x, blockDim.x);
     __syncthreads();
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= (long long)p.width * p.height) return;
+    const long long npx = (long long)p.width * p.height;
+    const long long pix = min((long long)blockIdx.x * blockDim.x + threadIdx.x, npx - 1);
+    const bool live = (long long)blockIdx.x * blockDim.x + threadIdx.x < npx;   // the rest mirror the last pixel
     const int px = (int)(pix % p.width), py = (int)(pix / p.width);
     const int c = ((px / 8 + py / 8) % p.n + p.step) % p.n;
     const RqcBrick& rb = p.bricks[c];
     const float tf_k = 255.0f / (p.tf.vmax - p.tf.vmin);
     const float tf_o = -p.tf.vmin * tf_k;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f, key = INFINITY;
+    unsigned long long evaluated = 0;
     const int lx = px - rb.roi_x0, ly = py - rb.roi_y0;
     RaySetup rs;
-    if (lx >= 0 && ly >= 0 && lx < rb.roi_w && ly < rb.roi_h && setup_ray(p.cam, rb.brick, p.dt, px, py, rs)) {
+    if (live && lx >= 0 && ly >= 0 && lx < rb.roi_w && ly < rb.roi_h &&
+        setup_ray(p.cam, rb.brick, p.dt, px, py, rs)) {
         key = (float)(((double)rs.kf + 0.5) * p.dt);
         const long long q0 = p.offsets[rb.entry0 + (long long)ly * rb.roi_w + lx];
         const float a0 = p.ambient, a1 = 1.0f - p.ambient;
@@ -245,6 +259,7 @@ __global__ __launch_bounds__(256) void rqc_primary_step(RqcParams p) {
             C1 = fmaf(w, e.g * f, C1);
             C2 = fmaf(w, e.b * f, C2);
             T = Tn;
+            ++evaluated;
             // the partial march tests termination after odd offsets
             return !(((k - rs.kf) & 1) && T < p.ert_eps);
         };
@@ -253,6 +268,8 @@ __global__ __launch_bounds__(256) void rqc_primary_step(RqcParams p) {
         else
             walk<float>(rb.brick, p.dt, p.inv_dt, rs, accumulate);
     }
+    count_samples(p.samples, evaluated);
+    if (!live) return;
     float* sg = p.segs + (pix * p.n + c) * 5;
     sg[0] = key;
     sg[1] = C0;

@@ -169,21 +169,21 @@ int main() {
         int64_t total = -1;
         vr_light light = {{1.0, 0.5, -0.25}, 0.3f, 0};
         float* frame = static_cast<float*>(aligned_buf(64 * 48 * 16));
-        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, nullptr, 0, frame) == VR_ERR_STATE);  // no plan
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, nullptr, 0, frame, nullptr) == VR_ERR_STATE);  // no plan
         EXPECT(vr_rqc_plan(ctx, 3, bricks, rws, rb - 1, &total) == VR_ERR_WORKSPACE);
         EXPECT(vr_rqc_plan(ctx, 3, bricks, rws, rb, &total) == VR_OK && total >= 0);
         float* shade = static_cast<float*>(aligned_buf((size_t)(total > 0 ? total : 1) * 4));
-        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, 0, frame) ==
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, 0, frame, nullptr) ==
                (total > 0 ? VR_ERR_WORKSPACE : VR_OK));
-        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, (size_t)total * 4, frame) == VR_OK);
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, (size_t)total * 4, frame, nullptr) == VR_OK);
         vr_light off = {{0.0, 0.0, 0.0}, 1.0f, 0};
-        EXPECT(vr_render_rqc(ctx, 3, bricks, &off, bg, rws, rb, nullptr, 0, frame) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &off, bg, rws, rb, nullptr, 0, frame, nullptr) == VR_ERR_INVALID_ARG);
         off.direction[1] = 1.0;
-        EXPECT(vr_render_rqc(ctx, 3, bricks, &off, bg, rws, rb, nullptr, 0, frame) == VR_OK);
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &off, bg, rws, rb, nullptr, 0, frame, nullptr) == VR_OK);
         light.ambient = 1.5f;
-        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, (size_t)total * 4, frame) ==
+        EXPECT(vr_render_rqc(ctx, 3, bricks, &light, bg, rws, rb, shade, (size_t)total * 4, frame, nullptr) ==
                VR_ERR_INVALID_ARG);
-        EXPECT(vr_render_rqc(ctx, 2, bricks, &off, bg, rws, rb, nullptr, 0, frame) == VR_ERR_STATE);  // other bricks
+        EXPECT(vr_render_rqc(ctx, 2, bricks, &off, bg, rws, rb, nullptr, 0, frame, nullptr) == VR_ERR_STATE);  // other bricks
         std::free(shade);
         std::free(frame);
         std::free(rws);

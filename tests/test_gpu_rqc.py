@@ -126,3 +126,31 @@ def test_rqc_plan_state_errors(dp):
         r.render_rqc((1, 0, 0), 1.0, BG)
     assert e.value.status == dp.VR_ERR_STATE
     r.close()
+
+
+def test_rqc_sample_counter(dp):
+    """Without early termination and shadows the counter sees each owned
+    primary sample once (the plan's slot count); with early termination it
+    matches the sort-last march's counter; shadow rays add their samples."""
+    sc = _scene(48, (24, 20, 16), 3, 40, 32)
+    r = _renderer(dp, sc, ert=0.0)
+    total = r.rqc_plan()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    r.render_rqc((1, 0, 0), 1.0, BG, samples=cnt)
+    r.synchronize()
+    assert int(cnt.item()) == total
+    cnt.zero_()
+    r.render_rqc((1, 0, 0), 0.5, BG, samples=cnt)
+    r.synchronize()
+    assert int(cnt.item()) > total
+    r.close()
+    r = _renderer(dp, sc, ert=2.0 ** -4)
+    r.reset_samples()
+    r.render(BG)
+    sort_last = int(r.sample_counts().sum())
+    r.rqc_plan()
+    cnt.zero_()
+    r.render_rqc((1, 0, 0), 1.0, BG, samples=cnt)
+    r.synchronize()
+    r.close()
+    assert int(cnt.item()) == sort_last
