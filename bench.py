@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint", "rqc"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint", "rqc", "stream"],
+                    default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default=None,
                     help="brick storage (default f32; c5 is a float16 workload: f16)")
     ap.add_argument("--path", choices=["staged", "direct"], default="staged",
@@ -795,6 +796,109 @@ def bench_rqc(args):
     return 0
 
 
+def stream_scenes(n_steps=6):
+    """Time-series workload: a 384x384x256 float32 field (16 blobs + a tanh
+    front) advected along x by 8 voxels per step, n_steps steps, 8 kd bricks,
+    1920x1080 orbit view, step 0.5, opacity scale 0.05."""
+    import synth
+    dims = (384, 384, 256)
+    rng = np.random.default_rng(7)
+    base = synth.tile_field(rng, dims, n_blobs=16, noise=0.0, shock=True)
+    boxes = synth.kd_split(dims, 8, rng)
+    cam = synth.orbit_camera((0, 0, 0), dims, 1920, 1080)
+    return [synth.scene_from_field(f"stream{t}", np.roll(base, 8 * t, axis=2), boxes, synth.default_tf(), cam,
+                                   0.5, 0.05) for t in range(n_steps)], cam
+
+
+def bench_stream(args):
+    """Playback of a time series with two resident steps (each frame uploads
+    the next step over the host link while the current one renders) against
+    the same frames with every step resident."""
+    import torch
+
+    import paper_2501_01628_amd as dp
+    t0 = time.perf_counter()
+    scenes, cam = stream_scenes()
+    log(f"generated {len(scenes)} time steps in {time.perf_counter() - t0:.1f} s")
+    steps = [[(b.voxels, b.lo) for b in sc.bricks] for sc in scenes]
+    sc0 = scenes[0]
+    T = len(scenes)
+    step_bytes = sum(int(np.prod(v.shape)) * 4 for v, _ in steps[0])
+
+    def play(slots, rounds):
+        sr = dp.StreamRenderer(steps, sc0.tf, sc0.vrange, sc0.opacity_scale, sc0.step, slots=slots)
+        sr.set_camera(cam)
+        order = [t for _ in range(rounds) for t in range(T)]
+        for i, t in enumerate(order[:T]):                 # warm-up pass (loads every step once)
+            sr.render(t, prefetch=order[i + 1] if i + 1 < len(order) else None)
+        torch.cuda.synchronize()
+        loads0, _ = sr.stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sr.stream)
+        timed = order[T:]
+        for i, t in enumerate(timed):
+            sr.render(t, prefetch=timed[i + 1] if i + 1 < len(timed) else None)
+        e1.record(sr.stream)
+        torch.cuda.synchronize()
+        loads, _ = sr.stats()
+        ms = e0.elapsed_time(e1) / len(timed)
+        frame = sr.frame.cpu().numpy()
+        sr.close()
+        return ms, loads - loads0, len(timed), frame
+
+    rounds = 1 + max(1, args.steps // T)
+    ms_stream, loads, frames, frame = play(2, rounds)
+    ms_resident, loads_res, _, _ = play(T, rounds)
+    W, H = cam["width"], cam["height"]
+    out = {"metric": "frames/s (time-series playback, 2 of 6 time steps resident, next step uploaded "
+                     "during each frame)",
+           "value": 1e3 / ms_stream, "unit": "frames/s", "n_gpus": 1, "steps": frames, "warmup": T,
+           "ms_per_step": ms_stream, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"stream: 384x384x256 f32 field advected 8 voxels per step, {T} steps, 8 kd "
+                                  f"bricks, {W}x{H} perspective, step 0.5, opacity 0.05, 2 resident slots"},
+           "ms_all_resident": ms_resident, "loads_per_frame": loads / frames,
+           "bytes_uploaded_per_step": step_bytes,
+           "h2d": {"achieved": step_bytes * loads / frames / (ms_stream * 1e-3) / 1e9, "peak": 64.0,
+                   "unit": "GB/s", "frac": step_bytes * loads / frames / (ms_stream * 1e-3) / 1e9 / 64.0,
+                   "peak_source": "PCIe 5.0 x16, one direction"},
+           "roofline": {"kernel": "time-series frame: host-to-device upload of the next step (copy stream) "
+                                  "overlapped with march + composite of the current one",
+                        "bound": "hbm", "traffic": None,
+                        "achieved": (step_bytes * loads / frames * 2) / (ms_stream * 1e-3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": (step_bytes * loads / frames * 2) / (ms_stream * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "note": "HBM bytes of the upload and its ingest (write + read of each step) per "
+                                "frame; the frame is bound by the host link (see h2d)"}}
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (oracle on a pixel sample of the last step) ...")
+        sc = scenes[(frames + T - 1) % T]
+        rng = np.random.default_rng(0)
+
+        def run(npix):
+            idx = rng.choice(W * H, min(npix, W * H), replace=False)
+            pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
+            t0 = time.perf_counter()
+            img, _, _ = oracle.render_scene(sc, pixels=pix)
+            return time.perf_counter() - t0, len(pix), (pix, img)
+        # rates in pixels/s x 1 / (W H) = frames/s
+        rr = _oracle_rates(run, args.cpu_seconds, 1.0 / (W * H), first=20000, cap=W * H)
+        pix, img = rr["payload"]
+        out["cpu_baseline"] = {"value": rr["value"], "unit": "frames/s", "cores": rr["cores"], "kind": "oracle",
+                               "sample": f"{len(pix)} random pixels of the last step's frame in "
+                                         f"{rr['seconds']:.1f} s, scaled by pixel count (no upload: the "
+                                         f"oracle reads host memory)",
+                               "one_core_value": rr["one_core_value"],
+                               "one_core_sample": f"{min(rr['one_core_n'], W * H)} random pixels, one thread, "
+                                                  f"{rr['one_core_seconds']:.1f} s", **host_info()}
+        out["max_abs_err_vs_oracle"] = {"value": float(np.max(np.abs(frame[pix[:, 1], pix[:, 0]] - img))),
+                                        "pixels": "the cpu_baseline sample", "bar": 1e-5}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -811,6 +915,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "rqc":
         return bench_rqc(args)
+    if args.workload == "stream":
+        return bench_stream(args)
     import torch
 
     import paper_2501_01628_amd as dp

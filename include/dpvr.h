@@ -452,6 +452,65 @@ vr_status vr_render_partial_backward(vr_context ctx, vr_brick brick, const vr_pa
                                      const float* d_part, float* grad_tf, float* grad_volume,
                                      const int32_t vol_dims[3], const int32_t lo[3]);
 
+/* ------------------------------------------------- time-step streaming */
+/* Time-varying data with only some time steps resident (paper Sec. 4: the
+ * time steps of the data set are loaded selectively and evicted later, so
+ * that the GPUs never hold the whole series).  A series owns `slots` sets of
+ * bricks (one brick per vr_brick_desc in every set) in a caller-provided
+ * device workspace; step t of brick b comes from host_voxels[t * n_bricks +
+ * b], a ghost-padded float32 host array (pinned memory lets the copy run
+ * asynchronously; borrowed for the series' lifetime).  Loading a step takes
+ * the least recently used slot, waits (on the GPU) for all render work
+ * enqueued on the context stream so far, then copies the step's arrays to a
+ * device staging buffer and ingests them into the slot's bricks, all on the
+ * series' own copy stream, so uploads overlap rendering. */
+typedef struct vr_timeseries_s* vr_timeseries;
+
+typedef struct {
+    int32_t dims[3];       /* owned voxels (nx, ny, nz) */
+    int32_t ghost;         /* must be 1 */
+    double origin[3];      /* as for vr_brick_create */
+    double spacing[3];
+    vr_dtype storage;
+    int32_t pad_;
+} vr_brick_desc;
+
+/* Host-only: device workspace bytes of a series of these bricks with
+ * `slots` resident steps (slots x the bricks' workspaces + one staging
+ * buffer of the largest float32 brick).  Errors: VR_ERR_INVALID_ARG. */
+vr_status vr_timeseries_workspace_size(int32_t n_bricks, const vr_brick_desc* bricks, int32_t slots, size_t* bytes);
+
+/* Create a series of n_steps steps of n_bricks bricks (1 <= n_bricks <=
+ * DPVR_MAX_PARTIALS) with `slots` >= 1 resident steps.  workspace: device,
+ * 256-byte aligned, vr_timeseries_workspace_size bytes, owned by the caller
+ * and kept until vr_timeseries_release.  Errors: VR_ERR_INVALID_HANDLE,
+ * VR_ERR_INVALID_ARG, VR_ERR_WORKSPACE, VR_ERR_OUT_OF_MEMORY, VR_ERR_DEVICE. */
+vr_status vr_timeseries_create(vr_context ctx, int32_t n_bricks, const vr_brick_desc* bricks, int32_t n_steps,
+                               const float* const* host_voxels, int32_t slots, void* workspace,
+                               size_t workspace_bytes, vr_timeseries* out);
+
+/* Start loading `step` if it is not resident (returns at once; the load
+ * runs on the copy stream).  Errors: VR_ERR_INVALID_HANDLE,
+ * VR_ERR_INVALID_ARG, VR_ERR_DEVICE. */
+vr_status vr_timeseries_prefetch(vr_timeseries ts, int32_t step);
+
+/* The bricks of `step` (loading it first if needed) into bricks[0 ..
+ * n_bricks): the context stream waits (on the GPU) until the step's load has
+ * run, so render calls enqueued after this one see its data.  The handles
+ * belong to the series (vr_brick_release refuses them) and hold this step
+ * until a later prefetch or acquire evicts their slot: enqueue the renders
+ * that read a step before a call that may evict it (an eviction waits for
+ * the work already enqueued on the context stream, not for later work).
+ * Errors: as vr_timeseries_prefetch. */
+vr_status vr_timeseries_acquire(vr_timeseries ts, int32_t step, vr_brick* bricks);
+
+/* Steps loaded so far, and the step each slot holds (-1: none; `slots`
+ * entries).  Either pointer may be NULL. */
+vr_status vr_timeseries_stats(vr_timeseries ts, int64_t* loads, int32_t* resident_steps);
+
+/* Release the series (waits for its copies and the context stream). */
+vr_status vr_timeseries_release(vr_timeseries ts);
+
 /* ---------------------------------------------------- ray-queue cycling */
 /* Data-parallel ray tracing by ray-queue cycling (paper Sec. 2.2 and Fig. 2:
  * rays are queued and batched, every ray is cycled through every rank's

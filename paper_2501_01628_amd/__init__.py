@@ -68,6 +68,11 @@ class vr_batch_frame(C.Structure):
                 ("pad_", C.c_int32), ("bg", C.c_float * 4), ("out", C.c_void_p)]
 
 
+class vr_brick_desc(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("ghost", C.c_int32), ("origin", C.c_double * 3),
+                ("spacing", C.c_double * 3), ("storage", C.c_int), ("pad_", C.c_int32)]
+
+
 class vr_light(C.Structure):
     _fields_ = [("direction", C.c_double * 3), ("ambient", C.c_float), ("pad_", C.c_int32)]
 
@@ -127,6 +132,15 @@ _SIGS = {
     "vr_render_partial_backward": ([C.c_void_p, C.c_void_p, C.POINTER(vr_partial), C.c_int32,
                                     C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                     _i3, _i3], _st),
+    "vr_timeseries_workspace_size": ([C.c_int32, C.POINTER(vr_brick_desc), C.c_int32, C.POINTER(C.c_size_t)],
+                                     _st),
+    "vr_timeseries_create": ([C.c_void_p, C.c_int32, C.POINTER(vr_brick_desc), C.c_int32,
+                              C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)],
+                             _st),
+    "vr_timeseries_prefetch": ([C.c_void_p, C.c_int32], _st),
+    "vr_timeseries_acquire": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)], _st),
+    "vr_timeseries_stats": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], _st),
+    "vr_timeseries_release": ([C.c_void_p], _st),
     "vr_rqc_workspace_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)], _st),
     "vr_rqc_plan": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t,
                      C.POINTER(C.c_int64)], _st),
@@ -260,6 +274,49 @@ def vr_composite(ctx, parts, bg, out):
     n = len(parts)
     arr = (vr_partial * max(n, 1))(*parts)
     _check(_lib.vr_composite(ctx, arr, n, _f4(*bg), _ptr(out)), ctx)
+
+
+def _brick_descs(descs):
+    arr = (vr_brick_desc * len(descs))()
+    for i, (dims, origin, spacing, storage) in enumerate(descs):
+        arr[i] = vr_brick_desc(_i3(*dims), 1, _d3(*origin), _d3(*spacing), int(storage), 0)
+    return arr
+
+
+def vr_timeseries_workspace_size(descs, slots):
+    """descs: [(dims, origin, spacing, storage)] (ghost 1)."""
+    n = C.c_size_t()
+    _check(_lib.vr_timeseries_workspace_size(len(descs), _brick_descs(descs), int(slots), C.byref(n)))
+    return n.value
+
+
+def vr_timeseries_create(ctx, descs, host_ptrs, n_steps, slots, workspace, workspace_bytes):
+    hp = (C.c_void_p * len(host_ptrs))(*host_ptrs)
+    h = C.c_void_p()
+    _check(_lib.vr_timeseries_create(ctx, len(descs), _brick_descs(descs), int(n_steps), hp, int(slots),
+                                     _ptr(workspace), int(workspace_bytes), C.byref(h)), ctx)
+    return h.value
+
+
+def vr_timeseries_prefetch(ts, step, ctx=None):
+    _check(_lib.vr_timeseries_prefetch(ts, int(step)), ctx)
+
+
+def vr_timeseries_acquire(ts, step, n_bricks, ctx=None):
+    out = (C.c_void_p * n_bricks)()
+    _check(_lib.vr_timeseries_acquire(ts, int(step), out), ctx)
+    return list(out)
+
+
+def vr_timeseries_stats(ts, slots, ctx=None):
+    loads = C.c_int64()
+    res = (C.c_int32 * slots)()
+    _check(_lib.vr_timeseries_stats(ts, C.byref(loads), res), ctx)
+    return loads.value, list(res)
+
+
+def vr_timeseries_release(ts, ctx=None):
+    _check(_lib.vr_timeseries_release(ts), ctx)
 
 
 def vr_rqc_workspace_size(ctx, bricks):
@@ -667,6 +724,96 @@ class BatchRenderer:
             self.batch = None
         for b in self.bricks:
             vr_brick_release(b)
+        vr_context_release(self.ctx)
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------ time-step streaming
+class StreamRenderer:
+    """Plays a time series of bricked volumes with only ``slots`` time steps
+    resident on the device.  ``steps[t]`` is a list of (voxels, lo) per brick
+    (ghost-padded float32 arrays, the same brick boxes at every step); the
+    arrays are copied once into pinned host memory, from which the library
+    uploads a step when it is needed (on its own copy stream)."""
+
+    def __init__(self, steps, tf, vrange=(0.0, 1.0), opacity_scale=1.0, dt=0.5, slots=2,
+                 ert_eps=2.0 ** -20, storage=VR_F32, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = vr_context_create(device, self.stream)
+        self.tf = torch.as_tensor(np.ascontiguousarray(tf, dtype=np.float32)).to(self.device)
+        vr_set_transfer_function(self.ctx, self.tf, TF_ENTRIES, vrange[0], vrange[1], opacity_scale)
+        vr_set_render_params(self.ctx, dt, ert_eps)
+        self.n_steps, self.n_bricks, self.slots = len(steps), len(steps[0]), int(slots)
+        descs = []
+        for vox, lo in steps[0]:
+            nz, ny, nx = (int(v) - 2 for v in np.shape(vox))
+            descs.append(((nx, ny, nz), tuple(float(x) for x in lo), (1.0, 1.0, 1.0), storage))
+        self._host = [torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).pin_memory()
+                      for step in steps for v, _ in step]
+        nbytes = vr_timeseries_workspace_size(descs, self.slots)
+        self._ws = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=self.device)
+        base = self._ws.data_ptr() + ((-self._ws.data_ptr()) % 256)
+        self.ts = vr_timeseries_create(self.ctx, descs, [h.data_ptr() for h in self._host], self.n_steps,
+                                       self.slots, base, nbytes)
+        self._bufs = {}
+        self.frame = None
+
+    def set_camera(self, cam):
+        set_camera(self.ctx, cam)
+        self.width, self.height = int(cam["width"]), int(cam["height"])
+        self.frame = self.torch.empty(self.height, self.width, 4, dtype=self.torch.float32, device=self.device)
+
+    def prefetch(self, step):
+        vr_timeseries_prefetch(self.ts, step, self.ctx)
+
+    def render(self, step, bg=(0.0, 0.0, 0.0, 0.0), prefetch=None):
+        """Frame of time step ``step`` (loaded now if it is not resident);
+        ``prefetch``: a step whose upload should start behind this frame."""
+        torch = self.torch
+        bricks = vr_timeseries_acquire(self.ts, step, self.n_bricks, self.ctx)
+        parts = []
+        for k, b in enumerate(bricks):
+            roi = vr_partial_roi(self.ctx, b)
+            key = (k, roi[2], roi[3])
+            if key not in self._bufs:
+                n = max(roi[2] * roi[3], 1)
+                self._bufs[key] = (torch.empty(n * 4, dtype=torch.float32, device=self.device),
+                                   torch.empty(n, dtype=torch.float32, device=self.device))
+            rgba, depth = self._bufs[key]
+            parts.append(make_partial(roi, rgba, depth))
+        need = vr_frame_workspace_size(len(bricks))
+        if getattr(self, "_fws", None) is None or self._fws_bytes < need:
+            self._fws = torch.empty(need // 4 + 64, dtype=torch.float32, device=self.device)
+            self._fws_bytes = need
+        base = self._fws.data_ptr() + ((-self._fws.data_ptr()) % 256)
+        vr_render_partials(self.ctx, bricks, parts, base, need)
+        vr_composite(self.ctx, parts, bg, self.frame)
+        # after the frame's work is enqueued: a load that evicts this step's
+        # slot waits for it
+        if prefetch is not None:
+            vr_timeseries_prefetch(self.ts, prefetch, self.ctx)
+        return self.frame
+
+    def stats(self):
+        return vr_timeseries_stats(self.ts, self.slots, self.ctx)
+
+    def synchronize(self):
+        vr_synchronize(self.ctx)
+
+    def close(self):
+        if self.ctx is None:
+            return
+        vr_synchronize(self.ctx)
+        vr_timeseries_release(self.ts, self.ctx)
         vr_context_release(self.ctx)
         self.ctx = None
 

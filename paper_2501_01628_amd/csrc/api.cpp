@@ -79,6 +79,7 @@ struct vr_brick_s {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     bool has_data = false;
+    const void* owner = nullptr;   // the time series whose slot holds this brick (NULL: the caller's)
 };
 
 namespace {
@@ -387,6 +388,7 @@ vr_status vr_brick_set_data(vr_brick b, const float* voxels) {
 
 vr_status vr_brick_release(vr_brick b) {
     if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_brick_release: invalid brick");
+    if (b->owner) return fail(b->ctx, VR_ERR_STATE, "vr_brick_release: the brick belongs to a time series");
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_live.erase(b);
@@ -1029,6 +1031,281 @@ vr_status vr_render_partial_backward(vr_context ctx, vr_brick b, const vr_partia
     hipError_t e = launch_march_backward(p, bp, b->storage == VR_F16 ? kF16 : kF32, ctx->stream);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partial_backward: %s", hipGetErrorString(e));
     return ok(ctx);
+}
+
+// ---------------------------------------------------- time-step streaming
+struct vr_timeseries_s {
+    vr_context ctx = nullptr;
+    int32_t n_bricks = 0, n_steps = 0, slots = 0;
+    std::vector<vr_brick_desc> desc;
+    std::vector<const float*> host;       // n_steps x n_bricks host pointers (borrowed)
+    std::vector<vr_brick> slot_bricks;    // slots x n_bricks
+    std::vector<int32_t> slot_step;       // step a slot holds (-1: none)
+    std::vector<uint64_t> slot_used;      // last acquire/prefetch (LRU clock)
+    std::vector<hipEvent_t> slot_ready;   // copy stream: the slot's last ingest done
+    std::vector<int32_t> step_slot;       // slot of a step (-1: not resident)
+    hipEvent_t render_mark = nullptr;     // render stream: work enqueued before an eviction
+    hipStream_t copy = nullptr;
+    float* staging = nullptr;             // device, largest float32 ghost-padded brick
+    uint64_t clock = 0;
+    int64_t loads = 0;
+};
+
+namespace {
+
+size_t ts_brick_bytes(const vr_brick_desc& d) {
+    size_t b = 0;
+    (void)vr_brick_workspace_size(d.dims, d.ghost, d.storage, &b);
+    return b;
+}
+
+// Bytes of a step's host array of one brick: the ghost-padded voxels as
+// float32, rows unpadded (the ingest kernel's source layout).
+size_t ts_source_bytes(const vr_brick_desc& d) {
+    return (size_t)(d.dims[0] + 2 * d.ghost) * (size_t)(d.dims[1] + 2 * d.ghost) *
+           (size_t)(d.dims[2] + 2 * d.ghost) * sizeof(float);
+}
+
+size_t ts_staging_bytes(const std::vector<vr_brick_desc>& desc) {
+    size_t m = 0;
+    for (const vr_brick_desc& d : desc) m = std::max(m, ts_source_bytes(d));
+    return (m + 255) & ~(size_t)255;
+}
+
+size_t ts_workspace_bytes(const std::vector<vr_brick_desc>& desc, int32_t slots) {
+    size_t per = 0;
+    for (const vr_brick_desc& d : desc) per += ts_brick_bytes(d);
+    return (size_t)slots * per + ts_staging_bytes(desc);
+}
+
+vr_status ts_check(vr_context ctx, int32_t n_bricks, const vr_brick_desc* bricks, int32_t slots, const char* who) {
+    if (n_bricks < 1 || n_bricks > DPVR_MAX_PARTIALS || !bricks)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: n_bricks = %d outside [1, %d] or NULL", who, n_bricks,
+                    DPVR_MAX_PARTIALS);
+    if (slots < 1) return fail(ctx, VR_ERR_INVALID_ARG, "%s: slots must be >= 1", who);
+    for (int i = 0; i < n_bricks; ++i) {
+        const vr_brick_desc& d = bricks[i];
+        size_t b = 0;
+        if (vr_brick_workspace_size(d.dims, d.ghost, d.storage, &b) != VR_OK)
+            return fail(ctx, VR_ERR_INVALID_ARG, "%s: brick %d: %s", who, i, t_err.c_str());
+        if (!finite3(d.origin)) return fail(ctx, VR_ERR_INVALID_ARG, "%s: brick %d: origin not finite", who, i);
+        for (int c = 0; c < 3; ++c)
+            if (!(d.spacing[c] > 0) || !std::isfinite(d.spacing[c]))
+                return fail(ctx, VR_ERR_INVALID_ARG, "%s: brick %d: spacing must be finite and > 0", who, i);
+    }
+    return VR_OK;
+}
+
+void ts_destroy(vr_timeseries ts) {
+    if (ts->copy) (void)hipStreamSynchronize(ts->copy);
+    for (vr_brick b : ts->slot_bricks) {
+        if (!b) continue;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_live.erase(b);
+        }
+        if (live(b->ctx)) b->ctx->live_bricks--;
+        delete b;
+    }
+    for (hipEvent_t e : ts->slot_ready)
+        if (e) (void)hipEventDestroy(e);
+    if (ts->render_mark) (void)hipEventDestroy(ts->render_mark);
+    if (ts->copy) (void)hipStreamDestroy(ts->copy);
+    delete ts;
+}
+
+// Make `step` resident (no-op if it is): take the least recently used slot,
+// let the copy stream wait for the render work enqueued so far (which is
+// all the work that can read the evicted step), then upload and ingest the
+// step's bricks on the copy stream and record the slot's ready event.
+vr_status ts_load(vr_timeseries ts, int32_t step, const char* who) {
+    vr_context ctx = ts->ctx;
+    ++ts->clock;
+    if (ts->step_slot[step] >= 0) {
+        ts->slot_used[ts->step_slot[step]] = ts->clock;
+        return VR_OK;
+    }
+    int s = -1;                           // an empty slot, else the least recently used one
+    for (int i = 0; i < ts->slots && s < 0; ++i)
+        if (ts->slot_step[i] < 0) s = i;
+    if (s < 0) {
+        s = 0;
+        for (int i = 1; i < ts->slots; ++i)
+            if (ts->slot_used[i] < ts->slot_used[s]) s = i;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+    hipError_t e = hipSuccess;
+    if (ts->slot_step[s] >= 0) {
+        ts->step_slot[ts->slot_step[s]] = -1;
+        e = hipEventRecord(ts->render_mark, ctx->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ts->copy, ts->render_mark, 0);
+    }
+    for (int b = 0; b < ts->n_bricks && e == hipSuccess; ++b) {
+        const vr_brick_desc& d = ts->desc[b];
+        int32_t sdim[3];
+        for (int c = 0; c < 3; ++c) sdim[c] = d.dims[c] + 2 * d.ghost;
+        e = hipMemcpyAsync(ts->staging, ts->host[(size_t)step * ts->n_bricks + b], ts_source_bytes(d),
+                           hipMemcpyHostToDevice, ts->copy);
+        if (e == hipSuccess)
+            e = launch_ingest(ts->staging, ts->slot_bricks[(size_t)s * ts->n_bricks + b]->ws, sdim,
+                              d.storage == VR_F16 ? kF16 : kF32, ts->copy);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ts->slot_ready[s], ts->copy);
+    if (e != hipSuccess) {
+        ts->slot_step[s] = -1;
+        return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    }
+    for (int b = 0; b < ts->n_bricks; ++b) ts->slot_bricks[(size_t)s * ts->n_bricks + b]->has_data = true;
+    ts->slot_step[s] = step;
+    ts->step_slot[step] = s;
+    ts->slot_used[s] = ts->clock;
+    ++ts->loads;
+    return VR_OK;
+}
+
+}  // namespace
+
+vr_status vr_timeseries_workspace_size(int32_t n_bricks, const vr_brick_desc* bricks, int32_t slots, size_t* bytes) {
+    static const char* who = "vr_timeseries_workspace_size";
+    if (!bytes) return fail(nullptr, VR_ERR_INVALID_ARG, "%s: bytes is NULL", who);
+    vr_status st = ts_check(nullptr, n_bricks, bricks, slots, who);
+    if (st != VR_OK) return st;
+    try {
+        *bytes = ts_workspace_bytes(std::vector<vr_brick_desc>(bricks, bricks + n_bricks), slots);
+    } catch (const std::bad_alloc&) {
+        return fail(nullptr, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
+    return VR_OK;
+}
+
+vr_status vr_timeseries_create(vr_context ctx, int32_t n_bricks, const vr_brick_desc* bricks, int32_t n_steps,
+                               const float* const* host_voxels, int32_t slots, void* workspace,
+                               size_t workspace_bytes, vr_timeseries* out) {
+    static const char* who = "vr_timeseries_create";
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (!out) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out is NULL", who);
+    *out = nullptr;
+    vr_status st = ts_check(ctx, n_bricks, bricks, slots, who);
+    if (st != VR_OK) return st;
+    if (n_steps < 1 || !host_voxels) return fail(ctx, VR_ERR_INVALID_ARG, "%s: n_steps < 1 or NULL host array", who);
+    for (int64_t i = 0; i < (int64_t)n_steps * n_bricks; ++i)
+        if (!host_voxels[i]) return fail(ctx, VR_ERR_INVALID_ARG, "%s: host voxel pointer %lld is NULL", who, (long long)i);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace NULL or not 256-byte aligned", who);
+    vr_timeseries ts = new (std::nothrow) vr_timeseries_s;
+    if (!ts) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    try {
+        ts->ctx = ctx;
+        ts->n_bricks = n_bricks;
+        ts->n_steps = n_steps;
+        ts->slots = slots;
+        ts->desc.assign(bricks, bricks + n_bricks);
+        const size_t need = ts_workspace_bytes(ts->desc, slots);
+        if (workspace_bytes < need) {
+            delete ts;
+            return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes, need %zu", who, workspace_bytes, need);
+        }
+        ts->host.assign(host_voxels, host_voxels + (size_t)n_steps * n_bricks);
+        ts->slot_step.assign(slots, -1);
+        ts->slot_used.assign(slots, 0);
+        ts->slot_ready.assign(slots, nullptr);
+        ts->step_slot.assign(n_steps, -1);
+        ts->slot_bricks.assign((size_t)slots * n_bricks, nullptr);
+        char* w = reinterpret_cast<char*>(workspace);
+        for (int s = 0; s < slots; ++s)
+            for (int b = 0; b < n_bricks; ++b) {
+                const vr_brick_desc& d = ts->desc[b];
+                vr_brick br = new vr_brick_s;
+                br->ctx = ctx;
+                for (int c = 0; c < 3; ++c) {
+                    br->dims[c] = d.dims[c];
+                    br->origin[c] = d.origin[c];
+                    br->spacing[c] = d.spacing[c];
+                }
+                br->ghost = d.ghost;
+                br->storage = d.storage;
+                br->ws = w;
+                br->ws_bytes = ts_brick_bytes(d);
+                br->owner = ts;
+                w += br->ws_bytes;
+                {
+                    std::lock_guard<std::mutex> lk(g_mu);
+                    g_live.insert(br);
+                }
+                ctx->live_bricks++;
+                ts->slot_bricks[(size_t)s * n_bricks + b] = br;
+            }
+        ts->staging = reinterpret_cast<float*>(w);
+        DeviceGuard g(ctx->device);
+        hipError_t e = g.ok ? hipSuccess : hipErrorInvalidDevice;
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&ts->copy, hipStreamNonBlocking);
+        for (int s = 0; s < slots && e == hipSuccess; ++s)
+            e = hipEventCreateWithFlags(&ts->slot_ready[s], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ts->render_mark, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            ts_destroy(ts);
+            return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(ts);
+    } catch (const std::bad_alloc&) {
+        ts_destroy(ts);
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
+    ctx->live_bricks++;   // the series pins the context like a brick does
+    *out = ts;
+    return ok(ctx);
+}
+
+vr_status vr_timeseries_prefetch(vr_timeseries ts, int32_t step) {
+    static const char* who = "vr_timeseries_prefetch";
+    if (!live(ts)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid time series", who);
+    if (step < 0 || step >= ts->n_steps)
+        return fail(ts->ctx, VR_ERR_INVALID_ARG, "%s: step %d outside [0, %d)", who, step, ts->n_steps);
+    vr_status st = ts_load(ts, step, who);
+    return st == VR_OK ? ok(ts->ctx) : st;
+}
+
+vr_status vr_timeseries_acquire(vr_timeseries ts, int32_t step, vr_brick* bricks) {
+    static const char* who = "vr_timeseries_acquire";
+    if (!live(ts)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid time series", who);
+    vr_context ctx = ts->ctx;
+    if (step < 0 || step >= ts->n_steps || !bricks)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: step %d outside [0, %d) or NULL output", who, step, ts->n_steps);
+    vr_status st = ts_load(ts, step, who);
+    if (st != VR_OK) return st;
+    const int s = ts->step_slot[step];
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+    const hipError_t e = hipStreamWaitEvent(ctx->stream, ts->slot_ready[s], 0);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    for (int b = 0; b < ts->n_bricks; ++b) bricks[b] = ts->slot_bricks[(size_t)s * ts->n_bricks + b];
+    return ok(ctx);
+}
+
+vr_status vr_timeseries_stats(vr_timeseries ts, int64_t* loads, int32_t* resident_steps) {
+    if (!live(ts)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_timeseries_stats: invalid time series");
+    if (loads) *loads = ts->loads;
+    if (resident_steps)
+        for (int s = 0; s < ts->slots; ++s) resident_steps[s] = ts->slot_step[s];
+    return ok(ts->ctx);
+}
+
+vr_status vr_timeseries_release(vr_timeseries ts) {
+    if (!live(ts)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_timeseries_release: invalid time series");
+    vr_context ctx = ts->ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.erase(ts);
+    }
+    if (live(ctx)) {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);   // renders that read the slots
+        ctx->live_bricks--;
+    }
+    ts_destroy(ts);
+    return VR_OK;
 }
 
 // ------------------------------------------------------- ray-queue cycling

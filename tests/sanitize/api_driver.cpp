@@ -189,6 +189,49 @@ int main() {
         std::free(rws);
     }
 
+    // time-step streaming: three steps of the three bricks, two resident
+    {
+        vr_brick_desc desc[3];
+        for (int i = 0; i < 3; ++i) {
+            std::memcpy(desc[i].dims, dims[i], sizeof desc[i].dims);
+            desc[i].ghost = 1;
+            std::memcpy(desc[i].origin, origins[i], sizeof desc[i].origin);
+            std::memcpy(desc[i].spacing, spacing, sizeof desc[i].spacing);
+            desc[i].storage = i == 2 ? VR_F16 : VR_F32;
+            desc[i].pad_ = 0;
+        }
+        size_t tb = 0;
+        EXPECT(vr_timeseries_workspace_size(3, desc, 0, &tb) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_timeseries_workspace_size(3, desc, 2, &tb) == VR_OK && tb > 0);
+        std::vector<std::vector<float>> host;
+        std::vector<const float*> ptrs;
+        for (int t = 0; t < 3; ++t)
+            for (int i = 0; i < 3; ++i)
+                host.emplace_back((size_t)(dims[i][0] + 2) * (dims[i][1] + 2) * (dims[i][2] + 2), 0.1f * t);
+        for (auto& h : host) ptrs.push_back(h.data());
+        void* tws = aligned_buf(tb);
+        vr_timeseries ts = nullptr;
+        EXPECT(vr_timeseries_create(ctx, 3, desc, 3, ptrs.data(), 2, tws, tb - 1, &ts) == VR_ERR_WORKSPACE);
+        EXPECT(vr_timeseries_create(ctx, 3, desc, 3, ptrs.data(), 2, tws, tb, &ts) == VR_OK);
+        vr_brick got[3];
+        EXPECT(vr_timeseries_acquire(ts, 3, got) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_timeseries_acquire(ts, 0, got) == VR_OK);
+        EXPECT(vr_brick_release(got[0]) == VR_ERR_STATE);
+        EXPECT(vr_render_partials_static(ctx, 3, got, parts) == VR_OK);
+        EXPECT(vr_timeseries_prefetch(ts, 1) == VR_OK);
+        EXPECT(vr_timeseries_acquire(ts, 2, got) == VR_OK);     // evicts step 0 (least recently used)
+        int64_t loads = 0;
+        int32_t res[2] = {-2, -2};
+        EXPECT(vr_timeseries_stats(ts, &loads, res) == VR_OK);
+        EXPECT(loads == 3 && ((res[0] == 2 && res[1] == 1) || (res[0] == 1 && res[1] == 2)));
+        EXPECT(vr_timeseries_acquire(ts, 1, got) == VR_OK);     // resident: no load
+        EXPECT(vr_timeseries_stats(ts, &loads, nullptr) == VR_OK && loads == 3);
+        EXPECT(vr_context_release(ctx) == VR_ERR_STATE);
+        EXPECT(vr_timeseries_release(ts) == VR_OK);
+        EXPECT(vr_timeseries_release(ts) == VR_ERR_INVALID_HANDLE);
+        std::free(tws);
+    }
+
     // checkpointed forward and adjoint of one partial
     size_t ck = 0;
     EXPECT(vr_checkpoint_size(ctx, bricks[0], &parts[0], 0, &ck) == VR_ERR_INVALID_ARG);

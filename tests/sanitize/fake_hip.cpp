@@ -42,6 +42,7 @@ hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned int) { *s = fresh<hipStream_t>(); return hipSuccess; }
 hipError_t hipStreamDestroy(hipStream_t s) { std::free(s); return hipSuccess; }
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned int) { return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t* e) { *e = fresh<hipEvent_t>(); return hipSuccess; }
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = fresh<hipEvent_t>(); return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) { std::free(e); return hipSuccess; }
