@@ -452,6 +452,38 @@ vr_status vr_render_partial_backward(vr_context ctx, vr_brick brick, const vr_pa
                                      const float* d_part, float* grad_tf, float* grad_volume,
                                      const int32_t vol_dims[3], const int32_t lo[3]);
 
+/* Host-only: device workspace bytes of vr_render_partials_checkpointed for
+ * n partials.  Errors: VR_ERR_INVALID_ARG. */
+vr_status vr_checkpointed_workspace_size(int32_t n, size_t* bytes);
+
+/* n calls of vr_render_partial_checkpointed in one launch per storage
+ * precision over all partials' 8x8 tiles (arrays of n entries; ckpts[i] of
+ * ckpt_bytes[i] bytes).  workspace: device, 256-byte aligned,
+ * vr_checkpointed_workspace_size bytes, written by this call and borrowed
+ * until the enqueued work has run.  Errors: as
+ * vr_render_partial_checkpointed, VR_ERR_WORKSPACE. */
+vr_status vr_render_partials_checkpointed(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_partial* parts,
+                                          int32_t interval, float* const* ckpts, const size_t* ckpt_bytes,
+                                          void* workspace, size_t workspace_bytes);
+
+/* Host-only: device workspace bytes of vr_render_partials_backward for n
+ * partials (their job table and workgroup prefix).  Errors:
+ * VR_ERR_INVALID_ARG. */
+vr_status vr_backward_workspace_size(int32_t n, size_t* bytes);
+
+/* The backward of n partials at once (same arguments as n calls of
+ * vr_render_partial_backward, arrays of n entries; los = n x 3 owned min
+ * corners): one launch per storage precision over all partials' tiles, so
+ * that partials of few tiles still fill the GPU.  workspace: device,
+ * 256-byte aligned, vr_backward_workspace_size bytes, written by this call
+ * (the table is copied from host memory) and borrowed until the enqueued
+ * work has run.  Errors: as vr_render_partial_backward, VR_ERR_WORKSPACE. */
+vr_status vr_render_partials_backward(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_partial* parts,
+                                      int32_t interval, const float* const* ckpts, const size_t* ckpt_bytes,
+                                      const float* const* d_parts, float* grad_tf, float* grad_volume,
+                                      const int32_t vol_dims[3], const int32_t* los, void* workspace,
+                                      size_t workspace_bytes);
+
 /* ------------------------------------------------- time-step streaming */
 /* Time-varying data with only some time steps resident (paper Sec. 4: the
  * time steps of the data set are loaded selectively and evicted later, so

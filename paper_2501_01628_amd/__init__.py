@@ -141,6 +141,15 @@ _SIGS = {
     "vr_timeseries_acquire": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)], _st),
     "vr_timeseries_stats": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], _st),
     "vr_timeseries_release": ([C.c_void_p], _st),
+    "vr_backward_workspace_size": ([C.c_int32, C.POINTER(C.c_size_t)], _st),
+    "vr_checkpointed_workspace_size": ([C.c_int32, C.POINTER(C.c_size_t)], _st),
+    "vr_render_partials_checkpointed": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_partial),
+                                         C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t), C.c_void_p,
+                                         C.c_size_t], _st),
+    "vr_render_partials_backward": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_partial), C.c_int32,
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_size_t), C.POINTER(C.c_void_p),
+                                     C.c_void_p, C.c_void_p, _i3, C.POINTER(C.c_int32), C.c_void_p, C.c_size_t],
+                                    _st),
     "vr_rqc_workspace_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)], _st),
     "vr_rqc_plan": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t,
                      C.POINTER(C.c_int64)], _st),
@@ -317,6 +326,44 @@ def vr_timeseries_stats(ts, slots, ctx=None):
 
 def vr_timeseries_release(ts, ctx=None):
     _check(_lib.vr_timeseries_release(ts), ctx)
+
+
+def vr_checkpointed_workspace_size(n):
+    b = C.c_size_t()
+    _check(_lib.vr_checkpointed_workspace_size(int(n), C.byref(b)))
+    return b.value
+
+
+def vr_render_partials_checkpointed(ctx, bricks, parts, interval, ckpts, workspace, workspace_bytes):
+    """ckpts: [(tensor, nbytes)] per partial."""
+    n = len(bricks)
+    hb = (C.c_void_p * max(n, 1))(*bricks)
+    hp = (vr_partial * max(n, 1))(*parts)
+    hc = (C.c_void_p * max(n, 1))(*[_ptr(c) for c, _ in ckpts])
+    hcb = (C.c_size_t * max(n, 1))(*[int(b) for _, b in ckpts])
+    _check(_lib.vr_render_partials_checkpointed(ctx, n, hb, hp, int(interval), hc, hcb, _ptr(workspace),
+                                                int(workspace_bytes)), ctx)
+
+
+def vr_backward_workspace_size(n):
+    b = C.c_size_t()
+    _check(_lib.vr_backward_workspace_size(int(n), C.byref(b)))
+    return b.value
+
+
+def vr_render_partials_backward(ctx, bricks, parts, interval, ckpts, d_parts, grad_tf, grad_volume, vol_dims, los,
+                                workspace, workspace_bytes):
+    """ckpts: [(tensor, nbytes)] per partial; los: [(x, y, z)] per partial."""
+    n = len(bricks)
+    hb = (C.c_void_p * max(n, 1))(*bricks)
+    hp = (vr_partial * max(n, 1))(*parts)
+    hc = (C.c_void_p * max(n, 1))(*[_ptr(c) for c, _ in ckpts])
+    hcb = (C.c_size_t * max(n, 1))(*[int(b) for _, b in ckpts])
+    hd = (C.c_void_p * max(n, 1))(*[_ptr(d) for d in d_parts])
+    hl = (C.c_int32 * max(3 * n, 1))(*[int(v) for lo in los for v in lo])
+    _check(_lib.vr_render_partials_backward(ctx, n, hb, hp, int(interval), hc, hcb, hd, _ptr(grad_tf),
+                                            _ptr(grad_volume), _i3(*vol_dims), hl, _ptr(workspace),
+                                            int(workspace_bytes)), ctx)
 
 
 def vr_rqc_workspace_size(ctx, bricks):
@@ -843,6 +890,7 @@ class DiffRenderer:
         self.vol_dims = tuple(int(v) for v in vol_dims)
         self.vrange, self.opacity_scale, self.dt = vrange, float(opacity_scale), float(dt)
         self.interval = int(interval)
+        self.batched_backward = True     # all bricks' checkpointed forwards, and adjoints, in one launch each
         self.bricks, self.los, self._ws = [], [], []
         vr_set_render_params(self.ctx, self.dt, 0.0)
         for lo, hi in boxes:
@@ -858,8 +906,15 @@ class DiffRenderer:
     def _load(self, tf, volume, cam):
         vr_set_transfer_function(self.ctx, tf, TF_ENTRIES, self.vrange[0], self.vrange[1],
                                  self.opacity_scale)
-        for b, lo in zip(self.bricks, self.los):
-            vr_brick_set_data_global(b, volume, self.vol_dims, lo, self.ctx)
+        # the bricks are re-gathered unless the volume is the tensor of the
+        # last gather (held here, so its memory cannot be another tensor's)
+        # with an unchanged version counter (in-place updates bump it)
+        last = getattr(self, "_loaded", None)
+        if (last is None or last[0].data_ptr() != volume.data_ptr() or last[1] != volume._version or
+                tuple(last[0].shape) != tuple(volume.shape)):
+            for b, lo in zip(self.bricks, self.los):
+                vr_brick_set_data_global(b, volume, self.vol_dims, lo, self.ctx)
+            self._loaded = (volume, volume._version)
         set_camera(self.ctx, cam)
 
     def render(self, tf, volume, cam, bg=(0.0, 0.0, 0.0, 0.0)):
@@ -869,6 +924,7 @@ class DiffRenderer:
         if self.ctx is None:
             return
         vr_synchronize(self.ctx)
+        self._loaded = None
         for b in self.bricks:
             vr_brick_release(b)
         vr_context_release(self.ctx)
@@ -901,10 +957,17 @@ def _autograd_function():
                 part = make_partial(roi, rgba, depth)
                 nb = max(vr_checkpoint_size(dr.ctx, b, part, dr.interval), 4)
                 ck = torch_.empty(nb // 4, dtype=torch_.float32, device=dr.device)
-                vr_render_partial_checkpointed(dr.ctx, b, part, dr.interval, ck, nb)
+                if not dr.batched_backward:
+                    vr_render_partial_checkpointed(dr.ctx, b, part, dr.interval, ck, nb)
                 parts.append(part)
                 keep.append((rgba, depth))
                 ckpts.append((ck, nb))
+            if dr.batched_backward:     # every brick's checkpointed forward in one launch
+                need = vr_checkpointed_workspace_size(len(dr.bricks))
+                ws = torch_.empty(need // 4 + 64, dtype=torch_.float32, device=dr.device)
+                vr_render_partials_checkpointed(dr.ctx, dr.bricks, parts, dr.interval, ckpts,
+                                                ws.data_ptr() + ((-ws.data_ptr()) % 256), need)
+                keep.append(ws)
             out = torch_.empty(H, W, 4, dtype=torch_.float32, device=dr.device)
             vr_composite(dr.ctx, parts, bg, out)
             fctx.dr, fctx.cam, fctx.bg = dr, cam, bg
@@ -925,9 +988,18 @@ def _autograd_function():
             vr_composite_backward(dr.ctx, fctx.parts, fctx.bg, g, d_parts)
             grad_tf = torch_.zeros(TF_ENTRIES, 4, dtype=torch_.float32, device=dr.device)
             grad_vol = torch_.zeros_like(vol_c)
-            for b, lo, part, (ck, nb), dp in zip(dr.bricks, dr.los, fctx.parts, fctx.ckpts, d_parts):
-                vr_render_partial_backward(dr.ctx, b, part, dr.interval, ck, nb, dp, grad_tf,
-                                           grad_vol, dr.vol_dims, lo)
+            if not dr.batched_backward:
+                for b, lo, part, (ck, nb), dp in zip(dr.bricks, dr.los, fctx.parts, fctx.ckpts, d_parts):
+                    vr_render_partial_backward(dr.ctx, b, part, dr.interval, ck, nb, dp, grad_tf, grad_vol,
+                                               dr.vol_dims, lo)
+                return grad_tf, grad_vol, None, None, None
+            # all bricks' adjoints in one launch (per storage precision)
+            need = vr_backward_workspace_size(len(dr.bricks))
+            ws = torch_.empty(need // 4 + 64, dtype=torch_.float32, device=dr.device)
+            base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+            vr_render_partials_backward(dr.ctx, dr.bricks, fctx.parts, dr.interval, fctx.ckpts, d_parts, grad_tf,
+                                        grad_vol, dr.vol_dims, dr.los, base, need)
+            fctx.bwd_ws = ws      # borrowed until the enqueued work has run (the stream orders its reuse)
             return grad_tf, grad_vol, None, None, None
 
     return RenderFn

@@ -35,8 +35,10 @@ constexpr int kWavesWide = 4;
 constexpr int kWideMinTiles = 2048;
 constexpr float kLn2 = 0.6931471805599453f;
 
+// One workgroup's work: tiles first_tile .. first_tile + kWaves - 1 of the
+// partial (p, bp), one per wavefront.
 template <typename TS, int kWaves>
-__global__ __launch_bounds__(kWaves * 64) void march_backward(MarchParams p, BackwardParams bp) {
+__device__ inline void backward_tiles(const MarchParams& p, const BackwardParams& bp, int first_tile) {
     __shared__ TFTable tft;
     __shared__ float gtf[256 * 4];
     __shared__ float tbuf_all[kWaves][kMaxCkptInterval * 64];
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(kWaves * 64) void march_backward(MarchParams p, Bac
     for (int e = threadIdx.x; e < 1024; e += kWaves * 64) gtf[e] = 0.0f;
     __syncthreads();
 
-    const int tile = blockIdx.x * kWaves + wave;
+    const int tile = first_tile + wave;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int lx = tx * kTile + (lane & 7), ly = ty * kTile + (lane >> 3);
     const bool valid = tile < p.tiles_x * p.tiles_y && lx < p.roi_w && ly < p.roi_h;
@@ -207,7 +209,44 @@ __global__ __launch_bounds__(kWaves * 64) void march_backward(MarchParams p, Bac
     }
 }
 
+template <typename TS, int kWaves>
+__global__ __launch_bounds__(kWaves * 64) void march_backward(MarchParams p, BackwardParams bp) {
+    backward_tiles<TS, kWaves>(p, bp, blockIdx.x * kWaves);
+}
+
+// Many partials in one launch: workgroup b takes kWaves tiles of job j, the
+// last j with block_start[j] <= b (so that partials of few tiles still fill
+// the GPU together).
+template <typename TS, int kWaves>
+__global__ __launch_bounds__(kWaves * 64) void march_backward_many(const BackwardJob* __restrict__ jobs,
+                                                                   const int32_t* __restrict__ block_start,
+                                                                   int32_t n_jobs) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (block_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);      // uniform: the job's fields load as scalars
+    const BackwardJob& J = jobs[lo];
+    backward_tiles<TS, kWaves>(J.p, J.bp, (b - __builtin_amdgcn_readfirstlane(block_start[lo])) * kWaves);
+}
+
 }  // namespace
+
+int backward_many_waves() { return kWavesWide; }
+
+hipError_t launch_march_backward_many(const BackwardJob* jobs, const int32_t* block_start, int32_t n_jobs,
+                                      int32_t total_blocks, StorageK storage, hipStream_t stream) {
+    if (n_jobs <= 0 || total_blocks <= 0) return hipSuccess;
+    if (storage == kF16)
+        hipLaunchKernelGGL((march_backward_many<__half, kWavesWide>), dim3(total_blocks), dim3(kWavesWide * 64), 0,
+                           stream, jobs, block_start, n_jobs);
+    else
+        hipLaunchKernelGGL((march_backward_many<float, kWavesWide>), dim3(total_blocks), dim3(kWavesWide * 64), 0,
+                           stream, jobs, block_start, n_jobs);
+    return hipGetLastError();
+}
 
 hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp, StorageK storage,
                                  hipStream_t stream) {

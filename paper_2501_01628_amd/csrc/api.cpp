@@ -990,29 +990,112 @@ vr_status vr_composite_backward(vr_context ctx, const vr_partial* parts, int32_t
     return ok(ctx);
 }
 
-vr_status vr_render_partial_backward(vr_context ctx, vr_brick b, const vr_partial* part,
-                                     int32_t interval, const float* ckpt, size_t ckpt_bytes,
-                                     const float* d_part, float* grad_tf, float* grad_volume,
-                                     const int32_t vol_dims[3], const int32_t lo[3]) {
-    MarchParams p;
-    vr_status st = prepare_march(ctx, b, part, "vr_render_partial_backward", p);
+// Workspace of vr_render_partials_checkpointed: [MarchParams x n | 256][tile prefix int32 x (n + 2) | 256].
+static size_t ckpt_ws_bytes(int32_t n, size_t* off_prefix) {
+    const size_t jobs = (((size_t)n * sizeof(MarchParams)) + 255) / 256 * 256;
+    if (off_prefix) *off_prefix = jobs;
+    return jobs + (((size_t)(n + 2) * sizeof(int32_t)) + 255) / 256 * 256;
+}
+
+vr_status vr_checkpointed_workspace_size(int32_t n, size_t* bytes) {
+    if (n < 0 || !bytes) return fail(nullptr, VR_ERR_INVALID_ARG, "vr_checkpointed_workspace_size: bad argument");
+    *bytes = ckpt_ws_bytes(n, nullptr);
+    return VR_OK;
+}
+
+vr_status vr_render_partials_checkpointed(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_partial* parts,
+                                          int32_t interval, float* const* ckpts, const size_t* ckpt_bytes,
+                                          void* workspace, size_t workspace_bytes) {
+    static const char* who = "vr_render_partials_checkpointed";
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (n < 0 || (n > 0 && (!bricks || !parts || !ckpts || !ckpt_bytes)))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: bad n or NULL arrays", who);
+    if (n == 0) return ok(ctx);
+    size_t off_prefix = 0;
+    const size_t need = ckpt_ws_bytes(n, &off_prefix);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes (256-aligned), need %zu", who,
+                    workspace_bytes, need);
+    try {
+        std::vector<MarchParams> jobs;
+        std::vector<int32_t> prefix(n + 2, 0);
+        int n32 = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            int32_t acc = 0;
+            const int base = pass == 0 ? 0 : n32 + 1;
+            int cnt = 0;
+            for (int i = 0; i < n; ++i) {
+                if (!live(bricks[i]) || bricks[i]->ctx != ctx)
+                    return fail(ctx, VR_ERR_INVALID_HANDLE, "%s: invalid brick %d", who, i);
+                if ((bricks[i]->storage == VR_F16) != (pass == 1)) continue;
+                MarchParams p;
+                vr_status st = prepare_march(ctx, bricks[i], &parts[i], who, p);
+                if (st != VR_OK) return st;
+                size_t nb = 0;
+                st = vr_checkpoint_size(ctx, bricks[i], &parts[i], interval, &nb);
+                if (st != VR_OK) return st;
+                if (!ckpts[i] || ckpt_bytes[i] < nb || (reinterpret_cast<uintptr_t>(ckpts[i]) & 3) != 0)
+                    return fail(ctx, VR_ERR_WORKSPACE, "%s: checkpoint buffer %d of %zu bytes, need %zu", who, i,
+                                ckpt_bytes[i], nb);
+                p.ert_eps = 0.0f;
+                p.ckpt = ckpts[i];
+                p.ckpt_interval = interval;
+                p.ckpt_nseg = (int32_t)ckpt_segments(bricks[i], ctx->dt, interval);
+                prefix[base + cnt] = acc;
+                acc += p.tiles_x * p.tiles_y;
+                jobs.push_back(p);
+                ++cnt;
+            }
+            prefix[base + cnt] = acc;
+            if (pass == 0) n32 = cnt;
+        }
+        char* ws = reinterpret_cast<char*>(workspace);
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+        hipError_t e = hipMemcpyAsync(ws, jobs.data(), jobs.size() * sizeof(MarchParams), hipMemcpyHostToDevice,
+                                      ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws + off_prefix, prefix.data(), prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               ctx->stream);
+        const MarchParams* dj = reinterpret_cast<const MarchParams*>(ws);
+        const int32_t* dp = reinterpret_cast<const int32_t*>(ws + off_prefix);
+        // a group of one partial takes the by-value kernel
+        if (e == hipSuccess && n32 == 1)
+            e = launch_march(jobs[0], kF32, ctx->stream);
+        else if (e == hipSuccess && n32 > 1)
+            e = launch_march_checkpointed_many(dj, dp, n32, prefix[n32], kF32, ctx->stream);
+        if (e == hipSuccess && n - n32 == 1)
+            e = launch_march(jobs[n32], kF16, ctx->stream);
+        else if (e == hipSuccess && n - n32 > 1)
+            e = launch_march_checkpointed_many(dj + n32, dp + n32 + 1, n - n32, prefix[n + 1], kF16, ctx->stream);
+        if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
+    return ok(ctx);
+}
+
+// Kernel parameters of the adjoint of one partial (validated).
+static vr_status prepare_backward(vr_context ctx, vr_brick b, const vr_partial* part, int32_t interval,
+                                  const float* ckpt, size_t ckpt_bytes, const float* d_part, float* grad_tf,
+                                  float* grad_volume, const int32_t vol_dims[3], const int32_t lo[3], const char* who,
+                                  MarchParams& p, BackwardParams& bp) {
+    vr_status st = prepare_march(ctx, b, part, who, p);
     if (st != VR_OK) return st;
     size_t need = 0;
     st = vr_checkpoint_size(ctx, b, part, interval, &need);
     if (st != VR_OK) return st;
     if (!ckpt || ckpt_bytes < need)
-        return fail(ctx, VR_ERR_WORKSPACE, "vr_render_partial_backward: checkpoint buffer of %zu bytes, need %zu",
-                    ckpt_bytes, need);
+        return fail(ctx, VR_ERR_WORKSPACE, "%s: checkpoint buffer of %zu bytes, need %zu", who, ckpt_bytes, need);
     if (!d_part || !grad_tf || !grad_volume || !vol_dims || !lo)
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_render_partial_backward: NULL argument");
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
     if ((reinterpret_cast<uintptr_t>(d_part) & 15) != 0 || (reinterpret_cast<uintptr_t>(grad_tf) & 3) != 0 ||
         (reinterpret_cast<uintptr_t>(grad_volume) & 3) != 0)
-        return fail(ctx, VR_ERR_INVALID_ARG, "vr_render_partial_backward: misaligned buffer");
-    BackwardParams bp{};
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: misaligned buffer", who);
+    bp = BackwardParams{};
     for (int c = 0; c < 3; ++c) {
         if (vol_dims[c] < 1 || lo[c] < 0 || (int64_t)lo[c] + b->dims[c] > vol_dims[c])
-            return fail(ctx, VR_ERR_INVALID_ARG,
-                        "vr_render_partial_backward: owned box [%d, %d) on axis %d outside the %d-voxel grid",
+            return fail(ctx, VR_ERR_INVALID_ARG, "%s: owned box [%d, %d) on axis %d outside the %d-voxel grid", who,
                         lo[c], lo[c] + b->dims[c], c, vol_dims[c]);
         bp.vol_dims[c] = vol_dims[c];
         bp.lo[c] = lo[c];
@@ -1020,16 +1103,111 @@ vr_status vr_render_partial_backward(vr_context ctx, vr_brick b, const vr_partia
     bp.d_part = d_part;
     bp.grad_tf = grad_tf;
     bp.grad_vox = grad_volume;
-    if (part->w == 0 || part->h == 0) return ok(ctx);
     p.ert_eps = 0.0f;
     p.ckpt = const_cast<float*>(ckpt);
     p.ckpt_interval = interval;
     p.ckpt_nseg = (int32_t)ckpt_segments(b, ctx->dt, interval);
     p.samples = nullptr;
+    return VR_OK;
+}
+
+vr_status vr_render_partial_backward(vr_context ctx, vr_brick b, const vr_partial* part,
+                                     int32_t interval, const float* ckpt, size_t ckpt_bytes,
+                                     const float* d_part, float* grad_tf, float* grad_volume,
+                                     const int32_t vol_dims[3], const int32_t lo[3]) {
+    static const char* who = "vr_render_partial_backward";
+    MarchParams p;
+    BackwardParams bp;
+    vr_status st = prepare_backward(ctx, b, part, interval, ckpt, ckpt_bytes, d_part, grad_tf, grad_volume, vol_dims,
+                                    lo, who, p, bp);
+    if (st != VR_OK) return st;
+    if (part->w == 0 || part->h == 0) return ok(ctx);
     DeviceGuard g(ctx->device);
-    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_render_partial_backward: cannot select device %d", ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
     hipError_t e = launch_march_backward(p, bp, b->storage == VR_F16 ? kF16 : kF32, ctx->stream);
-    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_render_partial_backward: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    return ok(ctx);
+}
+
+// Workspace of vr_render_partials_backward: [BackwardJob x n | 256][block prefix int32 x (n + 2) | 256].
+static size_t backward_ws_bytes(int32_t n, size_t* off_prefix) {
+    const size_t jobs = (((size_t)n * sizeof(BackwardJob)) + 255) / 256 * 256;
+    if (off_prefix) *off_prefix = jobs;
+    return jobs + (((size_t)(n + 2) * sizeof(int32_t)) + 255) / 256 * 256;
+}
+
+vr_status vr_backward_workspace_size(int32_t n, size_t* bytes) {
+    if (n < 0 || !bytes) return fail(nullptr, VR_ERR_INVALID_ARG, "vr_backward_workspace_size: bad argument");
+    *bytes = backward_ws_bytes(n, nullptr);
+    return VR_OK;
+}
+
+vr_status vr_render_partials_backward(vr_context ctx, int32_t n, const vr_brick* bricks, const vr_partial* parts,
+                                      int32_t interval, const float* const* ckpts, const size_t* ckpt_bytes,
+                                      const float* const* d_parts, float* grad_tf, float* grad_volume,
+                                      const int32_t vol_dims[3], const int32_t* los, void* workspace,
+                                      size_t workspace_bytes) {
+    static const char* who = "vr_render_partials_backward";
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (n < 0 || (n > 0 && (!bricks || !parts || !ckpts || !ckpt_bytes || !d_parts || !los)))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: bad n or NULL arrays", who);
+    if (n == 0) return ok(ctx);
+    size_t off_prefix = 0;
+    const size_t need = backward_ws_bytes(n, &off_prefix);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes (256-aligned), need %zu", who,
+                    workspace_bytes, need);
+    try {
+        // jobs grouped by storage precision (float32 first); each group is one launch
+        std::vector<BackwardJob> jobs;
+        std::vector<int32_t> prefix(n + 2, 0);
+        const int W = backward_many_waves();
+        int n32 = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            int32_t acc = 0;
+            const int base = pass == 0 ? 0 : n32 + 1;
+            int cnt = 0;
+            for (int i = 0; i < n; ++i) {
+                if (!live(bricks[i]) || bricks[i]->ctx != ctx)
+                    return fail(ctx, VR_ERR_INVALID_HANDLE, "%s: invalid brick %d", who, i);
+                if ((bricks[i]->storage == VR_F16) != (pass == 1)) continue;
+                BackwardJob j;
+                vr_status st = prepare_backward(ctx, bricks[i], &parts[i], interval, ckpts[i], ckpt_bytes[i],
+                                                d_parts[i], grad_tf, grad_volume, vol_dims, los + 3 * i, who, j.p,
+                                                j.bp);
+                if (st != VR_OK) return st;
+                prefix[base + cnt] = acc;
+                acc += (j.p.tiles_x * j.p.tiles_y + W - 1) / W;
+                jobs.push_back(j);
+                ++cnt;
+            }
+            prefix[base + cnt] = acc;
+            if (pass == 0) n32 = cnt;
+        }
+        char* ws = reinterpret_cast<char*>(workspace);
+        DeviceGuard g(ctx->device);
+        if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+        hipError_t e = hipMemcpyAsync(ws, jobs.data(), jobs.size() * sizeof(BackwardJob), hipMemcpyHostToDevice,
+                                      ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws + off_prefix, prefix.data(), prefix.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               ctx->stream);
+        const BackwardJob* dj = reinterpret_cast<const BackwardJob*>(ws);
+        const int32_t* dp = reinterpret_cast<const int32_t*>(ws + off_prefix);
+        // a group of one partial takes the by-value kernel (its parameters in
+        // kernel arguments rather than in the table)
+        if (e == hipSuccess && n32 == 1)
+            e = launch_march_backward(jobs[0].p, jobs[0].bp, kF32, ctx->stream);
+        else if (e == hipSuccess && n32 > 1)
+            e = launch_march_backward_many(dj, dp, n32, prefix[n32], kF32, ctx->stream);
+        if (e == hipSuccess && n - n32 == 1)
+            e = launch_march_backward(jobs[n32].p, jobs[n32].bp, kF16, ctx->stream);
+        else if (e == hipSuccess && n - n32 > 1)
+            e = launch_march_backward_many(dj + n32, dp + n32 + 1, n - n32, prefix[n + 1], kF16, ctx->stream);
+        if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
     return ok(ctx);
 }
 

@@ -180,6 +180,20 @@ hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* b
 inline int32_t composite_blocks(int32_t w, int32_t h) { return ((w + 63) / 64) * ((h + 3) / 4); }
 hipError_t launch_march_backward(const MarchParams& p, const BackwardParams& bp, StorageK storage,
                                  hipStream_t stream);
+// The adjoint of many partials in one launch (one storage precision): job j's
+// tiles are taken backward_many_waves() per workgroup, workgroups
+// block_start[j] .. block_start[j + 1] - 1.
+struct BackwardJob {
+    MarchParams p;
+    BackwardParams bp;
+};
+int backward_many_waves();
+// The checkpointed forward of many partials in one launch (one storage
+// precision): job j's 8x8 tiles are workgroups tile_start[j] .. tile_start[j + 1] - 1.
+hipError_t launch_march_checkpointed_many(const MarchParams* jobs, const int32_t* tile_start, int32_t n_jobs,
+                                          int32_t total_tiles, StorageK storage, hipStream_t stream);
+hipError_t launch_march_backward_many(const BackwardJob* jobs, const int32_t* block_start, int32_t n_jobs,
+                                      int32_t total_blocks, StorageK storage, hipStream_t stream);
 hipError_t launch_composite_backward(const CompositeParams& p, const CompositeBackParams& bp,
                                      hipStream_t stream);
 hipError_t launch_gather(const GatherParams& g, void* dst, StorageK storage, hipStream_t stream);

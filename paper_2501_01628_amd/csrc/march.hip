@@ -297,14 +297,15 @@ __device__ inline void finish(const MarchParams& p, bool valid, long long pix, f
 }
 
 // ------------------------------------------------------------ direct kernel
+// One 8x8 tile of partial p per 64-thread workgroup, every lane marching
+// from HBM.
 template <typename TS, bool kCkpt>
-__global__ __launch_bounds__(64) void march_direct(MarchParams p) {
+__device__ inline void march_tile_hbm(const MarchParams& p, int tile) {
     __shared__ TFTable tft;
     const int lane = threadIdx.x;
     load_tf(tft, p.tf, p.dt, lane, 64);
     __syncthreads();
 
-    const int tile = blockIdx.x;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int lx = tx * 8 + (lane & 7), ly = ty * 8 + (lane >> 3);
     const bool valid = lx < p.roi_w && ly < p.roi_h;
@@ -321,6 +322,27 @@ __global__ __launch_bounds__(64) void march_direct(MarchParams p) {
         march_ray_direct<TS, kCkpt>(p, tft, rs, pix, tf_k, tf_o, eps, s);
     }
     finish(p, valid, pix, depth, s, lane);
+}
+
+template <typename TS, bool kCkpt>
+__global__ __launch_bounds__(64) void march_direct(MarchParams p) {
+    march_tile_hbm<TS, kCkpt>(p, blockIdx.x);
+}
+
+// The checkpointed forward of many partials in one launch: workgroup b takes
+// tile b - tile_start[j] of job j, the last j with tile_start[j] <= b.
+template <typename TS>
+__global__ __launch_bounds__(64) void march_checkpointed_many(const MarchParams* __restrict__ jobs,
+                                                              const int32_t* __restrict__ tile_start,
+                                                              int32_t n_jobs) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    march_tile_hbm<TS, true>(jobs[lo], b - __builtin_amdgcn_readfirstlane(tile_start[lo]));
 }
 
 // ------------------------------------------------- shared by the staged kernels
@@ -1599,6 +1621,18 @@ int march_queue_workgroups_per_cu(StorageK storage, bool staged, int staging, in
     if (!valid_march_config(staging, tile_w, chunk)) return 1;
     if (staging == kStagingSlab) return storage == kF16 ? occupancy_slab<__half>() : occupancy_slab<float>();
     return staged_dispatch<OccupancyRing>(storage, tile_w, chunk);
+}
+
+hipError_t launch_march_checkpointed_many(const MarchParams* jobs, const int32_t* tile_start, int32_t n_jobs,
+                                          int32_t total_tiles, StorageK storage, hipStream_t stream) {
+    if (n_jobs <= 0 || total_tiles <= 0) return hipSuccess;
+    if (storage == kF16)
+        hipLaunchKernelGGL(march_checkpointed_many<__half>, dim3(total_tiles), dim3(64), 0, stream, jobs, tile_start,
+                           n_jobs);
+    else
+        hipLaunchKernelGGL(march_checkpointed_many<float>, dim3(total_tiles), dim3(64), 0, stream, jobs, tile_start,
+                           n_jobs);
+    return hipGetLastError();
 }
 
 hipError_t launch_march(const MarchParams& p, StorageK storage, hipStream_t stream) {

@@ -246,6 +246,37 @@ int main() {
                                       lo_ok) == VR_OK);
     EXPECT(vr_render_partial_backward(ctx, bricks[0], &parts[0], 16, ckpt, ck, d_parts[0], gtf, gvol, vol,
                                       lo_bad) == VR_ERR_INVALID_ARG);
+    {
+        size_t cb = 0;
+        EXPECT(vr_checkpointed_workspace_size(2, &cb) == VR_OK && cb > 0);
+        void* cws = aligned_buf(cb);
+        float* cks2[2] = {ckpt, ckpt};
+        const size_t ckb2[2] = {ck, ck - 4};
+        vr_brick two2[2] = {bricks[0], bricks[0]};
+        vr_partial pp2[2] = {parts[0], parts[0]};
+        EXPECT(vr_render_partials_checkpointed(ctx, 2, two2, pp2, 16, cks2, ckb2, cws, cb) == VR_ERR_WORKSPACE);
+        const size_t ckb3[2] = {ck, ck};
+        EXPECT(vr_render_partials_checkpointed(ctx, 2, two2, pp2, 16, cks2, ckb3, cws, cb) == VR_OK);
+        std::free(cws);
+    }
+    {
+        size_t bb = 0;
+        EXPECT(vr_backward_workspace_size(2, &bb) == VR_OK && bb > 0);
+        void* bws_ = aligned_buf(bb);
+        const float* cks[2] = {ckpt, ckpt};
+        const size_t ckb[2] = {ck, ck};
+        const float* dps[2] = {d_parts[0], d_parts[0]};
+        const int32_t los[6] = {0, 0, 0, 0, 0, 0};
+        vr_brick two[2] = {bricks[0], bricks[0]};
+        vr_partial pp[2] = {parts[0], parts[0]};
+        EXPECT(vr_render_partials_backward(ctx, 2, two, pp, 16, cks, ckb, dps, gtf, gvol, vol, los, bws_, bb - 1) ==
+               VR_ERR_WORKSPACE);
+        EXPECT(vr_render_partials_backward(ctx, 2, two, pp, 16, cks, ckb, dps, gtf, gvol, vol, los, bws_, bb) == VR_OK);
+        const int32_t los_bad[6] = {0, 0, 0, 40, 0, 0};
+        EXPECT(vr_render_partials_backward(ctx, 2, two, pp, 16, cks, ckb, dps, gtf, gvol, vol, los_bad, bws_, bb) ==
+               VR_ERR_INVALID_ARG);
+        std::free(bws_);
+    }
 
     // a batch of two frames (two cameras), its launch, tuning and release
     vr_camera_desc cams[2] = {};

@@ -84,5 +84,12 @@ hipError_t launch_rqc_plan(const RqcParams& p, long long*, long long* total, hip
     return hipSuccess;
 }
 long long rqc_scan_blocks(long long n_entries) { return (n_entries + 1023) / 1024; }
+int backward_many_waves() { return 4; }
+hipError_t launch_march_checkpointed_many(const MarchParams*, const int32_t*, int32_t, int32_t, StorageK, hipStream_t) {
+    return hipSuccess;
+}
+hipError_t launch_march_backward_many(const BackwardJob*, const int32_t*, int32_t, int32_t, StorageK, hipStream_t) {
+    return hipSuccess;
+}
 hipError_t launch_rqc_frame(RqcParams, int, hipStream_t) { return hipSuccess; }
 }  // namespace dpvr

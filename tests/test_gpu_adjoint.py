@@ -131,6 +131,27 @@ def test_f16_table_gradient_central_differences(dp):
     dr.close()
 
 
+@pytest.mark.parametrize("storage", [0, 1], ids=["f32", "f16"])
+def test_batched_backward_equals_per_brick_backward(dp, storage):
+    """One adjoint launch over all bricks' tiles gives the per-brick
+    launches' gradients up to the order of the float atomics."""
+    field, boxes, cams, tf, targets, scale = _small_case(seed=36, nb=6)
+    nx, ny, nz = field.shape[2], field.shape[1], field.shape[0]
+    grads = []
+    for batched in (True, False):
+        dr = dp.DiffRenderer((nx, ny, nz), boxes, (0.0, 1.0), scale, 0.5, 64, storage=storage)
+        dr.batched_backward = batched
+        tft = torch.tensor(tf, dtype=torch.float32, device="cuda", requires_grad=True)
+        vol = torch.tensor(field, dtype=torch.float32, device="cuda", requires_grad=True)
+        for cam, tgt in zip(cams, targets):
+            ((dr.render(tft, vol, cam, BG).double() - torch.tensor(tgt, device="cuda")) ** 2).sum().backward()
+        torch.cuda.synchronize()
+        grads.append((tft.grad.double().cpu().numpy(), vol.grad.double().cpu().numpy()))
+        dr.close()
+    for a, b in zip(grads[0], grads[1]):
+        assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b))
+
+
 def test_checkpoint_interval_invariance(dp):
     case = _small_case(seed=32, nb=2)
     ref = _gpu_grads(dp, *case, interval=64)
