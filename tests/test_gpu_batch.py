@@ -34,8 +34,8 @@ def c3_small():
                            n_blobs=10)
 
 
-def _build(dp, d, storage_of=lambda i: 0):
-    br = dp.BatchRenderer(dt=d["step"])
+def _build(dp, d, storage_of=lambda i: 0, stream=None):
+    br = dp.BatchRenderer(dt=d["step"], stream=stream)
     tf = br.add_tf(d["tf"], (0, 1), d["opacity_scale"])
     for i, (t, f, b, lo, vox) in enumerate(d["bricks"]):
         br.add_brick(vox, lo, storage=storage_of(i))
@@ -116,6 +116,34 @@ def test_autotune_keeps_bits_and_replays_are_stable(dp, c3_small, tmp_path, monk
     # a second tuning of the same shape comes from the cache
     assert br.autotune(reps=2) == -1.0
     br.close()
+
+
+def test_autotune_right_after_launch_on_a_side_stream(dp, c3_small, tmp_path, monkeypatch):
+    """Tuning rewrites the batch's job table; started right behind a launch
+    on a non-blocking side stream it must wait for that launch, so the
+    frames stay bit-identical to the reference."""
+    d = c3_small
+    br, frames = _build(dp, d)
+    br.launch()
+    br.synchronize()
+    ref = [br.frames[fi].cpu().numpy().copy() for _, fi in frames]
+    br.close()
+    monkeypatch.setenv("DPVR_AUTOTUNE_CACHE", str(tmp_path / "tune_side.txt"))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        br, frames = _build(dp, d, stream=side)
+        for fr in br.frames:
+            fr.fill_(-1.0)
+        br.launch()                 # no synchronisation before the tuning
+        br.autotune(reps=1)
+        for fr in br.frames:
+            fr.fill_(-1.0)
+        br.launch()
+        br.synchronize()
+        got = [br.frames[fi].cpu().numpy() for _, fi in frames]
+        br.close()
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)
 
 
 def test_batch_argument_errors(dp, c3_small):
