@@ -20,7 +20,9 @@
 // with one global atomic per touched entry; voxel gradients are
 // scattered with the 8 trilinear weights to the global voxels that the stored
 // (ghost-padded) voxels copy, so ghost contributions fold back to their source
-// (summed per lane while consecutive samples stay in one cell, then 8 atomics).
+// (summed per lane per corner while the walk stays in one cell; moving to a
+// neighbouring cell keeps the sums of the shared corners, so a corner is
+// added with one atomic when the walk leaves it).
 #include "march_common.h"
 
 namespace dpvr {
@@ -94,31 +96,73 @@ __device__ inline void backward_tiles(const MarchParams& p, const BackwardParams
             const Cell c = locate(an, st, (float)(k - kA), snx, sny, snz);
             return c;
         };
-        // voxel-gradient contributions of the current cell, not yet added
+        // voxel-gradient contributions of the current cell's 8 corners, not
+        // yet added (acc[cx + 2 cy + 4 cz] for corner (ix + cx, iy + cy,
+        // iz + cz) of the stored grid)
         int pend_key = -1, pend_ix = 0, pend_iy = 0, pend_iz = 0;
         float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float* G = bp.grad_vox;
+        const long long glo0 = (long long)bp.lo[0] - b.ghost, glo1 = (long long)bp.lo[1] - b.ghost,
+                        glo2 = (long long)bp.lo[2] - b.ghost;
+        // stored index s -> global index clamp(lo + s - ghost)
+        auto add_voxel = [&](int sx, int sy, int sz, float v) {
+            if (v == 0.0f) return;
+            const long long gx = min(max(glo0 + sx, 0LL), gnx - 1);
+            const long long gy = min(max(glo1 + sy, 0LL), gny - 1);
+            const long long gz = min(max(glo2 + sz, 0LL), gnz - 1);
+            atomicAdd(G + (gz * gny + gy) * gnx + gx, v);
+        };
         auto flush = [&]() {
             if (pend_key < 0) return;
-            // stored index s -> global index clamp(lo + s - ghost)
-            const long long gx0 = min(max((long long)bp.lo[0] + pend_ix - b.ghost, 0LL), gnx - 1);
-            const long long gx1 = min(max((long long)bp.lo[0] + pend_ix + 1 - b.ghost, 0LL), gnx - 1);
-            const long long gy0 = min(max((long long)bp.lo[1] + pend_iy - b.ghost, 0LL), gny - 1);
-            const long long gy1 = min(max((long long)bp.lo[1] + pend_iy + 1 - b.ghost, 0LL), gny - 1);
-            const long long gz0 = min(max((long long)bp.lo[2] + pend_iz - b.ghost, 0LL), gnz - 1);
-            const long long gz1 = min(max((long long)bp.lo[2] + pend_iz + 1 - b.ghost, 0LL), gnz - 1);
-            float* G = bp.grad_vox;
-            const long long r00 = (gz0 * gny + gy0) * gnx, r10 = (gz0 * gny + gy1) * gnx;
-            const long long r01 = (gz1 * gny + gy0) * gnx, r11 = (gz1 * gny + gy1) * gnx;
-            atomicAdd(G + r00 + gx0, acc[0]);
-            atomicAdd(G + r00 + gx1, acc[1]);
-            atomicAdd(G + r10 + gx0, acc[2]);
-            atomicAdd(G + r10 + gx1, acc[3]);
-            atomicAdd(G + r01 + gx0, acc[4]);
-            atomicAdd(G + r01 + gx1, acc[5]);
-            atomicAdd(G + r11 + gx0, acc[6]);
-            atomicAdd(G + r11 + gx1, acc[7]);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+            for (int i = 0; i < 8; ++i) {
+                add_voxel(pend_ix + (i & 1), pend_iy + ((i >> 1) & 1), pend_iz + (i >> 2), acc[i]);
+                acc[i] = 0.f;
+            }
+        };
+        // the walk moves to cell (nx, ny, nz): a corner the two cells share
+        // keeps its sum (moving by one cell along an axis keeps the 4 corners
+        // of the face crossed); the corners left behind are added now, one
+        // axis at a time; a jump of more than one cell adds all 8
+        auto move_to = [&](int nx, int ny, int nz, int key) {
+            const int dx = nx - pend_ix, dy = ny - pend_iy, dz = nz - pend_iz;
+            if (pend_key < 0 || dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) {
+                flush();
+            } else {
+                if (dx != 0) {
+#pragma unroll
+                    for (int yz = 0; yz < 4; ++yz) {   // corner pairs along x: acc[2 yz], acc[2 yz + 1]
+                        const int cy = yz & 1, cz = yz >> 1;
+                        const float a0 = acc[2 * yz], a1 = acc[2 * yz + 1];
+                        add_voxel(pend_ix + (dx > 0 ? 0 : 1), pend_iy + cy, pend_iz + cz, dx > 0 ? a0 : a1);
+                        acc[2 * yz] = dx > 0 ? a1 : 0.f;
+                        acc[2 * yz + 1] = dx > 0 ? 0.f : a0;
+                    }
+                }
+                if (dy != 0) {
+#pragma unroll
+                    for (int xz = 0; xz < 4; ++xz) {   // pairs along y: acc[i], acc[i + 2], i = cx + 4 cz
+                        const int cx = xz & 1, cz = xz >> 1, i = cx + 4 * cz;
+                        const float a0 = acc[i], a1 = acc[i + 2];
+                        add_voxel(nx + cx, pend_iy + (dy > 0 ? 0 : 1), pend_iz + cz, dy > 0 ? a0 : a1);
+                        acc[i] = dy > 0 ? a1 : 0.f;
+                        acc[i + 2] = dy > 0 ? 0.f : a0;
+                    }
+                }
+                if (dz != 0) {
+#pragma unroll
+                    for (int xy = 0; xy < 4; ++xy) {   // pairs along z: acc[i], acc[i + 4], i = cx + 2 cy
+                        const float a0 = acc[xy], a1 = acc[xy + 4];
+                        add_voxel(nx + (xy & 1), ny + (xy >> 1), pend_iz + (dz > 0 ? 0 : 1), dz > 0 ? a0 : a1);
+                        acc[xy] = dz > 0 ? a1 : 0.f;
+                        acc[xy + 4] = dz > 0 ? 0.f : a0;
+                    }
+                }
+            }
+            pend_key = key;
+            pend_ix = nx;
+            pend_iy = ny;
+            pend_iz = nz;
         };
         // table-gradient contributions of the current segment index, not
         // yet added (entries seg and seg + 1): consecutive samples mostly
@@ -177,11 +221,7 @@ __device__ inline void backward_tiles(const MarchParams& p, const BackwardParams
                         // consecutive samples mostly share a cell: sum their
                         // corner weights here, one set of atomics per cell
                         const int key = (c.iz * sny + c.iy) * snx + c.ix;
-                        if (key != pend_key) {
-                            flush();
-                            pend_key = key;
-                            pend_ix = c.ix; pend_iy = c.iy; pend_iz = c.iz;
-                        }
+                        if (key != pend_key) move_to(c.ix, c.iy, c.iz, key);
                         const float ux = 1.0f - c.fx, uy = 1.0f - c.fy, uz = 1.0f - c.fz;
                         acc[0] += dv * ux * uy * uz;
                         acc[1] += dv * c.fx * uy * uz;
