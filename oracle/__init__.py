@@ -65,6 +65,11 @@ class _TF(C.Structure):
 _dp = C.POINTER(C.c_double)
 
 
+class _TetPart(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_tets", C.c_int32), ("vertices", C.POINTER(C.c_double)),
+                ("values", C.POINTER(C.c_float)), ("tets", C.POINTER(C.c_int32))]
+
+
 def _load():
     global _lib
     with _lock:
@@ -92,6 +97,10 @@ def _load():
                                                      C.POINTER(C.c_int32), C.c_int64, _dp, _dp,
                                                      C.POINTER(C.c_int64)]
             lib.oc_render_brick_shadowed.restype = C.c_int
+            lib.oc_render_tets.argtypes = [C.POINTER(_Camera), C.c_int32, C.POINTER(_TetPart), C.POINTER(_TF),
+                                           C.c_double, _dp, C.POINTER(C.c_int32), C.c_int64, _dp,
+                                           C.POINTER(C.c_int64)]
+            lib.oc_render_tets.restype = None
             lib.oc_set_threads.argtypes = [C.c_int]
             lib.oc_set_threads.restype = None
             _lib = lib
@@ -326,6 +335,40 @@ def render_scene_shadowed(scene, light_dir, ambient, camera=None, bg=(0.0, 0.0, 
         parts.append((rgba, depth))
         counters += cnt
     return composite(parts, bg), parts, counters
+
+
+# ----------------------------------------------------- tetrahedral parts
+def render_tets(cam, parts, tf, vrange, opacity_scale, dt, bg=(0.0, 0.0, 0.0, 0.0), pixels=None):
+    """Image of the volume given as tetrahedral parts [(vertices (V, 3)
+    float64, values (V,) float32, tets (T, 4) int32)], over bg (R-tet,
+    R-ea).  Returns (image, counters) with counters = [samples held by a
+    tetrahedron, samples held by more than one]."""
+    lib = _load()
+    c = _camera(cam)
+    keep = []
+    arr = (_TetPart * max(len(parts), 1))()
+    for i, (v, f, t) in enumerate(parts):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        f = np.ascontiguousarray(f, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.int32)
+        keep += [v, f, t]
+        arr[i] = _TetPart(len(v), len(t), _ptr(v, C.c_double), _ptr(f, C.c_float), _ptr(t, C.c_int32))
+    tfr = _TFRef(tf, vrange, opacity_scale)
+    bgv = np.asarray(bg, dtype=np.float64)
+    if pixels is None:
+        n = c.width * c.height
+        pix_p = None
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        n = pix.shape[0]
+        pix_p = _ptr(pix, C.c_int32)
+    out = np.zeros(n * 4)
+    cnt = np.zeros(2, dtype=np.int64)
+    lib.oc_render_tets(C.byref(c), len(parts), arr, C.byref(tfr.s), float(dt), _ptr(bgv, C.c_double), pix_p, n,
+                       _ptr(out, C.c_double), _ptr(cnt, C.c_int64))
+    if pixels is None:
+        return out.reshape(c.height, c.width, 4), cnt
+    return out.reshape(n, 4), cnt
 
 
 # ---------------------------------------------------------------- scenes

@@ -19,6 +19,9 @@
  *     rays run through every brick (the secondary rays that data-parallel
  *     ray tracing must send to the ranks holding the occluders)
  *                                                  oc_render_brick_shadowed
+ *   - the image of a volume given as tetrahedral partitions (unstructured,
+ *     possibly non-convex), marched sample by sample through the element
+ *     that holds each sample                       oc_render_tets
  *
  * The paper (Zellmann, "Data Parallel Visualization and Rendering on the
  * RAMSES Supercomputer with ANARI") describes data-parallel ray tracing over
@@ -43,6 +46,11 @@
  *            p_k toward the light (samples p_k + (j + 1/2) dt l, j >= 0, each
  *            evaluated in the brick whose half-open box holds it, none
  *            outside every brick); a0 = 1: no shadows
+ *   R-tet    a point belongs to the tetrahedron whose four signed sub-volumes
+ *            are positive, a zero one counting when a fixed direction g
+ *            enters the tetrahedron across that face (so a point on shared
+ *            faces, edges or vertices of a conforming mesh has exactly one
+ *            owner); value = barycentric interpolation of vertex values
  * No early ray termination: every owned sample is evaluated.  The counters
  * report how many samples a renderer that stops once T < eps would evaluate.
  *
@@ -395,6 +403,128 @@ int oc_render_brick_shadowed(const oc_camera* cam, const oc_brick* b, int32_t nb
     }
     if (counters) { counters[0] += nom; counters[1] += ev; }
     return 0;
+}
+
+/* ------------------------------------------------- tetrahedral partitions */
+typedef struct {
+    int32_t n_vertices, n_tets;
+    const double* vertices;   /* n_vertices x 3 (x, y, z) */
+    const float* values;      /* n_vertices */
+    const int32_t* tets;      /* n_tets x 4 vertex indices, positive orientation */
+} oc_tetpart;
+
+/* Fixed direction of the face tie rule (exact binary fractions; no lattice
+ * normal is orthogonal to it). */
+static const double OC_TIE_G[3] = {1.0, 0.0009765625, 0.00000095367431640625};
+
+/* orient(a, b, c, p) = (b - a) . ((c - a) x (p - a)), in this order. */
+static double orient3(const double a[3], const double b[3], const double c[3], const double p[3]) {
+    double bx = b[0] - a[0], by = b[1] - a[1], bz = b[2] - a[2];
+    double cx = c[0] - a[0], cy = c[1] - a[1], cz = c[2] - a[2];
+    double px = p[0] - a[0], py = p[1] - a[1], pz = p[2] - a[2];
+    double x = cy * pz - cz * py, y = cz * px - cx * pz, z = cx * py - cy * px;
+    return bx * x + by * y + bz * z;
+}
+
+static int lex_less(const double a[3], const double b[3]) {
+    if (a[0] != b[0]) return a[0] < b[0];
+    if (a[1] != b[1]) return a[1] < b[1];
+    return a[2] < b[2];
+}
+
+/* R-tet: signed sub-volume of face i (opposite vertex i) of tetrahedron v
+ * with p, computed from the face's vertices in lexicographic order (so the
+ * tetrahedra sharing a face round it alike), signed positive toward v[i];
+ * *owned: whether g enters the tetrahedron across that face. */
+static double face_volume(const double* const v[4], int i, const double p[3], int* owned) {
+    const double* f[3];
+    int m = 0;
+    for (int j = 0; j < 4; ++j)
+        if (j != i) f[m++] = v[j];
+    for (int a = 1; a < 3; ++a)
+        for (int b = a; b > 0 && lex_less(f[b], f[b - 1]); --b) {
+            const double* t = f[b]; f[b] = f[b - 1]; f[b - 1] = t;
+        }
+    double s = orient3(f[0], f[1], f[2], v[i]) > 0.0 ? 1.0 : -1.0;
+    double e1[3] = {f[1][0] - f[0][0], f[1][1] - f[0][1], f[1][2] - f[0][2]};
+    double e2[3] = {f[2][0] - f[0][0], f[2][1] - f[0][1], f[2][2] - f[0][2]};
+    double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    *owned = s * (n[0] * OC_TIE_G[0] + n[1] * OC_TIE_G[1] + n[2] * OC_TIE_G[2]) > 0.0;
+    return s * orient3(f[0], f[1], f[2], p);
+}
+
+/* Whether tetrahedron t of part P holds p (R-tet); if so its interpolated
+ * value in *value. */
+static int tet_holds(const oc_tetpart* P, int32_t t, const double p[3], double* value) {
+    const double* v[4];
+    for (int j = 0; j < 4; ++j) v[j] = P->vertices + 3 * (int64_t)P->tets[4 * (int64_t)t + j];
+    double D[4];
+    for (int i = 0; i < 4; ++i) {
+        int owned;
+        D[i] = face_volume(v, i, p, &owned);
+        if (D[i] < 0.0 || (D[i] == 0.0 && !owned)) return 0;
+    }
+    double tot = D[0] + D[1] + D[2] + D[3];
+    double val = 0.0;
+    for (int i = 0; i < 4; ++i) val += (D[i] / tot) * (double)P->values[P->tets[4 * (int64_t)t + i]];
+    *value = val;
+    return 1;
+}
+
+/* Image of the volume given by n tetrahedral parts (all parts together form
+ * one mesh), pixels as for oc_render_brick, over bg: the ray's lattice
+ * samples t_k = (k + 1/2) dt inside the parts' common bounding box, each
+ * evaluated in the tetrahedron that holds it (R-tet; none: no
+ * contribution), accumulated front to back (R-ea).  counters: [0] += samples
+ * held by a tetrahedron, [1] += samples held by more than one (0 for a
+ * conforming mesh). */
+void oc_render_tets(const oc_camera* cam, int32_t n, const oc_tetpart* parts, const oc_tf* tf, double dt,
+                    const double bg[4], const int32_t* pix, int64_t npix, double* rgba, int64_t* counters) {
+    double LO[3] = {INFINITY, INFINITY, INFINITY}, HI[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t q = 0; q < n; ++q)
+        for (int32_t v = 0; v < parts[q].n_vertices; ++v)
+            for (int c = 0; c < 3; ++c) {
+                double x = parts[q].vertices[3 * (int64_t)v + c];
+                if (x < LO[c]) LO[c] = x;
+                if (x > HI[c]) HI[c] = x;
+            }
+    int64_t npx = pix ? npix : (int64_t)cam->width * cam->height;
+    int64_t held = 0, twice = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : held, twice)
+    for (int64_t q = 0; q < npx; ++q) {
+        int32_t i = pix ? pix[2 * q] : (int32_t)(q % cam->width);
+        int32_t j = pix ? pix[2 * q + 1] : (int32_t)(q / cam->width);
+        double o[3], d[3];
+        oc_ray(cam, i, j, o, d);
+        double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
+        int64_t k0, k1;
+        if (n > 0 && sample_range(o, d, LO, HI, dt, &k0, &k1)) {
+            for (int64_t k = k0; k <= k1; ++k) {
+                double t = ((double)k + 0.5) * dt;
+                double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+                double v = 0.0, w;
+                int owners = 0;
+                for (int32_t a = 0; a < n; ++a)
+                    for (int32_t e = 0; e < parts[a].n_tets; ++e)
+                        if (tet_holds(&parts[a], e, p, &w)) {
+                            if (owners == 0) v = w;
+                            ++owners;
+                        }
+                if (owners == 0) continue;
+                ++held;
+                if (owners > 1) ++twice;
+                double ev[4], phi; int32_t seg; int inside;
+                classify(tf, v, ev, &seg, &phi, &inside);
+                double alpha = 1.0 - exp(-tf->opacity_scale * ev[3] * dt);
+                for (int c = 0; c < 3; ++c) C[c] += T * alpha * ev[c];
+                T = T * (1.0 - alpha);
+            }
+        }
+        double A = 1.0 - T;
+        for (int c = 0; c < 3; ++c) rgba[4 * q + c] = C[c] + T * bg[c];
+        rgba[4 * q + 3] = A + T * bg[3];
+    }
+    if (counters) { counters[0] += held; counters[1] += twice; }
 }
 
 /* -------------------------------------------------------------- composite */

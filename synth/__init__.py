@@ -447,3 +447,81 @@ def config_c3(extent=(64, 320), pitch=336, n_bricks=14, steps=6, fields=3, size=
     cams = [orbit_camera((0, 0, 0), dims, size, size, az_deg=30.0 + 90.0 * c) for c in range(4)]
     return dict(bricks=bricks, cameras=cams, tf=default_tf(), dims=dims, step=0.5,
                 opacity_scale=0.1, extents=ext)
+
+
+# ------------------------------------------------------- tetrahedral meshes
+def tet_mesh(cells, jitter=0.0, rng=None, spacing=1.0):
+    """Conforming tetrahedral mesh of the box [0, cells * spacing]: vertices
+    on the (cells + 1)^3 lattice (interior vertices moved by U(-jitter,
+    jitter) x spacing per axis, boundary vertices kept on the box), every
+    lattice cube cut into the 6 tetrahedra around its main diagonal (the
+    same cut in every cube, so neighbouring cubes share faces).  Returns
+    (vertices (V, 3) float64 in x, y, z order, tets (T, 4) int32 with
+    positive orientation)."""
+    nx, ny, nz = (int(c) for c in cells)
+    gx, gy, gz = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    verts = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1).astype(np.float64)
+    if jitter > 0.0:
+        interior = ((verts[:, 0] > 0) & (verts[:, 0] < nx) & (verts[:, 1] > 0) & (verts[:, 1] < ny) &
+                    (verts[:, 2] > 0) & (verts[:, 2] < nz))
+        d = rng.uniform(-jitter, jitter, verts.shape)
+        verts[interior] += d[interior]
+    verts *= spacing
+
+    def vid(i, j, k):
+        return (i * (ny + 1) + j) * (nz + 1) + k
+
+    tets = []
+    perms = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                for p in perms:
+                    c = [i, j, k]
+                    t = [vid(*c)]
+                    for a in p:
+                        c[a] += 1
+                        t.append(vid(*c))
+                    tets.append(t)
+    tets = np.asarray(tets, dtype=np.int32)
+    # orient every tetrahedron positively
+    e = verts[tets[:, 1:]] - verts[tets[:, :1]]
+    vol = np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2]))
+    if np.any(vol == 0.0):
+        raise ValueError("degenerate tetrahedron (jitter too large)")
+    neg = vol < 0
+    tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    return verts, tets
+
+
+def tet_field(verts, rng, dims, n_blobs=6):
+    """Vertex values: Gaussian blobs (as :func:`draw_blobs`, sigma scaled
+    to the domain) evaluated at the vertex positions, clamped to [0, 1]."""
+    centres, sig, amps = draw_blobs(rng, n_blobs, dims, sigma=(max(dims) / 10, max(dims) / 4))
+    v = np.zeros(len(verts))
+    for c, s, a in zip(centres, sig, amps):
+        v += a * np.exp(-np.sum((verts - c) ** 2, 1) / (2.0 * s * s))
+    return np.clip(v, 0.0, 1.0).astype(np.float32)
+
+
+def tet_partitions(verts, tets, n_parts, rng):
+    """Uneven, non-convex partitions: each tetrahedron goes to the seed
+    nearest its centroid under a seeded weighted distance with a seeded
+    noise term (weights U(0.5, 2), noise up to an eighth of the longest box
+    edge), so parts differ in size, are not convex and have ragged
+    boundaries.  Returns a list of (vertices, tets, used) per part: local
+    vertex numbering (shared vertices copied), used = the global index of
+    each local vertex."""
+    cen = verts[tets].mean(1)
+    lo, hi = verts.min(0), verts.max(0)
+    seeds = lo + rng.uniform(0.0, 1.0, (n_parts, 3)) * (hi - lo)
+    w = rng.uniform(0.5, 2.0, n_parts)
+    noise = rng.uniform(0.0, 1.0, (len(tets), n_parts)) * np.max(hi - lo) / 8.0
+    d = np.sqrt(((cen[:, None, :] - seeds[None, :, :]) ** 2).sum(2)) / w[None, :] + noise
+    owner = np.argmin(d, 1)
+    parts = []
+    for p in range(n_parts):
+        sel = tets[owner == p]
+        used, inv = np.unique(sel.ravel(), return_inverse=True)
+        parts.append((verts[used].copy(), inv.reshape(-1, 4).astype(np.int32), used))
+    return parts
