@@ -593,6 +593,89 @@ vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const
                         void* workspace, size_t workspace_bytes, float* shade, size_t shade_bytes, float* out,
                         unsigned long long* samples);
 
+/* ---------------------------------------------------- tetrahedral parts */
+/* Unstructured data: a volume given as a tetrahedral mesh split into parts,
+ * each the share of one rank (paper Sec. 2.2 and Fig. 2: finite elements are
+ * distributed so that every rank holds a share; Sec. 4: the lander's
+ * mixed-element data keeps the simulation's partition, which is uneven in
+ * space).  A part need not be convex; together the parts of one frame must
+ * form one conforming mesh (neighbouring tetrahedra share whole faces, no
+ * two overlap).
+ *   locate   a lattice sample p belongs to the tetrahedron whose four signed
+ *            sub-volumes (p against each face, float64) are positive; a
+ *            sub-volume of exactly zero counts as inside when the fixed
+ *            direction g = (1, 2^-10, 2^-20) enters the tetrahedron across
+ *            that face.  Faces are evaluated from their vertices in
+ *            lexicographic order, so in a conforming mesh every sample has
+ *            at most one owner and the owners do not depend on the split.
+ *   value    barycentric interpolation of the four vertex values (the
+ *            sub-volumes over their sum), then the context's transfer
+ *            function, extinction and front-to-back accumulation as for
+ *            bricks; no early termination.
+ *   runs     a ray's samples held by one part fall into runs of consecutive
+ *            lattice indices (a non-convex part can hold several); each run
+ *            is accumulated on its own and the frame is the runs of all
+ *            parts in index order, "over" one another, over a background --
+ *            the same image as accumulating the ray through the whole mesh.
+ * The paper locates elements with a bounding volume hierarchy (Sec. 2.1);
+ * here each part keeps a uniform grid over its bounding box whose cells list
+ * the tetrahedra that can hold a point of the cell. */
+typedef struct vr_tetpart_s* vr_tetpart;
+
+#define DPVR_MAX_TET_PARTS 64        /* parts per vr_render_tetparts call */
+#define DPVR_MAX_TET_RUNS 32         /* runs per ray and part */
+
+/* Create a part from host arrays: vertices (n_vertices x 3 doubles, x, y, z),
+ * tets (n_tets x 4 vertex indices, either orientation).  Builds the part's
+ * location tables in host memory (face planes, tie bits, the grid); the
+ * arrays are not kept.  n_tets may be 0 (a part that owns nothing).
+ * Errors: VR_ERR_INVALID_HANDLE, VR_ERR_INVALID_ARG (index out of range,
+ * non-finite coordinate, zero-volume tetrahedron, more than 2^31 - 1 grid
+ * entries), VR_ERR_OUT_OF_MEMORY. */
+vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_vertices, const int32_t* tets,
+                            int32_t n_tets, vr_tetpart* out);
+
+/* The part's closed bounding box, grid cells per axis, grid entries and the
+ * bytes of device workspace it needs (any pointer may be NULL). */
+vr_status vr_tetpart_info(vr_tetpart part, double lo[3], double hi[3], int32_t grid[3], int64_t* grid_entries,
+                          size_t* workspace_bytes);
+
+/* Give the part its device workspace (caller-owned, 256-byte aligned, at
+ * least the bytes vr_tetpart_info reports, kept until the part is released)
+ * and enqueue the upload of its tables on the context stream.  Vertex values
+ * must be set (again) afterwards. */
+vr_status vr_tetpart_attach(vr_tetpart part, void* workspace, size_t workspace_bytes);
+
+/* Vertex values (a new time step or field): values is a device array of
+ * n_vertices floats, borrowed until the enqueued gather has run.
+ * Errors: VR_ERR_STATE (no workspace attached). */
+vr_status vr_tetpart_set_values(vr_tetpart part, const float* values);
+
+/* Release a part (waits for the context stream first, since uploads may
+ * still read its host tables; the caller frees the workspace). */
+vr_status vr_tetpart_release(vr_tetpart part);
+
+/* Bytes of the frame workspace of vr_render_tetparts for these parts
+ * (1 <= n <= DPVR_MAX_TET_PARTS, no part twice), max_runs (1 ..
+ * DPVR_MAX_TET_RUNS) and the context camera: the part table and, per part,
+ * run buffers over the pixels its bounding box covers.
+ * Errors: VR_ERR_INVALID_HANDLE, VR_ERR_INVALID_ARG, VR_ERR_STATE (no camera). */
+vr_status vr_tetparts_workspace_size(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs,
+                                     size_t* bytes);
+
+/* Render the parts into out (device, height x width x 4 floats,
+ * premultiplied, 16-byte aligned) over bg, with the context camera, transfer
+ * function and dt.  workspace: device, 256-byte aligned, at least
+ * vr_tetparts_workspace_size bytes.  samples: optional device counter
+ * (8-byte aligned) to which the samples held by a tetrahedron are added.  A
+ * ray that crosses a part in more than max_runs runs sets the device error
+ * word (reported as VR_ERR_DEVICE by vr_synchronize; that image is wrong).
+ * Enqueued on the context stream.  Errors: VR_ERR_INVALID_HANDLE,
+ * VR_ERR_INVALID_ARG, VR_ERR_STATE (no camera, transfer function or values),
+ * VR_ERR_WORKSPACE, VR_ERR_OUT_OF_MEMORY, VR_ERR_DEVICE. */
+vr_status vr_render_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
+                             void* workspace, size_t workspace_bytes, float* out, unsigned long long* samples);
+
 #ifdef __cplusplus
 }
 #endif

@@ -155,6 +155,15 @@ _SIGS = {
                      C.POINTER(C.c_int64)], _st),
     "vr_render_rqc": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_light), _f4, C.c_void_p,
                        C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], _st),
+    "vr_tetpart_create": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)], _st),
+    "vr_tetpart_info": ([C.c_void_p, _d3, _d3, _i3, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)], _st),
+    "vr_tetpart_attach": ([C.c_void_p, C.c_void_p, C.c_size_t], _st),
+    "vr_tetpart_set_values": ([C.c_void_p, C.c_void_p], _st),
+    "vr_tetpart_release": ([C.c_void_p], _st),
+    "vr_tetparts_workspace_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32,
+                                    C.POINTER(C.c_size_t)], _st),
+    "vr_render_tetparts": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, _f4, C.c_void_p, C.c_size_t,
+                            C.c_void_p, C.c_void_p], _st),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -388,6 +397,49 @@ def vr_render_rqc(ctx, bricks, light_dir, ambient, bg, ws, nbytes, shade, shade_
                               _ptr(samples)), ctx)
 
 
+def vr_tetpart_create(ctx, vertices, tets):
+    """A tetrahedral part from host arrays (vertices (V, 3) float64, tets
+    (T, 4) int32); the location tables are built on the host."""
+    v = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+    h = C.c_void_p()
+    _check(_lib.vr_tetpart_create(ctx, v.ctypes.data, len(v), t.ctypes.data, len(t), C.byref(h)), ctx)
+    return h
+
+
+def vr_tetpart_info(part, ctx=None):
+    lo, hi, grid = _d3(), _d3(), _i3()
+    entries, nbytes = C.c_int64(), C.c_size_t()
+    _check(_lib.vr_tetpart_info(part, lo, hi, grid, C.byref(entries), C.byref(nbytes)), ctx)
+    return dict(lo=tuple(lo), hi=tuple(hi), grid=tuple(grid), grid_entries=entries.value,
+                workspace_bytes=nbytes.value)
+
+
+def vr_tetpart_attach(part, workspace, workspace_bytes, ctx=None):
+    _check(_lib.vr_tetpart_attach(part, _ptr(workspace), int(workspace_bytes)), ctx)
+
+
+def vr_tetpart_set_values(part, values, ctx=None):
+    _check(_lib.vr_tetpart_set_values(part, _ptr(values)), ctx)
+
+
+def vr_tetpart_release(part, ctx=None):
+    _check(_lib.vr_tetpart_release(part), ctx)
+
+
+def vr_tetparts_workspace_size(ctx, parts, max_runs):
+    arr = (C.c_void_p * len(parts))(*[p.value if isinstance(p, C.c_void_p) else p for p in parts])
+    b = C.c_size_t()
+    _check(_lib.vr_tetparts_workspace_size(ctx, len(parts), arr, int(max_runs), C.byref(b)), ctx)
+    return b.value
+
+
+def vr_render_tetparts(ctx, parts, max_runs, bg, workspace, workspace_bytes, out, samples=None):
+    arr = (C.c_void_p * len(parts))(*[p.value if isinstance(p, C.c_void_p) else p for p in parts])
+    _check(_lib.vr_render_tetparts(ctx, len(parts), arr, int(max_runs), _f4(*bg), _ptr(workspace),
+                                   int(workspace_bytes), _ptr(out), _ptr(samples)), ctx)
+
+
 def vr_set_march_path(ctx, path):
     _check(_lib.vr_set_march_path(ctx, int(path)), ctx)
 
@@ -513,7 +565,74 @@ def set_camera(ctx, cam: dict):
                                    cam["width"], cam["height"])
 
 
-# ------------------------------------------------------------ frame helper
+# ------------------------------------------------------------ frame helpers
+class TetRenderer:
+    """Torch buffers and C-ABI calls for a volume given as tetrahedral parts
+    on one device.  ``parts`` is a list of (vertices (V, 3) float64, tets
+    (T, 4) int32) host arrays; vertex values come per part through
+    :meth:`set_values`."""
+
+    def __init__(self, parts, tf, vrange=(0.0, 1.0), opacity_scale=1.0, dt=0.5, device=0, stream=None,
+                 max_runs=8):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = vr_context_create(device, self.stream)
+        self.tf = torch.as_tensor(np.ascontiguousarray(tf, dtype=np.float32)).to(self.device)
+        vr_set_transfer_function(self.ctx, self.tf, TF_ENTRIES, vrange[0], vrange[1], opacity_scale)
+        vr_set_render_params(self.ctx, dt, 0.0)
+        self.max_runs = int(max_runs)
+        self.parts, self.workspaces, self.values, self.info = [], [], [], []
+        for verts, tets in parts:
+            h = vr_tetpart_create(self.ctx, verts, tets)
+            inf = vr_tetpart_info(h, self.ctx)
+            n = inf["workspace_bytes"]
+            ws = torch.empty(n // 4 + 64, dtype=torch.float32, device=self.device)
+            base = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+            vr_tetpart_attach(h, base, n, self.ctx)
+            self.parts.append(h)
+            self.workspaces.append(ws)
+            self.values.append(None)
+            self.info.append(inf)
+        self.frame = None
+        self._fws, self._fws_bytes = None, 0
+        self.samples = torch.zeros(1, dtype=torch.int64, device=self.device)
+
+    def set_values(self, k, values):
+        v = self.torch.as_tensor(values).to(self.device, self.torch.float32).contiguous()
+        vr_tetpart_set_values(self.parts[k], v, self.ctx)
+        self.values[k] = v                    # kept alive until the next sync
+
+    def set_camera(self, cam):
+        set_camera(self.ctx, cam)
+        self.width, self.height = int(cam["width"]), int(cam["height"])
+        need = vr_tetparts_workspace_size(self.ctx, self.parts, self.max_runs)
+        if self._fws is None or self._fws_bytes < need:
+            self._fws = self.torch.empty(need // 4 + 64, dtype=self.torch.float32, device=self.device)
+            self._fws_bytes = need
+        if self.frame is None or self.frame.numel() != self.width * self.height * 4:
+            self.frame = self.torch.empty(self.height, self.width, 4, dtype=self.torch.float32,
+                                          device=self.device)
+
+    def render(self, bg=(0.0, 0.0, 0.0, 0.0), count=False):
+        base = self._fws.data_ptr() + ((-self._fws.data_ptr()) % 256)
+        vr_render_tetparts(self.ctx, self.parts, self.max_runs, bg, base, self._fws_bytes, self.frame,
+                           self.samples if count else None)
+        return self.frame
+
+    def synchronize(self):
+        vr_synchronize(self.ctx)
+
+    def close(self):
+        for h in self.parts:
+            vr_tetpart_release(h, self.ctx)
+        self.parts = []
+        if self.ctx is not None:
+            vr_context_release(self.ctx)
+            self.ctx = None
+
+
 class Renderer:
     """Owns the torch buffers of one scene on one device and issues the
     C-ABI calls of a frame.  ``bricks`` is a list of (voxels, lo) with voxels a

@@ -18,8 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 ROOT = os.path.dirname(HERE)
 
 ARCH = os.environ.get("DPVR_OFFLOAD_ARCH", "gfx950")
-KERNEL_SOURCES = ["march.hip", "adjoint.hip", "composite.hip", "ingest.hip", "static_scratch.hip", "rqc.hip"]
-HOST_SOURCES = ["api.cpp"]
+KERNEL_SOURCES = ["march.hip", "adjoint.hip", "composite.hip", "ingest.hip", "static_scratch.hip", "rqc.hip", "tets.hip"]
+HOST_SOURCES = ["api.cpp", "tet_build.cpp"]
 
 
 def _hipcc() -> str:

@@ -18,8 +18,12 @@
 
 #include "../../include/dpvr.h"
 #include "dpvr_kernels.h"
+#include "tet_build.h"
 
 using namespace dpvr;
+
+static_assert(DPVR_MAX_TET_PARTS == kMaxTetParts && DPVR_MAX_TET_RUNS == kMaxTetRuns,
+              "tetrahedral-part limits of the header and the kernels differ");
 
 // Staged-march launch shape (see vr_set_march_config).
 struct MarchCfg {
@@ -44,6 +48,7 @@ struct vr_context_s {
     float ert_eps = 0x1p-20f;
     int32_t path = kPathStaged;
     int32_t live_bricks = 0;
+    int32_t live_tetparts = 0;
     std::string err;
     // vr_render_partials_static: this device's library-owned scratch array
     // (address from hipGetSymbolAddress at context creation) and two pinned
@@ -204,6 +209,7 @@ const char* vr_status_string(vr_status s) {
         case VR_ERR_UNSUPPORTED: return "VR_ERR_UNSUPPORTED";
         case VR_ERR_DEVICE: return "VR_ERR_DEVICE";
         case VR_ERR_STATE: return "VR_ERR_STATE";
+        case VR_ERR_OUT_OF_MEMORY: return "VR_ERR_OUT_OF_MEMORY";
     }
     return "VR_ERR_UNKNOWN";
 }
@@ -272,6 +278,8 @@ vr_status vr_context_release(vr_context ctx) {
     if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_context_release: invalid context");
     if (ctx->live_bricks > 0)
         return fail(ctx, VR_ERR_STATE, "vr_context_release: %d bricks still alive", ctx->live_bricks);
+    if (ctx->live_tetparts > 0)
+        return fail(ctx, VR_ERR_STATE, "vr_context_release: %d tetrahedral parts still alive", ctx->live_tetparts);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_live.erase(ctx);
@@ -304,9 +312,12 @@ vr_status vr_synchronize(vr_context ctx) {
     if (word != 0) {
         const int32_t zero = 0;
         (void)hipMemcpy(err_word(ctx), &zero, sizeof zero, hipMemcpyHostToDevice);
+        const char* what = (word & kErrSpin)   ? "a march kernel gave up a bounded wait"
+                           : (word & kErrRuns) ? "a ray crossed a tetrahedral part in more runs than max_runs"
+                                               : "a sample index exceeded 2^31 - 1";
         return fail(ctx, VR_ERR_DEVICE,
-                    "vr_synchronize: a march kernel gave up a bounded wait (device error bits 0x%x); "
-                    "images rendered since the last synchronisation are unreliable", (unsigned)word);
+                    "vr_synchronize: %s (device error bits 0x%x); images rendered since the last "
+                    "synchronisation are unreliable", what, (unsigned)word);
     }
     return ok(ctx);
 }
@@ -517,16 +528,12 @@ vr_status vr_set_march_config(vr_context ctx, vr_dtype storage, vr_staging stagi
     return ok(ctx);
 }
 
-// Pixel rectangle of the frame of `cam` whose rays can own samples of brick b:
-// the owned box's corners projected to the image plus one pixel of margin,
-// the whole frame when a corner lies at or behind the eye plane.
-static void roi_for(const CameraK& cam, vr_brick b, int32_t roi[4]) {
+// Pixel rectangle of the frame of `cam` whose rays can meet the box [lo, hi]
+// (a brick's owned box, a part's bounding box): the box corners projected to
+// the image plus one pixel of margin, the whole frame when a corner lies at
+// or behind the eye plane.
+static void roi_for_box(const CameraK& cam, const double lo[3], const double hi[3], int32_t roi[4]) {
     const int W = cam.width, H = cam.height;
-    double lo[3], hi[3];
-    for (int c = 0; c < 3; ++c) {
-        lo[c] = b->origin[c];
-        hi[c] = b->origin[c] + (double)b->dims[c] * b->spacing[c];
-    }
     double imin = INFINITY, imax = -INFINITY, jmin = INFINITY, jmax = -INFINITY;
     for (int k = 0; k < 8; ++k) {
         double p[3] = {(k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2]};
@@ -563,6 +570,15 @@ static void roi_for(const CameraK& cam, vr_brick b, int32_t roi[4]) {
     roi[1] = (int32_t)y0;
     roi[2] = (int32_t)(x1 - x0) + 1;
     roi[3] = (int32_t)(y1 - y0) + 1;
+}
+
+static void roi_for(const CameraK& cam, vr_brick b, int32_t roi[4]) {
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = b->origin[c];
+        hi[c] = b->origin[c] + (double)b->dims[c] * b->spacing[c];
+    }
+    roi_for_box(cam, lo, hi, roi);
 }
 
 vr_status vr_partial_roi(vr_context ctx, vr_brick b, int32_t roi[4]) {
@@ -1674,6 +1690,297 @@ vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
     const hipError_t e = launch_rqc_frame(p, ctx->cus, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    return ok(ctx);
+}
+
+// ------------------------------------------------------ tetrahedral parts
+struct vr_tetpart_s {
+    vr_context ctx = nullptr;
+    TetTables tab;
+    // device workspace: [planes][vals][owned][tets][cell_start][cell_tets], each 256-aligned
+    size_t off[6] = {0, 0, 0, 0, 0, 0};
+    size_t need = 0;
+    char* ws = nullptr;
+    bool has_values = false;
+};
+
+namespace {
+
+size_t tetpart_layout(const TetTables& t, size_t off[6]) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t nt = (size_t)t.n_tets;
+    size_t o = 0;
+    off[0] = o; o += up(nt * 16 * sizeof(double));
+    off[1] = o; o += up(nt * 4 * sizeof(float));
+    off[2] = o; o += up(nt * sizeof(uint32_t));
+    off[3] = o; o += up(nt * 4 * sizeof(int32_t));
+    off[4] = o; o += up(t.cell_start.size() * sizeof(int32_t));
+    off[5] = o; o += up(t.cell_tets.size() * sizeof(int32_t));
+    return o;
+}
+
+// Frame workspace of n parts: [TetPartK x n][tile prefix n + 1], then per
+// part [run counts][run keys x max_runs][run colours x max_runs] over its ROI,
+// each 256-aligned; ROIs from the context camera.
+size_t tetframe_layout(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs,
+                       std::vector<TetPartK>* jobs, std::vector<int32_t>* prefix) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    size_t o = up((size_t)n * sizeof(TetPartK)) + up((size_t)(n + 1) * sizeof(int32_t));
+    int32_t tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        const TetTables& t = parts[i]->tab;
+        int32_t roi[4] = {0, 0, 0, 0};
+        if (t.n_tets > 0) roi_for_box(ctx->cam, t.lo, t.hi, roi);
+        const size_t np = (size_t)roi[2] * roi[3];
+        if (jobs) {
+            TetPartK k{};
+            const vr_tetpart q = parts[i];
+            k.planes = reinterpret_cast<const double*>(q->ws + q->off[0]);
+            k.vals = reinterpret_cast<const float*>(q->ws + q->off[1]);
+            k.owned = reinterpret_cast<const uint32_t*>(q->ws + q->off[2]);
+            k.cell_start = reinterpret_cast<const int32_t*>(q->ws + q->off[4]);
+            k.cell_tets = reinterpret_cast<const int32_t*>(q->ws + q->off[5]);
+            for (int c = 0; c < 3; ++c) {
+                k.lo[c] = t.lo[c];
+                k.hi[c] = t.hi[c];
+                k.glo[c] = t.glo[c];
+                k.ginv[c] = t.ginv[c];
+                k.gdim[c] = t.gdim[c];
+            }
+            k.n_tets = t.n_tets;
+            k.roi_x0 = roi[0];
+            k.roi_y0 = roi[1];
+            k.roi_w = roi[2];
+            k.roi_h = roi[3];
+            // run buffers: offsets now, device addresses once the workspace is known
+            k.rcount = reinterpret_cast<int32_t*>(o);
+            k.rkey = reinterpret_cast<int32_t*>(o + up(np * sizeof(int32_t)));
+            k.rcol = reinterpret_cast<float*>(o + up(np * sizeof(int32_t)) + up(np * max_runs * sizeof(int32_t)));
+            jobs->push_back(k);
+            prefix->push_back(tiles);
+        }
+        tiles += tet_tiles(roi[2], roi[3]);
+        o += up(np * sizeof(int32_t)) + up(np * max_runs * sizeof(int32_t)) + up(np * max_runs * 4 * sizeof(float));
+    }
+    if (prefix) prefix->push_back(tiles);
+    return o;
+}
+
+vr_status tetparts_check(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const char* who,
+                         bool need_values) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (n < 1 || n > kMaxTetParts || !parts)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: n = %d outside [1, %d] or NULL parts", who, n, kMaxTetParts);
+    if (max_runs < 1 || max_runs > kMaxTetRuns)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: max_runs = %d outside [1, %d]", who, max_runs, kMaxTetRuns);
+    if (!ctx->has_camera) return fail(ctx, VR_ERR_STATE, "%s: no camera set", who);
+    for (int i = 0; i < n; ++i) {
+        vr_tetpart q = parts[i];
+        if (!live(q) || q->ctx != ctx) return fail(ctx, VR_ERR_INVALID_HANDLE, "%s: invalid part %d", who, i);
+        if (need_values && (!q->ws || !q->has_values))
+            return fail(ctx, VR_ERR_STATE, "%s: part %d has no workspace or no vertex values", who, i);
+        for (int j = 0; j < i; ++j)
+            if (parts[j] == q) return fail(ctx, VR_ERR_INVALID_ARG, "%s: part %d repeats part %d", who, i, j);
+    }
+    return VR_OK;
+}
+
+// Copy `bytes` from host memory to device memory at dst, in stream order,
+// through the next of the context's two pinned host slots (once the copy that
+// last read that slot has run; a slot smaller than `bytes` is reallocated).
+hipError_t stage_copy(vr_context ctx, void* dst, const void* src, size_t bytes) {
+    const int slot = ctx->pinned_next;
+    ctx->pinned_next ^= 1;
+    hipError_t e = hipEventSynchronize(ctx->pinned_done[slot]);
+    if (e != hipSuccess) return e;
+    if (ctx->pinned_bytes[slot] < bytes) {
+        (void)hipHostFree(ctx->pinned[slot]);
+        ctx->pinned[slot] = nullptr;
+        ctx->pinned_bytes[slot] = 0;
+        e = hipHostMalloc(&ctx->pinned[slot], bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        ctx->pinned_bytes[slot] = bytes;
+    }
+    std::memcpy(ctx->pinned[slot], src, bytes);
+    e = hipMemcpyAsync(dst, ctx->pinned[slot], bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->pinned_done[slot], ctx->stream);
+    return e;
+}
+
+}  // namespace
+
+vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_vertices, const int32_t* tets,
+                            int32_t n_tets, vr_tetpart* out) {
+    static const char* who = "vr_tetpart_create";
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
+    if (!out) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out is NULL", who);
+    *out = nullptr;
+    if (n_vertices < 0 || n_tets < 0 || (n_vertices > 0 && !vertices) || (n_tets > 0 && !tets))
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: negative count or NULL array", who);
+    std::unique_ptr<vr_tetpart_s> q(new (std::nothrow) vr_tetpart_s);
+    if (!q) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    try {
+        std::string msg;
+        if (!build_tet_tables(vertices, n_vertices, tets, n_tets, q->tab, msg))
+            return fail(ctx, VR_ERR_INVALID_ARG, "%s: %s", who, msg.c_str());
+        q->need = tetpart_layout(q->tab, q->off);
+        q->ctx = ctx;
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(q.get());
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory for the location tables", who);
+    }
+    ctx->live_tetparts++;
+    *out = q.release();
+    return ok(ctx);
+}
+
+vr_status vr_tetpart_info(vr_tetpart q, double lo[3], double hi[3], int32_t grid[3], int64_t* grid_entries,
+                          size_t* workspace_bytes) {
+    if (!live(q)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_tetpart_info: invalid part");
+    for (int c = 0; c < 3; ++c) {
+        if (lo) lo[c] = q->tab.lo[c];
+        if (hi) hi[c] = q->tab.hi[c];
+        if (grid) grid[c] = q->tab.gdim[c];
+    }
+    if (grid_entries) *grid_entries = (int64_t)q->tab.cell_tets.size();
+    if (workspace_bytes) *workspace_bytes = q->need;
+    return ok(q->ctx);
+}
+
+vr_status vr_tetpart_attach(vr_tetpart q, void* workspace, size_t workspace_bytes) {
+    static const char* who = "vr_tetpart_attach";
+    if (!live(q)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid part", who);
+    vr_context ctx = q->ctx;
+    if (!workspace || workspace_bytes < q->need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes (256-aligned), need %zu", who,
+                    workspace_bytes, q->need);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+    char* ws = reinterpret_cast<char*>(workspace);
+    const TetTables& t = q->tab;
+    // the tables stay in the part's host memory until it is released, which
+    // waits for the context stream
+    struct {
+        size_t off;
+        const void* src;
+        size_t bytes;
+    } copies[5] = {{q->off[0], t.planes.data(), t.planes.size() * sizeof(double)},
+                   {q->off[2], t.owned.data(), t.owned.size() * sizeof(uint32_t)},
+                   {q->off[3], t.tets.data(), t.tets.size() * sizeof(int32_t)},
+                   {q->off[4], t.cell_start.data(), t.cell_start.size() * sizeof(int32_t)},
+                   {q->off[5], t.cell_tets.data(), t.cell_tets.size() * sizeof(int32_t)}};
+    hipError_t e = hipSuccess;
+    for (const auto& c : copies)
+        if (e == hipSuccess && c.bytes > 0)
+            e = hipMemcpyAsync(ws + c.off, c.src, c.bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    q->ws = ws;
+    q->has_values = false;
+    return ok(ctx);
+}
+
+vr_status vr_tetpart_set_values(vr_tetpart q, const float* values) {
+    static const char* who = "vr_tetpart_set_values";
+    if (!live(q)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid part", who);
+    vr_context ctx = q->ctx;
+    if (!q->ws) return fail(ctx, VR_ERR_STATE, "%s: no workspace attached", who);
+    if (!values && q->tab.n_vertices > 0) return fail(ctx, VR_ERR_INVALID_ARG, "%s: values is NULL", who);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+    hipError_t e = launch_tet_values(values, reinterpret_cast<const int32_t*>(q->ws + q->off[3]), q->tab.n_tets,
+                                     reinterpret_cast<float*>(q->ws + q->off[1]), ctx->stream);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    q->has_values = true;
+    return ok(ctx);
+}
+
+vr_status vr_tetpart_release(vr_tetpart q) {
+    if (!live(q)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_tetpart_release: invalid part");
+    vr_context ctx = q->ctx;
+    if (q->ws) {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);   // copies out of the host tables may still run
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.erase(q);
+    }
+    if (live(ctx)) ctx->live_tetparts--;
+    delete q;
+    return VR_OK;
+}
+
+vr_status vr_tetparts_workspace_size(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs,
+                                     size_t* bytes) {
+    static const char* who = "vr_tetparts_workspace_size";
+    vr_status st = tetparts_check(ctx, n, parts, max_runs, who, false);
+    if (st != VR_OK) return st;
+    if (!bytes) return fail(ctx, VR_ERR_INVALID_ARG, "%s: bytes is NULL", who);
+    *bytes = tetframe_layout(ctx, n, parts, max_runs, nullptr, nullptr);
+    return ok(ctx);
+}
+
+vr_status vr_render_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
+                             void* workspace, size_t workspace_bytes, float* out, unsigned long long* samples) {
+    static const char* who = "vr_render_tetparts";
+    vr_status st = tetparts_check(ctx, n, parts, max_runs, who, true);
+    if (st != VR_OK) return st;
+    if (!ctx->has_tf) return fail(ctx, VR_ERR_STATE, "%s: no transfer function set", who);
+    if (!bg || !out) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
+    for (int c = 0; c < 4; ++c)
+        if (!std::isfinite(bg[c])) return fail(ctx, VR_ERR_INVALID_ARG, "%s: background not finite", who);
+    if ((reinterpret_cast<uintptr_t>(out) & 15) != 0 || (reinterpret_cast<uintptr_t>(samples) & 7) != 0)
+        return fail(ctx, VR_ERR_INVALID_ARG, "%s: out must be 16-, samples 8-byte aligned", who);
+    std::vector<TetPartK> jobs;
+    std::vector<int32_t> prefix;
+    size_t need = 0;
+    try {
+        jobs.reserve(n);
+        prefix.reserve(n + 1);
+        need = tetframe_layout(ctx, n, parts, max_runs, &jobs, &prefix);
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes (256-aligned), need %zu", who,
+                    workspace_bytes, need);
+    char* ws = reinterpret_cast<char*>(workspace);
+    for (auto& k : jobs) {
+        k.rcount = reinterpret_cast<int32_t*>(ws + reinterpret_cast<uintptr_t>(k.rcount));
+        k.rkey = reinterpret_cast<int32_t*>(ws + reinterpret_cast<uintptr_t>(k.rkey));
+        k.rcol = reinterpret_cast<float*>(ws + reinterpret_cast<uintptr_t>(k.rcol));
+    }
+    const size_t jb = ((size_t)n * sizeof(TetPartK) + 255) / 256 * 256;
+    std::vector<char> tables;
+    try {
+        tables.assign(jb + (size_t)(n + 1) * sizeof(int32_t), 0);
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+    }
+    std::memcpy(tables.data(), jobs.data(), (size_t)n * sizeof(TetPartK));
+    std::memcpy(tables.data() + jb, prefix.data(), (size_t)(n + 1) * sizeof(int32_t));
+    TetFrameParams f{};
+    f.cam = ctx->cam;
+    f.tf = ctx->tf;
+    f.dt = ctx->dt;
+    f.parts = reinterpret_cast<const TetPartK*>(ws);
+    f.tile_start = reinterpret_cast<const int32_t*>(ws + jb);
+    f.n = n;
+    f.total_tiles = prefix[n];
+    f.max_runs = max_runs;
+    f.width = ctx->cam.width;
+    f.height = ctx->cam.height;
+    for (int c = 0; c < 4; ++c) f.bg[c] = bg[c];
+    f.out = out;
+    f.samples = samples;
+    f.err = err_word(ctx);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
+    hipError_t e = stage_copy(ctx, ws, tables.data(), tables.size());
+    if (e == hipErrorOutOfMemory) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: pinned staging", who);
+    if (e == hipSuccess) e = launch_tet_frame(f, ctx->stream);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
     return ok(ctx);
 }

@@ -84,7 +84,7 @@ struct QueueParams {
 
 // Error bits of the device error word, which sits at byte kErrWordOffset of
 // the library's static scratch array of each device (zero at load).
-enum : int32_t { kErrSpin = 1, kErrRange = 2 };
+enum : int32_t { kErrSpin = 1, kErrRange = 2 };   // kErrRuns = 4 below
 constexpr size_t kErrWordOffset = 128;
 
 // Launch-configuration knobs of the staged march.
@@ -234,5 +234,48 @@ struct RqcParams {
 hipError_t launch_rqc_plan(const RqcParams& p, long long* scan_sums, long long* total, hipStream_t stream);
 long long rqc_scan_blocks(long long n_entries);
 hipError_t launch_rqc_frame(RqcParams p, int cus, hipStream_t stream);
+
+// Tetrahedral parts (tets.hip).  A part's location tables (built on the host,
+// tet_build.h) as the kernels see them, and its share of a frame: the runs
+// (maximal stretches of consecutive lattice samples the part holds) of every
+// ROI pixel's ray.
+constexpr int kMaxTetRuns = 32;
+constexpr int kMaxTetParts = 64;
+struct TetPartK {
+    const double* planes;       // n_tets x 16: per face (nx, ny, nz, c), D = n.p - c >= 0 inside
+    const float* vals;          // n_tets x 4: vertex values in vertex order (16-byte aligned)
+    const uint32_t* owned;      // n_tets: tie-rule bits
+    const int32_t* cell_start;  // grid cells + 1
+    const int32_t* cell_tets;
+    double lo[3], hi[3];        // closed bounding box
+    double glo[3], ginv[3];     // grid origin, cells per world unit
+    int32_t gdim[3];
+    int32_t n_tets;
+    int32_t roi_x0, roi_y0, roi_w, roi_h;
+    int32_t* rcount;            // roi_h x roi_w: runs of the pixel's ray
+    int32_t* rkey;              // max_runs x roi_h x roi_w: first sample index of each run
+    float* rcol;                // max_runs x roi_h x roi_w x 4: premultiplied colour, alpha of each run
+};
+
+struct TetFrameParams {
+    CameraK cam;
+    TFK tf;
+    double dt;
+    const TetPartK* parts;      // device, n
+    const int32_t* tile_start;  // device, n + 1: exclusive prefix of 16 x 16 tiles
+    int32_t n, total_tiles, max_runs;
+    int32_t width, height;
+    float bg[4];
+    float* out;                 // height x width x 4
+    unsigned long long* samples;  // optional: += samples held by a tetrahedron
+    int32_t* err;               // device error word
+};
+
+constexpr int32_t kErrRuns = 4;   // a ray crossed a part in more than max_runs runs
+
+inline int32_t tet_tiles(int32_t w, int32_t h) { return ((w + 15) / 16) * ((h + 15) / 16); }
+hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, int32_t n_tets, float* vals,
+                             hipStream_t stream);
+hipError_t launch_tet_frame(const TetFrameParams& p, hipStream_t stream);
 
 }  // namespace dpvr

@@ -1,0 +1,180 @@
+// Location tables of a tetrahedral part (host, float64, no contraction: the
+// library is compiled with -ffp-contract=off, so every plane is computed
+// with plain rounded multiplies and adds).
+#include "tet_build.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+namespace dpvr {
+namespace {
+
+bool lex_less(const double* a, const double* b) {
+    if (a[0] != b[0]) return a[0] < b[0];
+    if (a[1] != b[1]) return a[1] < b[1];
+    return a[2] < b[2];
+}
+
+// Plane of face i of the tetrahedron with vertex positions v[0..3]; returns
+// false for a degenerate tetrahedron (the opposite vertex on the face plane).
+bool face_plane(const double* const v[4], int i, double plane[4], bool* owned) {
+    const double* f[3];
+    int m = 0;
+    for (int j = 0; j < 4; ++j)
+        if (j != i) f[m++] = v[j];
+    std::sort(f, f + 3, lex_less);
+    const double e1[3] = {f[1][0] - f[0][0], f[1][1] - f[0][1], f[1][2] - f[0][2]};
+    const double e2[3] = {f[2][0] - f[0][0], f[2][1] - f[0][1], f[2][2] - f[0][2]};
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                         e1[0] * e2[1] - e1[1] * e2[0]};
+    const double c = (n[0] * f[0][0] + n[1] * f[0][1]) + n[2] * f[0][2];
+    const double di = ((n[0] * v[i][0] + n[1] * v[i][1]) + n[2] * v[i][2]) - c;
+    if (!(di != 0.0) || !std::isfinite(di)) return false;
+    const double s = di > 0.0 ? 1.0 : -1.0;
+    for (int a = 0; a < 3; ++a) plane[a] = s * n[a];
+    plane[3] = s * c;
+    *owned = s * ((n[0] * kTieG[0] + n[1] * kTieG[1]) + n[2] * kTieG[2]) > 0.0;
+    return true;
+}
+
+// Whether a tetrahedron with these planes can hold a point of the box
+// centred at ctr with half extents h: no face has the whole box on its
+// outer side (D is affine, so its maximum over the box is D(ctr) + sum |n_a| h_a).
+bool may_hold(const double* planes, const double ctr[3], const double h[3]) {
+    for (int i = 0; i < 4; ++i) {
+        const double* p = planes + 4 * i;
+        const double dc = ((p[0] * ctr[0] + p[1] * ctr[1]) + p[2] * ctr[2]) - p[3];
+        const double reach = std::fabs(p[0]) * h[0] + std::fabs(p[1]) * h[1] + std::fabs(p[2]) * h[2];
+        // slack for rounding: relative to the plane's magnitude at the box
+        const double mag = std::fabs(p[0] * ctr[0]) + std::fabs(p[1] * ctr[1]) + std::fabs(p[2] * ctr[2]) +
+                           std::fabs(p[3]) + reach;
+        if (dc + reach < -1e-12 * mag) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+bool build_tet_tables(const double* V, int32_t nv, const int32_t* T, int32_t nt, TetTables& out,
+                      std::string& err) {
+    char buf[256];
+    out = TetTables{};
+    out.n_tets = nt;
+    out.n_vertices = nv;
+    out.planes.resize((size_t)nt * 16);
+    out.owned.resize(nt);
+    out.tets.assign(T, T + (size_t)nt * 4);
+    for (int c = 0; c < 3; ++c) {
+        out.lo[c] = INFINITY;
+        out.hi[c] = -INFINITY;
+    }
+    for (int32_t e = 0; e < nt; ++e) {
+        const double* v[4];
+        for (int j = 0; j < 4; ++j) {
+            const int32_t q = T[4 * (size_t)e + j];
+            if (q < 0 || q >= nv) {
+                snprintf(buf, sizeof buf, "tetrahedron %d: vertex index %d outside [0, %d)", e, q, nv);
+                err = buf;
+                return false;
+            }
+            v[j] = V + 3 * (size_t)q;
+            for (int c = 0; c < 3; ++c) {
+                if (!std::isfinite(v[j][c])) {
+                    snprintf(buf, sizeof buf, "vertex %d has a non-finite coordinate", q);
+                    err = buf;
+                    return false;
+                }
+                out.lo[c] = std::fmin(out.lo[c], v[j][c]);
+                out.hi[c] = std::fmax(out.hi[c], v[j][c]);
+            }
+        }
+        uint32_t bits = 0;
+        for (int i = 0; i < 4; ++i) {
+            bool own = false;
+            if (!face_plane(v, i, &out.planes[16 * (size_t)e + 4 * i], &own)) {
+                snprintf(buf, sizeof buf, "tetrahedron %d has zero volume", e);
+                err = buf;
+                return false;
+            }
+            if (own) bits |= 1u << i;
+        }
+        out.owned[e] = bits;
+    }
+    if (nt == 0) {
+        for (int c = 0; c < 3; ++c) {
+            out.lo[c] = out.hi[c] = out.glo[c] = 0.0;
+            out.ginv[c] = 1.0;
+            out.gdim[c] = 1;
+        }
+        out.cell_start.assign(2, 0);
+        return true;
+    }
+    // Grid: about one cell per tetrahedron, cubic cells, over the box grown
+    // by a small margin (so points that round onto the box faces still fall
+    // in a cell).
+    double ext[3], vol = 1.0, emax = 0.0;
+    for (int c = 0; c < 3; ++c) emax = std::fmax(emax, out.hi[c] - out.lo[c]);
+    const double margin = 1e-7 * emax;
+    for (int c = 0; c < 3; ++c) {
+        ext[c] = (out.hi[c] - out.lo[c]) + 2.0 * margin;
+        out.glo[c] = out.lo[c] - margin;
+        vol *= ext[c];
+    }
+    const double cell = std::cbrt(vol / (double)nt);
+    size_t cells = 1;
+    for (int c = 0; c < 3; ++c) {
+        const double g = std::ceil(ext[c] / cell);
+        out.gdim[c] = (int32_t)std::min(std::max(g, 1.0), 1024.0);
+        out.ginv[c] = (double)out.gdim[c] / ext[c];
+        cells *= (size_t)out.gdim[c];
+    }
+    const double cw[3] = {ext[0] / out.gdim[0], ext[1] / out.gdim[1], ext[2] / out.gdim[2]};
+    // cells tested for tetrahedron e: those its bounding box touches, widened
+    // by a millionth of a cell; each is grown by that much too
+    auto range = [&](int32_t e, int32_t r0[3], int32_t r1[3]) {
+        double a[3] = {INFINITY, INFINITY, INFINITY}, b[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int j = 0; j < 4; ++j) {
+            const double* p = V + 3 * (size_t)T[4 * (size_t)e + j];
+            for (int c = 0; c < 3; ++c) {
+                a[c] = std::fmin(a[c], p[c]);
+                b[c] = std::fmax(b[c], p[c]);
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            r0[c] = (int32_t)std::max(std::floor((a[c] - out.glo[c]) * out.ginv[c] - 1e-6), 0.0);
+            r1[c] = (int32_t)std::min(std::floor((b[c] - out.glo[c]) * out.ginv[c] + 1e-6),
+                                      (double)(out.gdim[c] - 1));
+        }
+    };
+    const double h[3] = {0.5 * cw[0] * (1.0 + 2e-6), 0.5 * cw[1] * (1.0 + 2e-6), 0.5 * cw[2] * (1.0 + 2e-6)};
+    auto for_cells = [&](int32_t e, auto&& fn) {
+        int32_t r0[3], r1[3];
+        range(e, r0, r1);
+        const double* pl = &out.planes[16 * (size_t)e];
+        for (int32_t z = r0[2]; z <= r1[2]; ++z)
+            for (int32_t y = r0[1]; y <= r1[1]; ++y)
+                for (int32_t x = r0[0]; x <= r1[0]; ++x) {
+                    const double ctr[3] = {out.glo[0] + (x + 0.5) * cw[0], out.glo[1] + (y + 0.5) * cw[1],
+                                           out.glo[2] + (z + 0.5) * cw[2]};
+                    if (may_hold(pl, ctr, h))
+                        fn(((size_t)z * out.gdim[1] + y) * out.gdim[0] + x);
+                }
+    };
+    std::vector<int64_t> count(cells + 1, 0);
+    for (int32_t e = 0; e < nt; ++e) for_cells(e, [&](size_t q) { ++count[q + 1]; });
+    for (size_t q = 0; q < cells; ++q) count[q + 1] += count[q];
+    if (count[cells] > INT32_MAX) {
+        snprintf(buf, sizeof buf, "location grid of %lld entries exceeds 2^31 - 1", (long long)count[cells]);
+        err = buf;
+        return false;
+    }
+    out.cell_start.resize(cells + 1);
+    for (size_t q = 0; q <= cells; ++q) out.cell_start[q] = (int32_t)count[q];
+    out.cell_tets.resize((size_t)count[cells]);
+    std::vector<int32_t> fill(out.cell_start.begin(), out.cell_start.end() - 1);
+    for (int32_t e = 0; e < nt; ++e) for_cells(e, [&](size_t q) { out.cell_tets[fill[q]++] = e; });
+    return true;
+}
+
+}  // namespace dpvr

@@ -1,0 +1,47 @@
+// Host-side construction of a tetrahedral part's location tables (no HIP
+// dependency): the four face planes of every tetrahedron with the tie rule
+// folded in, and a uniform grid over the part's bounding box whose cells
+// list the tetrahedra that can hold a point of the cell.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace dpvr {
+
+// Fixed direction of the face tie rule: a point on a face belongs to the
+// tetrahedron that this direction enters across the face (exact binary
+// fractions, so no face normal of a lattice-aligned mesh is orthogonal to it).
+constexpr double kTieG[3] = {1.0, 0x1p-10, 0x1p-20};
+
+struct TetTables {
+    int32_t n_tets = 0, n_vertices = 0;
+    // Face i of tetrahedron e (the face opposite vertex i): planes[16 e + 4 i
+    // + (0, 1, 2, 3)] = (nx, ny, nz, c) such that the signed sub-volume of a
+    // point p against that face is D_i(p) = (nx px + ny py) + nz pz - c,
+    // positive toward vertex i.  The normal is computed from the face's
+    // vertices in lexicographic order, so the two tetrahedra sharing a face
+    // compute the same D up to sign.
+    std::vector<double> planes;
+    // bit i: a point with D_i = 0 counts as inside across face i (the tie
+    // direction enters the tetrahedron there)
+    std::vector<uint32_t> owned;
+    std::vector<int32_t> tets;        // 4 vertex indices per tetrahedron (value gather)
+    double lo[3], hi[3];              // closed bounding box of the vertices the tetrahedra use
+    double glo[3], ginv[3];           // grid origin and cells per world unit
+    int32_t gdim[3];
+    std::vector<int32_t> cell_start;  // gdim product + 1 (exclusive prefix)
+    std::vector<int32_t> cell_tets;   // tetrahedra of each cell, ascending
+};
+
+// Builds the tables of a part given as host arrays (vertices: n_vertices x 3
+// doubles x, y, z; tets: n_tets x 4 indices, either orientation).  Returns
+// false with a message on invalid input (index out of range, non-finite
+// coordinate, zero-volume tetrahedron, too many grid entries) and throws
+// std::bad_alloc when host memory runs out.
+bool build_tet_tables(const double* vertices, int32_t n_vertices, const int32_t* tets, int32_t n_tets,
+                      TetTables& out, std::string& err);
+
+}  // namespace dpvr

@@ -1,0 +1,252 @@
+// Tetrahedral parts: volume ray casting of unstructured meshes split into
+// (possibly non-convex) parts, the parts standing in for the ranks that own
+// a share of a finite-element data set.
+//
+// A frame, for n parts and the context camera:
+//   march     one workgroup per 16 x 16 pixel tile of a part's ROI (the
+//             part's bounding box projected), four wavefronts of 8 x 8 rays.
+//             Every lattice sample t_k = (k + 1/2) dt of the ray inside the
+//             part's bounding box is located in the part: first in the
+//             tetrahedron that held the ray's previous sample, else among the
+//             tetrahedra listed in the sample's cell of the part's uniform
+//             grid.  A tetrahedron holds p when its four signed sub-volumes
+//             are positive, a zero one counting when the tie direction enters
+//             across that face, so a sample has one owner in the whole mesh
+//             and the first tetrahedron found is that owner.  The value is
+//             the barycentric interpolation of the vertex values, classified
+//             and accumulated front to back as in the brick march.  A part
+//             that is not convex can hold several stretches of a ray: each
+//             maximal run of consecutive held samples becomes a run
+//             (first sample index, premultiplied colour, alpha).
+//   resolve   per pixel, the runs of all parts in sample-index order with
+//             "over", then the background.  Runs of different parts never
+//             share a sample, so this equals accumulating the whole ray.
+// Locations use float64 with contraction off (the planes come from the host
+// in float64), so the owner of a sample does not depend on the launch.
+#include "march_common.h"
+
+namespace dpvr {
+namespace {
+
+typedef __attribute__((address_space(1))) const double gdouble;
+typedef __attribute__((address_space(1))) const float gfloat_t;
+typedef __attribute__((address_space(1))) const int32_t gint;
+typedef __attribute__((address_space(1))) const uint32_t guint;
+
+__global__ __launch_bounds__(256) void tet_values(const float* __restrict__ vv, const int4* __restrict__ tets,
+                                                  int32_t n, float4* __restrict__ vals) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const int4 t = tets[e];
+    vals[e] = make_float4(vv[t.x], vv[t.y], vv[t.z], vv[t.w]);
+}
+
+// Candidate sample indices [k0, k1] of the ray against the closed box
+// [lo, hi], widened by two samples on each side (rounding of the slab
+// parameters never drops a sample; ownership is decided per sample).
+__device__ inline bool box_range(const CamRay& r, const double lo[3], const double hi[3], double dt,
+                                 long long& k0, long long& k1) {
+#pragma clang fp contract(off)
+    double tin = 0.0, tout = INFINITY;
+    for (int c = 0; c < 3; ++c) {
+        if (r.d[c] == 0.0) {
+            if (r.o[c] < lo[c] || r.o[c] > hi[c]) return false;
+            continue;
+        }
+        const double ta = (lo[c] - r.o[c]) / r.d[c], tb = (hi[c] - r.o[c]) / r.d[c];
+        tin = fmax(tin, fmin(ta, tb));
+        tout = fmin(tout, fmax(ta, tb));
+    }
+    if (!(tout >= tin - 2.0 * dt)) return false;
+    const double a = fmax(floor(tin / dt - 0.5) - 2.0, 0.0), b = ceil(tout / dt - 0.5) + 2.0;
+    if (!(b >= a)) return false;
+    k0 = (long long)a;
+    k1 = (long long)b;
+    return true;
+}
+
+// Whether tetrahedron e holds p; if so its four sub-volumes in D.
+__device__ inline bool holds(const TetPartK& P, int e, double p0, double p1, double p2, double D[4]) {
+#pragma clang fp contract(off)
+    gdouble* pl = ((gdouble*)P.planes) + 16 * (long long)e;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        D[i] = ((pl[4 * i] * p0 + pl[4 * i + 1] * p1) + pl[4 * i + 2] * p2) - pl[4 * i + 3];
+        if (D[i] < 0.0) return false;
+        if (D[i] == 0.0 && !((((guint*)P.owned)[e] >> i) & 1u)) return false;
+    }
+    return true;
+}
+
+// Adds every lane's n to *counter (one atomic per wavefront); all lanes of
+// the wavefront call it.
+__device__ inline void count_held(unsigned long long* counter, unsigned long long n) {
+    if (!counter) return;
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off);
+    if ((threadIdx.x & 63) == 0 && n) atomicAdd(counter, n);
+}
+
+__global__ __launch_bounds__(256) void tet_march(TetFrameParams f) {
+    __shared__ TFTable tft;
+    load_tf(tft, f.tf, f.dt, threadIdx.x, 256);
+    __syncthreads();
+    const int wg = blockIdx.x;
+    int lo = 0, hi = f.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (f.tile_start[mid] <= wg) lo = mid; else hi = mid - 1;
+    }
+    const int j = __builtin_amdgcn_readfirstlane(lo);
+    const TetPartK& P = f.parts[j];
+    const int tile = wg - f.tile_start[j];
+    const int tiles_x = (P.roi_w + 15) / 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lx = (tile % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int ly = (tile / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const bool live = lx < P.roi_w && ly < P.roi_h;
+    const long long npix = (long long)P.roi_w * P.roi_h;
+    const long long li = (long long)ly * P.roi_w + lx;
+    const float tf_k = 255.0f / (f.tf.vmax - f.tf.vmin);
+    const float tf_o = -f.tf.vmin * tf_k;
+    unsigned long long held = 0;
+    int nrun = 0;
+    long long k0 = 0, k1 = -1;
+    CamRay r{};
+    if (live) {
+        r = camera_ray(f.cam, P.roi_x0 + lx, P.roi_y0 + ly);
+        if (box_range(r, P.lo, P.hi, f.dt, k0, k1) && k1 > 0x7fffffffLL) {
+            if (f.err) atomicOr(f.err, kErrRange);
+            k1 = k0 - 1;
+        }
+    }
+    bool in_run = false, overflow = false;
+    int key = 0, last = -1;
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+    auto close_run = [&]() {
+        if (nrun < f.max_runs) {
+            const long long q = (long long)nrun * npix + li;
+            P.rkey[q] = key;
+            reinterpret_cast<float4*>(P.rcol)[q] = make_float4(C0, C1, C2, 1.0f - T);
+            ++nrun;
+        } else {
+            overflow = true;
+        }
+        in_run = false;
+    };
+    for (long long k = k0; k <= k1; ++k) {
+#pragma clang fp contract(off)
+        const double t = ((double)k + 0.5) * f.dt;
+        const double p0 = r.o[0] + t * r.d[0], p1 = r.o[1] + t * r.d[1], p2 = r.o[2] + t * r.d[2];
+        double D[4];
+        int e = -1;
+        if (last >= 0 && holds(P, last, p0, p1, p2, D)) {
+            e = last;
+        } else {
+            const double u0 = (p0 - P.glo[0]) * P.ginv[0], u1 = (p1 - P.glo[1]) * P.ginv[1],
+                         u2 = (p2 - P.glo[2]) * P.ginv[2];
+            if (u0 >= 0.0 && u1 >= 0.0 && u2 >= 0.0 && u0 < (double)P.gdim[0] && u1 < (double)P.gdim[1] &&
+                u2 < (double)P.gdim[2]) {
+                const long long cell = ((long long)(int)u2 * P.gdim[1] + (int)u1) * P.gdim[0] + (int)u0;
+                const int q0 = ((gint*)P.cell_start)[cell];
+                const int q1 = ((gint*)P.cell_start)[cell + 1];
+                for (int q = q0; q < q1; ++q) {
+                    const int c = ((gint*)P.cell_tets)[q];
+                    if (c != last && holds(P, c, p0, p1, p2, D)) {
+                        e = c;
+                        break;
+                    }
+                }
+            }
+        }
+        if (e < 0) {
+            if (in_run) close_run();
+            continue;
+        }
+        last = e;
+        gfloat_t* vv = ((gfloat_t*)P.vals) + 4 * (long long)e;
+        const double s = ((D[0] + D[1]) + D[2]) + D[3];
+        const double vd = (((D[0] * (double)vv[0] + D[1] * (double)vv[1]) + D[2] * (double)vv[2]) +
+                           D[3] * (double)vv[3]) / s;
+        if (!in_run) {
+            in_run = true;
+            key = (int)k;
+            C0 = C1 = C2 = 0.f;
+            T = 1.f;
+        }
+        const Classified c = classify(tft, (float)vd, tf_k, tf_o);
+        const float Tn = T * trans_exp2(-c.a);
+        const float w = T - Tn;
+        C0 = fmaf(w, c.r, C0);
+        C1 = fmaf(w, c.g, C1);
+        C2 = fmaf(w, c.b, C2);
+        T = Tn;
+        ++held;
+    }
+    if (in_run) close_run();
+    if (overflow && f.err) atomicOr(f.err, kErrRuns);
+    if (live) P.rcount[li] = nrun;
+    count_held(f.samples, held);
+}
+
+// Per pixel: the runs of every part whose ROI holds the pixel, merged by
+// first sample index (each part's runs are already in ray order), each
+// "over" the result so far, then over the background.
+__global__ __launch_bounds__(256) void tet_resolve(TetFrameParams f) {
+    __shared__ uint8_t head[kMaxTetParts * 256];
+    const int tid = threadIdx.x;
+    for (int q = 0; q < f.n; ++q) head[q * 256 + tid] = 0;
+    const long long npx = (long long)f.width * f.height;
+    const long long pix = (long long)blockIdx.x * 256 + tid;
+    if (pix >= npx) return;
+    const int px = (int)(pix % f.width), py = (int)(pix / f.width);
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+    for (;;) {
+        int best = 0x7fffffff, bq = -1;
+        long long bslot = 0;
+        for (int q = 0; q < f.n; ++q) {
+            const TetPartK& P = f.parts[q];
+            const int lx = px - P.roi_x0, ly = py - P.roi_y0;
+            if (lx < 0 || ly < 0 || lx >= P.roi_w || ly >= P.roi_h) continue;
+            const long long li = (long long)ly * P.roi_w + lx;
+            const int h = head[q * 256 + tid];
+            if (h >= P.rcount[li]) continue;
+            const long long slot = (long long)h * P.roi_w * P.roi_h + li;
+            const int k = P.rkey[slot];
+            if (k < best) {
+                best = k;
+                bq = q;
+                bslot = slot;
+            }
+        }
+        if (bq < 0) break;
+        const float4 c = reinterpret_cast<const float4*>(f.parts[bq].rcol)[bslot];
+        const float w = 1.0f - A;
+        C0 = fmaf(w, c.x, C0);
+        C1 = fmaf(w, c.y, C1);
+        C2 = fmaf(w, c.z, C2);
+        A = fmaf(w, c.w, A);
+        ++head[bq * 256 + tid];
+    }
+    const float w = 1.0f - A;
+    reinterpret_cast<float4*>(f.out)[pix] =
+        make_float4(fmaf(w, f.bg[0], C0), fmaf(w, f.bg[1], C1), fmaf(w, f.bg[2], C2), fmaf(w, f.bg[3], A));
+}
+
+}  // namespace
+
+hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, int32_t n_tets, float* vals,
+                             hipStream_t stream) {
+    if (n_tets <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tet_values, dim3((n_tets + 255) / 256), dim3(256), 0, stream, vertex_values,
+                       reinterpret_cast<const int4*>(tets), n_tets, reinterpret_cast<float4*>(vals));
+    return hipGetLastError();
+}
+
+hipError_t launch_tet_frame(const TetFrameParams& p, hipStream_t stream) {
+    if (p.total_tiles > 0) hipLaunchKernelGGL(tet_march, dim3(p.total_tiles), dim3(256), 0, stream, p);
+    const long long npx = (long long)p.width * p.height;
+    hipLaunchKernelGGL(tet_resolve, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, stream, p);
+    return hipGetLastError();
+}
+
+}  // namespace dpvr

@@ -189,6 +189,88 @@ int main() {
         std::free(rws);
     }
 
+    // tetrahedral parts: a cube of 2 x 2 x 2 lattice cells, 6 tetrahedra
+    // each, split into two parts, plus an empty part
+    {
+        std::vector<double> tv;
+        for (int i = 0; i <= 2; ++i)
+            for (int j = 0; j <= 2; ++j)
+                for (int k = 0; k <= 2; ++k) {
+                    tv.push_back(i);
+                    tv.push_back(j);
+                    tv.push_back(k);
+                }
+        auto vid = [](int i, int j, int k) { return (i * 3 + j) * 3 + k; };
+        const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        std::vector<int32_t> tt;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int k = 0; k < 2; ++k)
+                    for (const auto& pm : perms) {
+                        int c[3] = {i, j, k};
+                        tt.push_back(vid(c[0], c[1], c[2]));
+                        for (int a = 0; a < 3; ++a) {
+                            ++c[pm[a]];
+                            tt.push_back(vid(c[0], c[1], c[2]));
+                        }
+                    }
+        const int nt = (int)tt.size() / 4, nv = (int)tv.size() / 3;
+        vr_tetpart tp[3] = {nullptr, nullptr, nullptr};
+        EXPECT(vr_tetpart_create(ctx, tv.data(), nv, tt.data(), 20, &tp[0]) == VR_OK);
+        EXPECT(vr_tetpart_create(ctx, tv.data(), nv, tt.data() + 80, nt - 20, &tp[1]) == VR_OK);
+        EXPECT(vr_tetpart_create(ctx, tv.data(), 0, tt.data(), 0, &tp[2]) == VR_OK);
+        vr_tetpart bad = nullptr;
+        std::vector<int32_t> tbad(tt.begin(), tt.begin() + 4);
+        tbad[3] = nv;
+        EXPECT(vr_tetpart_create(ctx, tv.data(), nv, tbad.data(), 1, &bad) == VR_ERR_INVALID_ARG && !bad);
+        tbad[3] = tbad[0];
+        EXPECT(vr_tetpart_create(ctx, tv.data(), nv, tbad.data(), 1, &bad) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_tetpart_create(ctx, nullptr, nv, tt.data(), 1, &bad) == VR_ERR_INVALID_ARG);
+        std::vector<double> tnan(tv);
+        tnan[5] = NAN;
+        EXPECT(vr_tetpart_create(ctx, tnan.data(), nv, tt.data(), nt, &bad) == VR_ERR_INVALID_ARG);
+        double lo[3], hi[3];
+        int32_t grid[3];
+        int64_t entries = 0;
+        size_t need[3] = {0, 0, 0};
+        for (int q = 0; q < 3; ++q) EXPECT(vr_tetpart_info(tp[q], lo, hi, grid, &entries, &need[q]) == VR_OK);
+        EXPECT(vr_tetpart_info(tp[1], lo, hi, grid, &entries, nullptr) == VR_OK && entries >= nt - 20);
+        EXPECT(hi[0] == 2.0 && lo[0] == 0.0 && grid[0] >= 1);
+        float* vals = static_cast<float*>(aligned_buf(nv * 4));
+        for (int v = 0; v < nv; ++v) vals[v] = 0.1f * v;
+        void* tws[3];
+        for (int q = 0; q < 3; ++q) {
+            tws[q] = aligned_buf(need[q]);
+            EXPECT(vr_tetpart_set_values(tp[q], vals) == VR_ERR_STATE);   // no workspace yet
+            EXPECT(vr_tetpart_attach(tp[q], tws[q], need[q] - 1) == VR_ERR_WORKSPACE);
+            EXPECT(vr_tetpart_attach(tp[q], tws[q], need[q]) == VR_OK);
+        }
+        size_t fb = 0;
+        EXPECT(vr_tetparts_workspace_size(ctx, 3, tp, 0, &fb) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_tetparts_workspace_size(ctx, 3, tp, DPVR_MAX_TET_RUNS + 1, &fb) == VR_ERR_INVALID_ARG);
+        vr_tetpart twice[2] = {tp[0], tp[0]};
+        EXPECT(vr_tetparts_workspace_size(ctx, 2, twice, 4, &fb) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_tetparts_workspace_size(ctx, 3, tp, 4, &fb) == VR_OK && fb > 0);
+        void* fw = aligned_buf(fb);
+        float* frame = static_cast<float*>(aligned_buf(64 * 48 * 16));
+        EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame, nullptr) == VR_ERR_STATE);   // no values
+        for (int q = 0; q < 3; ++q) EXPECT(vr_tetpart_set_values(tp[q], vals) == VR_OK);
+        EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg, fw, fb - 1, frame, nullptr) == VR_ERR_WORKSPACE);
+        EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg_bad, fw, fb, frame, nullptr) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame + 1, nullptr) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame, nullptr) == VR_OK);
+        EXPECT(vr_render_tetparts(ctx, 2, tp + 1, 1, bg, fw, fb, frame, nullptr) == VR_OK);
+        EXPECT(frame[0] == bg[0] && frame[3] == bg[3]);
+        EXPECT(vr_context_release(ctx) == VR_ERR_STATE);     // parts still live
+        for (int q = 0; q < 3; ++q) EXPECT(vr_tetpart_release(tp[q]) == VR_OK);
+        EXPECT(vr_tetpart_release(tp[0]) == VR_ERR_INVALID_HANDLE);
+        EXPECT(vr_render_tetparts(ctx, 1, tp, 4, bg, fw, fb, frame, nullptr) == VR_ERR_INVALID_HANDLE);
+        for (int q = 0; q < 3; ++q) std::free(tws[q]);
+        std::free(fw);
+        std::free(frame);
+        std::free(vals);
+    }
+
     // time-step streaming: three steps of the three bricks, two resident
     {
         vr_brick_desc desc[3];

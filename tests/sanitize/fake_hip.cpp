@@ -92,4 +92,33 @@ hipError_t launch_march_backward_many(const BackwardJob*, const int32_t*, int32_
     return hipSuccess;
 }
 hipError_t launch_rqc_frame(RqcParams, int, hipStream_t) { return hipSuccess; }
+// The tetrahedral-part launchers touch every byte their kernels may touch,
+// so that a layout the host code sized wrongly shows up under ASan.
+hipError_t launch_tet_values(const float* vv, const int32_t* tets, int32_t n, float* vals, hipStream_t) {
+    for (int32_t e = 0; e < n; ++e)
+        for (int j = 0; j < 4; ++j) vals[4 * e + j] = vv[tets[4 * e + j]];
+    return hipSuccess;
+}
+hipError_t launch_tet_frame(const TetFrameParams& f, hipStream_t) {
+    int32_t tiles = 0;
+    for (int32_t q = 0; q < f.n; ++q) {
+        const TetPartK& P = f.parts[q];
+        if (f.tile_start[q] != tiles) return hipErrorInvalidValue;
+        tiles += tet_tiles(P.roi_w, P.roi_h);
+        const long long np = (long long)P.roi_w * P.roi_h;
+        for (long long i = 0; i < np; ++i) P.rcount[i] = 0;
+        for (long long i = 0; i < np * f.max_runs; ++i) P.rkey[i] = 0;
+        for (long long i = 0; i < np * f.max_runs * 4; ++i) P.rcol[i] = 0.0f;
+        if (P.n_tets > 0) {
+            volatile double x = P.planes[16LL * P.n_tets - 1] + P.vals[4LL * P.n_tets - 1] + P.owned[P.n_tets - 1];
+            const long long cells = (long long)P.gdim[0] * P.gdim[1] * P.gdim[2];
+            const int32_t entries = P.cell_start[cells];
+            if (entries > 0) x = x + P.cell_tets[entries - 1];
+            (void)x;
+        }
+    }
+    if (f.tile_start[f.n] != tiles || f.total_tiles != tiles) return hipErrorInvalidValue;
+    for (long long i = 0; i < 4LL * f.width * f.height; ++i) f.out[i] = f.bg[i & 3];
+    return hipSuccess;
+}
 }  // namespace dpvr

@@ -1,0 +1,183 @@
+"""GPU parity of tetrahedral parts (vr_render_tetparts) against the oracle's
+oc_render_tets: the image within 1e-5 per channel and the count of samples
+held by a tetrahedron exactly, on conforming meshes split into uneven,
+non-convex parts; samples placed on mesh vertices, edges and faces; the eye
+inside the mesh; a part with no tetrahedra; the run-overflow error; and new
+vertex values on the same tables."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _dp():
+    import paper_2501_01628_amd as dp
+    return dp
+
+
+def _scene(cells, jitter, n_parts, seed, linear=False):
+    rng = np.random.default_rng(seed)
+    v, t = synth.tet_mesh(cells, jitter=jitter, rng=rng)
+    if linear:
+        v = np.round(v * 1024.0) / 1024.0
+        vals = (0.25 + 0.125 * v[:, 0] + 0.0625 * v[:, 1] - 0.03125 * v[:, 2]).astype(np.float32)
+    else:
+        vals = synth.tet_field(v, rng, cells)
+    if n_parts == 1:
+        parts = [(v, t, np.arange(len(v)))]
+    else:
+        parts = synth.tet_partitions(v, t, n_parts, rng)
+    return vals, parts
+
+
+def _tf():
+    return synth.hidden_tf(11), (0.02, 0.95), 1.3
+
+
+def _gpu(parts, vals, cam, dt, bg, max_runs=8):
+    dp = _dp()
+    tf, vr, s = _tf()
+    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, vr, s, dt, max_runs=max_runs)
+    try:
+        for k, (_, _, used) in enumerate(parts):
+            r.set_values(k, vals[used])
+        r.set_camera(cam)
+        r.samples.zero_()
+        img = r.render(bg, count=True)
+        r.synchronize()
+        return img.cpu().numpy().astype(np.float64), int(r.samples.item())
+    finally:
+        r.close()
+
+
+def _ref(parts, vals, cam, dt, bg):
+    tf, vr, s = _tf()
+    img, cnt = oracle.render_tets(cam, [(pv, vals[used], pt) for pv, pt, used in parts], tf, vr, s, dt, bg)
+    assert cnt[1] == 0
+    return img, int(cnt[0])
+
+
+def _compare(parts, vals, cam, dt, bg=(0.0, 0.0, 0.0, 0.0), max_runs=8):
+    print(f"tets: {sum(len(p[1]) for p in parts)} in {len(parts)} parts, {cam['width']}x{cam['height']}, dt {dt}",
+          flush=True)
+    img, held = _gpu(parts, vals, cam, dt, bg, max_runs)
+    ref, rheld = _ref(parts, vals, cam, dt, bg)
+    assert held == rheld
+    err = np.max(np.abs(img - ref))
+    assert err <= TOL, err
+    return img
+
+
+@pytest.mark.parametrize("n_parts,seed", [(1, 1), (5, 2), (9, 3)])
+def test_jittered_mesh_in_parts(n_parts, seed):
+    cells = (6, 5, 7)
+    vals, parts = _scene(cells, 0.25, n_parts, seed)
+    cam = synth.orbit_camera((0, 0, 0), cells, 61, 47, az_deg=30.0 + 20 * seed, el_deg=20.0, radius_factor=1.5)
+    _compare(parts, vals, cam, 0.37, (0.05, 0.1, 0.15, 0.3))
+
+
+def test_samples_on_vertices_edges_and_faces():
+    # orthographic view along +z with pixel centres on half-integer lines and
+    # samples on the planes z = m / 2 of an unjittered mesh
+    cells = (4, 3, 5)
+    vals, parts = _scene(cells, 0.0, 1, 4, linear=True)
+    cam = dict(kind="ortho", eye=(0.25, 0.25, -1.25), dir=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0),
+               width=16, height=16, view_height=8.0)
+    _compare(parts, vals, cam, 0.5)
+    vals, parts = _scene(cells, 0.0, 3, 5, linear=True)
+    _compare(parts, vals, cam, 0.5)
+
+
+def test_eye_inside_the_mesh():
+    cells = (6, 6, 6)
+    vals, parts = _scene(cells, 0.2, 4, 6)
+    cam = synth.inside_camera((0, 0, 0), cells, 40, 33, az_deg=-40.0, el_deg=15.0, fovy_deg=75.0)
+    _compare(parts, vals, cam, 0.23)
+
+
+def test_empty_part_and_single_tetrahedron_parts():
+    cells = (3, 3, 3)
+    vals, parts = _scene(cells, 0.2, 2, 7)
+    v0, t0, u0 = parts[0]
+    one = [(v0, t0[:1], u0), (v0, t0[1:], u0)]
+    empty = (np.zeros((0, 3)), np.zeros((0, 4), dtype=np.int32), np.zeros(0, dtype=np.int64))
+    cam = synth.orbit_camera((0, 0, 0), cells, 33, 29, az_deg=70.0, el_deg=-25.0, radius_factor=1.4)
+    _compare(one + [parts[1], empty], vals, cam, 0.31)
+
+
+def test_runs_overflow_is_reported_and_recovers():
+    dp = _dp()
+    cells = (8, 6, 6)
+    vals, parts = _scene(cells, 0.25, 6, 8)
+    cam = synth.orbit_camera((0, 0, 0), cells, 48, 40, az_deg=10.0, el_deg=5.0, radius_factor=1.3)
+    ref, _ = _ref(parts, vals, cam, 0.2, (0.0, 0.0, 0.0, 0.0))
+    tf, vr, s = _tf()
+    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, vr, s, 0.2, max_runs=1)
+    try:
+        for k, (_, _, used) in enumerate(parts):
+            r.set_values(k, vals[used])
+        r.set_camera(cam)
+        r.render()
+        with pytest.raises(dp.VRError, match="max_runs"):
+            r.synchronize()
+        r.max_runs = 16
+        r.set_camera(cam)
+        img = r.render()
+        r.synchronize()
+        assert np.max(np.abs(img.cpu().numpy() - ref)) <= TOL
+    finally:
+        r.close()
+
+
+def test_new_values_on_the_same_tables():
+    dp = _dp()
+    cells = (5, 4, 4)
+    vals, parts = _scene(cells, 0.2, 3, 9)
+    vals2 = np.ascontiguousarray(vals[::-1])
+    cam = synth.orbit_camera((0, 0, 0), cells, 37, 31, az_deg=-60.0, el_deg=30.0, radius_factor=1.6)
+    tf, vr, s = _tf()
+    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, vr, s, 0.29)
+    try:
+        r.set_camera(cam)
+        for vv in (vals, vals2):
+            for k, (_, _, used) in enumerate(parts):
+                r.set_values(k, vv[used])
+            img = r.render().cpu().numpy()
+            r.synchronize()
+            ref, _ = _ref(parts, vv, cam, 0.29, (0.0, 0.0, 0.0, 0.0))
+            assert np.max(np.abs(img - ref)) <= TOL
+    finally:
+        r.close()
+
+
+def test_rejected_calls():
+    dp = _dp()
+    ctx = dp.vr_context_create(0)
+    try:
+        v = np.zeros((4, 3))
+        v[1, 0] = v[2, 1] = 1.0            # v[3] at the origin too: zero volume
+        with pytest.raises(dp.VRError, match="zero volume"):
+            dp.vr_tetpart_create(ctx, v, np.array([[0, 1, 2, 3]], dtype=np.int32))
+        v[3, 2] = 1.0
+        with pytest.raises(dp.VRError, match="outside"):
+            dp.vr_tetpart_create(ctx, v, np.array([[0, 1, 2, 4]], dtype=np.int32))
+        h = dp.vr_tetpart_create(ctx, v, np.array([[0, 1, 2, 3]], dtype=np.int32))
+        with pytest.raises(dp.VRError, match="VR_ERR_STATE"):
+            dp.vr_tetpart_set_values(h, 0, ctx)          # no workspace yet
+        with pytest.raises(dp.VRError, match="VR_ERR_STATE"):
+            dp.vr_tetparts_workspace_size(ctx, [h], 4)   # no camera
+        dp.set_camera(ctx, synth.orbit_camera((0, 0, 0), (1, 1, 1), 8, 8))
+        with pytest.raises(dp.VRError, match="max_runs"):
+            dp.vr_tetparts_workspace_size(ctx, [h], 0)
+        with pytest.raises(dp.VRError, match="repeats"):
+            dp.vr_tetparts_workspace_size(ctx, [h, h], 4)
+        with pytest.raises(dp.VRError, match="VR_ERR_STATE"):
+            dp.vr_context_release(ctx)                   # a part is alive
+        dp.vr_tetpart_release(h, ctx)
+    finally:
+        dp.vr_context_release(ctx)

@@ -6,6 +6,8 @@
   stand-in for the HIP runtime and the kernel launchers
   (``tests/sanitize/fake_hip.cpp``), driven through valid and rejected calls
   (``tests/sanitize/api_driver.cpp``).
+* The tetrahedral location tables (``tet_build.cpp``) checked point by point
+  against brute force (``tests/sanitize/tet_driver.cpp``).
 * The oracle's C code built with gcc sanitizers and run on small inputs and
   edge cases (``tests/sanitize/oracle_driver.c``).
 
@@ -40,9 +42,23 @@ def test_api_host_code_under_sanitizers(tmp_path):
     inc = ["-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(ROOT, "paper_2501_01628_amd", "csrc")]
     exe = str(tmp_path / "api_driver")
-    rc, log = _run(["g++", *inc, *FLAGS, os.path.join(SAN, "api_driver.cpp"),
+    rc, log = _run(["g++", *inc, *FLAGS, "-ffp-contract=off", os.path.join(SAN, "api_driver.cpp"),
                     os.path.join(ROOT, "paper_2501_01628_amd", "csrc", "api.cpp"),
+                    os.path.join(ROOT, "paper_2501_01628_amd", "csrc", "tet_build.cpp"),
                     os.path.join(SAN, "fake_hip.cpp"), "-o", exe], str(tmp_path))
+    assert rc == 0, log[-4000:]
+    rc, log = _run([exe], str(tmp_path))
+    _check(rc, log)
+    assert "OK: 0 failed expectations" in log
+
+
+def test_tet_location_tables_under_sanitizers(tmp_path):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ is missing")
+    exe = str(tmp_path / "tet_driver")
+    rc, log = _run(["g++", "-std=c++17", *FLAGS, "-ffp-contract=off", "-I",
+                    os.path.join(ROOT, "paper_2501_01628_amd", "csrc"), os.path.join(SAN, "tet_driver.cpp"),
+                    os.path.join(ROOT, "paper_2501_01628_amd", "csrc", "tet_build.cpp"), "-o", exe], str(tmp_path))
     assert rc == 0, log[-4000:]
     rc, log = _run([exe], str(tmp_path))
     _check(rc, log)
