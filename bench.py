@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint", "rqc", "stream"],
+    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint", "rqc", "stream", "tets"],
                     default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default=None,
                     help="brick storage (default f32; c5 is a float16 workload: f16)")
@@ -899,6 +899,142 @@ def bench_stream(args):
     return 0
 
 
+def tet_scene(cells=(128, 96, 96), n_parts=16, width=1920, height=1080):
+    """Tetrahedral workload: a 128x96x96-cube box cut into 7.1 M tetrahedra
+    (6 per cube, interior vertices jittered by up to 0.25 of a cube, 1.2 M
+    vertices), 8 Gaussian blobs evaluated at the vertices, 16 uneven
+    non-convex parts (weighted nearest seed + noise per tetrahedron),
+    1920x1080 orbit view, step 0.5 cube, opacity scale 0.05."""
+    import synth
+    rng = np.random.default_rng(12)
+    v, t = synth.tet_mesh(cells, jitter=0.25, rng=rng)
+    vals = synth.tet_field(v, rng, cells, n_blobs=8)
+    parts = synth.tet_partitions(v, t, n_parts, rng)
+    cam = synth.orbit_camera((0, 0, 0), cells, width, height)
+    return vals, parts, cam, len(t), len(v)
+
+
+# fp64 operations per held sample in the tetrahedral march when the first
+# tetrahedron tested holds it: the sample position (t = (k + 1/2) dt, p = o +
+# t d: 8), four face sub-volumes (3 multiplies + 3 adds each: 24) and the
+# barycentric value (3 adds for the sum, 4 multiplies + 3 adds, 1 divide: 11)
+TET_FP64_OPS_PER_SAMPLE = 43
+FP64_VECTOR_PEAK = 78.6e12
+
+
+def bench_tets(args):
+    """Unstructured data: a tetrahedral mesh in 16 non-convex parts; one step
+    = the march of every part into runs + the per-pixel resolve."""
+    import torch
+
+    import paper_2501_01628_amd as dp
+    import synth
+    t0 = time.perf_counter()
+    vals, parts, cam, n_tets, n_verts = tet_scene()
+    log(f"generated {n_tets} tetrahedra in {len(parts)} parts in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    tf = synth.default_tf()
+    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, (0.0, 1.0), 0.05, 0.5, max_runs=32)
+    host_build_s = time.perf_counter() - t0
+    for k, (_, _, used) in enumerate(parts):
+        r.set_values(k, vals[used])
+    r.set_camera(cam)
+    r.synchronize()
+    r.values = [None] * len(parts)
+    torch.cuda.empty_cache()
+    grid_entries = sum(i["grid_entries"] for i in r.info)
+    table_bytes = sum(i["workspace_bytes"] for i in r.info)
+    log(f"tables built in {host_build_s:.1f} s: {table_bytes / 1e9:.2f} GB on the device, "
+        f"{grid_entries} grid entries ({grid_entries / n_tets:.1f} per tetrahedron)")
+    bg = (0.0, 0.0, 0.0, 0.0)
+    for _ in range(args.warmup):
+        r.render(bg)
+    r.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(r.stream)
+        r.march()
+        ev[s][1].record(r.stream)
+        r.resolve(bg)
+        ev[s][2].record(r.stream)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    r.synchronize()
+    ms_per_step = t_total / args.steps * 1e3
+    march_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    resolve_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+    r.samples.zero_()
+    r.render(bg, count=True)
+    r.synchronize()
+    held = int(r.samples.item())
+    frame = r.frame.cpu().numpy().astype(np.float64)
+    r.close()
+    log(f"timed {args.steps} frames: {ms_per_step:.3f} ms/frame, march {march_ms:.3f} ms, resolve "
+        f"{resolve_ms:.3f} ms, {held} held samples/frame")
+    W, H = cam["width"], cam["height"]
+    achieved = held * TET_FP64_OPS_PER_SAMPLE / (march_ms * 1e-3)
+    out = {"metric": "Msamples/s (tetrahedral parts: samples held by a tetrahedron per frame x frames/s)",
+           "value": held / (ms_per_step * 1e-3) / 1e6, "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "fps": 1e3 / ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64 location, f32 shading", "data": "synthetic",
+           "config": {"workload": f"tets: {n_tets} tetrahedra ({n_verts} vertices, jittered 128x96x96 cubes), "
+                                  f"8 blobs, {len(parts)} non-convex parts, {W}x{H} perspective, step 0.5, "
+                                  f"opacity 0.05, max 32 runs per ray and part"},
+           "samples_per_frame": held, "ms_march": march_ms, "ms_resolve": resolve_ms,
+           "host_table_build_s": host_build_s, "device_table_bytes": table_bytes,
+           "grid_entries_per_tet": grid_entries / n_tets,
+           "roofline": {"kernel": "tet_march", "bound": "alu", "achieved": achieved / 1e12,
+                        "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
+                        "traffic": None,
+                        "model": f"{TET_FP64_OPS_PER_SAMPLE} fp64 operations per held sample (position, four "
+                                 f"face sub-volumes, barycentric value) over the march launch; peak = fp64 "
+                                 f"vector 78.6 TFLOP/s"}}
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (oracle, brute-force location, on a pixel sample) ...")
+        rng = np.random.default_rng(5)
+        tparts = [(pv, vals[used], pt) for pv, pt, used in parts]
+        # The oracle tests every sample against every tetrahedron (about 0.3 s
+        # per sample here), so the sample is pixels whose rays cross the mesh
+        # box in a short chord (8 to 24 samples; the mesh fills its box, so
+        # every one of them is held): its rate per sample is the oracle's.
+        hit = np.argwhere(frame[..., 3] > 0.0)
+        cand = hit[rng.choice(len(hit), min(20000, len(hit)), replace=False)]
+        hi = np.array([128.0, 96.0, 96.0])
+        short = []
+        for j, i in cand:
+            o, d = oracle.ray(cam, int(i), int(j))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                ta, tb = (0.0 - o) / d, (hi - o) / d
+            chord = np.min(np.maximum(ta, tb)) - max(np.max(np.minimum(ta, tb)), 0.0)
+            if 8 * 0.5 <= chord <= 24 * 0.5:
+                short.append((i, j))
+        short = np.array(short, dtype=np.int32)
+
+        def run(npix):
+            pix = short[rng.choice(len(short), min(npix, len(short)), replace=False)]
+            log(f"oracle on {len(pix)} pixels with {oracle.threads()} threads ...")
+            t0 = time.perf_counter()
+            img, cnt = oracle.render_tets(cam, tparts, tf, (0.0, 1.0), 0.05, 0.5, bg, pixels=pix)
+            return time.perf_counter() - t0, int(cnt[0]), (pix, img)
+        rr = _oracle_rates(run, args.cpu_seconds, 1e-6, first=oracle.threads(), cap=len(short))
+        pix, img = rr["payload"]
+        out["cpu_baseline"] = {
+            "value": rr["value"], "unit": "Msamples/s", "cores": rr["cores"], "kind": "oracle",
+            "sample": f"{len(pix)} random pixels whose rays cross the mesh box in 8 to 24 samples, "
+                      f"{rr['work']} held samples in {rr['seconds']:.1f} s (every sample tested against all "
+                      f"{n_tets} tetrahedra)",
+            "one_core_value": rr["one_core_value"],
+            "one_core_sample": f"{rr['one_core_n']} random pixels, one thread, {rr['one_core_seconds']:.1f} s",
+            **host_info()}
+        out["max_abs_err_vs_oracle"] = {"value": float(np.max(np.abs(frame[pix[:, 1], pix[:, 0]] - img))),
+                                        "pixels": "the cpu_baseline sample", "bar": 1e-5}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -917,6 +1053,8 @@ def main():
         return bench_rqc(args)
     if args.workload == "stream":
         return bench_stream(args)
+    if args.workload == "tets":
+        return bench_tets(args)
     import torch
 
     import paper_2501_01628_amd as dp

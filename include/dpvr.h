@@ -627,11 +627,11 @@ typedef struct vr_tetpart_s* vr_tetpart;
 
 /* Create a part from host arrays: vertices (n_vertices x 3 doubles, x, y, z),
  * tets (n_tets x 4 vertex indices, either orientation).  Builds the part's
- * location tables in host memory (face planes, tie bits, the grid); the
- * arrays are not kept.  n_tets may be 0 (a part that owns nothing).
+ * location tables in host memory (face planes, tie bits, face neighbours,
+ * the grid); the arrays are not kept.  n_tets may be 0 (a part that owns nothing).
  * Errors: VR_ERR_INVALID_HANDLE, VR_ERR_INVALID_ARG (index out of range,
- * non-finite coordinate, zero-volume tetrahedron, more than 2^31 - 1 grid
- * entries), VR_ERR_OUT_OF_MEMORY. */
+ * non-finite coordinate, zero-volume tetrahedron, a face shared by more than
+ * two tetrahedra, more than 2^31 - 1 grid entries), VR_ERR_OUT_OF_MEMORY. */
 vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_vertices, const int32_t* tets,
                             int32_t n_tets, vr_tetpart* out);
 
@@ -675,6 +675,18 @@ vr_status vr_tetparts_workspace_size(vr_context ctx, int32_t n, const vr_tetpart
  * VR_ERR_WORKSPACE, VR_ERR_OUT_OF_MEMORY, VR_ERR_DEVICE. */
 vr_status vr_render_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
                              void* workspace, size_t workspace_bytes, float* out, unsigned long long* samples);
+
+/* The two stages of vr_render_tetparts on their own (same arguments): the
+ * march leaves every part's runs in the workspace -- the per-rank step of a
+ * data-parallel renderer, whose runs would travel to the compositing rank --
+ * and the resolve merges them into out.  vr_resolve_tetparts requires that
+ * the last vr_march_tetparts (or vr_render_tetparts) of the context used
+ * the same workspace, parts, max_runs and camera (VR_ERR_STATE otherwise);
+ * it needs no transfer function or vertex values. */
+vr_status vr_march_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, void* workspace,
+                            size_t workspace_bytes, unsigned long long* samples);
+vr_status vr_resolve_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
+                              void* workspace, size_t workspace_bytes, float* out);
 
 #ifdef __cplusplus
 }

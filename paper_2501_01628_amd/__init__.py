@@ -164,6 +164,10 @@ _SIGS = {
                                     C.POINTER(C.c_size_t)], _st),
     "vr_render_tetparts": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, _f4, C.c_void_p, C.c_size_t,
                             C.c_void_p, C.c_void_p], _st),
+    "vr_march_tetparts": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t,
+                           C.c_void_p], _st),
+    "vr_resolve_tetparts": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, _f4, C.c_void_p, C.c_size_t,
+                             C.c_void_p], _st),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -440,6 +444,18 @@ def vr_render_tetparts(ctx, parts, max_runs, bg, workspace, workspace_bytes, out
                                    int(workspace_bytes), _ptr(out), _ptr(samples)), ctx)
 
 
+def vr_march_tetparts(ctx, parts, max_runs, workspace, workspace_bytes, samples=None):
+    arr = (C.c_void_p * len(parts))(*[p.value if isinstance(p, C.c_void_p) else p for p in parts])
+    _check(_lib.vr_march_tetparts(ctx, len(parts), arr, int(max_runs), _ptr(workspace), int(workspace_bytes),
+                                  _ptr(samples)), ctx)
+
+
+def vr_resolve_tetparts(ctx, parts, max_runs, bg, workspace, workspace_bytes, out):
+    arr = (C.c_void_p * len(parts))(*[p.value if isinstance(p, C.c_void_p) else p for p in parts])
+    _check(_lib.vr_resolve_tetparts(ctx, len(parts), arr, int(max_runs), _f4(*bg), _ptr(workspace),
+                                    int(workspace_bytes), _ptr(out)), ctx)
+
+
 def vr_set_march_path(ctx, path):
     _check(_lib.vr_set_march_path(ctx, int(path)), ctx)
 
@@ -615,10 +631,22 @@ class TetRenderer:
             self.frame = self.torch.empty(self.height, self.width, 4, dtype=self.torch.float32,
                                           device=self.device)
 
+    def _base(self):
+        return self._fws.data_ptr() + ((-self._fws.data_ptr()) % 256)
+
     def render(self, bg=(0.0, 0.0, 0.0, 0.0), count=False):
-        base = self._fws.data_ptr() + ((-self._fws.data_ptr()) % 256)
-        vr_render_tetparts(self.ctx, self.parts, self.max_runs, bg, base, self._fws_bytes, self.frame,
+        vr_render_tetparts(self.ctx, self.parts, self.max_runs, bg, self._base(), self._fws_bytes, self.frame,
                            self.samples if count else None)
+        return self.frame
+
+    def march(self, count=False):
+        """The march stage alone (runs of every part into the workspace)."""
+        vr_march_tetparts(self.ctx, self.parts, self.max_runs, self._base(), self._fws_bytes,
+                          self.samples if count else None)
+
+    def resolve(self, bg=(0.0, 0.0, 0.0, 0.0)):
+        """The resolve stage alone (after :meth:`march`)."""
+        vr_resolve_tetparts(self.ctx, self.parts, self.max_runs, bg, self._base(), self._fws_bytes, self.frame)
         return self.frame
 
     def synchronize(self):

@@ -73,6 +73,14 @@ struct vr_context_s {
         double dt = 0.0;
         long long entries = 0, total = -1;
     } rqc;
+    // the last vr_march_tetparts / vr_render_tetparts: workspace, parts,
+    // max_runs and camera (vr_resolve_tetparts must match them)
+    struct {
+        const void* ws = nullptr;
+        std::vector<const void*> parts;
+        int32_t max_runs = 0;
+        CameraK cam{};
+    } tetmarch;
 };
 
 struct vr_brick_s {
@@ -1698,8 +1706,8 @@ vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const
 struct vr_tetpart_s {
     vr_context ctx = nullptr;
     TetTables tab;
-    // device workspace: [planes][vals][owned][tets][cell_start][cell_tets], each 256-aligned
-    size_t off[6] = {0, 0, 0, 0, 0, 0};
+    // device workspace: [planes][vals][owned][tets][cell_start][cell_tets][nbr], each 256-aligned
+    size_t off[7] = {0, 0, 0, 0, 0, 0, 0};
     size_t need = 0;
     char* ws = nullptr;
     bool has_values = false;
@@ -1707,7 +1715,7 @@ struct vr_tetpart_s {
 
 namespace {
 
-size_t tetpart_layout(const TetTables& t, size_t off[6]) {
+size_t tetpart_layout(const TetTables& t, size_t off[7]) {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t nt = (size_t)t.n_tets;
     size_t o = 0;
@@ -1717,6 +1725,7 @@ size_t tetpart_layout(const TetTables& t, size_t off[6]) {
     off[3] = o; o += up(nt * 4 * sizeof(int32_t));
     off[4] = o; o += up(t.cell_start.size() * sizeof(int32_t));
     off[5] = o; o += up(t.cell_tets.size() * sizeof(int32_t));
+    off[6] = o; o += up(t.nbr.size() * sizeof(int32_t));
     return o;
 }
 
@@ -1741,6 +1750,7 @@ size_t tetframe_layout(vr_context ctx, int32_t n, const vr_tetpart* parts, int32
             k.owned = reinterpret_cast<const uint32_t*>(q->ws + q->off[2]);
             k.cell_start = reinterpret_cast<const int32_t*>(q->ws + q->off[4]);
             k.cell_tets = reinterpret_cast<const int32_t*>(q->ws + q->off[5]);
+            k.nbr = reinterpret_cast<const int32_t*>(q->ws + q->off[6]);
             for (int c = 0; c < 3; ++c) {
                 k.lo[c] = t.lo[c];
                 k.hi[c] = t.hi[c];
@@ -1866,11 +1876,12 @@ vr_status vr_tetpart_attach(vr_tetpart q, void* workspace, size_t workspace_byte
         size_t off;
         const void* src;
         size_t bytes;
-    } copies[5] = {{q->off[0], t.planes.data(), t.planes.size() * sizeof(double)},
+    } copies[6] = {{q->off[0], t.planes.data(), t.planes.size() * sizeof(double)},
                    {q->off[2], t.owned.data(), t.owned.size() * sizeof(uint32_t)},
                    {q->off[3], t.tets.data(), t.tets.size() * sizeof(int32_t)},
                    {q->off[4], t.cell_start.data(), t.cell_start.size() * sizeof(int32_t)},
-                   {q->off[5], t.cell_tets.data(), t.cell_tets.size() * sizeof(int32_t)}};
+                   {q->off[5], t.cell_tets.data(), t.cell_tets.size() * sizeof(int32_t)},
+                   {q->off[6], t.nbr.data(), t.nbr.size() * sizeof(int32_t)}};
     hipError_t e = hipSuccess;
     for (const auto& c : copies)
         if (e == hipSuccess && c.bytes > 0)
@@ -1922,17 +1933,27 @@ vr_status vr_tetparts_workspace_size(vr_context ctx, int32_t n, const vr_tetpart
     return ok(ctx);
 }
 
-vr_status vr_render_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
-                             void* workspace, size_t workspace_bytes, float* out, unsigned long long* samples) {
-    static const char* who = "vr_render_tetparts";
-    vr_status st = tetparts_check(ctx, n, parts, max_runs, who, true);
+// The frame of n parts, stages 1 (march into the workspace's run buffers),
+// 2 (resolve them into out) or both.
+static vr_status tet_frame(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
+                           void* workspace, size_t workspace_bytes, float* out, unsigned long long* samples,
+                           int stages, const char* who) {
+    vr_status st = tetparts_check(ctx, n, parts, max_runs, who, stages & 1);
     if (st != VR_OK) return st;
-    if (!ctx->has_tf) return fail(ctx, VR_ERR_STATE, "%s: no transfer function set", who);
-    if (!bg || !out) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
-    for (int c = 0; c < 4; ++c)
-        if (!std::isfinite(bg[c])) return fail(ctx, VR_ERR_INVALID_ARG, "%s: background not finite", who);
+    if ((stages & 1) && !ctx->has_tf) return fail(ctx, VR_ERR_STATE, "%s: no transfer function set", who);
+    if ((stages & 2) && (!bg || !out)) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
+    if (stages & 2)
+        for (int c = 0; c < 4; ++c)
+            if (!std::isfinite(bg[c])) return fail(ctx, VR_ERR_INVALID_ARG, "%s: background not finite", who);
     if ((reinterpret_cast<uintptr_t>(out) & 15) != 0 || (reinterpret_cast<uintptr_t>(samples) & 7) != 0)
         return fail(ctx, VR_ERR_INVALID_ARG, "%s: out must be 16-, samples 8-byte aligned", who);
+    if (stages == 2) {
+        const auto& lm = ctx->tetmarch;
+        if (lm.ws != workspace || lm.max_runs != max_runs || (int32_t)lm.parts.size() != n ||
+            !std::equal(lm.parts.begin(), lm.parts.end(), parts) || std::memcmp(&lm.cam, &ctx->cam, sizeof(CameraK)))
+            return fail(ctx, VR_ERR_STATE, "%s: no vr_march_tetparts of these parts, max_runs and camera into "
+                        "this workspace", who);
+    }
     std::vector<TetPartK> jobs;
     std::vector<int32_t> prefix;
     size_t need = 0;
@@ -1972,17 +1993,48 @@ vr_status vr_render_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts,
     f.max_runs = max_runs;
     f.width = ctx->cam.width;
     f.height = ctx->cam.height;
-    for (int c = 0; c < 4; ++c) f.bg[c] = bg[c];
+    for (int c = 0; c < 4; ++c) f.bg[c] = bg ? bg[c] : 0.0f;
     f.out = out;
     f.samples = samples;
     f.err = err_word(ctx);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
-    hipError_t e = stage_copy(ctx, ws, tables.data(), tables.size());
-    if (e == hipErrorOutOfMemory) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: pinned staging", who);
-    if (e == hipSuccess) e = launch_tet_frame(f, ctx->stream);
+    hipError_t e = hipSuccess;
+    if (stages & 1) {
+        e = stage_copy(ctx, ws, tables.data(), tables.size());
+        if (e == hipErrorOutOfMemory) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: pinned staging", who);
+    }
+    if (e == hipSuccess) e = launch_tet_frame(f, stages, ctx->stream);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+    if (stages & 1) {
+        try {
+            ctx->tetmarch.parts.assign(parts, parts + n);
+        } catch (const std::bad_alloc&) {
+            ctx->tetmarch.ws = nullptr;
+            return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+        }
+        ctx->tetmarch.ws = workspace;
+        ctx->tetmarch.max_runs = max_runs;
+        ctx->tetmarch.cam = ctx->cam;
+    }
     return ok(ctx);
+}
+
+vr_status vr_render_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
+                             void* workspace, size_t workspace_bytes, float* out, unsigned long long* samples) {
+    return tet_frame(ctx, n, parts, max_runs, bg, workspace, workspace_bytes, out, samples, 3, "vr_render_tetparts");
+}
+
+vr_status vr_march_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, void* workspace,
+                            size_t workspace_bytes, unsigned long long* samples) {
+    return tet_frame(ctx, n, parts, max_runs, nullptr, workspace, workspace_bytes, nullptr, samples, 1,
+                     "vr_march_tetparts");
+}
+
+vr_status vr_resolve_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
+                              void* workspace, size_t workspace_bytes, float* out) {
+    return tet_frame(ctx, n, parts, max_runs, bg, workspace, workspace_bytes, out, nullptr, 2,
+                     "vr_resolve_tetparts");
 }
 
 // ---------------------------------------------------------------- batches

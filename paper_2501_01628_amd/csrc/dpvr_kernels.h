@@ -247,6 +247,7 @@ struct TetPartK {
     const uint32_t* owned;      // n_tets: tie-rule bits
     const int32_t* cell_start;  // grid cells + 1
     const int32_t* cell_tets;
+    const int32_t* nbr;         // n_tets x 4: tetrahedron across each face (-1: none in the part)
     double lo[3], hi[3];        // closed bounding box
     double glo[3], ginv[3];     // grid origin, cells per world unit
     int32_t gdim[3];
@@ -276,6 +277,7 @@ constexpr int32_t kErrRuns = 4;   // a ray crossed a part in more than max_runs 
 inline int32_t tet_tiles(int32_t w, int32_t h) { return ((w + 15) / 16) * ((h + 15) / 16); }
 hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, int32_t n_tets, float* vals,
                              hipStream_t stream);
-hipError_t launch_tet_frame(const TetFrameParams& p, hipStream_t stream);
+// stages: 1 = march (runs), 2 = resolve (frame), 3 = both
+hipError_t launch_tet_frame(const TetFrameParams& p, int stages, hipStream_t stream);
 
 }  // namespace dpvr

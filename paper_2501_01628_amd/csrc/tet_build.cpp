@@ -101,6 +101,48 @@ bool build_tet_tables(const double* V, int32_t nv, const int32_t* T, int32_t nt,
         }
         out.owned[e] = bits;
     }
+    // face neighbours: the faces of all tetrahedra sorted by their vertex
+    // triple; two equal neighbours are the tetrahedra sharing that face
+    {
+        struct Face {
+            int32_t v[3];
+            int32_t id;   // 4 e + i
+        };
+        std::vector<Face> faces((size_t)nt * 4);
+        for (int32_t e = 0; e < nt; ++e)
+            for (int i = 0; i < 4; ++i) {
+                Face& f = faces[4 * (size_t)e + i];
+                int m = 0;
+                for (int j = 0; j < 4; ++j)
+                    if (j != i) f.v[m++] = T[4 * (size_t)e + j];
+                std::sort(f.v, f.v + 3);
+                f.id = 4 * e + i;
+            }
+        std::sort(faces.begin(), faces.end(), [](const Face& a, const Face& b) {
+            if (a.v[0] != b.v[0]) return a.v[0] < b.v[0];
+            if (a.v[1] != b.v[1]) return a.v[1] < b.v[1];
+            if (a.v[2] != b.v[2]) return a.v[2] < b.v[2];
+            return a.id < b.id;
+        });
+        out.nbr.assign((size_t)nt * 4, -1);
+        for (size_t q = 0; q < faces.size();) {
+            size_t r = q + 1;
+            while (r < faces.size() && faces[r].v[0] == faces[q].v[0] && faces[r].v[1] == faces[q].v[1] &&
+                   faces[r].v[2] == faces[q].v[2])
+                ++r;
+            if (r - q > 2) {
+                snprintf(buf, sizeof buf, "a face (vertices %d, %d, %d) is shared by %d tetrahedra", faces[q].v[0],
+                         faces[q].v[1], faces[q].v[2], (int)(r - q));
+                err = buf;
+                return false;
+            }
+            if (r - q == 2) {
+                out.nbr[faces[q].id] = faces[q + 1].id / 4;
+                out.nbr[faces[q + 1].id] = faces[q].id / 4;
+            }
+            q = r;
+        }
+    }
     if (nt == 0) {
         for (int c = 0; c < 3; ++c) {
             out.lo[c] = out.hi[c] = out.glo[c] = 0.0;

@@ -29,6 +29,9 @@ struct TetTables {
     // direction enters the tetrahedron there)
     std::vector<uint32_t> owned;
     std::vector<int32_t> tets;        // 4 vertex indices per tetrahedron (value gather)
+    // nbr[4 e + i]: the tetrahedron of the part across face i of e (-1 on the
+    // part's boundary), for the walk from one sample's tetrahedron to the next
+    std::vector<int32_t> nbr;
     double lo[3], hi[3];              // closed bounding box of the vertices the tetrahedra use
     double glo[3], ginv[3];           // grid origin and cells per world unit
     int32_t gdim[3];
@@ -39,7 +42,8 @@ struct TetTables {
 // Builds the tables of a part given as host arrays (vertices: n_vertices x 3
 // doubles x, y, z; tets: n_tets x 4 indices, either orientation).  Returns
 // false with a message on invalid input (index out of range, non-finite
-// coordinate, zero-volume tetrahedron, too many grid entries) and throws
+// coordinate, zero-volume tetrahedron, a face of more than two tetrahedra,
+// too many grid entries) and throws
 // std::bad_alloc when host memory runs out.
 bool build_tet_tables(const double* vertices, int32_t n_vertices, const int32_t* tets, int32_t n_tets,
                       TetTables& out, std::string& err);

@@ -6,10 +6,11 @@
 //   march     one workgroup per 16 x 16 pixel tile of a part's ROI (the
 //             part's bounding box projected), four wavefronts of 8 x 8 rays.
 //             Every lattice sample t_k = (k + 1/2) dt of the ray inside the
-//             part's bounding box is located in the part: first in the
-//             tetrahedron that held the ray's previous sample, else among the
-//             tetrahedra listed in the sample's cell of the part's uniform
-//             grid.  A tetrahedron holds p when its four signed sub-volumes
+//             part's bounding box is located in the part: by a short walk
+//             from the tetrahedron that held the ray's previous sample (to the
+//             neighbour across the first face that rejects the sample), else
+//             among the tetrahedra listed in the sample's cell of the part's
+//             uniform grid.  A tetrahedron holds p when its four signed sub-volumes
 //             are positive, a zero one counting when the tie direction enters
 //             across that face, so a sample has one owner in the whole mesh
 //             and the first tetrahedron found is that owner.  The value is
@@ -65,18 +66,25 @@ __device__ inline bool box_range(const CamRay& r, const double lo[3], const doub
     return true;
 }
 
-// Whether tetrahedron e holds p; if so its four sub-volumes in D.
-__device__ inline bool holds(const TetPartK& P, int e, double p0, double p1, double p2, double D[4]) {
+// Whether tetrahedron e holds p; if so its four sub-volumes in D, if not
+// the first face that rejects p in *out.
+__device__ inline bool holds(const TetPartK& P, int e, double p0, double p1, double p2, double D[4], int* out) {
 #pragma clang fp contract(off)
     gdouble* pl = ((gdouble*)P.planes) + 16 * (long long)e;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         D[i] = ((pl[4 * i] * p0 + pl[4 * i + 1] * p1) + pl[4 * i + 2] * p2) - pl[4 * i + 3];
-        if (D[i] < 0.0) return false;
-        if (D[i] == 0.0 && !((((guint*)P.owned)[e] >> i) & 1u)) return false;
+        if (D[i] < 0.0 || (D[i] == 0.0 && !((((guint*)P.owned)[e] >> i) & 1u))) {
+            *out = i;
+            return false;
+        }
     }
     return true;
 }
+
+// Steps of the walk from the previous sample's tetrahedron across rejecting
+// faces before the grid is searched.
+constexpr int kWalkSteps = 4;
 
 // Adds every lane's n to *counter (one atomic per wavefront); all lanes of
 // the wavefront call it.
@@ -138,10 +146,15 @@ __global__ __launch_bounds__(256) void tet_march(TetFrameParams f) {
         const double t = ((double)k + 0.5) * f.dt;
         const double p0 = r.o[0] + t * r.d[0], p1 = r.o[1] + t * r.d[1], p2 = r.o[2] + t * r.d[2];
         double D[4];
-        int e = -1;
-        if (last >= 0 && holds(P, last, p0, p1, p2, D)) {
-            e = last;
-        } else {
+        int e = -1, at = last, face = 0;
+        for (int step = 0; step < kWalkSteps && at >= 0; ++step) {
+            if (holds(P, at, p0, p1, p2, D, &face)) {
+                e = at;
+                break;
+            }
+            at = ((gint*)P.nbr)[4 * (long long)at + face];
+        }
+        if (e < 0) {
             const double u0 = (p0 - P.glo[0]) * P.ginv[0], u1 = (p1 - P.glo[1]) * P.ginv[1],
                          u2 = (p2 - P.glo[2]) * P.ginv[2];
             if (u0 >= 0.0 && u1 >= 0.0 && u2 >= 0.0 && u0 < (double)P.gdim[0] && u1 < (double)P.gdim[1] &&
@@ -151,7 +164,7 @@ __global__ __launch_bounds__(256) void tet_march(TetFrameParams f) {
                 const int q1 = ((gint*)P.cell_start)[cell + 1];
                 for (int q = q0; q < q1; ++q) {
                     const int c = ((gint*)P.cell_tets)[q];
-                    if (c != last && holds(P, c, p0, p1, p2, D)) {
+                    if (holds(P, c, p0, p1, p2, D, &face)) {
                         e = c;
                         break;
                     }
@@ -159,6 +172,7 @@ __global__ __launch_bounds__(256) void tet_march(TetFrameParams f) {
             }
         }
         if (e < 0) {
+            last = -1;
             if (in_run) close_run();
             continue;
         }
@@ -209,7 +223,7 @@ __global__ __launch_bounds__(256) void tet_resolve(TetFrameParams f) {
             if (lx < 0 || ly < 0 || lx >= P.roi_w || ly >= P.roi_h) continue;
             const long long li = (long long)ly * P.roi_w + lx;
             const int h = head[q * 256 + tid];
-            if (h >= P.rcount[li]) continue;
+            if (h >= min(P.rcount[li], f.max_runs)) continue;
             const long long slot = (long long)h * P.roi_w * P.roi_h + li;
             const int k = P.rkey[slot];
             if (k < best) {
@@ -242,10 +256,11 @@ hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, in
     return hipGetLastError();
 }
 
-hipError_t launch_tet_frame(const TetFrameParams& p, hipStream_t stream) {
-    if (p.total_tiles > 0) hipLaunchKernelGGL(tet_march, dim3(p.total_tiles), dim3(256), 0, stream, p);
+hipError_t launch_tet_frame(const TetFrameParams& p, int stages, hipStream_t stream) {
+    if ((stages & 1) && p.total_tiles > 0)
+        hipLaunchKernelGGL(tet_march, dim3(p.total_tiles), dim3(256), 0, stream, p);
     const long long npx = (long long)p.width * p.height;
-    hipLaunchKernelGGL(tet_resolve, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, stream, p);
+    if (stages & 2) hipLaunchKernelGGL(tet_resolve, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 

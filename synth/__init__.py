@@ -468,22 +468,16 @@ def tet_mesh(cells, jitter=0.0, rng=None, spacing=1.0):
         verts[interior] += d[interior]
     verts *= spacing
 
-    def vid(i, j, k):
-        return (i * (ny + 1) + j) * (nz + 1) + k
-
-    tets = []
+    ci, cj, ck = (a.ravel() for a in np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"))
     perms = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
-    for i in range(nx):
-        for j in range(ny):
-            for k in range(nz):
-                for p in perms:
-                    c = [i, j, k]
-                    t = [vid(*c)]
-                    for a in p:
-                        c[a] += 1
-                        t.append(vid(*c))
-                    tets.append(t)
-    tets = np.asarray(tets, dtype=np.int32)
+    tets = np.empty((len(ci), 6, 4), dtype=np.int64)
+    for q, p in enumerate(perms):
+        c = [ci.copy(), cj.copy(), ck.copy()]
+        tets[:, q, 0] = (c[0] * (ny + 1) + c[1]) * (nz + 1) + c[2]
+        for m, a in enumerate(p):
+            c[a] += 1
+            tets[:, q, m + 1] = (c[0] * (ny + 1) + c[1]) * (nz + 1) + c[2]
+    tets = tets.reshape(-1, 4).astype(np.int32)
     # orient every tetrahedron positively
     e = verts[tets[:, 1:]] - verts[tets[:, :1]]
     vol = np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2]))
@@ -504,21 +498,37 @@ def tet_field(verts, rng, dims, n_blobs=6):
     return np.clip(v, 0.0, 1.0).astype(np.float32)
 
 
-def tet_partitions(verts, tets, n_parts, rng):
+def tet_partitions(verts, tets, n_parts, rng, rough=False):
     """Uneven, non-convex partitions: each tetrahedron goes to the seed
-    nearest its centroid under a seeded weighted distance with a seeded
-    noise term (weights U(0.5, 2), noise up to an eighth of the longest box
-    edge), so parts differ in size, are not convex and have ragged
-    boundaries.  Returns a list of (vertices, tets, used) per part: local
-    vertex numbering (shared vertices copied), used = the global index of
-    each local vertex."""
+    nearest its centroid under a seeded weighted distance (weights U(0.5, 2))
+    plus a seeded perturbation of up to an eighth of the longest box edge,
+    so parts differ in size and are not convex.  The perturbation is smooth
+    (three random plane waves of a third of the box per part: contiguous
+    parts with wavy boundaries, like a simulation's domain decomposition) or,
+    with ``rough``, independent per tetrahedron (ragged, scattered parts
+    whose rays enter and leave them many times).  Returns a list of
+    (vertices, tets, used) per part: local vertex numbering (shared vertices
+    copied), used = the global index of each local vertex."""
     cen = verts[tets].mean(1)
     lo, hi = verts.min(0), verts.max(0)
     seeds = lo + rng.uniform(0.0, 1.0, (n_parts, 3)) * (hi - lo)
     w = rng.uniform(0.5, 2.0, n_parts)
-    noise = rng.uniform(0.0, 1.0, (len(tets), n_parts)) * np.max(hi - lo) / 8.0
-    d = np.sqrt(((cen[:, None, :] - seeds[None, :, :]) ** 2).sum(2)) / w[None, :] + noise
-    owner = np.argmin(d, 1)
+    amp = np.max(hi - lo) / 8.0
+    kmag = 2.0 * np.pi / (np.max(hi - lo) / 3.0)
+    best = np.full(len(tets), np.inf)
+    owner = np.zeros(len(tets), dtype=np.int64)
+    for p in range(n_parts):        # one part at a time: memory stays O(tets)
+        d = np.sqrt(((cen - seeds[p]) ** 2).sum(1)) / w[p]
+        if rough:
+            d += rng.uniform(0.0, 1.0, len(tets)) * amp
+        else:
+            for _ in range(3):
+                k = rng.normal(size=3)
+                k *= kmag / np.linalg.norm(k)
+                d += (amp / 3.0) * (1.0 + np.sin(cen @ k + rng.uniform(0.0, 2.0 * np.pi)))
+        better = d < best
+        best[better] = d[better]
+        owner[better] = p
     parts = []
     for p in range(n_parts):
         sel = tets[owner == p]

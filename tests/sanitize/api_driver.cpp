@@ -260,6 +260,10 @@ int main() {
         EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame + 1, nullptr) == VR_ERR_INVALID_ARG);
         EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame, nullptr) == VR_OK);
         EXPECT(vr_render_tetparts(ctx, 2, tp + 1, 1, bg, fw, fb, frame, nullptr) == VR_OK);
+        EXPECT(vr_resolve_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame) == VR_ERR_STATE);   // last march: other parts
+        EXPECT(vr_march_tetparts(ctx, 3, tp, 4, fw, fb, nullptr) == VR_OK);
+        EXPECT(vr_resolve_tetparts(ctx, 3, tp, 2, bg, fw, fb, frame) == VR_ERR_STATE);   // other max_runs
+        EXPECT(vr_resolve_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame) == VR_OK);
         EXPECT(frame[0] == bg[0] && frame[3] == bg[3]);
         EXPECT(vr_context_release(ctx) == VR_ERR_STATE);     // parts still live
         for (int q = 0; q < 3; ++q) EXPECT(vr_tetpart_release(tp[q]) == VR_OK);

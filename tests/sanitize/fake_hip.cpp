@@ -99,7 +99,7 @@ hipError_t launch_tet_values(const float* vv, const int32_t* tets, int32_t n, fl
         for (int j = 0; j < 4; ++j) vals[4 * e + j] = vv[tets[4 * e + j]];
     return hipSuccess;
 }
-hipError_t launch_tet_frame(const TetFrameParams& f, hipStream_t) {
+hipError_t launch_tet_frame(const TetFrameParams& f, int stages, hipStream_t) {
     int32_t tiles = 0;
     for (int32_t q = 0; q < f.n; ++q) {
         const TetPartK& P = f.parts[q];
@@ -110,7 +110,8 @@ hipError_t launch_tet_frame(const TetFrameParams& f, hipStream_t) {
         for (long long i = 0; i < np * f.max_runs; ++i) P.rkey[i] = 0;
         for (long long i = 0; i < np * f.max_runs * 4; ++i) P.rcol[i] = 0.0f;
         if (P.n_tets > 0) {
-            volatile double x = P.planes[16LL * P.n_tets - 1] + P.vals[4LL * P.n_tets - 1] + P.owned[P.n_tets - 1];
+            volatile double x = P.planes[16LL * P.n_tets - 1] + P.vals[4LL * P.n_tets - 1] + P.owned[P.n_tets - 1] +
+                                P.nbr[4LL * P.n_tets - 1];
             const long long cells = (long long)P.gdim[0] * P.gdim[1] * P.gdim[2];
             const int32_t entries = P.cell_start[cells];
             if (entries > 0) x = x + P.cell_tets[entries - 1];
@@ -118,7 +119,8 @@ hipError_t launch_tet_frame(const TetFrameParams& f, hipStream_t) {
         }
     }
     if (f.tile_start[f.n] != tiles || f.total_tiles != tiles) return hipErrorInvalidValue;
-    for (long long i = 0; i < 4LL * f.width * f.height; ++i) f.out[i] = f.bg[i & 3];
+    if (stages & 2)
+        for (long long i = 0; i < 4LL * f.width * f.height; ++i) f.out[i] = f.bg[i & 3];
     return hipSuccess;
 }
 }  // namespace dpvr

@@ -20,7 +20,7 @@ def _dp():
     return dp
 
 
-def _scene(cells, jitter, n_parts, seed, linear=False):
+def _scene(cells, jitter, n_parts, seed, linear=False, rough=True):
     rng = np.random.default_rng(seed)
     v, t = synth.tet_mesh(cells, jitter=jitter, rng=rng)
     if linear:
@@ -31,7 +31,7 @@ def _scene(cells, jitter, n_parts, seed, linear=False):
     if n_parts == 1:
         parts = [(v, t, np.arange(len(v)))]
     else:
-        parts = synth.tet_partitions(v, t, n_parts, rng)
+        parts = synth.tet_partitions(v, t, n_parts, rng, rough=rough)
     return vals, parts
 
 
@@ -73,10 +73,10 @@ def _compare(parts, vals, cam, dt, bg=(0.0, 0.0, 0.0, 0.0), max_runs=8):
     return img
 
 
-@pytest.mark.parametrize("n_parts,seed", [(1, 1), (5, 2), (9, 3)])
-def test_jittered_mesh_in_parts(n_parts, seed):
+@pytest.mark.parametrize("n_parts,seed,rough", [(1, 1, True), (5, 2, True), (9, 3, True), (6, 12, False)])
+def test_jittered_mesh_in_parts(n_parts, seed, rough):
     cells = (6, 5, 7)
-    vals, parts = _scene(cells, 0.25, n_parts, seed)
+    vals, parts = _scene(cells, 0.25, n_parts, seed, rough=rough)
     cam = synth.orbit_camera((0, 0, 0), cells, 61, 47, az_deg=30.0 + 20 * seed, el_deg=20.0, radius_factor=1.5)
     _compare(parts, vals, cam, 0.37, (0.05, 0.1, 0.15, 0.3))
 
@@ -181,3 +181,28 @@ def test_rejected_calls():
         dp.vr_tetpart_release(h, ctx)
     finally:
         dp.vr_context_release(ctx)
+
+
+def test_march_and_resolve_stages_equal_the_frame_call():
+    dp = _dp()
+    cells = (6, 4, 5)
+    vals, parts = _scene(cells, 0.2, 4, 10)
+    cam = synth.orbit_camera((0, 0, 0), cells, 45, 38, az_deg=20.0, el_deg=35.0, radius_factor=1.5)
+    tf, vr, s = _tf()
+    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, vr, s, 0.33)
+    try:
+        for k, (_, _, used) in enumerate(parts):
+            r.set_values(k, vals[used])
+        r.set_camera(cam)
+        whole = r.render((0.1, 0.0, 0.2, 0.5)).clone()
+        r.frame.zero_()
+        r.march()
+        staged = r.resolve((0.1, 0.0, 0.2, 0.5))
+        r.synchronize()
+        assert bool((whole == staged).all())
+        # a resolve whose march used another max_runs is refused
+        r.max_runs = 4
+        with pytest.raises(dp.VRError, match="VR_ERR_STATE"):
+            r.resolve()
+    finally:
+        r.close()

@@ -119,14 +119,14 @@ def test_eye_inside_mesh():
     np.testing.assert_allclose(img, ref, rtol=0, atol=1e-11)
 
 
-@pytest.mark.parametrize("n_parts,seed", [(3, 5), (7, 6)])
-def test_split_into_parts_is_invariant(n_parts, seed):
+@pytest.mark.parametrize("n_parts,seed,rough", [(3, 5, False), (7, 6, True)])
+def test_split_into_parts_is_invariant(n_parts, seed, rough):
     cam = synth.orbit_camera((0, 0, 0), CELLS, 22, 18, az_deg=-20.0, el_deg=40.0, radius_factor=1.5)
     rng = np.random.default_rng(seed)
     v, t = synth.tet_mesh(CELLS, jitter=0.25, rng=rng)
     vals = synth.tet_field(v, rng, CELLS)
     whole, c1 = _tet_image(cam, [(v, vals, t)], 0.31, (0.0, 0.0, 0.0, 0.0))
-    parts = [(pv, vals[used], pt) for pv, pt, used in synth.tet_partitions(v, t, n_parts, rng)]
+    parts = [(pv, vals[used], pt) for pv, pt, used in synth.tet_partitions(v, t, n_parts, rng, rough=rough)]
     assert sum(len(p[2]) for p in parts) == len(t)
     split, c2 = _tet_image(cam, parts, 0.31, (0.0, 0.0, 0.0, 0.0))
     assert np.array_equal(whole, split)
