@@ -901,13 +901,13 @@ def bench_stream(args):
 
 def tet_scene(cells=(128, 96, 96), n_parts=16, width=1920, height=1080):
     """Tetrahedral workload: a 128x96x96-cube box cut into 7.1 M tetrahedra
-    (6 per cube, interior vertices jittered by up to 0.25 of a cube, 1.2 M
+    (6 per cube, interior vertices jittered by up to 0.15 of a cube, 1.2 M
     vertices), 8 Gaussian blobs evaluated at the vertices, 16 uneven
     non-convex parts (weighted nearest seed + noise per tetrahedron),
     1920x1080 orbit view, step 0.5 cube, opacity scale 0.05."""
     import synth
     rng = np.random.default_rng(12)
-    v, t = synth.tet_mesh(cells, jitter=0.25, rng=rng)
+    v, t = synth.tet_mesh(cells, jitter=0.15, rng=rng)
     vals = synth.tet_field(v, rng, cells, n_blobs=8)
     parts = synth.tet_partitions(v, t, n_parts, rng)
     cam = synth.orbit_camera((0, 0, 0), cells, width, height)

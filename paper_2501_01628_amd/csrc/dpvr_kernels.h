@@ -263,7 +263,7 @@ struct TetFrameParams {
     TFK tf;
     double dt;
     const TetPartK* parts;      // device, n
-    const int32_t* tile_start;  // device, n + 1: exclusive prefix of 16 x 16 tiles
+    const int32_t* tile_start;  // device, n + 1: exclusive prefix of tiles (tet_tiles)
     int32_t n, total_tiles, max_runs;
     int32_t width, height;
     float bg[4];
@@ -274,7 +274,12 @@ struct TetFrameParams {
 
 constexpr int32_t kErrRuns = 4;   // a ray crossed a part in more than max_runs runs
 
-inline int32_t tet_tiles(int32_t w, int32_t h) { return ((w + 15) / 16) * ((h + 15) / 16); }
+// Tiles of the tetrahedral march: kTetTile x kTetTile pixels, one workgroup
+// of (kTetTile / 8)^2 wavefronts of 8 x 8 rays each.
+constexpr int kTetTile = 16;
+inline int32_t tet_tiles(int32_t w, int32_t h) {
+    return ((w + kTetTile - 1) / kTetTile) * ((h + kTetTile - 1) / kTetTile);
+}
 hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, int32_t n_tets, float* vals,
                              hipStream_t stream);
 // stages: 1 = march (runs), 2 = resolve (frame), 3 = both

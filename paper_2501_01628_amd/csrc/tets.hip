@@ -3,8 +3,8 @@
 // a share of a finite-element data set.
 //
 // A frame, for n parts and the context camera:
-//   march     one workgroup per 16 x 16 pixel tile of a part's ROI (the
-//             part's bounding box projected), four wavefronts of 8 x 8 rays.
+//   march     one workgroup per tile of a part's ROI (the part's bounding
+//             box projected), wavefronts of 8 x 8 rays.
 //             Every lattice sample t_k = (k + 1/2) dt of the ray inside the
 //             part's bounding box is located in the part: by a short walk
 //             from the tetrahedron that held the ray's previous sample (to the
@@ -94,9 +94,11 @@ __device__ inline void count_held(unsigned long long* counter, unsigned long lon
     if ((threadIdx.x & 63) == 0 && n) atomicAdd(counter, n);
 }
 
-__global__ __launch_bounds__(256) void tet_march(TetFrameParams f) {
+constexpr int kTetThreads = kTetTile * kTetTile;
+
+__global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
     __shared__ TFTable tft;
-    load_tf(tft, f.tf, f.dt, threadIdx.x, 256);
+    load_tf(tft, f.tf, f.dt, threadIdx.x, kTetThreads);
     __syncthreads();
     const int wg = blockIdx.x;
     int lo = 0, hi = f.n - 1;
@@ -105,12 +107,14 @@ __global__ __launch_bounds__(256) void tet_march(TetFrameParams f) {
         if (f.tile_start[mid] <= wg) lo = mid; else hi = mid - 1;
     }
     const int j = __builtin_amdgcn_readfirstlane(lo);
-    const TetPartK& P = f.parts[j];
+    // a copy in registers: the run stores below cannot alias it, so its
+    // fields are loaded once
+    const TetPartK P = f.parts[j];
     const int tile = wg - f.tile_start[j];
-    const int tiles_x = (P.roi_w + 15) / 16;
+    const int tiles_x = (P.roi_w + kTetTile - 1) / kTetTile;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lx = (tile % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
-    const int ly = (tile / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int lx = (tile % tiles_x) * kTetTile + (wave % (kTetTile / 8)) * 8 + (lane & 7);
+    const int ly = (tile / tiles_x) * kTetTile + (wave / (kTetTile / 8)) * 8 + (lane >> 3);
     const bool live = lx < P.roi_w && ly < P.roi_h;
     const long long npix = (long long)P.roi_w * P.roi_h;
     const long long li = (long long)ly * P.roi_w + lx;
@@ -145,31 +149,33 @@ __global__ __launch_bounds__(256) void tet_march(TetFrameParams f) {
 #pragma clang fp contract(off)
         const double t = ((double)k + 0.5) * f.dt;
         const double p0 = r.o[0] + t * r.d[0], p1 = r.o[1] + t * r.d[1], p2 = r.o[2] + t * r.d[2];
+        // One candidate per trip, so that the lanes of a wavefront stay on
+        // the same code: first the walk from the previous sample's
+        // tetrahedron (kWalkSteps tests), then the tetrahedra of the grid cell.
         double D[4];
-        int e = -1, at = last, face = 0;
-        for (int step = 0; step < kWalkSteps && at >= 0; ++step) {
-            if (holds(P, at, p0, p1, p2, D, &face)) {
-                e = at;
-                break;
-            }
-            at = ((gint*)P.nbr)[4 * (long long)at + face];
-        }
-        if (e < 0) {
-            const double u0 = (p0 - P.glo[0]) * P.ginv[0], u1 = (p1 - P.glo[1]) * P.ginv[1],
-                         u2 = (p2 - P.glo[2]) * P.ginv[2];
-            if (u0 >= 0.0 && u1 >= 0.0 && u2 >= 0.0 && u0 < (double)P.gdim[0] && u1 < (double)P.gdim[1] &&
-                u2 < (double)P.gdim[2]) {
-                const long long cell = ((long long)(int)u2 * P.gdim[1] + (int)u1) * P.gdim[0] + (int)u0;
-                const int q0 = ((gint*)P.cell_start)[cell];
-                const int q1 = ((gint*)P.cell_start)[cell + 1];
-                for (int q = q0; q < q1; ++q) {
-                    const int c = ((gint*)P.cell_tets)[q];
-                    if (holds(P, c, p0, p1, p2, D, &face)) {
-                        e = c;
-                        break;
+        int e = -1, cand = last, face = 0, walk = kWalkSteps, q = 0, qend = 0;
+        bool grid = false;
+        for (;;) {
+            if (cand < 0) {
+                if (!grid) {
+                    grid = true;
+                    const double u0 = (p0 - P.glo[0]) * P.ginv[0], u1 = (p1 - P.glo[1]) * P.ginv[1],
+                                 u2 = (p2 - P.glo[2]) * P.ginv[2];
+                    if (u0 >= 0.0 && u1 >= 0.0 && u2 >= 0.0 && u0 < (double)P.gdim[0] &&
+                        u1 < (double)P.gdim[1] && u2 < (double)P.gdim[2]) {
+                        const long long cell = ((long long)(int)u2 * P.gdim[1] + (int)u1) * P.gdim[0] + (int)u0;
+                        q = ((gint*)P.cell_start)[cell];
+                        qend = ((gint*)P.cell_start)[cell + 1];
                     }
                 }
+                if (q >= qend) break;
+                cand = ((gint*)P.cell_tets)[q++];
             }
+            if (holds(P, cand, p0, p1, p2, D, &face)) {
+                e = cand;
+                break;
+            }
+            cand = !grid && --walk > 0 ? ((gint*)P.nbr)[4 * (long long)cand + face] : -1;
         }
         if (e < 0) {
             last = -1;
@@ -178,16 +184,19 @@ __global__ __launch_bounds__(256) void tet_march(TetFrameParams f) {
         }
         last = e;
         gfloat_t* vv = ((gfloat_t*)P.vals) + 4 * (long long)e;
+        // barycentric value: the weighted sum in float64, one float32
+        // division (the value is classified in float32)
         const double s = ((D[0] + D[1]) + D[2]) + D[3];
-        const double vd = (((D[0] * (double)vv[0] + D[1] * (double)vv[1]) + D[2] * (double)vv[2]) +
-                           D[3] * (double)vv[3]) / s;
+        const double num = ((D[0] * (double)vv[0] + D[1] * (double)vv[1]) + D[2] * (double)vv[2]) +
+                           D[3] * (double)vv[3];
+        const float vd = __fdividef((float)num, (float)s);
         if (!in_run) {
             in_run = true;
             key = (int)k;
             C0 = C1 = C2 = 0.f;
             T = 1.f;
         }
-        const Classified c = classify(tft, (float)vd, tf_k, tf_o);
+        const Classified c = classify(tft, vd, tf_k, tf_o);
         const float Tn = T * trans_exp2(-c.a);
         const float w = T - Tn;
         C0 = fmaf(w, c.r, C0);
@@ -258,7 +267,7 @@ hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, in
 
 hipError_t launch_tet_frame(const TetFrameParams& p, int stages, hipStream_t stream) {
     if ((stages & 1) && p.total_tiles > 0)
-        hipLaunchKernelGGL(tet_march, dim3(p.total_tiles), dim3(256), 0, stream, p);
+        hipLaunchKernelGGL(tet_march, dim3(p.total_tiles), dim3(kTetThreads), 0, stream, p);
     const long long npx = (long long)p.width * p.height;
     if (stages & 2) hipLaunchKernelGGL(tet_resolve, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, stream, p);
     return hipGetLastError();

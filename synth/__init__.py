@@ -457,7 +457,8 @@ def tet_mesh(cells, jitter=0.0, rng=None, spacing=1.0):
     lattice cube cut into the 6 tetrahedra around its main diagonal (the
     same cut in every cube, so neighbouring cubes share faces).  Returns
     (vertices (V, 3) float64 in x, y, z order, tets (T, 4) int32 with
-    positive orientation)."""
+    positive orientation).  Raises if the jitter inverts a tetrahedron (at
+    0.15 none is; from about 0.2 a large mesh has a few)."""
     nx, ny, nz = (int(c) for c in cells)
     gx, gy, gz = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
     verts = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1).astype(np.float64)
@@ -478,13 +479,16 @@ def tet_mesh(cells, jitter=0.0, rng=None, spacing=1.0):
             c[a] += 1
             tets[:, q, m + 1] = (c[0] * (ny + 1) + c[1]) * (nz + 1) + c[2]
     tets = tets.reshape(-1, 4).astype(np.int32)
-    # orient every tetrahedron positively
-    e = verts[tets[:, 1:]] - verts[tets[:, :1]]
-    vol = np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2]))
-    if np.any(vol == 0.0):
-        raise ValueError("degenerate tetrahedron (jitter too large)")
-    neg = vol < 0
+    # orient every tetrahedron positively on the lattice, then require the
+    # jittered mesh to keep every orientation (an inverted tetrahedron would
+    # overlap its neighbours: the mesh would no longer be conforming)
+    gv = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1).astype(np.float64)
+    e = gv[tets[:, 1:]] - gv[tets[:, :1]]
+    neg = np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2])) < 0
     tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    e = verts[tets[:, 1:]] - verts[tets[:, :1]]
+    if np.any(np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2])) <= 0.0):
+        raise ValueError("jitter inverts a tetrahedron: the mesh would not be conforming")
     return verts, tets
 
 

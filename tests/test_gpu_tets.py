@@ -206,3 +206,48 @@ def test_march_and_resolve_stages_equal_the_frame_call():
             r.resolve()
     finally:
         r.close()
+
+
+def test_bench_size_split_invariance_and_linear_field():
+    """At the benchmark's size (7.1 M tetrahedra, 1920x1080): the frame of
+    16 non-convex parts equals the frame of the whole mesh as one part (same
+    held-sample count, 1e-5), and a linear field renders as the brick
+    oracle renders it at sampled pixels."""
+    dp = _dp()
+    cells = (128, 96, 96)
+    rng = np.random.default_rng(12)
+    v, t = synth.tet_mesh(cells, jitter=0.15, rng=rng)
+    vals = synth.tet_field(v, rng, cells, n_blobs=8)
+    parts = synth.tet_partitions(v, t, 16, rng)
+    cam = synth.orbit_camera((0, 0, 0), cells, 1920, 1080)
+    print("bench-size mesh generated", flush=True)
+    tf, vr, s = _tf()
+
+    def frame(pp, vv, count=True):
+        r = dp.TetRenderer([(pv, pt) for pv, pt, _ in pp], tf, vr, s, 0.5, max_runs=32)
+        try:
+            for k, (_, _, used) in enumerate(pp):
+                r.set_values(k, vv[used])
+            r.set_camera(cam)
+            r.samples.zero_()
+            img = r.render(count=count)
+            r.synchronize()
+            return img.cpu().numpy().astype(np.float64), int(r.samples.item())
+        finally:
+            r.close()
+    split, n16 = frame(parts, vals)
+    whole, n1 = frame([(v, t, np.arange(len(v)))], vals)
+    print(f"held {n16} / {n1}", flush=True)
+    assert n16 == n1 > 0
+    assert np.max(np.abs(split - whole)) <= TOL
+    lin = (0.1 + 0.004 * v[:, 0] + 0.003 * v[:, 1] + 0.002 * v[:, 2]).astype(np.float32)
+    img, _ = frame(parts, lin, count=False)
+    nx, ny, nz = cells
+    z, y, x = np.meshgrid(np.arange(nz + 2), np.arange(ny + 2), np.arange(nx + 2), indexing="ij")
+    vox = (0.1 + 0.004 * (x - 0.5) + 0.003 * (y - 0.5) + 0.002 * (z - 0.5)).astype(np.float32)
+    pick = np.random.default_rng(0)
+    pix = np.stack([pick.integers(0, 1920, 48), pick.integers(0, 1080, 48)], 1).astype(np.int32)
+    ref, _, _ = oracle.render_brick(cam, vox, cells, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), tf, vr, s, 0.5,
+                                    pixels=pix)
+    err = np.max(np.abs(img[pix[:, 1], pix[:, 0]] - ref))
+    assert err <= TOL, err
