@@ -101,6 +101,10 @@ def _load():
                                            C.c_double, _dp, C.POINTER(C.c_int32), C.c_int64, _dp,
                                            C.POINTER(C.c_int64)]
             lib.oc_render_tets.restype = None
+            lib.oc_render_tets_shadowed.argtypes = [C.POINTER(_Camera), C.c_int32, C.POINTER(_TetPart),
+                                                    C.POINTER(_TF), C.c_double, _dp, C.c_double, _dp,
+                                                    C.POINTER(C.c_int32), C.c_int64, _dp, C.POINTER(C.c_int64)]
+            lib.oc_render_tets_shadowed.restype = C.c_int
             lib.oc_set_threads.argtypes = [C.c_int]
             lib.oc_set_threads.restype = None
             _lib = lib
@@ -343,6 +347,20 @@ def render_tets(cam, parts, tf, vrange, opacity_scale, dt, bg=(0.0, 0.0, 0.0, 0.
     float64, values (V,) float32, tets (T, 4) int32)], over bg (R-tet,
     R-ea).  Returns (image, counters) with counters = [samples held by a
     tetrahedron, samples held by more than one]."""
+    return _render_tets(cam, parts, tf, vrange, opacity_scale, dt, bg, pixels, None, None)
+
+
+def render_tets_shadowed(cam, parts, tf, vrange, opacity_scale, dt, light_dir, ambient,
+                         bg=(0.0, 0.0, 0.0, 0.0), pixels=None):
+    """render_tets with one directional light (R-shadow): every held primary
+    sample's colour scaled by ambient + (1 - ambient) S, S the transmittance
+    of its shadow ray through all parts.  Returns (image, counters) with
+    counters = [primary samples held, held more than once, shadow samples
+    held]."""
+    return _render_tets(cam, parts, tf, vrange, opacity_scale, dt, bg, pixels, light_dir, ambient)
+
+
+def _render_tets(cam, parts, tf, vrange, opacity_scale, dt, bg, pixels, light_dir, ambient):
     lib = _load()
     c = _camera(cam)
     keep = []
@@ -363,9 +381,18 @@ def render_tets(cam, parts, tf, vrange, opacity_scale, dt, bg=(0.0, 0.0, 0.0, 0.
         n = pix.shape[0]
         pix_p = _ptr(pix, C.c_int32)
     out = np.zeros(n * 4)
-    cnt = np.zeros(2, dtype=np.int64)
-    lib.oc_render_tets(C.byref(c), len(parts), arr, C.byref(tfr.s), float(dt), _ptr(bgv, C.c_double), pix_p, n,
-                       _ptr(out, C.c_double), _ptr(cnt, C.c_int64))
+    if light_dir is None:
+        cnt = np.zeros(2, dtype=np.int64)
+        lib.oc_render_tets(C.byref(c), len(parts), arr, C.byref(tfr.s), float(dt), _ptr(bgv, C.c_double), pix_p,
+                           n, _ptr(out, C.c_double), _ptr(cnt, C.c_int64))
+    else:
+        cnt = np.zeros(3, dtype=np.int64)
+        lv = np.asarray(light_dir, dtype=np.float64)
+        rc = lib.oc_render_tets_shadowed(C.byref(c), len(parts), arr, C.byref(tfr.s), float(dt),
+                                         _ptr(lv, C.c_double), float(ambient), _ptr(bgv, C.c_double), pix_p, n,
+                                         _ptr(out, C.c_double), _ptr(cnt, C.c_int64))
+        if rc != 0:
+            raise ValueError("light direction must be non-zero and ambient in [0, 1]")
     if pixels is None:
         return out.reshape(c.height, c.width, 4), cnt
     return out.reshape(n, 4), cnt

@@ -22,6 +22,8 @@
  *   - the image of a volume given as tetrahedral partitions (unstructured,
  *     possibly non-convex), marched sample by sample through the element
  *     that holds each sample                       oc_render_tets
+ *     and with the directional light's shadow rays through all parts
+ *                                                  oc_render_tets_shadowed
  *
  * The paper (Zellmann, "Data Parallel Visualization and Rendering on the
  * RAMSES Supercomputer with ANARI") describes data-parallel ray tracing over
@@ -471,6 +473,32 @@ static int tet_holds(const oc_tetpart* P, int32_t t, const double p[3], double* 
     return 1;
 }
 
+/* Closed bounding box of the vertices of all parts. */
+static void tets_box(int32_t n, const oc_tetpart* parts, double LO[3], double HI[3]) {
+    for (int c = 0; c < 3; ++c) { LO[c] = INFINITY; HI[c] = -INFINITY; }
+    for (int32_t q = 0; q < n; ++q)
+        for (int32_t v = 0; v < parts[q].n_vertices; ++v)
+            for (int c = 0; c < 3; ++c) {
+                double x = parts[q].vertices[3 * (int64_t)v + c];
+                if (x < LO[c]) LO[c] = x;
+                if (x > HI[c]) HI[c] = x;
+            }
+}
+
+/* R-tet: the number of tetrahedra (over all parts) that hold p; the value
+ * at p from the first of them, in (part, tetrahedron) order, in *value. */
+static int tets_locate(int32_t n, const oc_tetpart* parts, const double p[3], double* value) {
+    int owners = 0;
+    double w;
+    for (int32_t a = 0; a < n; ++a)
+        for (int32_t e = 0; e < parts[a].n_tets; ++e)
+            if (tet_holds(&parts[a], e, p, &w)) {
+                if (owners == 0) *value = w;
+                ++owners;
+            }
+    return owners;
+}
+
 /* Image of the volume given by n tetrahedral parts (all parts together form
  * one mesh), pixels as for oc_render_brick, over bg: the ray's lattice
  * samples t_k = (k + 1/2) dt inside the parts' common bounding box, each
@@ -480,14 +508,8 @@ static int tet_holds(const oc_tetpart* P, int32_t t, const double p[3], double* 
  * conforming mesh). */
 void oc_render_tets(const oc_camera* cam, int32_t n, const oc_tetpart* parts, const oc_tf* tf, double dt,
                     const double bg[4], const int32_t* pix, int64_t npix, double* rgba, int64_t* counters) {
-    double LO[3] = {INFINITY, INFINITY, INFINITY}, HI[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int32_t q = 0; q < n; ++q)
-        for (int32_t v = 0; v < parts[q].n_vertices; ++v)
-            for (int c = 0; c < 3; ++c) {
-                double x = parts[q].vertices[3 * (int64_t)v + c];
-                if (x < LO[c]) LO[c] = x;
-                if (x > HI[c]) HI[c] = x;
-            }
+    double LO[3], HI[3];
+    tets_box(n, parts, LO, HI);
     int64_t npx = pix ? npix : (int64_t)cam->width * cam->height;
     int64_t held = 0, twice = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : held, twice)
@@ -502,14 +524,8 @@ void oc_render_tets(const oc_camera* cam, int32_t n, const oc_tetpart* parts, co
             for (int64_t k = k0; k <= k1; ++k) {
                 double t = ((double)k + 0.5) * dt;
                 double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
-                double v = 0.0, w;
-                int owners = 0;
-                for (int32_t a = 0; a < n; ++a)
-                    for (int32_t e = 0; e < parts[a].n_tets; ++e)
-                        if (tet_holds(&parts[a], e, p, &w)) {
-                            if (owners == 0) v = w;
-                            ++owners;
-                        }
+                double v = 0.0;
+                int owners = tets_locate(n, parts, p, &v);
                 if (owners == 0) continue;
                 ++held;
                 if (owners > 1) ++twice;
@@ -525,6 +541,79 @@ void oc_render_tets(const oc_camera* cam, int32_t n, const oc_tetpart* parts, co
         rgba[4 * q + 3] = A + T * bg[3];
     }
     if (counters) { counters[0] += held; counters[1] += twice; }
+}
+
+/* R-shadow for tetrahedral parts: transmittance from p toward the light
+ * along unit l, the shadow samples q_j = p + (j + 1/2) dt l (j >= 0) inside
+ * the parts' bounding box, each held one evaluated as a primary sample and
+ * multiplying S by 1 - alpha(q_j).  *held += shadow samples held. */
+static double tets_shadow(int32_t n, const oc_tetpart* parts, const double LO[3], const double HI[3],
+                          const oc_tf* tf, double dt, const double p[3], const double l[3], int64_t* held) {
+    int64_t j0, j1;
+    if (n == 0 || !sample_range(p, l, LO, HI, dt, &j0, &j1)) return 1.0;
+    double S = 1.0;
+    for (int64_t j = j0; j <= j1; ++j) {
+        double t = ((double)j + 0.5) * dt;
+        double q[3] = {p[0] + t * l[0], p[1] + t * l[1], p[2] + t * l[2]};
+        double v = 0.0;
+        if (tets_locate(n, parts, q, &v) == 0) continue;
+        double e[4], phi; int32_t seg; int inside;
+        classify(tf, v, e, &seg, &phi, &inside);
+        double alpha = 1.0 - exp(-tf->opacity_scale * e[3] * dt);
+        S = S * (1.0 - alpha);
+        ++*held;
+    }
+    return S;
+}
+
+/* oc_render_tets with R-shadow (light direction normalised here, ambient a0
+ * in [0, 1]): the colour of every held primary sample is scaled by
+ * a0 + (1 - a0) S, S its shadow ray's transmittance through all parts;
+ * alpha and T are unchanged.  counters: [0] += primary samples held,
+ * [1] += primary samples held by more than one tetrahedron, [2] += shadow
+ * samples held.  Returns -1 on bad input. */
+int oc_render_tets_shadowed(const oc_camera* cam, int32_t n, const oc_tetpart* parts, const oc_tf* tf,
+                            double dt, const double light_dir[3], double a0, const double bg[4],
+                            const int32_t* pix, int64_t npix, double* rgba, int64_t* counters) {
+    double l[3] = {light_dir[0], light_dir[1], light_dir[2]};
+    double nl = sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+    if (!(nl > 0.0) || !(a0 >= 0.0 && a0 <= 1.0)) return -1;
+    l[0] = l[0] / nl; l[1] = l[1] / nl; l[2] = l[2] / nl;
+    double LO[3], HI[3];
+    tets_box(n, parts, LO, HI);
+    int64_t npx = pix ? npix : (int64_t)cam->width * cam->height;
+    int64_t held = 0, twice = 0, shadow = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : held, twice, shadow)
+    for (int64_t q = 0; q < npx; ++q) {
+        int32_t i = pix ? pix[2 * q] : (int32_t)(q % cam->width);
+        int32_t j = pix ? pix[2 * q + 1] : (int32_t)(q / cam->width);
+        double o[3], d[3];
+        oc_ray(cam, i, j, o, d);
+        double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
+        int64_t k0, k1;
+        if (n > 0 && sample_range(o, d, LO, HI, dt, &k0, &k1)) {
+            for (int64_t k = k0; k <= k1; ++k) {
+                double t = ((double)k + 0.5) * dt;
+                double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+                double v = 0.0;
+                int owners = tets_locate(n, parts, p, &v);
+                if (owners == 0) continue;
+                ++held;
+                if (owners > 1) ++twice;
+                double ev[4], phi; int32_t seg; int inside;
+                classify(tf, v, ev, &seg, &phi, &inside);
+                double alpha = 1.0 - exp(-tf->opacity_scale * ev[3] * dt);
+                double f = a0 + (1.0 - a0) * tets_shadow(n, parts, LO, HI, tf, dt, p, l, &shadow);
+                for (int c = 0; c < 3; ++c) C[c] += T * alpha * ev[c] * f;
+                T = T * (1.0 - alpha);
+            }
+        }
+        double A = 1.0 - T;
+        for (int c = 0; c < 3; ++c) rgba[4 * q + c] = C[c] + T * bg[c];
+        rgba[4 * q + 3] = A + T * bg[3];
+    }
+    if (counters) { counters[0] += held; counters[1] += twice; counters[2] += shadow; }
+    return 0;
 }
 
 /* -------------------------------------------------------------- composite */

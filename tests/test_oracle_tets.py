@@ -152,3 +152,50 @@ def test_mesh_generator_is_conforming():
     nx, ny, nz = CELLS
     boundary = 2 * 2 * (nx * ny + ny * nz + nx * nz)
     assert np.sum(counts == 1) == boundary and np.all(counts <= 2)
+
+
+# ---------------------------------------------------------------- shadows
+def _brick_shadowed_image(cam, cells, dt, light, a0, bg):
+    tf, vr, s = _tf()
+    b = (_brick_of_linear(cells), cells, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    rgba, _, cnt = oracle.render_brick_shadowed(cam, b, [b], tf, vr, s, dt, light, a0)
+    a = rgba[..., 3:4]
+    return rgba + (1.0 - a) * np.asarray(bg), int(cnt[0])
+
+
+@pytest.mark.parametrize("jitter,seed,light,a0", [(0.0, 11, (0.3, 1.0, -0.5), 0.2),
+                                                  (0.2, 12, (-1.0, 0.0, 0.0), 0.0),
+                                                  (0.15, 13, (0.0, -0.4, 1.0), 0.6)])
+def test_shadowed_linear_field_equals_shadowed_brick(jitter, seed, light, a0):
+    """The shadow rays' samples are lattice points of the box like the
+    primary ones, so on a mesh of the box they are the brick's samples."""
+    cam = synth.orbit_camera((0, 0, 0), CELLS, 18, 14, az_deg=25.0, el_deg=30.0, radius_factor=1.6)
+    bg = (0.05, 0.0, 0.1, 0.3)
+    tf, vr, s = _tf()
+    img, cnt = oracle.render_tets_shadowed(cam, _mesh_parts(jitter, seed, 1), tf, vr, s, 0.41, light, a0, bg)
+    ref, nref = _brick_shadowed_image(cam, CELLS, 0.41, light, a0, bg)
+    assert cnt[1] == 0 and cnt[0] == nref and cnt[2] > 0
+    np.testing.assert_allclose(img, ref, rtol=0, atol=1e-11)
+
+
+def test_shadowed_ambient_one_is_unshadowed_bitwise():
+    cam = synth.orbit_camera((0, 0, 0), CELLS, 16, 12, az_deg=-35.0, el_deg=15.0, radius_factor=1.5)
+    parts = _mesh_parts(0.2, 14, 1)
+    tf, vr, s = _tf()
+    img, _ = oracle.render_tets_shadowed(cam, parts, tf, vr, s, 0.37, (1.0, 2.0, 0.5), 1.0)
+    ref, _ = oracle.render_tets(cam, parts, tf, vr, s, 0.37)
+    assert np.array_equal(img, ref)
+
+
+def test_shadowed_split_into_parts_is_invariant():
+    cam = synth.orbit_camera((0, 0, 0), CELLS, 16, 14, az_deg=50.0, el_deg=-20.0, radius_factor=1.5)
+    rng = np.random.default_rng(15)
+    v, t = synth.tet_mesh(CELLS, jitter=0.2, rng=rng)
+    vals = synth.tet_field(v, rng, CELLS)
+    tf, vr, s = _tf()
+    whole, c1 = oracle.render_tets_shadowed(cam, [(v, vals, t)], tf, vr, s, 0.33, (0.5, 1.0, 0.2), 0.25)
+    parts = [(pv, vals[used], pt) for pv, pt, used in synth.tet_partitions(v, t, 5, rng, rough=True)]
+    split, c2 = oracle.render_tets_shadowed(cam, parts, tf, vr, s, 0.33, (0.5, 1.0, 0.2), 0.25)
+    assert np.array_equal(whole, split) and np.array_equal(c1, c2)
+    with pytest.raises(ValueError):
+        oracle.render_tets_shadowed(cam, parts, tf, vr, s, 0.33, (0.0, 0.0, 0.0), 0.25)
