@@ -688,6 +688,41 @@ vr_status vr_march_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, 
 vr_status vr_resolve_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
                               void* workspace, size_t workspace_bytes, float* out);
 
+/* Shadow rays through tetrahedral parts (paper Fig. 2: the hit lies in one
+ * rank's elements, its occluder in another's, so the shadow ray must visit
+ * every rank; Sec. 2.2).  One directional light as for vr_render_rqc: every
+ * held primary sample's emitted colour is scaled by ambient + (1 - ambient)
+ * S, S the transmittance of its shadow ray (samples p + (j + 1/2) dt l,
+ * j >= 0, each located in the parts as a primary sample); alpha and T are
+ * unchanged.  The shadow rays are queued per part and cycled: in step s the
+ * queue of part h is traced through part (h + s) mod n.
+ *
+ * vr_tetparts_shadow_plan_size: bytes of the plan buffer for these parts and
+ * the context camera (one slot offset per ROI pixel of every part).
+ * vr_tetparts_shadow_plan: counts every ray's held samples per part (one
+ * march without shading into the plan; workspace as for vr_render_tetparts)
+ * and gives each a slot (device scan), then synchronises the context stream
+ * and returns the slot count; depends on geometry, camera and dt only.
+ * vr_tetparts_slot_bytes: bytes of the slot buffer for that count (a sample
+ * index and a transmittance per slot).
+ * vr_render_tetparts_shadowed: the frame of the last plan (same plan buffer,
+ * parts, camera and dt, else VR_ERR_STATE): records the slots' sample
+ * indices, runs n shadow cycle steps, marches the shaded runs and resolves
+ * them into out over bg.  plan, slots: device, 256-byte aligned, kept by the
+ * caller; samples (optional) counts primary and shadow samples held.
+ * Errors: as vr_render_tetparts, VR_ERR_WORKSPACE for a short plan or slot
+ * buffer, VR_ERR_INVALID_ARG for a zero or non-finite light direction or an
+ * ambient outside [0, 1]. */
+vr_status vr_tetparts_shadow_plan_size(vr_context ctx, int32_t n, const vr_tetpart* parts, size_t* bytes);
+vr_status vr_tetparts_shadow_plan(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs,
+                                  void* workspace, size_t workspace_bytes, void* plan, size_t plan_bytes,
+                                  int64_t* total_samples);
+vr_status vr_tetparts_slot_bytes(int64_t total_samples, size_t* bytes);
+vr_status vr_render_tetparts_shadowed(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs,
+                                      const vr_light* light, const float bg[4], void* workspace,
+                                      size_t workspace_bytes, void* plan, size_t plan_bytes, void* slots,
+                                      size_t slot_bytes, float* out, unsigned long long* samples);
+
 #ifdef __cplusplus
 }
 #endif

@@ -168,6 +168,13 @@ _SIGS = {
                            C.c_void_p], _st),
     "vr_resolve_tetparts": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, _f4, C.c_void_p, C.c_size_t,
                              C.c_void_p], _st),
+    "vr_tetparts_shadow_plan_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)], _st),
+    "vr_tetparts_shadow_plan": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t,
+                                 C.c_void_p, C.c_size_t, C.POINTER(C.c_int64)], _st),
+    "vr_tetparts_slot_bytes": ([C.c_int64, C.POINTER(C.c_size_t)], _st),
+    "vr_render_tetparts_shadowed": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(vr_light),
+                                     _f4, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
+                                     C.c_void_p, C.c_void_p], _st),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -456,6 +463,38 @@ def vr_resolve_tetparts(ctx, parts, max_runs, bg, workspace, workspace_bytes, ou
                                     int(workspace_bytes), _ptr(out)), ctx)
 
 
+def _parts_array(parts):
+    return (C.c_void_p * len(parts))(*[p.value if isinstance(p, C.c_void_p) else p for p in parts])
+
+
+def vr_tetparts_shadow_plan_size(ctx, parts):
+    b = C.c_size_t()
+    _check(_lib.vr_tetparts_shadow_plan_size(ctx, len(parts), _parts_array(parts), C.byref(b)), ctx)
+    return b.value
+
+
+def vr_tetparts_shadow_plan(ctx, parts, max_runs, workspace, workspace_bytes, plan, plan_bytes):
+    total = C.c_int64()
+    _check(_lib.vr_tetparts_shadow_plan(ctx, len(parts), _parts_array(parts), int(max_runs), _ptr(workspace),
+                                        int(workspace_bytes), _ptr(plan), int(plan_bytes), C.byref(total)), ctx)
+    return total.value
+
+
+def vr_tetparts_slot_bytes(total):
+    b = C.c_size_t()
+    _check(_lib.vr_tetparts_slot_bytes(int(total), C.byref(b)))
+    return b.value
+
+
+def vr_render_tetparts_shadowed(ctx, parts, max_runs, light_dir, ambient, bg, workspace, workspace_bytes, plan,
+                                plan_bytes, slots, slot_bytes, out, samples=None):
+    lt = vr_light((C.c_double * 3)(*[float(x) for x in light_dir]), float(ambient), 0)
+    _check(_lib.vr_render_tetparts_shadowed(ctx, len(parts), _parts_array(parts), int(max_runs), C.byref(lt),
+                                            _f4(*bg), _ptr(workspace), int(workspace_bytes), _ptr(plan),
+                                            int(plan_bytes), _ptr(slots), int(slot_bytes), _ptr(out),
+                                            _ptr(samples)), ctx)
+
+
 def vr_set_march_path(ctx, path):
     _check(_lib.vr_set_march_path(ctx, int(path)), ctx)
 
@@ -647,6 +686,30 @@ class TetRenderer:
     def resolve(self, bg=(0.0, 0.0, 0.0, 0.0)):
         """The resolve stage alone (after :meth:`march`)."""
         vr_resolve_tetparts(self.ctx, self.parts, self.max_runs, bg, self._base(), self._fws_bytes, self.frame)
+        return self.frame
+
+    def shadow_plan(self):
+        """Plan the shadow rays of the current camera (plan and slot buffers
+        allocated here; synchronises); returns the number of slots."""
+        torch = self.torch
+        pb = vr_tetparts_shadow_plan_size(self.ctx, self.parts)
+        plan = torch.empty(pb // 4 + 64, dtype=torch.float32, device=self.device)
+        pbase = plan.data_ptr() + ((-plan.data_ptr()) % 256)
+        total = vr_tetparts_shadow_plan(self.ctx, self.parts, self.max_runs, self._base(), self._fws_bytes, pbase,
+                                        pb)
+        sb = vr_tetparts_slot_bytes(total)
+        slots = torch.empty(sb // 4 + 64, dtype=torch.float32, device=self.device)
+        sbase = slots.data_ptr() + ((-slots.data_ptr()) % 256)
+        self._shadow = (plan, pbase, pb, slots, sbase, sb)
+        return total
+
+    def render_shadowed(self, light_dir, ambient, bg=(0.0, 0.0, 0.0, 0.0), count=False):
+        """The frame with one directional light (plan first with
+        :meth:`shadow_plan`)."""
+        _, pbase, pb, _, sbase, sb = self._shadow
+        vr_render_tetparts_shadowed(self.ctx, self.parts, self.max_runs, light_dir, ambient, bg, self._base(),
+                                    self._fws_bytes, pbase, pb, sbase, sb, self.frame,
+                                    self.samples if count else None)
         return self.frame
 
     def synchronize(self):

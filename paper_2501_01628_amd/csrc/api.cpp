@@ -73,6 +73,15 @@ struct vr_context_s {
         double dt = 0.0;
         long long entries = 0, total = -1;
     } rqc;
+    // the last vr_tetparts_shadow_plan: its plan buffer, parts, camera,
+    // spacing, entries and slots (vr_render_tetparts_shadowed must match it)
+    struct {
+        const void* plan = nullptr;
+        std::vector<const void*> parts;
+        CameraK cam{};
+        double dt = 0.0;
+        long long entries = 0, total = -1;
+    } tetplan;
     // the last vr_march_tetparts / vr_render_tetparts: workspace, parts,
     // max_runs and camera (vr_resolve_tetparts must match them)
     struct {
@@ -1733,10 +1742,11 @@ size_t tetpart_layout(const TetTables& t, size_t off[7]) {
 // part [run counts][run keys x max_runs][run colours x max_runs] over its ROI,
 // each 256-aligned; ROIs from the context camera.
 size_t tetframe_layout(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs,
-                       std::vector<TetPartK>* jobs, std::vector<int32_t>* prefix) {
+                       std::vector<TetPartK>* jobs, std::vector<int32_t>* prefix, long long* entries = nullptr) {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     size_t o = up((size_t)n * sizeof(TetPartK)) + up((size_t)(n + 1) * sizeof(int32_t));
     int32_t tiles = 0;
+    long long E = 0;
     for (int i = 0; i < n; ++i) {
         const TetTables& t = parts[i]->tab;
         int32_t roi[4] = {0, 0, 0, 0};
@@ -1763,6 +1773,7 @@ size_t tetframe_layout(vr_context ctx, int32_t n, const vr_tetpart* parts, int32
             k.roi_y0 = roi[1];
             k.roi_w = roi[2];
             k.roi_h = roi[3];
+            k.entry0 = E;
             // run buffers: offsets now, device addresses once the workspace is known
             k.rcount = reinterpret_cast<int32_t*>(o);
             k.rkey = reinterpret_cast<int32_t*>(o + up(np * sizeof(int32_t)));
@@ -1771,14 +1782,33 @@ size_t tetframe_layout(vr_context ctx, int32_t n, const vr_tetpart* parts, int32
             prefix->push_back(tiles);
         }
         tiles += tet_tiles(roi[2], roi[3]);
+        E += (long long)np;
         o += up(np * sizeof(int32_t)) + up(np * max_runs * sizeof(int32_t)) + up(np * max_runs * 4 * sizeof(float));
     }
     if (prefix) prefix->push_back(tiles);
+    if (entries) *entries = E;
     return o;
 }
 
+// Shadow plan of a tetrahedral frame: [offsets int64 x (E + 1)][scan block
+// sums int64], each 256-aligned; E = the parts' ROI pixels.
+size_t tetplan_layout(long long E, size_t* off_sums) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t a = up((size_t)(E + 1) * sizeof(long long));
+    if (off_sums) *off_sums = a;
+    return a + up((size_t)(scan_blocks(E) + 1) * sizeof(long long));
+}
+
+// Slots of a shadowed tetrahedral frame: [sample index int32 x total][shadow
+// transmittance float x total], the second 256-aligned.
+size_t tetslot_bytes(long long total, size_t* off_shade) {
+    const size_t a = ((size_t)total * sizeof(int32_t) + 255) / 256 * 256;
+    if (off_shade) *off_shade = a;
+    return a + (size_t)total * sizeof(float);
+}
+
 vr_status tetparts_check(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const char* who,
-                         bool need_values) {
+                         bool need_values, bool need_tables = false) {
     if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
     if (n < 1 || n > kMaxTetParts || !parts)
         return fail(ctx, VR_ERR_INVALID_ARG, "%s: n = %d outside [1, %d] or NULL parts", who, n, kMaxTetParts);
@@ -1790,6 +1820,7 @@ vr_status tetparts_check(vr_context ctx, int32_t n, const vr_tetpart* parts, int
         if (!live(q) || q->ctx != ctx) return fail(ctx, VR_ERR_INVALID_HANDLE, "%s: invalid part %d", who, i);
         if (need_values && (!q->ws || !q->has_values))
             return fail(ctx, VR_ERR_STATE, "%s: part %d has no workspace or no vertex values", who, i);
+        if (need_tables && !q->ws) return fail(ctx, VR_ERR_STATE, "%s: part %d has no workspace", who, i);
         for (int j = 0; j < i; ++j)
             if (parts[j] == q) return fail(ctx, VR_ERR_INVALID_ARG, "%s: part %d repeats part %d", who, i, j);
     }
@@ -1933,21 +1964,35 @@ vr_status vr_tetparts_workspace_size(vr_context ctx, int32_t n, const vr_tetpart
     return ok(ctx);
 }
 
-// The frame of n parts, stages 1 (march into the workspace's run buffers),
-// 2 (resolve them into out) or both.
+// Shadow inputs of a tetrahedral frame: the plan call fills the plan and
+// reports the slot count; the shadowed render reads the plan and uses the
+// slots.
+struct TetShadowArgs {
+    void* plan = nullptr;
+    size_t plan_bytes = 0;
+    void* slots = nullptr;
+    size_t slot_bytes = 0;
+    const vr_light* light = nullptr;
+    int64_t* total_out = nullptr;
+};
+
+// The frame of n parts, `stages` a mask of the kTet* stages (march into the
+// workspace's run buffers, resolve into out; with `sh`: count + scan into
+// the plan, or record + shadow steps + shaded march).
 static vr_status tet_frame(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
                            void* workspace, size_t workspace_bytes, float* out, unsigned long long* samples,
-                           int stages, const char* who) {
-    vr_status st = tetparts_check(ctx, n, parts, max_runs, who, stages & 1);
+                           int stages, const char* who, const TetShadowArgs* sh = nullptr) {
+    const bool shading = stages & (kTetMarch | kTetShadow | kTetShaded);
+    vr_status st = tetparts_check(ctx, n, parts, max_runs, who, shading, true);
     if (st != VR_OK) return st;
-    if ((stages & 1) && !ctx->has_tf) return fail(ctx, VR_ERR_STATE, "%s: no transfer function set", who);
-    if ((stages & 2) && (!bg || !out)) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
-    if (stages & 2)
+    if (shading && !ctx->has_tf) return fail(ctx, VR_ERR_STATE, "%s: no transfer function set", who);
+    if ((stages & kTetResolve) && (!bg || !out)) return fail(ctx, VR_ERR_INVALID_ARG, "%s: NULL argument", who);
+    if (stages & kTetResolve)
         for (int c = 0; c < 4; ++c)
             if (!std::isfinite(bg[c])) return fail(ctx, VR_ERR_INVALID_ARG, "%s: background not finite", who);
     if ((reinterpret_cast<uintptr_t>(out) & 15) != 0 || (reinterpret_cast<uintptr_t>(samples) & 7) != 0)
         return fail(ctx, VR_ERR_INVALID_ARG, "%s: out must be 16-, samples 8-byte aligned", who);
-    if (stages == 2) {
+    if (stages == kTetResolve) {
         const auto& lm = ctx->tetmarch;
         if (lm.ws != workspace || lm.max_runs != max_runs || (int32_t)lm.parts.size() != n ||
             !std::equal(lm.parts.begin(), lm.parts.end(), parts) || std::memcmp(&lm.cam, &ctx->cam, sizeof(CameraK)))
@@ -1957,16 +2002,51 @@ static vr_status tet_frame(vr_context ctx, int32_t n, const vr_tetpart* parts, i
     std::vector<TetPartK> jobs;
     std::vector<int32_t> prefix;
     size_t need = 0;
+    long long E = 0;
     try {
         jobs.reserve(n);
         prefix.reserve(n + 1);
-        need = tetframe_layout(ctx, n, parts, max_runs, &jobs, &prefix);
+        need = tetframe_layout(ctx, n, parts, max_runs, &jobs, &prefix, &E);
     } catch (const std::bad_alloc&) {
         return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
     }
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(ctx, VR_ERR_WORKSPACE, "%s: workspace of %zu bytes (256-aligned), need %zu", who,
                     workspace_bytes, need);
+    TetFrameParams f{};
+    if (sh) {
+        size_t off_sums = 0;
+        const size_t pneed = tetplan_layout(E, &off_sums);
+        if (!sh->plan || sh->plan_bytes < pneed || (reinterpret_cast<uintptr_t>(sh->plan) & 255) != 0)
+            return fail(ctx, VR_ERR_WORKSPACE, "%s: plan of %zu bytes (256-aligned), need %zu", who, sh->plan_bytes,
+                        pneed);
+        f.offsets = reinterpret_cast<long long*>(sh->plan);
+        f.n_entries = E;
+        if (stages & kTetRecord) {
+            const auto& pl = ctx->tetplan;
+            if (pl.plan != sh->plan || pl.total < 0 || (int32_t)pl.parts.size() != n ||
+                !std::equal(pl.parts.begin(), pl.parts.end(), parts) ||
+                std::memcmp(&pl.cam, &ctx->cam, sizeof(CameraK)) != 0 || pl.dt != ctx->dt || pl.entries != E)
+                return fail(ctx, VR_ERR_STATE, "%s: no vr_tetparts_shadow_plan of this plan for these parts, camera "
+                            "and spacing", who);
+            if (!sh->light) return fail(ctx, VR_ERR_INVALID_ARG, "%s: light is NULL", who);
+            const double* L = sh->light->direction;
+            const double ln = std::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+            if (!finite3(L) || !(ln > 0.0) || !(sh->light->ambient >= 0.0f && sh->light->ambient <= 1.0f))
+                return fail(ctx, VR_ERR_INVALID_ARG, "%s: light direction must be finite and non-zero, ambient in "
+                            "[0, 1]", who);
+            size_t off_shade = 0;
+            const size_t sneed = tetslot_bytes(pl.total, &off_shade);
+            if (pl.total > 0 && (!sh->slots || sh->slot_bytes < sneed || (reinterpret_cast<uintptr_t>(sh->slots) & 255)))
+                return fail(ctx, VR_ERR_WORKSPACE, "%s: slots of %zu bytes (256-aligned), need %zu", who,
+                            sh->slot_bytes, sneed);
+            f.total = pl.total;
+            f.slot_k = reinterpret_cast<int32_t*>(sh->slots);
+            f.shade = sh->slots ? reinterpret_cast<float*>(reinterpret_cast<char*>(sh->slots) + off_shade) : nullptr;
+            for (int c = 0; c < 3; ++c) f.light[c] = L[c] / ln;
+            f.ambient = sh->light->ambient;
+        }
+    }
     char* ws = reinterpret_cast<char*>(workspace);
     for (auto& k : jobs) {
         k.rcount = reinterpret_cast<int32_t*>(ws + reinterpret_cast<uintptr_t>(k.rcount));
@@ -1982,7 +2062,6 @@ static vr_status tet_frame(vr_context ctx, int32_t n, const vr_tetpart* parts, i
     }
     std::memcpy(tables.data(), jobs.data(), (size_t)n * sizeof(TetPartK));
     std::memcpy(tables.data() + jb, prefix.data(), (size_t)(n + 1) * sizeof(int32_t));
-    TetFrameParams f{};
     f.cam = ctx->cam;
     f.tf = ctx->tf;
     f.dt = ctx->dt;
@@ -2000,13 +2079,38 @@ static vr_status tet_frame(vr_context ctx, int32_t n, const vr_tetpart* parts, i
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
     hipError_t e = hipSuccess;
-    if (stages & 1) {
+    if (stages != kTetResolve) {
         e = stage_copy(ctx, ws, tables.data(), tables.size());
         if (e == hipErrorOutOfMemory) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: pinned staging", who);
     }
     if (e == hipSuccess) e = launch_tet_frame(f, stages, ctx->stream);
+    if (stages & kTetCount) {
+        // the plan: scan the counts into slots, then read the total back
+        size_t off_sums = 0;
+        (void)tetplan_layout(E, &off_sums);
+        long long total = 0;
+        if (e == hipSuccess && E > 0)
+            e = launch_exclusive_scan(f.offsets, E, reinterpret_cast<long long*>(reinterpret_cast<char*>(sh->plan) +
+                                                                                   off_sums), ctx->stream);
+        if (e == hipSuccess && E > 0)
+            e = hipMemcpyAsync(&total, f.offsets + E, sizeof(long long), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+        try {
+            ctx->tetplan.parts.assign(parts, parts + n);
+        } catch (const std::bad_alloc&) {
+            ctx->tetplan.plan = nullptr;
+            return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
+        }
+        ctx->tetplan.plan = sh->plan;
+        ctx->tetplan.cam = ctx->cam;
+        ctx->tetplan.dt = ctx->dt;
+        ctx->tetplan.entries = E;
+        ctx->tetplan.total = total;
+        *sh->total_out = total;
+    }
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
-    if (stages & 1) {
+    if (stages & (kTetMarch | kTetShaded)) {
         try {
             ctx->tetmarch.parts.assign(parts, parts + n);
         } catch (const std::bad_alloc&) {
@@ -2022,19 +2126,64 @@ static vr_status tet_frame(vr_context ctx, int32_t n, const vr_tetpart* parts, i
 
 vr_status vr_render_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
                              void* workspace, size_t workspace_bytes, float* out, unsigned long long* samples) {
-    return tet_frame(ctx, n, parts, max_runs, bg, workspace, workspace_bytes, out, samples, 3, "vr_render_tetparts");
+    return tet_frame(ctx, n, parts, max_runs, bg, workspace, workspace_bytes, out, samples, kTetMarch | kTetResolve,
+                     "vr_render_tetparts");
 }
 
 vr_status vr_march_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, void* workspace,
                             size_t workspace_bytes, unsigned long long* samples) {
-    return tet_frame(ctx, n, parts, max_runs, nullptr, workspace, workspace_bytes, nullptr, samples, 1,
+    return tet_frame(ctx, n, parts, max_runs, nullptr, workspace, workspace_bytes, nullptr, samples, kTetMarch,
                      "vr_march_tetparts");
 }
 
 vr_status vr_resolve_tetparts(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs, const float bg[4],
                               void* workspace, size_t workspace_bytes, float* out) {
-    return tet_frame(ctx, n, parts, max_runs, bg, workspace, workspace_bytes, out, nullptr, 2,
+    return tet_frame(ctx, n, parts, max_runs, bg, workspace, workspace_bytes, out, nullptr, kTetResolve,
                      "vr_resolve_tetparts");
+}
+
+vr_status vr_tetparts_shadow_plan_size(vr_context ctx, int32_t n, const vr_tetpart* parts, size_t* bytes) {
+    static const char* who = "vr_tetparts_shadow_plan_size";
+    vr_status st = tetparts_check(ctx, n, parts, 1, who, false);
+    if (st != VR_OK) return st;
+    if (!bytes) return fail(ctx, VR_ERR_INVALID_ARG, "%s: bytes is NULL", who);
+    long long E = 0;
+    (void)tetframe_layout(ctx, n, parts, 1, nullptr, nullptr, &E);
+    *bytes = tetplan_layout(E, nullptr);
+    return ok(ctx);
+}
+
+vr_status vr_tetparts_shadow_plan(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs,
+                                  void* workspace, size_t workspace_bytes, void* plan, size_t plan_bytes,
+                                  int64_t* total_samples) {
+    static const char* who = "vr_tetparts_shadow_plan";
+    if (!total_samples) return fail(live(ctx) ? ctx : nullptr, VR_ERR_INVALID_ARG, "%s: total_samples is NULL", who);
+    TetShadowArgs sh;
+    sh.plan = plan;
+    sh.plan_bytes = plan_bytes;
+    sh.total_out = total_samples;
+    return tet_frame(ctx, n, parts, max_runs, nullptr, workspace, workspace_bytes, nullptr, nullptr, kTetCount, who,
+                     &sh);
+}
+
+vr_status vr_render_tetparts_shadowed(vr_context ctx, int32_t n, const vr_tetpart* parts, int32_t max_runs,
+                                      const vr_light* light, const float bg[4], void* workspace,
+                                      size_t workspace_bytes, void* plan, size_t plan_bytes, void* slots,
+                                      size_t slot_bytes, float* out, unsigned long long* samples) {
+    TetShadowArgs sh;
+    sh.plan = plan;
+    sh.plan_bytes = plan_bytes;
+    sh.slots = slots;
+    sh.slot_bytes = slot_bytes;
+    sh.light = light;
+    return tet_frame(ctx, n, parts, max_runs, bg, workspace, workspace_bytes, out, samples,
+                     kTetRecord | kTetShadow | kTetShaded | kTetResolve, "vr_render_tetparts_shadowed", &sh);
+}
+
+vr_status vr_tetparts_slot_bytes(int64_t total_samples, size_t* bytes) {
+    if (total_samples < 0 || !bytes) return fail(nullptr, VR_ERR_INVALID_ARG, "vr_tetparts_slot_bytes: bad argument");
+    *bytes = tetslot_bytes(total_samples, nullptr);
+    return VR_OK;
 }
 
 // ---------------------------------------------------------------- batches

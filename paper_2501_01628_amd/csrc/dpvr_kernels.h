@@ -253,6 +253,7 @@ struct TetPartK {
     int32_t gdim[3];
     int32_t n_tets;
     int32_t roi_x0, roi_y0, roi_w, roi_h;
+    long long entry0;           // first frame entry of the part (its ROI pixels, row-major, after the previous parts')
     int32_t* rcount;            // roi_h x roi_w: runs of the pixel's ray
     int32_t* rkey;              // max_runs x roi_h x roi_w: first sample index of each run
     float* rcol;                // max_runs x roi_h x roi_w x 4: premultiplied colour, alpha of each run
@@ -268,9 +269,24 @@ struct TetFrameParams {
     int32_t width, height;
     float bg[4];
     float* out;                 // height x width x 4
-    unsigned long long* samples;  // optional: += samples held by a tetrahedron
+    unsigned long long* samples;  // optional: += samples held by a tetrahedron (primary and shadow)
     int32_t* err;               // device error word
+    // shadow rays (one directional light): per frame entry the first slot of
+    // its held primary samples (offsets[n_entries] = total), per slot the
+    // sample index and the shadow transmittance
+    long long n_entries, total;
+    long long* offsets;
+    int32_t* slot_k;
+    float* shade;
+    double light[3];            // unit direction toward the light
+    float ambient;              // a0: emission scaled by a0 + (1 - a0) S
+    int32_t step;               // cycle step of a shadow launch
 };
+
+// Stages of a tetrahedral frame (bit mask): the plain march into runs, the
+// resolve; with shadows: count the held samples per entry, record their
+// sample indices, the shadow cycle steps, the shaded march into runs.
+enum : int { kTetMarch = 1, kTetResolve = 2, kTetCount = 4, kTetRecord = 8, kTetShadow = 16, kTetShaded = 32 };
 
 constexpr int32_t kErrRuns = 4;   // a ray crossed a part in more than max_runs runs
 
@@ -282,7 +298,10 @@ inline int32_t tet_tiles(int32_t w, int32_t h) {
 }
 hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, int32_t n_tets, float* vals,
                              hipStream_t stream);
-// stages: 1 = march (runs), 2 = resolve (frame), 3 = both
-hipError_t launch_tet_frame(const TetFrameParams& p, int stages, hipStream_t stream);
+// stages: a mask of the kTet* stages above, run in the order listed there
+hipError_t launch_tet_frame(TetFrameParams p, int stages, hipStream_t stream);
+// Exclusive scan of v[0 .. n) in place, v[n] = total (sums: scan_blocks(n) + 1 entries).
+hipError_t launch_exclusive_scan(long long* v, long long n, long long* sums, hipStream_t stream);
+long long scan_blocks(long long n);
 
 }  // namespace dpvr

@@ -318,17 +318,25 @@ inline int grid_for(long long n, int per) { return (int)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t launch_rqc_plan(const RqcParams& p, long long* scan_sums_buf, long long* total, hipStream_t stream) {
-    if (p.n_entries <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rqc_count, dim3(grid_for(p.n_entries, 256)), dim3(256), 0, stream, p);
-    const long long nb = (p.n_entries + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(scan_blocks, dim3((unsigned)nb), dim3(256), 0, stream, p.offsets, p.n_entries, scan_sums_buf);
-    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(256), 0, stream, scan_sums_buf, nb, total);
-    hipLaunchKernelGGL(scan_add, dim3((unsigned)nb), dim3(256), 0, stream, p.offsets, p.n_entries, scan_sums_buf);
+hipError_t launch_exclusive_scan(long long* v, long long n, long long* sums, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(scan_blocks, dim3((unsigned)nb), dim3(256), 0, stream, v, n, sums);
+    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(256), 0, stream, sums, nb, v + n);
+    hipLaunchKernelGGL(scan_add, dim3((unsigned)nb), dim3(256), 0, stream, v, n, sums);
     return hipGetLastError();
 }
 
-long long rqc_scan_blocks(long long n_entries) { return (n_entries + kScanBlock - 1) / kScanBlock; }
+long long scan_blocks(long long n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_rqc_plan(const RqcParams& p, long long* scan_sums_buf, long long* total, hipStream_t stream) {
+    if (p.n_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rqc_count, dim3(grid_for(p.n_entries, 256)), dim3(256), 0, stream, p);
+    (void)total;   // the scan leaves the total in p.offsets[n_entries]
+    return launch_exclusive_scan(p.offsets, p.n_entries, scan_sums_buf, stream);
+}
+
+long long rqc_scan_blocks(long long n_entries) { return scan_blocks(n_entries); }
 
 hipError_t launch_rqc_frame(RqcParams p, int cus, hipStream_t stream) {
     const long long npx = (long long)p.width * p.height;

@@ -22,6 +22,11 @@
 //   resolve   per pixel, the runs of all parts in sample-index order with
 //             "over", then the background.  Runs of different parts never
 //             share a sample, so this equals accumulating the whole ray.
+// With one directional light, before the march: a count pass (held samples
+// per ROI pixel of every part), an exclusive scan (a slot per held sample), a
+// record pass (each slot's sample index), then n cycle steps in which every
+// slot's shadow ray visits part (home + s) mod n, and the march scales each
+// held sample's emission by a0 + (1 - a0) S from its slot.
 // Locations use float64 with contraction off (the planes come from the host
 // in float64), so the owner of a sample does not depend on the launch.
 #include "march_common.h"
@@ -94,12 +99,60 @@ __device__ inline void count_held(unsigned long long* counter, unsigned long lon
     if ((threadIdx.x & 63) == 0 && n) atomicAdd(counter, n);
 }
 
+// The tetrahedron of part P that holds p (-1: none): one candidate per loop
+// trip, so that the lanes of a wavefront stay on the same code -- first the
+// walk from tetrahedron `from` (kWalkSteps tests, across the first face that
+// rejects p), then the tetrahedra of p's grid cell.  D: its sub-volumes.
+__device__ inline int locate(const TetPartK& P, int from, double p0, double p1, double p2, double D[4]) {
+#pragma clang fp contract(off)
+    int cand = from, face = 0, walk = kWalkSteps, q = 0, qend = 0;
+    bool grid = false;
+    for (;;) {
+        if (cand < 0) {
+            if (!grid) {
+                grid = true;
+                const double u0 = (p0 - P.glo[0]) * P.ginv[0], u1 = (p1 - P.glo[1]) * P.ginv[1],
+                             u2 = (p2 - P.glo[2]) * P.ginv[2];
+                if (u0 >= 0.0 && u1 >= 0.0 && u2 >= 0.0 && u0 < (double)P.gdim[0] && u1 < (double)P.gdim[1] &&
+                    u2 < (double)P.gdim[2]) {
+                    const long long cell = ((long long)(int)u2 * P.gdim[1] + (int)u1) * P.gdim[0] + (int)u0;
+                    q = ((gint*)P.cell_start)[cell];
+                    qend = ((gint*)P.cell_start)[cell + 1];
+                }
+            }
+            if (q >= qend) return -1;
+            cand = ((gint*)P.cell_tets)[q++];
+        }
+        if (holds(P, cand, p0, p1, p2, D, &face)) return cand;
+        cand = !grid && --walk > 0 ? ((gint*)P.nbr)[4 * (long long)cand + face] : -1;
+    }
+}
+
+// Barycentric value of a point with sub-volumes D in tetrahedron e: the
+// weighted sum in float64, one float32 division (the value is classified in
+// float32).
+__device__ inline float tet_value(const TetPartK& P, int e, const double D[4]) {
+#pragma clang fp contract(off)
+    gfloat_t* vv = ((gfloat_t*)P.vals) + 4 * (long long)e;
+    const double s = ((D[0] + D[1]) + D[2]) + D[3];
+    const double num = ((D[0] * (double)vv[0] + D[1] * (double)vv[1]) + D[2] * (double)vv[2]) + D[3] * (double)vv[3];
+    return __fdividef((float)num, (float)s);
+}
+
 constexpr int kTetThreads = kTetTile * kTetTile;
 
+// The march of every part's ROI rays, in one of four modes: kTetMarch
+// (runs), kTetCount (held samples per frame entry into offsets), kTetRecord
+// (the sample index of every held sample into its slot) and kTetShaded (runs
+// with every held sample's emission scaled by a0 + (1 - a0) S from its slot).
+template <int kMode>
 __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
+    constexpr bool kRuns = kMode == kTetMarch || kMode == kTetShaded;
     __shared__ TFTable tft;
-    load_tf(tft, f.tf, f.dt, threadIdx.x, kTetThreads);
-    __syncthreads();
+    if (kRuns) {
+        load_tf(tft, f.tf, f.dt, threadIdx.x, kTetThreads);
+        __syncthreads();
+    }
     const int wg = blockIdx.x;
     int lo = 0, hi = f.n - 1;
     while (lo < hi) {
@@ -120,9 +173,10 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
     const long long li = (long long)ly * P.roi_w + lx;
     const float tf_k = 255.0f / (f.tf.vmax - f.tf.vmin);
     const float tf_o = -f.tf.vmin * tf_k;
+    const float a0 = f.ambient, a1 = 1.0f - f.ambient;
     unsigned long long held = 0;
     int nrun = 0;
-    long long k0 = 0, k1 = -1;
+    long long k0 = 0, k1 = -1, slot0 = 0;
     CamRay r{};
     if (live) {
         r = camera_ray(f.cam, P.roi_x0 + lx, P.roi_y0 + ly);
@@ -130,6 +184,7 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
             if (f.err) atomicOr(f.err, kErrRange);
             k1 = k0 - 1;
         }
+        if (kMode == kTetRecord || kMode == kTetShaded) slot0 = f.offsets[P.entry0 + li];
     }
     bool in_run = false, overflow = false;
     int key = 0, last = -1;
@@ -149,66 +204,104 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
 #pragma clang fp contract(off)
         const double t = ((double)k + 0.5) * f.dt;
         const double p0 = r.o[0] + t * r.d[0], p1 = r.o[1] + t * r.d[1], p2 = r.o[2] + t * r.d[2];
-        // One candidate per trip, so that the lanes of a wavefront stay on
-        // the same code: first the walk from the previous sample's
-        // tetrahedron (kWalkSteps tests), then the tetrahedra of the grid cell.
         double D[4];
-        int e = -1, cand = last, face = 0, walk = kWalkSteps, q = 0, qend = 0;
-        bool grid = false;
-        for (;;) {
-            if (cand < 0) {
-                if (!grid) {
-                    grid = true;
-                    const double u0 = (p0 - P.glo[0]) * P.ginv[0], u1 = (p1 - P.glo[1]) * P.ginv[1],
-                                 u2 = (p2 - P.glo[2]) * P.ginv[2];
-                    if (u0 >= 0.0 && u1 >= 0.0 && u2 >= 0.0 && u0 < (double)P.gdim[0] &&
-                        u1 < (double)P.gdim[1] && u2 < (double)P.gdim[2]) {
-                        const long long cell = ((long long)(int)u2 * P.gdim[1] + (int)u1) * P.gdim[0] + (int)u0;
-                        q = ((gint*)P.cell_start)[cell];
-                        qend = ((gint*)P.cell_start)[cell + 1];
-                    }
-                }
-                if (q >= qend) break;
-                cand = ((gint*)P.cell_tets)[q++];
-            }
-            if (holds(P, cand, p0, p1, p2, D, &face)) {
-                e = cand;
-                break;
-            }
-            cand = !grid && --walk > 0 ? ((gint*)P.nbr)[4 * (long long)cand + face] : -1;
-        }
+        const int e = locate(P, last, p0, p1, p2, D);
+        last = e;
         if (e < 0) {
-            last = -1;
-            if (in_run) close_run();
+            if (kRuns && in_run) close_run();
             continue;
         }
-        last = e;
-        gfloat_t* vv = ((gfloat_t*)P.vals) + 4 * (long long)e;
-        // barycentric value: the weighted sum in float64, one float32
-        // division (the value is classified in float32)
-        const double s = ((D[0] + D[1]) + D[2]) + D[3];
-        const double num = ((D[0] * (double)vv[0] + D[1] * (double)vv[1]) + D[2] * (double)vv[2]) +
-                           D[3] * (double)vv[3];
-        const float vd = __fdividef((float)num, (float)s);
+        if (kMode == kTetCount) {
+            ++held;
+            continue;
+        }
+        if (kMode == kTetRecord) {
+            f.slot_k[slot0 + (long long)held] = (int)k;
+            ++held;
+            continue;
+        }
         if (!in_run) {
             in_run = true;
             key = (int)k;
             C0 = C1 = C2 = 0.f;
             T = 1.f;
         }
-        const Classified c = classify(tft, vd, tf_k, tf_o);
+        const Classified c = classify(tft, tet_value(P, e, D), tf_k, tf_o);
+        float sh = 1.0f;
+        if (kMode == kTetShaded) sh = a0 + a1 * f.shade[slot0 + (long long)held];
         const float Tn = T * trans_exp2(-c.a);
         const float w = T - Tn;
-        C0 = fmaf(w, c.r, C0);
-        C1 = fmaf(w, c.g, C1);
-        C2 = fmaf(w, c.b, C2);
+        C0 = fmaf(w, c.r * sh, C0);
+        C1 = fmaf(w, c.g * sh, C1);
+        C2 = fmaf(w, c.b * sh, C2);
         T = Tn;
         ++held;
     }
+    if (kMode == kTetCount) {
+        if (live) f.offsets[P.entry0 + li] = (long long)held;
+        return;
+    }
+    if (kMode == kTetRecord) return;
     if (in_run) close_run();
     if (overflow && f.err) atomicOr(f.err, kErrRuns);
     if (live) P.rcount[li] = nrun;
     count_held(f.samples, held);
+}
+
+// Cycle step s of the shadow rays: the shadow ray of every held primary
+// sample (its slot) through part (home + s) mod n, home the part that holds
+// the sample; the slot's transmittance is multiplied by the part's (products
+// commute, so the visiting order does not matter to the value).
+__global__ __launch_bounds__(256) void tet_shadow_step(TetFrameParams f) {
+    __shared__ TFTable tft;
+    load_tf(tft, f.tf, f.dt, threadIdx.x, 256);
+    __syncthreads();
+    const float tf_k = 255.0f / (f.tf.vmax - f.tf.vmin);
+    const float tf_o = -f.tf.vmin * tf_k;
+    unsigned long long evaluated = 0;
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < f.total; q += (long long)gridDim.x * 256) {
+        // the slot's entry (largest e with offsets[e] <= q) and home part
+        long long elo = 0, ehi = f.n_entries - 1;
+        while (elo < ehi) {
+            const long long mid = (elo + ehi + 1) >> 1;
+            if (f.offsets[mid] <= q) elo = mid; else ehi = mid - 1;
+        }
+        int hlo = 0, hhi = f.n - 1;
+        while (hlo < hhi) {
+            const int mid = (hlo + hhi + 1) >> 1;
+            if (f.parts[mid].entry0 <= elo) hlo = mid; else hhi = mid - 1;
+        }
+        const TetPartK& home = f.parts[hlo];
+        const TetPartK& at = f.parts[(hlo + f.step) % f.n];
+        const long long r = elo - home.entry0;
+        const CamRay cr = camera_ray(f.cam, home.roi_x0 + (int)(r % home.roi_w), home.roi_y0 + (int)(r / home.roi_w));
+        CamRay sr;
+        {
+#pragma clang fp contract(off)
+            const double t = ((double)f.slot_k[q] + 0.5) * f.dt;
+            for (int a = 0; a < 3; ++a) {
+                sr.o[a] = cr.o[a] + t * cr.d[a];
+                sr.d[a] = f.light[a];
+            }
+        }
+        float S = 1.0f;
+        long long j0, j1;
+        if (at.n_tets > 0 && box_range(sr, at.lo, at.hi, f.dt, j0, j1)) {
+            int last = -1;
+            for (long long jj = j0; jj <= j1; ++jj) {
+#pragma clang fp contract(off)
+                const double t = ((double)jj + 0.5) * f.dt;
+                const double p0 = sr.o[0] + t * sr.d[0], p1 = sr.o[1] + t * sr.d[1], p2 = sr.o[2] + t * sr.d[2];
+                double D[4];
+                last = locate(at, last, p0, p1, p2, D);
+                if (last < 0) continue;
+                S = S * trans_exp2(-classify(tft, tet_value(at, last, D), tf_k, tf_o).a);
+                ++evaluated;
+            }
+        }
+        f.shade[q] = f.step == 0 ? S : f.shade[q] * S;
+    }
+    count_held(f.samples, evaluated);
 }
 
 // Per pixel: the runs of every part whose ROI holds the pixel, merged by
@@ -265,11 +358,24 @@ hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, in
     return hipGetLastError();
 }
 
-hipError_t launch_tet_frame(const TetFrameParams& p, int stages, hipStream_t stream) {
-    if ((stages & 1) && p.total_tiles > 0)
-        hipLaunchKernelGGL(tet_march, dim3(p.total_tiles), dim3(kTetThreads), 0, stream, p);
+hipError_t launch_tet_frame(TetFrameParams p, int stages, hipStream_t stream) {
+    const dim3 tiles(p.total_tiles), threads(kTetThreads);
+    if (p.total_tiles > 0) {
+        if (stages & kTetCount) hipLaunchKernelGGL(tet_march<kTetCount>, tiles, threads, 0, stream, p);
+        if (stages & kTetRecord) hipLaunchKernelGGL(tet_march<kTetRecord>, tiles, threads, 0, stream, p);
+        if ((stages & kTetShadow) && p.total > 0) {
+            const unsigned grid = (unsigned)min((p.total + 255) / 256, (long long)65536);
+            for (int s = 0; s < p.n; ++s) {
+                p.step = s;
+                hipLaunchKernelGGL(tet_shadow_step, dim3(grid), dim3(256), 0, stream, p);
+            }
+        }
+        if (stages & kTetMarch) hipLaunchKernelGGL(tet_march<kTetMarch>, tiles, threads, 0, stream, p);
+        if (stages & kTetShaded) hipLaunchKernelGGL(tet_march<kTetShaded>, tiles, threads, 0, stream, p);
+    }
     const long long npx = (long long)p.width * p.height;
-    if (stages & 2) hipLaunchKernelGGL(tet_resolve, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, stream, p);
+    if (stages & kTetResolve)
+        hipLaunchKernelGGL(tet_resolve, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 

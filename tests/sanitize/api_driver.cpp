@@ -264,6 +264,34 @@ int main() {
         EXPECT(vr_march_tetparts(ctx, 3, tp, 4, fw, fb, nullptr) == VR_OK);
         EXPECT(vr_resolve_tetparts(ctx, 3, tp, 2, bg, fw, fb, frame) == VR_ERR_STATE);   // other max_runs
         EXPECT(vr_resolve_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame) == VR_OK);
+        // shadow rays: plan, slots, render
+        size_t pb = 0, sb = 0;
+        int64_t total = -1;
+        EXPECT(vr_tetparts_shadow_plan_size(ctx, 3, tp, &pb) == VR_OK && pb > 0);
+        void* plan = aligned_buf(pb);
+        vr_light tl = {{0.2, 1.0, -0.3}, 0.25f, 0};
+        EXPECT(vr_render_tetparts_shadowed(ctx, 3, tp, 4, &tl, bg, fw, fb, plan, pb, nullptr, 0, frame, nullptr) ==
+               VR_ERR_STATE);   // no plan yet
+        EXPECT(vr_tetparts_shadow_plan(ctx, 3, tp, 4, fw, fb, plan, pb - 1, &total) == VR_ERR_WORKSPACE);
+        EXPECT(vr_tetparts_shadow_plan(ctx, 3, tp, 4, fw, fb, plan, pb, nullptr) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_tetparts_shadow_plan(ctx, 3, tp, 4, fw, fb, plan, pb, &total) == VR_OK && total >= 0);
+        EXPECT(vr_tetparts_slot_bytes(total, &sb) == VR_OK);
+        EXPECT(vr_tetparts_slot_bytes(-1, &sb) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_tetparts_slot_bytes(total, &sb) == VR_OK);
+        void* slots = aligned_buf(sb > 0 ? sb : 1);
+        if (total > 0)
+            EXPECT(vr_render_tetparts_shadowed(ctx, 3, tp, 4, &tl, bg, fw, fb, plan, pb, slots, sb - 1, frame,
+                                               nullptr) == VR_ERR_WORKSPACE);
+        EXPECT(vr_render_tetparts_shadowed(ctx, 3, tp, 4, &tl, bg, fw, fb, plan, pb, slots, sb, frame, nullptr) ==
+               VR_OK);
+        vr_light zero = {{0.0, 0.0, 0.0}, 0.5f, 0};
+        EXPECT(vr_render_tetparts_shadowed(ctx, 3, tp, 4, &zero, bg, fw, fb, plan, pb, slots, sb, frame, nullptr) ==
+               VR_ERR_INVALID_ARG);
+        EXPECT(vr_render_tetparts_shadowed(ctx, 2, tp, 4, &tl, bg, fw, fb, plan, pb, slots, sb, frame, nullptr) ==
+               VR_ERR_STATE);   // other parts than planned
+        EXPECT(vr_resolve_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame) == VR_OK);   // the shaded march counts
+        std::free(plan);
+        std::free(slots);
         EXPECT(frame[0] == bg[0] && frame[3] == bg[3]);
         EXPECT(vr_context_release(ctx) == VR_ERR_STATE);     // parts still live
         for (int q = 0; q < 3; ++q) EXPECT(vr_tetpart_release(tp[q]) == VR_OK);

@@ -99,7 +99,27 @@ hipError_t launch_tet_values(const float* vv, const int32_t* tets, int32_t n, fl
         for (int j = 0; j < 4; ++j) vals[4 * e + j] = vv[tets[4 * e + j]];
     return hipSuccess;
 }
-hipError_t launch_tet_frame(const TetFrameParams& f, int stages, hipStream_t) {
+long long scan_blocks(long long n) { return (n + 1023) / 1024; }
+hipError_t launch_exclusive_scan(long long* v, long long n, long long* sums, hipStream_t) {
+    long long acc = 0;
+    for (long long i = 0; i < n; ++i) {
+        const long long x = v[i];
+        v[i] = acc;
+        acc += x;
+    }
+    v[n] = acc;
+    for (long long b = 0; b <= scan_blocks(n); ++b) sums[b] = 0;
+    return hipSuccess;
+}
+hipError_t launch_tet_frame(TetFrameParams f, int stages, hipStream_t) {
+    // every ROI pixel of every part one held sample (count), then its slot
+    // written (record, shadow)
+    if (stages & kTetCount)
+        for (long long e = 0; e < f.n_entries; ++e) f.offsets[e] = 1;
+    if (stages & kTetRecord)
+        for (long long q = 0; q < f.total; ++q) f.slot_k[q] = 0;
+    if (stages & kTetShadow)
+        for (long long q = 0; q < f.total; ++q) f.shade[q] = 1.0f;
     int32_t tiles = 0;
     for (int32_t q = 0; q < f.n; ++q) {
         const TetPartK& P = f.parts[q];

@@ -251,3 +251,55 @@ def test_bench_size_split_invariance_and_linear_field():
                                     pixels=pix)
     err = np.max(np.abs(img[pix[:, 1], pix[:, 0]] - ref))
     assert err <= TOL, err
+
+
+# ----------------------------------------------------------- shadow rays
+def _gpu_shadowed(parts, vals, cam, dt, light, a0, bg, max_runs=8):
+    dp = _dp()
+    tf, vr, s = _tf()
+    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, vr, s, dt, max_runs=max_runs)
+    try:
+        for k, (_, _, used) in enumerate(parts):
+            r.set_values(k, vals[used])
+        r.set_camera(cam)
+        total = r.shadow_plan()
+        r.samples.zero_()
+        img = r.render_shadowed(light, a0, bg, count=True)
+        r.synchronize()
+        out = img.cpu().numpy().astype(np.float64), total, int(r.samples.item())
+        plain = r.render(bg).cpu().numpy().astype(np.float64)
+        r.synchronize()
+        return out + (plain,)
+    finally:
+        r.close()
+
+
+@pytest.mark.parametrize("n_parts,seed,rough,light,a0", [(1, 21, True, (0.3, 1.0, -0.4), 0.3),
+                                                         (4, 22, True, (-1.0, 0.0, 0.0), 0.0),
+                                                         (5, 23, False, (0.0, 0.5, 1.0), 0.45)])
+def test_shadowed_parts_match_oracle(n_parts, seed, rough, light, a0):
+    cells = (5, 4, 5)
+    vals, parts = _scene(cells, 0.2, n_parts, seed, rough=rough)
+    cam = synth.orbit_camera((0, 0, 0), cells, 37, 29, az_deg=15.0 * seed, el_deg=25.0, radius_factor=1.5)
+    bg = (0.02, 0.04, 0.08, 0.1)
+    print(f"shadowed tets: {n_parts} parts, light {light}, a0 {a0}", flush=True)
+    img, total, counted, plain = _gpu_shadowed(parts, vals, cam, 0.35, light, a0, bg)
+    tf, vr, s = _tf()
+    tparts = [(pv, vals[used], pt) for pv, pt, used in parts]
+    ref, cnt = oracle.render_tets_shadowed(cam, tparts, tf, vr, s, 0.35, light, a0, bg)
+    assert cnt[1] == 0
+    assert total == cnt[0]
+    assert counted == cnt[0] + cnt[2]
+    err = np.max(np.abs(img - ref))
+    assert err <= TOL, err
+    if a0 < 1.0 and cnt[2] > 0:
+        assert np.max(np.abs(img - plain)) > 1e-3      # the shadows change the image
+
+
+def test_shadowed_ambient_one_equals_plain_frame_bitwise():
+    cells = (4, 4, 4)
+    vals, parts = _scene(cells, 0.15, 3, 24)
+    cam = synth.inside_camera((0, 0, 0), cells, 30, 26, az_deg=30.0, el_deg=-10.0, fovy_deg=70.0)
+    img, total, _, plain = _gpu_shadowed(parts, vals, cam, 0.29, (1.0, 1.0, 1.0), 1.0, (0.0, 0.0, 0.0, 0.0))
+    assert total > 0
+    assert np.array_equal(img, plain)
