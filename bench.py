@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint", "rqc", "stream", "tets"],
+    ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint", "rqc", "stream", "tets",
+                                                 "tets-shadow"],
                     default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default=None,
                     help="brick storage (default f32; c5 is a float16 workload: f16)")
@@ -1035,6 +1036,109 @@ def bench_tets(args):
     return 0
 
 
+def bench_tets_shadow(args):
+    """Shadow rays through tetrahedral parts: a 64x48x48-cube box (884,736
+    tetrahedra, jitter 0.15), 8 blobs, 8 smooth non-convex parts, 768x768
+    orbit view, step 0.5, opacity 0.1, light (0.8, 1.0, -0.4), ambient 0.3.
+    One step = record + 8 shadow cycle steps + shaded march + resolve (the
+    plan, which depends on geometry and camera only, is made once)."""
+    import torch
+
+    import paper_2501_01628_amd as dp
+    import synth
+    cells, n_parts, light, a0 = (64, 48, 48), 8, (0.8, 1.0, -0.4), 0.3
+    rng = np.random.default_rng(13)
+    v, t = synth.tet_mesh(cells, jitter=0.15, rng=rng)
+    vals = synth.tet_field(v, rng, cells, n_blobs=8)
+    parts = synth.tet_partitions(v, t, n_parts, rng)
+    cam = synth.orbit_camera((0, 0, 0), cells, 768, 768)
+    tf = synth.default_tf()
+    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, (0.0, 1.0), 0.1, 0.5, max_runs=32)
+    for k, (_, _, used) in enumerate(parts):
+        r.set_values(k, vals[used])
+    r.set_camera(cam)
+    total = r.shadow_plan()
+    bg = (0.0, 0.0, 0.0, 0.0)
+    for _ in range(args.warmup):
+        r.render_shadowed(light, a0, bg)
+    r.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(r.stream)
+    for _ in range(args.steps):
+        r.render_shadowed(light, a0, bg)
+    e1.record(r.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    r.samples.zero_()
+    r.render_shadowed(light, a0, bg, count=True)
+    r.synchronize()
+    samples = int(r.samples.item())
+    frame = r.frame.cpu().numpy().astype(np.float64)
+    e0.record(r.stream)
+    for _ in range(args.steps):
+        r.render(bg)
+    e1.record(r.stream)
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / args.steps
+    r.close()
+    log(f"shadowed frame {ms:.3f} ms ({total} primary + {samples - total} shadow samples), unshadowed {ms_plain:.3f} ms")
+    achieved = samples * TET_FP64_OPS_PER_SAMPLE / (ms * 1e-3)
+    W, H = cam["width"], cam["height"]
+    out = {"metric": "Msamples/s (tetrahedral parts with shadow rays: primary + shadow samples held per frame x "
+                     "frames/s)",
+           "value": samples / (ms * 1e-3) / 1e6, "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 location, f32 shading", "data": "synthetic",
+           "config": {"workload": f"tets-shadow: {len(t)} tetrahedra (jittered 64x48x48 cubes), 8 blobs, {n_parts} "
+                                  f"non-convex parts, {W}x{H} perspective, step 0.5, opacity 0.1, light {light}, "
+                                  f"ambient {a0}"},
+           "samples_per_frame": samples, "primary_samples_per_frame": total, "ms_without_shadows": ms_plain,
+           "roofline": {"kernel": "tet_march<record> + tet_shadow_step x 8 + tet_march<shaded> + tet_resolve",
+                        "bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+                        "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
+                        "model": f"{TET_FP64_OPS_PER_SAMPLE} fp64 operations per held (primary or shadow) sample "
+                                 f"over the frame; peak = fp64 vector 78.6 TFLOP/s"}}
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (oracle with shadow rays, brute-force location, on a pixel sample) ...")
+        tparts = [(pv, vals[used], pt) for pv, pt, used in parts]
+        hit = np.argwhere(frame[..., 3] > 0.0)
+        pick = np.random.default_rng(3)
+        cand = hit[pick.choice(len(hit), min(20000, len(hit)), replace=False)]
+        hi = np.array(cells, dtype=np.float64)
+        short = []
+        for j, i in cand:
+            o, d = oracle.ray(cam, int(i), int(j))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                ta, tb = (0.0 - o) / d, (hi - o) / d
+            chord = np.min(np.maximum(ta, tb)) - max(np.max(np.minimum(ta, tb)), 0.0)
+            if 2 * 0.5 <= chord <= 6 * 0.5:
+                short.append((i, j))
+        short = np.array(short, dtype=np.int32)
+
+        def run(npix):
+            pix = short[pick.choice(len(short), min(npix, len(short)), replace=False)]
+            log(f"oracle on {len(pix)} pixels with {oracle.threads()} threads ...")
+            t0 = time.perf_counter()
+            img, cnt = oracle.render_tets_shadowed(cam, tparts, tf, (0.0, 1.0), 0.1, 0.5, light, a0, bg, pixels=pix)
+            return time.perf_counter() - t0, int(cnt[0] + cnt[2]), (pix, img)
+        rr = _oracle_rates(run, args.cpu_seconds, 1e-6, first=oracle.threads(), cap=len(short))
+        pix, img = rr["payload"]
+        out["cpu_baseline"] = {
+            "value": rr["value"], "unit": "Msamples/s", "cores": rr["cores"], "kind": "oracle",
+            "sample": f"{len(pix)} random pixels whose rays cross the mesh box in 2 to 6 samples, {rr['work']} "
+                      f"primary + shadow samples in {rr['seconds']:.1f} s (every sample tested against all "
+                      f"{len(t)} tetrahedra)",
+            "one_core_value": rr["one_core_value"],
+            "one_core_sample": f"{rr['one_core_n']} random pixels, one thread, {rr['one_core_seconds']:.1f} s",
+            **host_info()}
+        out["max_abs_err_vs_oracle"] = {"value": float(np.max(np.abs(frame[pix[:, 1], pix[:, 0]] - img))),
+                                        "pixels": "the cpu_baseline sample", "bar": 1e-5}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1055,6 +1159,8 @@ def main():
         return bench_stream(args)
     if args.workload == "tets":
         return bench_tets(args)
+    if args.workload == "tets-shadow":
+        return bench_tets_shadow(args)
     import torch
 
     import paper_2501_01628_amd as dp
