@@ -331,7 +331,8 @@ vr_status vr_synchronize(vr_context ctx) {
         (void)hipMemcpy(err_word(ctx), &zero, sizeof zero, hipMemcpyHostToDevice);
         const char* what = (word & kErrSpin)   ? "a march kernel gave up a bounded wait"
                            : (word & kErrRuns) ? "a ray crossed a tetrahedral part in more runs than max_runs"
-                                               : "a sample index exceeded 2^31 - 1";
+                                               : "a sample index exceeded 2^31 - 1, or a shadow plan's counts "
+                                                 "did not match its frame";
         return fail(ctx, VR_ERR_DEVICE,
                     "vr_synchronize: %s (device error bits 0x%x); images rendered since the last "
                     "synchronisation are unreliable", what, (unsigned)word);

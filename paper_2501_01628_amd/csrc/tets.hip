@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
     const float a0 = f.ambient, a1 = 1.0f - f.ambient;
     unsigned long long held = 0;
     int nrun = 0;
-    long long k0 = 0, k1 = -1, slot0 = 0;
+    long long k0 = 0, k1 = -1, slot0 = 0, slots = 0;
     CamRay r{};
     if (live) {
         r = camera_ray(f.cam, P.roi_x0 + lx, P.roi_y0 + ly);
@@ -184,7 +184,10 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
             if (f.err) atomicOr(f.err, kErrRange);
             k1 = k0 - 1;
         }
-        if (kMode == kTetRecord || kMode == kTetShaded) slot0 = f.offsets[P.entry0 + li];
+        if (kMode == kTetRecord || kMode == kTetShaded) {
+            slot0 = f.offsets[P.entry0 + li];
+            slots = f.offsets[P.entry0 + li + 1] - slot0;   // the count pass's held samples of this ray
+        }
     }
     bool in_run = false, overflow = false;
     int key = 0, last = -1;
@@ -216,7 +219,11 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
             continue;
         }
         if (kMode == kTetRecord) {
-            f.slot_k[slot0 + (long long)held] = (int)k;
+            // the passes locate alike, so a ray holds as many samples as
+            // counted; a mismatch (which only a logic error could cause) is
+            // reported and never writes outside the ray's slots
+            if ((long long)held < slots) f.slot_k[slot0 + (long long)held] = (int)k;
+            else if (f.err) atomicOr(f.err, kErrRange);
             ++held;
             continue;
         }
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
         }
         const Classified c = classify(tft, tet_value(P, e, D), tf_k, tf_o);
         float sh = 1.0f;
-        if (kMode == kTetShaded) sh = a0 + a1 * f.shade[slot0 + (long long)held];
+        if (kMode == kTetShaded) sh = a0 + a1 * ((long long)held < slots ? f.shade[slot0 + (long long)held] : 1.0f);
         const float Tn = T * trans_exp2(-c.a);
         const float w = T - Tn;
         C0 = fmaf(w, c.r * sh, C0);
