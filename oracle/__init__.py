@@ -350,6 +350,65 @@ def render_tets(cam, parts, tf, vrange, opacity_scale, dt, bg=(0.0, 0.0, 0.0, 0.
     return _render_tets(cam, parts, tf, vrange, opacity_scale, dt, bg, pixels, None, None)
 
 
+def _quad(q, ids):
+    """Triangles of the quadrilateral q (cyclic) cut along the diagonal
+    through its vertex of smallest id (R-cells)."""
+    a, b, c, d = q
+    m = min(range(4), key=lambda i: ids[q[i]])
+    if m in (0, 2):
+        return [(a, b, c), (a, c, d)]
+    return [(a, b, d), (b, c, d)]
+
+
+_WEDGE_FACES = ((0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5))
+_HEX_FACES = ((0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7))
+
+
+def cells_to_tets(vertices, values, sizes, cell_vertices, vertex_ids=None):
+    """R-cells: the tetrahedra of a mixed-element part.  Tetrahedra stay;
+    a pyramid is its base's two triangles joined to the apex; a wedge and a
+    hexahedron get a centre vertex (position: the sum of the node positions
+    in node order over the node count, float64; value: the mean of the node
+    values) joined to every triangle of its faces.  Every quadrilateral is
+    cut along the diagonal through its vertex of smallest id (vertex_ids,
+    default the vertex index), so cells that share it cut it alike.
+    Returns (vertices, values (float32), tets (T, 4) int32) with the centre
+    vertices appended."""
+    V = [tuple(float(x) for x in v) for v in np.asarray(vertices, dtype=np.float64).reshape(-1, 3)]
+    F = [float(x) for x in np.asarray(values, dtype=np.float32)]
+    ids = list(range(len(V))) if vertex_ids is None else [int(x) for x in vertex_ids]
+    out = []
+    pos = 0
+    for n in (int(x) for x in sizes):
+        cell = [int(x) for x in cell_vertices[pos:pos + n]]
+        pos += n
+        if n == 4:
+            out.append(tuple(cell))
+        elif n == 5:
+            for t in _quad(cell[:4], ids):
+                out.append(t + (cell[4],))
+        elif n in (6, 8):
+            c = len(V)
+            sx = sy = sz = 0.0
+            sv = 0.0
+            for q in cell:
+                sx += V[q][0]
+                sy += V[q][1]
+                sz += V[q][2]
+                sv += F[q]
+            V.append((sx / n, sy / n, sz / n))
+            F.append(sv / n)
+            ids.append(-1)                  # a centre vertex lies on no quadrilateral
+            for f in (_WEDGE_FACES if n == 6 else _HEX_FACES):
+                nodes = [cell[i] for i in f]
+                for t in ([tuple(nodes)] if len(nodes) == 3 else _quad(nodes, ids)):
+                    out.append(t + (c,))
+        else:
+            raise ValueError(f"cell with {n} vertices")
+    return (np.asarray(V, dtype=np.float64).reshape(-1, 3), np.asarray(F, dtype=np.float32),
+            np.asarray(out, dtype=np.int32).reshape(-1, 4))
+
+
 def render_tets_shadowed(cam, parts, tf, vrange, opacity_scale, dt, light_dir, ambient,
                          bg=(0.0, 0.0, 0.0, 0.0), pixels=None):
     """render_tets with one directional light (R-shadow): every held primary

@@ -513,18 +513,28 @@ def tet_partitions(verts, tets, n_parts, rng, rough=False):
     whose rays enter and leave them many times).  Returns a list of
     (vertices, tets, used) per part: local vertex numbering (shared vertices
     copied), used = the global index of each local vertex."""
-    cen = verts[tets].mean(1)
-    lo, hi = verts.min(0), verts.max(0)
+    owner = _partition_owner(verts[tets].mean(1), verts.min(0), verts.max(0), n_parts, rng, rough)
+    parts = []
+    for p in range(n_parts):
+        sel = tets[owner == p]
+        used, inv = np.unique(sel.ravel(), return_inverse=True)
+        parts.append((verts[used].copy(), inv.reshape(-1, 4).astype(np.int32), used))
+    return parts
+
+
+def _partition_owner(cen, lo, hi, n_parts, rng, rough):
+    """Part of every element (centroids cen) under the rule of
+    :func:`tet_partitions`."""
     seeds = lo + rng.uniform(0.0, 1.0, (n_parts, 3)) * (hi - lo)
     w = rng.uniform(0.5, 2.0, n_parts)
     amp = np.max(hi - lo) / 8.0
     kmag = 2.0 * np.pi / (np.max(hi - lo) / 3.0)
-    best = np.full(len(tets), np.inf)
-    owner = np.zeros(len(tets), dtype=np.int64)
-    for p in range(n_parts):        # one part at a time: memory stays O(tets)
+    best = np.full(len(cen), np.inf)
+    owner = np.zeros(len(cen), dtype=np.int64)
+    for p in range(n_parts):        # one part at a time: memory stays O(elements)
         d = np.sqrt(((cen - seeds[p]) ** 2).sum(1)) / w[p]
         if rough:
-            d += rng.uniform(0.0, 1.0, len(tets)) * amp
+            d += rng.uniform(0.0, 1.0, len(cen)) * amp
         else:
             for _ in range(3):
                 k = rng.normal(size=3)
@@ -533,9 +543,91 @@ def tet_partitions(verts, tets, n_parts, rng, rough=False):
         better = d < best
         best[better] = d[better]
         owner[better] = p
+    return owner
+
+
+# Node order of the cell types (the common finite-element convention):
+# tetrahedron v0..v3; pyramid: base v0..v3 in cyclic order, apex v4; wedge:
+# bottom triangle v0 v1 v2, top v3 v4 v5 (v3 above v0, ...); hexahedron:
+# bottom v0..v3 cyclic, top v4..v7 (v4 above v0, ...).
+CELL_TET, CELL_PYRAMID, CELL_WEDGE, CELL_HEX = 4, 5, 6, 8
+
+
+def mixed_mesh(cells, jitter=0.0, rng=None, kind=None):
+    """Conforming mixed-element mesh of the box [0, cells] (lattice vertices
+    as :func:`tet_mesh`, numbered (i (ny+1) + j)(nz+1) + k, interior ones
+    jittered).  Each lattice cube becomes, by ``kind(i, j, k)`` (default: the
+    four kinds in a 2x2x1 block pattern of 2-cube blocks): 8 one hexahedron,
+    6 two wedges (cut along the diagonal plane through its lowest corner and
+    the opposite vertical edge), 5 six pyramids on its faces around an added
+    centre vertex (the mean of its corners, appended after the lattice), or
+    4 the six Kuhn tetrahedra of :func:`tet_mesh`.  Every quadrilateral face
+    that two cells share is cut by either along the diagonal through its
+    lowest-numbered vertex, the cut the Kuhn tetrahedra and the wedges
+    already have, so the mesh is conforming.  Returns (vertices (V, 3)
+    float64, sizes (C,) uint8 = vertices per cell, cell_vertices (sum of
+    sizes,) int32 in the node order above)."""
+    nx, ny, nz = (int(c) for c in cells)
+    gx, gy, gz = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    verts = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1).astype(np.float64)
+    if jitter > 0.0:
+        interior = ((verts[:, 0] > 0) & (verts[:, 0] < nx) & (verts[:, 1] > 0) & (verts[:, 1] < ny) &
+                    (verts[:, 2] > 0) & (verts[:, 2] < nz))
+        d = rng.uniform(-jitter, jitter, verts.shape)
+        verts[interior] += d[interior]
+    if kind is None:
+        def kind(i, j, k):
+            return (CELL_HEX, CELL_WEDGE, CELL_PYRAMID, CELL_TET)[((i // 2) % 2) + 2 * ((j // 2) % 2)]
+
+    def vid(i, j, k):
+        return (i * (ny + 1) + j) * (nz + 1) + k
+
+    sizes, cv, centres = [], [], []
+    perms = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                h = [vid(i, j, k), vid(i + 1, j, k), vid(i + 1, j + 1, k), vid(i, j + 1, k),
+                     vid(i, j, k + 1), vid(i + 1, j, k + 1), vid(i + 1, j + 1, k + 1), vid(i, j + 1, k + 1)]
+                t = kind(i, j, k)
+                if t == CELL_HEX:
+                    sizes.append(8)
+                    cv += h
+                elif t == CELL_WEDGE:
+                    sizes += [6, 6]
+                    cv += [h[0], h[1], h[2], h[4], h[5], h[6], h[0], h[2], h[3], h[4], h[6], h[7]]
+                elif t == CELL_PYRAMID:
+                    c = len(verts) + len(centres)
+                    centres.append(verts[h].sum(0) / 8.0)
+                    for f in ((0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)):
+                        sizes.append(5)
+                        cv += [h[f[0]], h[f[1]], h[f[2]], h[f[3]], c]
+                else:
+                    for p in perms:
+                        c = [i, j, k]
+                        tt = [vid(*c)]
+                        for a in p:
+                            c[a] += 1
+                            tt.append(vid(*c))
+                        sizes.append(4)
+                        cv += tt
+    if centres:
+        verts = np.concatenate([verts, np.asarray(centres)], 0)
+    return verts, np.asarray(sizes, dtype=np.uint8), np.asarray(cv, dtype=np.int32)
+
+
+def mixed_partitions(verts, sizes, cell_vertices, n_parts, rng, rough=False):
+    """Parts of a mixed mesh by the rule of :func:`tet_partitions` on cell
+    centroids.  Returns a list of (vertices, sizes, cell_vertices, used) per
+    part: local numbering, used = the global index of each local vertex."""
+    start = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])
+    cen = np.stack([verts[cell_vertices[start[c]:start[c + 1]]].mean(0) for c in range(len(sizes))])
+    owner = _partition_owner(cen, verts.min(0), verts.max(0), n_parts, rng, rough)
     parts = []
     for p in range(n_parts):
-        sel = tets[owner == p]
-        used, inv = np.unique(sel.ravel(), return_inverse=True)
-        parts.append((verts[used].copy(), inv.reshape(-1, 4).astype(np.int32), used))
+        idx = np.nonzero(owner == p)[0]
+        sel = np.concatenate([cell_vertices[start[c]:start[c + 1]] for c in idx]) if len(idx) else \
+            np.zeros(0, dtype=np.int32)
+        used, inv = np.unique(sel, return_inverse=True)
+        parts.append((verts[used].copy(), sizes[idx].copy(), inv.astype(np.int32), used))
     return parts

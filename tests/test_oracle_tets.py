@@ -199,3 +199,61 @@ def test_shadowed_split_into_parts_is_invariant():
     assert np.array_equal(whole, split) and np.array_equal(c1, c2)
     with pytest.raises(ValueError):
         oracle.render_tets_shadowed(cam, parts, tf, vr, s, 0.33, (0.0, 0.0, 0.0), 0.25)
+
+
+# ------------------------------------------------------ mixed elements
+MCELLS = (4, 4, 3)
+
+
+def _mixed(jitter, seed):
+    rng = np.random.default_rng(seed)
+    v, sz, cv = synth.mixed_mesh(MCELLS, jitter=jitter, rng=rng)
+    v = np.round(v * 1024.0) / 1024.0
+    return v, sz, cv
+
+
+def test_mixed_mesh_decomposes_into_a_conforming_mesh():
+    v, sz, cv = _mixed(0.15, 31)
+    assert set(np.unique(sz)) == {4, 5, 6, 8}
+    vals = np.zeros(len(v), dtype=np.float32)
+    V, F, T = oracle.cells_to_tets(v, vals, sz, cv)
+    e = V[T[:, 1:]] - V[T[:, :1]]
+    vol = np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2])) / 6.0
+    assert np.all(np.abs(vol) > 1e-6)
+    assert abs(np.abs(vol).sum() - np.prod(MCELLS)) < 1e-9
+    faces = np.sort(np.concatenate([T[:, [1, 2, 3]], T[:, [0, 2, 3]], T[:, [0, 1, 3]], T[:, [0, 1, 2]]]), 1)
+    _, counts = np.unique(faces, axis=0, return_counts=True)
+    nx, ny, nz = MCELLS
+    assert np.sum(counts == 1) == 2 * 2 * (nx * ny + ny * nz + nx * nz) and np.all(counts <= 2)
+
+
+@pytest.mark.parametrize("jitter,seed", [(0.0, 32), (0.15, 33)])
+def test_mixed_linear_field_equals_brick(jitter, seed):
+    """A linear field is reproduced by every cell's tetrahedra (the centre
+    vertices carry the mean of a linear field's node values, which is its
+    value at the node centroid), so the mixed mesh renders as the brick."""
+    v, sz, cv = _mixed(jitter, seed)
+    vals = _lin(v).astype(np.float32)
+    V, F, T = oracle.cells_to_tets(v, vals, sz, cv)
+    cam = synth.orbit_camera((0, 0, 0), MCELLS, 20, 18, az_deg=-25.0, el_deg=35.0, radius_factor=1.6)
+    bg = (0.0, 0.1, 0.0, 0.25)
+    tf, vr, s = _tf()
+    img, cnt = oracle.render_tets(cam, [(V, F, T)], tf, vr, s, 0.33, bg)
+    ref, nref = _brick_image(cam, MCELLS, 0.33, bg)
+    assert cnt[1] == 0 and cnt[0] == nref
+    # centre values are float32 means (sixths are not dyadic): 1e-6
+    np.testing.assert_allclose(img, ref, rtol=0, atol=1e-6)
+
+
+def test_mixed_split_into_parts_is_invariant():
+    rng = np.random.default_rng(34)
+    v, sz, cv = synth.mixed_mesh(MCELLS, jitter=0.15, rng=rng)
+    vals = synth.tet_field(v, rng, MCELLS)
+    cam = synth.orbit_camera((0, 0, 0), MCELLS, 18, 16, az_deg=40.0, el_deg=15.0, radius_factor=1.5)
+    tf, vr, s = _tf()
+    whole, c1 = oracle.render_tets(cam, [oracle.cells_to_tets(v, vals, sz, cv)], tf, vr, s, 0.31)
+    parts = []
+    for pv, psz, pcv, used in synth.mixed_partitions(v, sz, cv, 4, rng, rough=True):
+        parts.append(oracle.cells_to_tets(pv, vals[used], psz, pcv, vertex_ids=used))
+    split, c2 = oracle.render_tets(cam, parts, tf, vr, s, 0.31)
+    assert np.array_equal(whole, split) and np.array_equal(c1, c2) and c1[1] == 0
