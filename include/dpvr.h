@@ -635,10 +635,32 @@ typedef struct vr_tetpart_s* vr_tetpart;
 vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_vertices, const int32_t* tets,
                             int32_t n_tets, vr_tetpart* out);
 
-/* The part's closed bounding box, grid cells per axis, grid entries and the
- * bytes of device workspace it needs (any pointer may be NULL). */
+/* Mixed finite elements (the paper's lander data mixes element types,
+ * Sec. 4), read as tetrahedra: cell c has cell_sizes[c] = 4, 5, 6 or 8 nodes
+ * (tetrahedron v0..v3; pyramid: base v0..v3 in cyclic order, apex v4; wedge:
+ * bottom triangle v0 v1 v2, top v3 v4 v5 with v3 above v0; hexahedron:
+ * bottom v0..v3 cyclic, top v4..v7 with v4 above v0), cell_vertices their
+ * node indices one cell after another.  Every quadrilateral face is cut
+ * along the diagonal through its node of smallest vertex_ids value (a
+ * global id per vertex, so that parts sharing the face cut it alike; NULL
+ * = the vertex index); a pyramid becomes its two base triangles joined to
+ * the apex; a wedge or a hexahedron gets a centre vertex (position: the
+ * sum of its node positions in node order over the node count; value: the
+ * mean of its node values, recomputed at every vr_tetpart_set_values) joined
+ * to every triangle of its faces.  The field is then piecewise linear on
+ * these tetrahedra, not the elements' own interpolation.  vertices and the
+ * values of vr_tetpart_set_values are the n_vertices input vertices.
+ * Errors: as vr_tetpart_create, VR_ERR_INVALID_ARG also for a cell size
+ * other than 4, 5, 6, 8. */
+vr_status vr_tetpart_create_cells(vr_context ctx, const double* vertices, int32_t n_vertices, const int64_t* vertex_ids,
+                                  const uint8_t* cell_sizes, const int32_t* cell_vertices, int32_t n_cells,
+                                  vr_tetpart* out);
+
+/* The part's closed bounding box, grid cells per axis, grid entries, the
+ * bytes of device workspace it needs and its tetrahedra (any pointer may be
+ * NULL). */
 vr_status vr_tetpart_info(vr_tetpart part, double lo[3], double hi[3], int32_t grid[3], int64_t* grid_entries,
-                          size_t* workspace_bytes);
+                          size_t* workspace_bytes, int32_t* n_tets);
 
 /* Give the part its device workspace (caller-owned, 256-byte aligned, at
  * least the bytes vr_tetpart_info reports, kept until the part is released)
@@ -647,7 +669,8 @@ vr_status vr_tetpart_info(vr_tetpart part, double lo[3], double hi[3], int32_t g
 vr_status vr_tetpart_attach(vr_tetpart part, void* workspace, size_t workspace_bytes);
 
 /* Vertex values (a new time step or field): values is a device array of
- * n_vertices floats, borrowed until the enqueued gather has run.
+ * n_vertices floats (the vertices the part was created with), borrowed until
+ * the enqueued gather has run.
  * Errors: VR_ERR_STATE (no workspace attached). */
 vr_status vr_tetpart_set_values(vr_tetpart part, const float* values);
 

@@ -156,7 +156,10 @@ _SIGS = {
     "vr_render_rqc": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_light), _f4, C.c_void_p,
                        C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], _st),
     "vr_tetpart_create": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)], _st),
-    "vr_tetpart_info": ([C.c_void_p, _d3, _d3, _i3, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)], _st),
+    "vr_tetpart_info": ([C.c_void_p, _d3, _d3, _i3, C.POINTER(C.c_int64), C.POINTER(C.c_size_t),
+                         C.POINTER(C.c_int32)], _st),
+    "vr_tetpart_create_cells": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.POINTER(C.c_void_p)], _st),
     "vr_tetpart_attach": ([C.c_void_p, C.c_void_p, C.c_size_t], _st),
     "vr_tetpart_set_values": ([C.c_void_p, C.c_void_p], _st),
     "vr_tetpart_release": ([C.c_void_p], _st),
@@ -418,12 +421,26 @@ def vr_tetpart_create(ctx, vertices, tets):
     return h
 
 
+def vr_tetpart_create_cells(ctx, vertices, sizes, cell_vertices, vertex_ids=None):
+    """A part from mixed cells (host arrays: vertices (V, 3) float64, sizes
+    (C,) uint8 in {4, 5, 6, 8}, cell_vertices int32, optional vertex_ids (V,)
+    int64 global ids for the quadrilateral cuts)."""
+    v = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1, 3)
+    sz = np.ascontiguousarray(sizes, dtype=np.uint8)
+    cv = np.ascontiguousarray(cell_vertices, dtype=np.int32)
+    ids = None if vertex_ids is None else np.ascontiguousarray(vertex_ids, dtype=np.int64)
+    h = C.c_void_p()
+    _check(_lib.vr_tetpart_create_cells(ctx, v.ctypes.data, len(v), None if ids is None else ids.ctypes.data,
+                                        sz.ctypes.data, cv.ctypes.data, len(sz), C.byref(h)), ctx)
+    return h
+
+
 def vr_tetpart_info(part, ctx=None):
     lo, hi, grid = _d3(), _d3(), _i3()
-    entries, nbytes = C.c_int64(), C.c_size_t()
-    _check(_lib.vr_tetpart_info(part, lo, hi, grid, C.byref(entries), C.byref(nbytes)), ctx)
+    entries, nbytes, nt = C.c_int64(), C.c_size_t(), C.c_int32()
+    _check(_lib.vr_tetpart_info(part, lo, hi, grid, C.byref(entries), C.byref(nbytes), C.byref(nt)), ctx)
     return dict(lo=tuple(lo), hi=tuple(hi), grid=tuple(grid), grid_entries=entries.value,
-                workspace_bytes=nbytes.value)
+                workspace_bytes=nbytes.value, n_tets=nt.value)
 
 
 def vr_tetpart_attach(part, workspace, workspace_bytes, ctx=None):
@@ -624,7 +641,8 @@ def set_camera(ctx, cam: dict):
 class TetRenderer:
     """Torch buffers and C-ABI calls for a volume given as tetrahedral parts
     on one device.  ``parts`` is a list of (vertices (V, 3) float64, tets
-    (T, 4) int32) host arrays; vertex values come per part through
+    (T, 4) int32) host arrays, or of (vertices, sizes, cell_vertices,
+    vertex_ids) for mixed cells; vertex values come per part through
     :meth:`set_values`."""
 
     def __init__(self, parts, tf, vrange=(0.0, 1.0), opacity_scale=1.0, dt=0.5, device=0, stream=None,
@@ -639,8 +657,8 @@ class TetRenderer:
         vr_set_render_params(self.ctx, dt, 0.0)
         self.max_runs = int(max_runs)
         self.parts, self.workspaces, self.values, self.info = [], [], [], []
-        for verts, tets in parts:
-            h = vr_tetpart_create(self.ctx, verts, tets)
+        for part in parts:
+            h = vr_tetpart_create(self.ctx, *part) if len(part) == 2 else vr_tetpart_create_cells(self.ctx, *part)
             inf = vr_tetpart_info(h, self.ctx)
             n = inf["workspace_bytes"]
             ws = torch.empty(n // 4 + 64, dtype=torch.float32, device=self.device)

@@ -1716,8 +1716,11 @@ vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const
 struct vr_tetpart_s {
     vr_context ctx = nullptr;
     TetTables tab;
-    // device workspace: [planes][vals][owned][tets][cell_start][cell_tets][nbr], each 256-aligned
-    size_t off[7] = {0, 0, 0, 0, 0, 0, 0};
+    int32_t n_input_vertices = 0;        // vertices whose values the caller gives
+    std::vector<int32_t> centre_nodes;   // cell centres: 8 node indices each (-1 padded)
+    // device workspace: [planes][vals][owned][tets][cell_start][cell_tets][nbr][centre_nodes],
+    // each 256-aligned
+    size_t off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     size_t need = 0;
     char* ws = nullptr;
     bool has_values = false;
@@ -1725,7 +1728,7 @@ struct vr_tetpart_s {
 
 namespace {
 
-size_t tetpart_layout(const TetTables& t, size_t off[7]) {
+size_t tetpart_layout(const TetTables& t, const std::vector<int32_t>& centre_nodes, size_t off[8]) {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t nt = (size_t)t.n_tets;
     size_t o = 0;
@@ -1736,6 +1739,7 @@ size_t tetpart_layout(const TetTables& t, size_t off[7]) {
     off[4] = o; o += up(t.cell_start.size() * sizeof(int32_t));
     off[5] = o; o += up(t.cell_tets.size() * sizeof(int32_t));
     off[6] = o; o += up(t.nbr.size() * sizeof(int32_t));
+    off[7] = o; o += up(centre_nodes.size() * sizeof(int32_t));
     return o;
 }
 
@@ -1852,21 +1856,33 @@ hipError_t stage_copy(vr_context ctx, void* dst, const void* src, size_t bytes) 
 
 }  // namespace
 
-vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_vertices, const int32_t* tets,
-                            int32_t n_tets, vr_tetpart* out) {
-    static const char* who = "vr_tetpart_create";
+// A part from tetrahedra (cells == NULL) or from mixed cells.
+static vr_status tetpart_create(vr_context ctx, const double* vertices, int32_t n_vertices, const int64_t* ids,
+                                const int32_t* tets, int32_t n_tets, const uint8_t* sizes, const int32_t* cells,
+                                int32_t n_cells, vr_tetpart* out, const char* who) {
     if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid context", who);
     if (!out) return fail(ctx, VR_ERR_INVALID_ARG, "%s: out is NULL", who);
     *out = nullptr;
-    if (n_vertices < 0 || n_tets < 0 || (n_vertices > 0 && !vertices) || (n_tets > 0 && !tets))
+    if (n_vertices < 0 || n_tets < 0 || n_cells < 0 || (n_vertices > 0 && !vertices) || (n_tets > 0 && !tets) ||
+        (n_cells > 0 && (!sizes || !cells)))
         return fail(ctx, VR_ERR_INVALID_ARG, "%s: negative count or NULL array", who);
     std::unique_ptr<vr_tetpart_s> q(new (std::nothrow) vr_tetpart_s);
     if (!q) return fail(ctx, VR_ERR_OUT_OF_MEMORY, "%s: out of host memory", who);
     try {
         std::string msg;
-        if (!build_tet_tables(vertices, n_vertices, tets, n_tets, q->tab, msg))
-            return fail(ctx, VR_ERR_INVALID_ARG, "%s: %s", who, msg.c_str());
-        q->need = tetpart_layout(q->tab, q->off);
+        q->n_input_vertices = n_vertices;
+        bool okb;
+        if (sizes) {
+            std::vector<double> v;
+            std::vector<int32_t> t;
+            if (!decompose_cells(vertices, n_vertices, ids, sizes, cells, n_cells, v, t, q->centre_nodes, msg))
+                return fail(ctx, VR_ERR_INVALID_ARG, "%s: %s", who, msg.c_str());
+            okb = build_tet_tables(v.data(), (int32_t)(v.size() / 3), t.data(), (int32_t)(t.size() / 4), q->tab, msg);
+        } else {
+            okb = build_tet_tables(vertices, n_vertices, tets, n_tets, q->tab, msg);
+        }
+        if (!okb) return fail(ctx, VR_ERR_INVALID_ARG, "%s: %s", who, msg.c_str());
+        q->need = tetpart_layout(q->tab, q->centre_nodes, q->off);
         q->ctx = ctx;
         std::lock_guard<std::mutex> lk(g_mu);
         g_live.insert(q.get());
@@ -1878,9 +1894,23 @@ vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_ve
     return ok(ctx);
 }
 
+vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_vertices, const int32_t* tets,
+                            int32_t n_tets, vr_tetpart* out) {
+    return tetpart_create(ctx, vertices, n_vertices, nullptr, tets, n_tets, nullptr, nullptr, 0, out,
+                          "vr_tetpart_create");
+}
+
+vr_status vr_tetpart_create_cells(vr_context ctx, const double* vertices, int32_t n_vertices, const int64_t* vertex_ids,
+                                  const uint8_t* cell_sizes, const int32_t* cell_vertices, int32_t n_cells,
+                                  vr_tetpart* out) {
+    return tetpart_create(ctx, vertices, n_vertices, vertex_ids, nullptr, 0, cell_sizes, cell_vertices, n_cells, out,
+                          "vr_tetpart_create_cells");
+}
+
 vr_status vr_tetpart_info(vr_tetpart q, double lo[3], double hi[3], int32_t grid[3], int64_t* grid_entries,
-                          size_t* workspace_bytes) {
+                          size_t* workspace_bytes, int32_t* n_tets) {
     if (!live(q)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_tetpart_info: invalid part");
+    if (n_tets) *n_tets = q->tab.n_tets;
     for (int c = 0; c < 3; ++c) {
         if (lo) lo[c] = q->tab.lo[c];
         if (hi) hi[c] = q->tab.hi[c];
@@ -1908,12 +1938,13 @@ vr_status vr_tetpart_attach(vr_tetpart q, void* workspace, size_t workspace_byte
         size_t off;
         const void* src;
         size_t bytes;
-    } copies[6] = {{q->off[0], t.planes.data(), t.planes.size() * sizeof(double)},
+    } copies[7] = {{q->off[0], t.planes.data(), t.planes.size() * sizeof(double)},
                    {q->off[2], t.owned.data(), t.owned.size() * sizeof(uint32_t)},
                    {q->off[3], t.tets.data(), t.tets.size() * sizeof(int32_t)},
                    {q->off[4], t.cell_start.data(), t.cell_start.size() * sizeof(int32_t)},
                    {q->off[5], t.cell_tets.data(), t.cell_tets.size() * sizeof(int32_t)},
-                   {q->off[6], t.nbr.data(), t.nbr.size() * sizeof(int32_t)}};
+                   {q->off[6], t.nbr.data(), t.nbr.size() * sizeof(int32_t)},
+                   {q->off[7], q->centre_nodes.data(), q->centre_nodes.size() * sizeof(int32_t)}};
     hipError_t e = hipSuccess;
     for (const auto& c : copies)
         if (e == hipSuccess && c.bytes > 0)
@@ -1929,10 +1960,11 @@ vr_status vr_tetpart_set_values(vr_tetpart q, const float* values) {
     if (!live(q)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "%s: invalid part", who);
     vr_context ctx = q->ctx;
     if (!q->ws) return fail(ctx, VR_ERR_STATE, "%s: no workspace attached", who);
-    if (!values && q->tab.n_vertices > 0) return fail(ctx, VR_ERR_INVALID_ARG, "%s: values is NULL", who);
+    if (!values && q->n_input_vertices > 0) return fail(ctx, VR_ERR_INVALID_ARG, "%s: values is NULL", who);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
-    hipError_t e = launch_tet_values(values, reinterpret_cast<const int32_t*>(q->ws + q->off[3]), q->tab.n_tets,
+    hipError_t e = launch_tet_values(values, q->n_input_vertices, reinterpret_cast<const int32_t*>(q->ws + q->off[7]),
+                                     reinterpret_cast<const int32_t*>(q->ws + q->off[3]), q->tab.n_tets,
                                      reinterpret_cast<float*>(q->ws + q->off[1]), ctx->stream);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
     q->has_values = true;

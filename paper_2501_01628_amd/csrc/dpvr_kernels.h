@@ -296,8 +296,11 @@ constexpr int kTetTile = 16;
 inline int32_t tet_tiles(int32_t w, int32_t h) {
     return ((w + kTetTile - 1) / kTetTile) * ((h + kTetTile - 1) / kTetTile);
 }
-hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, int32_t n_tets, float* vals,
-                             hipStream_t stream);
+// Per tetrahedron its four vertex values: vertex v < n_input from
+// vertex_values, a cell centre v >= n_input the mean of its cell's nodes
+// (centre_nodes[8 (v - n_input) + i], -1 after the last).
+hipError_t launch_tet_values(const float* vertex_values, int32_t n_input, const int32_t* centre_nodes,
+                             const int32_t* tets, int32_t n_tets, float* vals, hipStream_t stream);
 // stages: a mask of the kTet* stages above, run in the order listed there
 hipError_t launch_tet_frame(TetFrameParams p, int stages, hipStream_t stream);
 // Exclusive scan of v[0 .. n) in place, v[n] = total (sums: scan_blocks(n) + 1 entries).

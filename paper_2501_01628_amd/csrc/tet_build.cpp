@@ -219,4 +219,88 @@ bool build_tet_tables(const double* V, int32_t nv, const int32_t* T, int32_t nt,
     return true;
 }
 
+bool decompose_cells(const double* V, int32_t nv, const int64_t* ids, const uint8_t* sizes, const int32_t* C,
+                     int32_t n_cells, std::vector<double>& out_v, std::vector<int32_t>& out_t,
+                     std::vector<int32_t>& centre_nodes, std::string& err) {
+    char buf[256];
+    out_v.assign(V, V + 3 * (size_t)nv);
+    out_t.clear();
+    centre_nodes.clear();
+    auto id = [&](int32_t q) { return ids ? ids[q] : (int64_t)q; };
+    auto tet = [&](int32_t a, int32_t b, int32_t c, int32_t d) {
+        out_t.push_back(a);
+        out_t.push_back(b);
+        out_t.push_back(c);
+        out_t.push_back(d);
+    };
+    // the two triangles of quadrilateral (a, b, c, d), cyclic, each joined to apex x
+    auto quad = [&](int32_t a, int32_t b, int32_t c, int32_t d, int32_t x) {
+        const int32_t q[4] = {a, b, c, d};
+        int m = 0;
+        for (int i = 1; i < 4; ++i)
+            if (id(q[i]) < id(q[m])) m = i;
+        if (m == 0 || m == 2) {
+            tet(a, b, c, x);
+            tet(a, c, d, x);
+        } else {
+            tet(a, b, d, x);
+            tet(b, c, d, x);
+        }
+    };
+    static const int kWedge[5][4] = {{0, 1, 2, -1}, {3, 4, 5, -1}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
+    static const int kHex[6][4] = {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}};
+    size_t pos = 0;
+    for (int32_t c = 0; c < n_cells; ++c) {
+        const int n = sizes[c];
+        if (n != 4 && n != 5 && n != 6 && n != 8) {
+            snprintf(buf, sizeof buf, "cell %d has %d nodes (4, 5, 6 or 8 expected)", c, n);
+            err = buf;
+            return false;
+        }
+        const int32_t* q = C + pos;
+        pos += (size_t)n;
+        for (int i = 0; i < n; ++i)
+            if (q[i] < 0 || q[i] >= nv) {
+                snprintf(buf, sizeof buf, "cell %d: vertex index %d outside [0, %d)", c, q[i], nv);
+                err = buf;
+                return false;
+            }
+        if (n == 4) {
+            tet(q[0], q[1], q[2], q[3]);
+        } else if (n == 5) {
+            quad(q[0], q[1], q[2], q[3], q[4]);
+        } else {
+            const size_t centre = out_v.size() / 3;
+            if (centre > (size_t)INT32_MAX) {
+                err = "more than 2^31 - 1 vertices with the cell centres";
+                return false;
+            }
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int i = 0; i < n; ++i) {
+                sx += V[3 * (size_t)q[i]];
+                sy += V[3 * (size_t)q[i] + 1];
+                sz += V[3 * (size_t)q[i] + 2];
+            }
+            out_v.push_back(sx / n);
+            out_v.push_back(sy / n);
+            out_v.push_back(sz / n);
+            for (int i = 0; i < 8; ++i) centre_nodes.push_back(i < n ? q[i] : -1);
+            const int32_t x = (int32_t)centre;
+            if (n == 6) {
+                for (const auto& f : kWedge) {
+                    if (f[3] < 0) tet(q[f[0]], q[f[1]], q[f[2]], x);
+                    else quad(q[f[0]], q[f[1]], q[f[2]], q[f[3]], x);
+                }
+            } else {
+                for (const auto& f : kHex) quad(q[f[0]], q[f[1]], q[f[2]], q[f[3]], x);
+            }
+        }
+        if (out_t.size() / 4 > (size_t)INT32_MAX) {
+            err = "more than 2^31 - 1 tetrahedra";
+            return false;
+        }
+    }
+    return true;
+}
+
 }  // namespace dpvr

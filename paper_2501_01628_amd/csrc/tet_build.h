@@ -39,6 +39,21 @@ struct TetTables {
     std::vector<int32_t> cell_tets;   // tetrahedra of each cell, ascending
 };
 
+// Tetrahedra of a part given as mixed cells (host arrays): sizes[c] = 4, 5,
+// 6 or 8 nodes (tetrahedron, pyramid, wedge, hexahedron; node orders as in
+// dpvr.h), their node indices one cell after another.  Every quadrilateral
+// is cut along the diagonal through its node of smallest id (ids: one per
+// vertex, NULL = the vertex index), a pyramid is its two base triangles
+// joined to its apex, and a wedge or hexahedron gets a centre vertex (the
+// sum of its node positions in node order over the node count) joined to
+// every triangle of its faces.  Appends the centre vertices to `vertices`
+// (a copy of the input first) and, per centre vertex, its cell's nodes to
+// `centre_nodes` (8 per centre, -1 after the last).  Returns false with a
+// message on invalid input.
+bool decompose_cells(const double* vertices, int32_t n_vertices, const int64_t* ids, const uint8_t* sizes,
+                     const int32_t* cell_vertices, int32_t n_cells, std::vector<double>& out_vertices,
+                     std::vector<int32_t>& out_tets, std::vector<int32_t>& centre_nodes, std::string& err);
+
 // Builds the tables of a part given as host arrays (vertices: n_vertices x 3
 // doubles x, y, z; tets: n_tets x 4 indices, either orientation).  Returns
 // false with a message on invalid input (index out of range, non-finite

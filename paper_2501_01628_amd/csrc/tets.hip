@@ -39,12 +39,27 @@ typedef __attribute__((address_space(1))) const float gfloat_t;
 typedef __attribute__((address_space(1))) const int32_t gint;
 typedef __attribute__((address_space(1))) const uint32_t guint;
 
-__global__ __launch_bounds__(256) void tet_values(const float* __restrict__ vv, const int4* __restrict__ tets,
-                                                  int32_t n, float4* __restrict__ vals) {
+// Value of vertex v: given, or (a cell centre) the mean of its cell's
+// nodes, summed in node order.
+__device__ inline float vertex_value(const float* __restrict__ vv, int32_t n_input,
+                                     const int32_t* __restrict__ centre_nodes, int32_t v) {
+    if (v < n_input) return vv[v];
+    const int32_t* c = centre_nodes + 8 * (long long)(v - n_input);
+    float s = 0.0f;
+    int n = 0;
+    for (; n < 8 && c[n] >= 0; ++n) s += vv[c[n]];
+    return s / (float)n;
+}
+
+__global__ __launch_bounds__(256) void tet_values(const float* __restrict__ vv, int32_t n_input,
+                                                  const int32_t* __restrict__ centre_nodes,
+                                                  const int4* __restrict__ tets, int32_t n,
+                                                  float4* __restrict__ vals) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
     const int4 t = tets[e];
-    vals[e] = make_float4(vv[t.x], vv[t.y], vv[t.z], vv[t.w]);
+    vals[e] = make_float4(vertex_value(vv, n_input, centre_nodes, t.x), vertex_value(vv, n_input, centre_nodes, t.y),
+                          vertex_value(vv, n_input, centre_nodes, t.z), vertex_value(vv, n_input, centre_nodes, t.w));
 }
 
 // Candidate sample indices [k0, k1] of the ray against the closed box
@@ -357,11 +372,11 @@ __global__ __launch_bounds__(256) void tet_resolve(TetFrameParams f) {
 
 }  // namespace
 
-hipError_t launch_tet_values(const float* vertex_values, const int32_t* tets, int32_t n_tets, float* vals,
-                             hipStream_t stream) {
+hipError_t launch_tet_values(const float* vertex_values, int32_t n_input, const int32_t* centre_nodes,
+                             const int32_t* tets, int32_t n_tets, float* vals, hipStream_t stream) {
     if (n_tets <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tet_values, dim3((n_tets + 255) / 256), dim3(256), 0, stream, vertex_values,
-                       reinterpret_cast<const int4*>(tets), n_tets, reinterpret_cast<float4*>(vals));
+    hipLaunchKernelGGL(tet_values, dim3((n_tets + 255) / 256), dim3(256), 0, stream, vertex_values, n_input,
+                       centre_nodes, reinterpret_cast<const int4*>(tets), n_tets, reinterpret_cast<float4*>(vals));
     return hipGetLastError();
 }
 

@@ -233,9 +233,49 @@ int main() {
         int32_t grid[3];
         int64_t entries = 0;
         size_t need[3] = {0, 0, 0};
-        for (int q = 0; q < 3; ++q) EXPECT(vr_tetpart_info(tp[q], lo, hi, grid, &entries, &need[q]) == VR_OK);
-        EXPECT(vr_tetpart_info(tp[1], lo, hi, grid, &entries, nullptr) == VR_OK && entries >= nt - 20);
+        int32_t ntets = 0;
+        for (int q = 0; q < 3; ++q) EXPECT(vr_tetpart_info(tp[q], lo, hi, grid, &entries, &need[q], nullptr) == VR_OK);
+        EXPECT(vr_tetpart_info(tp[1], lo, hi, grid, &entries, nullptr, &ntets) == VR_OK && entries >= nt - 20 &&
+               ntets == nt - 20);
         EXPECT(hi[0] == 2.0 && lo[0] == 0.0 && grid[0] >= 1);
+        // mixed cells: one hexahedron, two wedges and a pyramid on the unit cubes of the lattice
+        {
+            auto h8 = [&](int i, int j, int k, int32_t out8[8]) {
+                const int c[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+                for (int a = 0; a < 8; ++a) out8[a] = vid(i + c[a][0], j + c[a][1], k + c[a][2]);
+            };
+            int32_t h[8], w[8];
+            h8(0, 0, 0, h);
+            h8(1, 0, 0, w);
+            std::vector<uint8_t> sizes = {8, 6, 6, 5};
+            std::vector<int32_t> cells(h, h + 8);
+            for (int a : {0, 1, 2, 4, 5, 6, 0, 2, 3, 4, 6, 7}) cells.push_back(w[a]);
+            int32_t pz[8];
+            h8(0, 1, 0, pz);
+            for (int a : {0, 1, 2, 3}) cells.push_back(pz[a]);
+            cells.push_back(pz[6]);   // apex on the opposite corner (a valid, if skewed, pyramid)
+            std::vector<int64_t> ids(nv);
+            for (int v = 0; v < nv; ++v) ids[v] = 1000 + v;
+            vr_tetpart mp = nullptr;
+            EXPECT(vr_tetpart_create_cells(ctx, tv.data(), nv, ids.data(), sizes.data(), cells.data(), 4, &mp) == VR_OK);
+            size_t mneed = 0;
+            EXPECT(vr_tetpart_info(mp, lo, hi, grid, &entries, &mneed, &ntets) == VR_OK && ntets == 12 + 8 + 8 + 2);
+            std::vector<uint8_t> bad = {8, 7};
+            vr_tetpart bp = nullptr;
+            EXPECT(vr_tetpart_create_cells(ctx, tv.data(), nv, nullptr, bad.data(), cells.data(), 2, &bp) ==
+                   VR_ERR_INVALID_ARG && !bp);
+            cells[3] = nv + 5;
+            EXPECT(vr_tetpart_create_cells(ctx, tv.data(), nv, nullptr, sizes.data(), cells.data(), 4, &bp) ==
+                   VR_ERR_INVALID_ARG);
+            void* mws = aligned_buf(mneed);
+            EXPECT(vr_tetpart_attach(mp, mws, mneed) == VR_OK);
+            float* mv = static_cast<float*>(aligned_buf(nv * 4));
+            for (int v = 0; v < nv; ++v) mv[v] = 0.5f;
+            EXPECT(vr_tetpart_set_values(mp, mv) == VR_OK);
+            EXPECT(vr_tetpart_release(mp) == VR_OK);
+            std::free(mws);
+            std::free(mv);
+        }
         float* vals = static_cast<float*>(aligned_buf(nv * 4));
         for (int v = 0; v < nv; ++v) vals[v] = 0.1f * v;
         void* tws[3];

@@ -94,9 +94,20 @@ hipError_t launch_march_backward_many(const BackwardJob*, const int32_t*, int32_
 hipError_t launch_rqc_frame(RqcParams, int, hipStream_t) { return hipSuccess; }
 // The tetrahedral-part launchers touch every byte their kernels may touch,
 // so that a layout the host code sized wrongly shows up under ASan.
-hipError_t launch_tet_values(const float* vv, const int32_t* tets, int32_t n, float* vals, hipStream_t) {
+hipError_t launch_tet_values(const float* vv, int32_t n_input, const int32_t* centre_nodes, const int32_t* tets,
+                             int32_t n, float* vals, hipStream_t) {
     for (int32_t e = 0; e < n; ++e)
-        for (int j = 0; j < 4; ++j) vals[4 * e + j] = vv[tets[4 * e + j]];
+        for (int j = 0; j < 4; ++j) {
+            const int32_t v = tets[4 * e + j];
+            if (v < n_input) {
+                vals[4 * e + j] = vv[v];
+                continue;
+            }
+            float s = 0.0f;
+            int m = 0;
+            for (; m < 8 && centre_nodes[8 * (v - n_input) + m] >= 0; ++m) s += vv[centre_nodes[8 * (v - n_input) + m]];
+            vals[4 * e + j] = s / (float)m;
+        }
     return hipSuccess;
 }
 long long scan_blocks(long long n) { return (n + 1023) / 1024; }

@@ -303,3 +303,58 @@ def test_shadowed_ambient_one_equals_plain_frame_bitwise():
     img, total, _, plain = _gpu_shadowed(parts, vals, cam, 0.29, (1.0, 1.0, 1.0), 1.0, (0.0, 0.0, 0.0, 0.0))
     assert total > 0
     assert np.array_equal(img, plain)
+
+
+# -------------------------------------------------------- mixed cells
+def _mixed_gpu(parts, vals, cam, dt, bg=(0.0, 0.0, 0.0, 0.0)):
+    dp = _dp()
+    tf, vr, s = _tf()
+    r = dp.TetRenderer([(pv, psz, pcv, used) for pv, psz, pcv, used in parts], tf, vr, s, dt)
+    try:
+        for k, (_, _, _, used) in enumerate(parts):
+            r.set_values(k, vals[used])
+        r.set_camera(cam)
+        r.samples.zero_()
+        img = r.render(bg, count=True)
+        r.synchronize()
+        ntets = sum(i["n_tets"] for i in r.info)
+        return img.cpu().numpy().astype(np.float64), int(r.samples.item()), ntets
+    finally:
+        r.close()
+
+
+@pytest.mark.parametrize("n_parts,seed,rough", [(1, 41, False), (4, 42, True), (6, 43, False)])
+def test_mixed_cells_match_oracle(n_parts, seed, rough):
+    cells = (6, 5, 4)
+    rng = np.random.default_rng(seed)
+    v, sz, cv = synth.mixed_mesh(cells, jitter=0.15, rng=rng)
+    vals = synth.tet_field(v, rng, cells)
+    if n_parts == 1:
+        parts = [(v, sz, cv, np.arange(len(v)))]
+    else:
+        parts = synth.mixed_partitions(v, sz, cv, n_parts, rng, rough=rough)
+    cam = synth.orbit_camera((0, 0, 0), cells, 53, 41, az_deg=20.0 + 10 * seed, el_deg=30.0, radius_factor=1.5)
+    print(f"mixed cells: {len(sz)} in {n_parts} parts", flush=True)
+    img, held, ntets = _mixed_gpu(parts, vals, cam, 0.31, (0.1, 0.0, 0.05, 0.2))
+    tf, vr, s = _tf()
+    tparts = [oracle.cells_to_tets(pv, vals[used], psz, pcv, vertex_ids=used) for pv, psz, pcv, used in parts]
+    ref, cnt = oracle.render_tets(cam, tparts, tf, vr, s, 0.31, (0.1, 0.0, 0.05, 0.2))
+    assert ntets == sum(len(t[2]) for t in tparts)
+    assert cnt[1] == 0 and held == cnt[0]
+    assert np.max(np.abs(img - ref)) <= TOL
+
+
+def test_mixed_cells_linear_field_equals_brick():
+    cells = (5, 4, 3)
+    rng = np.random.default_rng(44)
+    v, sz, cv = synth.mixed_mesh(cells, jitter=0.1, rng=rng)
+    vals = (0.2 + 0.05 * v[:, 0] + 0.03 * v[:, 1] + 0.04 * v[:, 2]).astype(np.float32)
+    parts = synth.mixed_partitions(v, sz, cv, 3, rng)
+    cam = synth.orbit_camera((0, 0, 0), cells, 40, 36, az_deg=-30.0, el_deg=20.0, radius_factor=1.6)
+    img, _, _ = _mixed_gpu(parts, vals, cam, 0.27)
+    nx, ny, nz = cells
+    z, y, x = np.meshgrid(np.arange(nz + 2), np.arange(ny + 2), np.arange(nx + 2), indexing="ij")
+    vox = (0.2 + 0.05 * (x - 0.5) + 0.03 * (y - 0.5) + 0.04 * (z - 0.5)).astype(np.float32)
+    tf, vr, s = _tf()
+    ref, _, _ = oracle.render_brick(cam, vox, cells, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), tf, vr, s, 0.27)
+    assert np.max(np.abs(img - ref)) <= TOL
