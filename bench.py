@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["c2", "c1", "c3", "c4", "c5", "c5-adjoint", "rqc", "stream", "tets",
-                                                 "tets-shadow"],
+                                                 "tets-mixed", "tets-shadow"],
                     default="c2")
     ap.add_argument("--storage", choices=["f32", "f16"], default=None,
                     help="brick storage (default f32; c5 is a float16 workload: f16)")
@@ -926,22 +926,45 @@ TET_FP64_OPS_PER_SAMPLE = 43
 FP64_VECTOR_PEAK = 78.6e12
 
 
+def mixed_scene(cells=(96, 72, 72), n_parts=16, width=1920, height=1080):
+    """Mixed-element workload: a 96x72x72-cube box (jitter 0.15) whose
+    cubes are, by 2-cube blocks, hexahedra, wedge pairs, six pyramids around
+    a centre vertex, or six Kuhn tetrahedra (1,866,240 cells, 641,329
+    vertices), 8 blobs at the vertices, 16 smooth non-convex parts by cell
+    centroid, 1920x1080 orbit view, step 0.5 cube, opacity 0.05."""
+    import synth
+    rng = np.random.default_rng(14)
+    v, sz, cv = synth.mixed_mesh(cells, jitter=0.15, rng=rng)
+    vals = synth.tet_field(v, rng, cells, n_blobs=8)
+    parts = synth.mixed_partitions(v, sz, cv, n_parts, rng)
+    cam = synth.orbit_camera((0, 0, 0), cells, width, height)
+    return vals, parts, cam, len(sz), len(v)
+
+
 def bench_tets(args):
-    """Unstructured data: a tetrahedral mesh in 16 non-convex parts; one step
-    = the march of every part into runs + the per-pixel resolve."""
+    """Unstructured data: a tetrahedral (or, for tets-mixed, mixed-element)
+    mesh in 16 non-convex parts; one step = the march of every part into
+    runs + the per-pixel resolve."""
     import torch
 
     import paper_2501_01628_amd as dp
     import synth
+    mixed = args.workload == "tets-mixed"
     t0 = time.perf_counter()
-    vals, parts, cam, n_tets, n_verts = tet_scene()
-    log(f"generated {n_tets} tetrahedra in {len(parts)} parts in {time.perf_counter() - t0:.1f} s")
+    if mixed:
+        vals, parts, cam, n_cells, n_verts = mixed_scene()
+        box = (96.0, 72.0, 72.0)
+    else:
+        vals, parts, cam, n_cells, n_verts = tet_scene()
+        box = (128.0, 96.0, 96.0)
+    log(f"generated {n_cells} cells in {len(parts)} parts in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     tf = synth.default_tf()
-    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, (0.0, 1.0), 0.05, 0.5, max_runs=32)
+    r = dp.TetRenderer([p if mixed else p[:2] for p in parts], tf, (0.0, 1.0), 0.05, 0.5, max_runs=32)
     host_build_s = time.perf_counter() - t0
-    for k, (_, _, used) in enumerate(parts):
-        r.set_values(k, vals[used])
+    n_tets = sum(i["n_tets"] for i in r.info)
+    for k, part in enumerate(parts):
+        r.set_values(k, vals[part[-1]])
     r.set_camera(cam)
     r.synchronize()
     r.values = [None] * len(parts)
@@ -978,13 +1001,19 @@ def bench_tets(args):
         f"{resolve_ms:.3f} ms, {held} held samples/frame")
     W, H = cam["width"], cam["height"]
     achieved = held * TET_FP64_OPS_PER_SAMPLE / (march_ms * 1e-3)
+    if mixed:
+        wl = (f"tets-mixed: {n_cells} cells (hexahedra, wedges, pyramids, tetrahedra of jittered 96x72x72 "
+              f"cubes; {n_tets} tetrahedra after the cut, {n_verts} vertices), 8 blobs, {len(parts)} non-convex "
+              f"parts, {W}x{H} perspective, step 0.5, opacity 0.05, max 32 runs per ray and part")
+    else:
+        wl = (f"tets: {n_tets} tetrahedra ({n_verts} vertices, jittered 128x96x96 cubes), 8 blobs, "
+              f"{len(parts)} non-convex parts, {W}x{H} perspective, step 0.5, opacity 0.05, max 32 runs per ray "
+              f"and part")
     out = {"metric": "Msamples/s (tetrahedral parts: samples held by a tetrahedron per frame x frames/s)",
            "value": held / (ms_per_step * 1e-3) / 1e6, "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "fps": 1e3 / ms_per_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64 location, f32 shading", "data": "synthetic",
-           "config": {"workload": f"tets: {n_tets} tetrahedra ({n_verts} vertices, jittered 128x96x96 cubes), "
-                                  f"8 blobs, {len(parts)} non-convex parts, {W}x{H} perspective, step 0.5, "
-                                  f"opacity 0.05, max 32 runs per ray and part"},
+           "config": {"workload": wl},
            "samples_per_frame": held, "ms_march": march_ms, "ms_resolve": resolve_ms,
            "host_table_build_s": host_build_s, "device_table_bytes": table_bytes,
            "grid_entries_per_tet": grid_entries / n_tets,
@@ -999,14 +1028,17 @@ def bench_tets(args):
         import oracle
         log("cpu baseline (oracle, brute-force location, on a pixel sample) ...")
         rng = np.random.default_rng(5)
-        tparts = [(pv, vals[used], pt) for pv, pt, used in parts]
+        if mixed:
+            tparts = [oracle.cells_to_tets(pv, vals[used], psz, pcv, vertex_ids=used) for pv, psz, pcv, used in parts]
+        else:
+            tparts = [(pv, vals[used], pt) for pv, pt, used in parts]
         # The oracle tests every sample against every tetrahedron (about 0.3 s
         # per sample here), so the sample is pixels whose rays cross the mesh
         # box in a short chord (8 to 24 samples; the mesh fills its box, so
         # every one of them is held): its rate per sample is the oracle's.
         hit = np.argwhere(frame[..., 3] > 0.0)
         cand = hit[rng.choice(len(hit), min(20000, len(hit)), replace=False)]
-        hi = np.array([128.0, 96.0, 96.0])
+        hi = np.array(box)
         short = []
         for j, i in cand:
             o, d = oracle.ray(cam, int(i), int(j))
@@ -1160,7 +1192,7 @@ def main():
         return bench_rqc(args)
     if args.workload == "stream":
         return bench_stream(args)
-    if args.workload == "tets":
+    if args.workload in ("tets", "tets-mixed"):
         return bench_tets(args)
     if args.workload == "tets-shadow":
         return bench_tets_shadow(args)

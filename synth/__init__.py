@@ -620,14 +620,14 @@ def mixed_partitions(verts, sizes, cell_vertices, n_parts, rng, rough=False):
     """Parts of a mixed mesh by the rule of :func:`tet_partitions` on cell
     centroids.  Returns a list of (vertices, sizes, cell_vertices, used) per
     part: local numbering, used = the global index of each local vertex."""
-    start = np.concatenate([[0], np.cumsum(sizes.astype(np.int64))])
-    cen = np.stack([verts[cell_vertices[start[c]:start[c + 1]]].mean(0) for c in range(len(sizes))])
+    n = sizes.astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(n)])
+    cen = np.add.reduceat(verts[cell_vertices], start[:-1], axis=0) / n[:, None]
     owner = _partition_owner(cen, verts.min(0), verts.max(0), n_parts, rng, rough)
+    slot_owner = np.repeat(owner, n)
     parts = []
     for p in range(n_parts):
-        idx = np.nonzero(owner == p)[0]
-        sel = np.concatenate([cell_vertices[start[c]:start[c + 1]] for c in idx]) if len(idx) else \
-            np.zeros(0, dtype=np.int32)
+        sel = cell_vertices[slot_owner == p]
         used, inv = np.unique(sel, return_inverse=True)
-        parts.append((verts[used].copy(), sizes[idx].copy(), inv.astype(np.int32), used))
+        parts.append((verts[used].copy(), sizes[owner == p].copy(), inv.astype(np.int32), used))
     return parts
