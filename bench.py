@@ -1177,7 +1177,7 @@ def bench_tets_shadow(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU only: --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes, not built)"}))
         return 2
     if args.summarize_pmc:

@@ -74,7 +74,7 @@ typedef enum {
     VR_ERR_INVALID_ARG = -1,     /* argument out of range or inconsistent */
     VR_ERR_INVALID_HANDLE = -2,  /* NULL or released handle */
     VR_ERR_WORKSPACE = -3,       /* caller workspace too small or misaligned */
-    VR_ERR_UNSUPPORTED = -4,     /* valid request this build does not implement */
+    VR_ERR_UNSUPPORTED = -4,     /* valid request the library does not implement */
     VR_ERR_DEVICE = -5,          /* HIP runtime error (launch or asynchronous fault) */
     VR_ERR_STATE = -6,           /* required state (camera, transfer function) not set */
     VR_ERR_OUT_OF_MEMORY = -7    /* a host (or pinned host) allocation of the library failed */
