@@ -1178,7 +1178,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: --gpus must be 1 "
-                                   "(multi-GPU sharding is described in the design notes, not built)"}))
+                                   "(sharding over several GPUs is not built)"}))
         return 2
     if args.summarize_pmc:
         return summarize_pmc(args)
