@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--view", type=float, nargs=2, metavar=("AZ", "EL"), default=None,
                     help="c1/c2/c5: orbit the camera to azimuth/elevation AZ EL degrees instead of the "
                          "workload's 30/20 (e.g. 90 0: rays along x, which no staged slab axis takes)")
+    ap.add_argument("--tet-locator", choices=["grid", "bvh"], default="grid",
+                    help="tets workloads: where a sample the walk misses is searched (same images)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -960,7 +962,8 @@ def bench_tets(args):
     log(f"generated {n_cells} cells in {len(parts)} parts in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     tf = synth.default_tf()
-    r = dp.TetRenderer([p if mixed else p[:2] for p in parts], tf, (0.0, 1.0), 0.05, 0.5, max_runs=32)
+    r = dp.TetRenderer([p if mixed else p[:2] for p in parts], tf, (0.0, 1.0), 0.05, 0.5, max_runs=32,
+                       locator=dp.VR_TET_BVH if args.tet_locator == "bvh" else dp.VR_TET_GRID)
     host_build_s = time.perf_counter() - t0
     n_tets = sum(i["n_tets"] for i in r.info)
     for k, part in enumerate(parts):
@@ -1013,7 +1016,7 @@ def bench_tets(args):
            "value": held / (ms_per_step * 1e-3) / 1e6, "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "fps": 1e3 / ms_per_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64 location, f32 shading", "data": "synthetic",
-           "config": {"workload": wl},
+           "config": {"workload": wl, "locator": args.tet_locator},
            "samples_per_frame": held, "ms_march": march_ms, "ms_resolve": resolve_ms,
            "host_table_build_s": host_build_s, "device_table_bytes": table_bytes,
            "grid_entries_per_tet": grid_entries / n_tets,
@@ -1088,7 +1091,8 @@ def bench_tets_shadow(args):
     parts = synth.tet_partitions(v, t, n_parts, rng)
     cam = synth.orbit_camera((0, 0, 0), cells, 768, 768)
     tf = synth.default_tf()
-    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, (0.0, 1.0), 0.1, 0.5, max_runs=32)
+    r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, (0.0, 1.0), 0.1, 0.5, max_runs=32,
+                       locator=dp.VR_TET_BVH if args.tet_locator == "bvh" else dp.VR_TET_GRID)
     for k, (_, _, used) in enumerate(parts):
         r.set_values(k, vals[used])
     r.set_camera(cam)

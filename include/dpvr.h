@@ -618,8 +618,10 @@ vr_status vr_render_rqc(vr_context ctx, int32_t n, const vr_brick* bricks, const
  *            parts in index order, "over" one another, over a background --
  *            the same image as accumulating the ray through the whole mesh.
  * The paper locates elements with a bounding volume hierarchy (Sec. 2.1);
- * here each part keeps a uniform grid over its bounding box whose cells list
- * the tetrahedra that can hold a point of the cell. */
+ * here a sample is first sought by a walk from the previous sample's
+ * tetrahedron across face neighbours, then in a uniform grid over the part's
+ * bounding box whose cells list the tetrahedra that can hold a point of the
+ * cell (or, by vr_set_tet_locator, in a BVH). */
 typedef struct vr_tetpart_s* vr_tetpart;
 
 #define DPVR_MAX_TET_PARTS 64        /* parts per vr_render_tetparts call */
@@ -628,7 +630,8 @@ typedef struct vr_tetpart_s* vr_tetpart;
 /* Create a part from host arrays: vertices (n_vertices x 3 doubles, x, y, z),
  * tets (n_tets x 4 vertex indices, either orientation).  Builds the part's
  * location tables in host memory (face planes, tie bits, face neighbours,
- * the grid); the arrays are not kept.  n_tets may be 0 (a part that owns nothing).
+ * the grid, the BVH); the arrays are not kept.  At most 2^28 - 1
+ * tetrahedra per part.  n_tets may be 0 (a part that owns nothing).
  * Errors: VR_ERR_INVALID_HANDLE, VR_ERR_INVALID_ARG (index out of range,
  * non-finite coordinate, zero-volume tetrahedron, a face shared by more than
  * two tetrahedra, more than 2^31 - 1 grid entries), VR_ERR_OUT_OF_MEMORY. */
@@ -655,6 +658,16 @@ vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_ve
 vr_status vr_tetpart_create_cells(vr_context ctx, const double* vertices, int32_t n_vertices, const int64_t* vertex_ids,
                                   const uint8_t* cell_sizes, const int32_t* cell_vertices, int32_t n_cells,
                                   vr_tetpart* out);
+
+/* Where a sample is searched when the walk from the previous sample's
+ * tetrahedron does not find it (every choice locates the same owner, so
+ * images are bit-identical): VR_TET_GRID, the part's uniform grid of
+ * candidate lists (default); VR_TET_BVH, a bounding volume hierarchy over
+ * the part's tetrahedra (the paper's element-location structure, Sec. 2.1:
+ * boxes tested top down, tetrahedra at the leaves), traversed without a
+ * stack through skip links. */
+typedef enum { VR_TET_GRID = 0, VR_TET_BVH = 1 } vr_tet_locator;
+vr_status vr_set_tet_locator(vr_context ctx, vr_tet_locator locator);
 
 /* The part's closed bounding box, grid cells per axis, grid entries, the
  * bytes of device workspace it needs and its tetrahedra (any pointer may be

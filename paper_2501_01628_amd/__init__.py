@@ -160,6 +160,7 @@ _SIGS = {
                          C.POINTER(C.c_int32)], _st),
     "vr_tetpart_create_cells": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.POINTER(C.c_void_p)], _st),
+    "vr_set_tet_locator": ([C.c_void_p, C.c_int], _st),
     "vr_tetpart_attach": ([C.c_void_p, C.c_void_p, C.c_size_t], _st),
     "vr_tetpart_set_values": ([C.c_void_p, C.c_void_p], _st),
     "vr_tetpart_release": ([C.c_void_p], _st),
@@ -435,6 +436,13 @@ def vr_tetpart_create_cells(ctx, vertices, sizes, cell_vertices, vertex_ids=None
     return h
 
 
+VR_TET_GRID, VR_TET_BVH = 0, 1
+
+
+def vr_set_tet_locator(ctx, locator):
+    _check(_lib.vr_set_tet_locator(ctx, int(locator)), ctx)
+
+
 def vr_tetpart_info(part, ctx=None):
     lo, hi, grid = _d3(), _d3(), _i3()
     entries, nbytes, nt = C.c_int64(), C.c_size_t(), C.c_int32()
@@ -646,7 +654,7 @@ class TetRenderer:
     :meth:`set_values`."""
 
     def __init__(self, parts, tf, vrange=(0.0, 1.0), opacity_scale=1.0, dt=0.5, device=0, stream=None,
-                 max_runs=8):
+                 max_runs=8, locator=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -655,6 +663,8 @@ class TetRenderer:
         self.tf = torch.as_tensor(np.ascontiguousarray(tf, dtype=np.float32)).to(self.device)
         vr_set_transfer_function(self.ctx, self.tf, TF_ENTRIES, vrange[0], vrange[1], opacity_scale)
         vr_set_render_params(self.ctx, dt, 0.0)
+        if locator is not None:
+            vr_set_tet_locator(self.ctx, locator)
         self.max_runs = int(max_runs)
         self.parts, self.workspaces, self.values, self.info = [], [], [], []
         for part in parts:

@@ -49,6 +49,7 @@ struct vr_context_s {
     int32_t path = kPathStaged;
     int32_t live_bricks = 0;
     int32_t live_tetparts = 0;
+    int32_t tet_locator = kTetGrid;   // structure searched after the walk (vr_set_tet_locator)
     std::string err;
     // vr_render_partials_static: this device's library-owned scratch array
     // (address from hipGetSymbolAddress at context creation) and two pinned
@@ -1718,9 +1719,9 @@ struct vr_tetpart_s {
     TetTables tab;
     int32_t n_input_vertices = 0;        // vertices whose values the caller gives
     std::vector<int32_t> centre_nodes;   // cell centres: 8 node indices each (-1 padded)
-    // device workspace: [planes][vals][owned][tets][cell_start][cell_tets][nbr][centre_nodes],
-    // each 256-aligned
-    size_t off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // device workspace: [planes][vals][owned][tets][cell_start][cell_tets][nbr][centre_nodes]
+    // [bvh_nodes][bvh_tets], each 256-aligned
+    size_t off[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     size_t need = 0;
     char* ws = nullptr;
     bool has_values = false;
@@ -1728,7 +1729,7 @@ struct vr_tetpart_s {
 
 namespace {
 
-size_t tetpart_layout(const TetTables& t, const std::vector<int32_t>& centre_nodes, size_t off[8]) {
+size_t tetpart_layout(const TetTables& t, const std::vector<int32_t>& centre_nodes, size_t off[10]) {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t nt = (size_t)t.n_tets;
     size_t o = 0;
@@ -1740,6 +1741,8 @@ size_t tetpart_layout(const TetTables& t, const std::vector<int32_t>& centre_nod
     off[5] = o; o += up(t.cell_tets.size() * sizeof(int32_t));
     off[6] = o; o += up(t.nbr.size() * sizeof(int32_t));
     off[7] = o; o += up(centre_nodes.size() * sizeof(int32_t));
+    off[8] = o; o += up(t.bvh_nodes.size() * sizeof(int32_t));
+    off[9] = o; o += up(t.bvh_tets.size() * sizeof(int32_t));
     return o;
 }
 
@@ -1766,6 +1769,8 @@ size_t tetframe_layout(vr_context ctx, int32_t n, const vr_tetpart* parts, int32
             k.cell_start = reinterpret_cast<const int32_t*>(q->ws + q->off[4]);
             k.cell_tets = reinterpret_cast<const int32_t*>(q->ws + q->off[5]);
             k.nbr = reinterpret_cast<const int32_t*>(q->ws + q->off[6]);
+            k.bvh_nodes = reinterpret_cast<const int32_t*>(q->ws + q->off[8]);
+            k.bvh_tets = reinterpret_cast<const int32_t*>(q->ws + q->off[9]);
             for (int c = 0; c < 3; ++c) {
                 k.lo[c] = t.lo[c];
                 k.hi[c] = t.hi[c];
@@ -1894,6 +1899,14 @@ static vr_status tetpart_create(vr_context ctx, const double* vertices, int32_t 
     return ok(ctx);
 }
 
+vr_status vr_set_tet_locator(vr_context ctx, vr_tet_locator locator) {
+    if (!live(ctx)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_set_tet_locator: invalid context");
+    if (locator != VR_TET_GRID && locator != VR_TET_BVH)
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_set_tet_locator: unknown locator %d", (int)locator);
+    ctx->tet_locator = locator == VR_TET_BVH ? kTetBvh : kTetGrid;
+    return ok(ctx);
+}
+
 vr_status vr_tetpart_create(vr_context ctx, const double* vertices, int32_t n_vertices, const int32_t* tets,
                             int32_t n_tets, vr_tetpart* out) {
     return tetpart_create(ctx, vertices, n_vertices, nullptr, tets, n_tets, nullptr, nullptr, 0, out,
@@ -1938,13 +1951,15 @@ vr_status vr_tetpart_attach(vr_tetpart q, void* workspace, size_t workspace_byte
         size_t off;
         const void* src;
         size_t bytes;
-    } copies[7] = {{q->off[0], t.planes.data(), t.planes.size() * sizeof(double)},
+    } copies[9] = {{q->off[0], t.planes.data(), t.planes.size() * sizeof(double)},
                    {q->off[2], t.owned.data(), t.owned.size() * sizeof(uint32_t)},
                    {q->off[3], t.tets.data(), t.tets.size() * sizeof(int32_t)},
                    {q->off[4], t.cell_start.data(), t.cell_start.size() * sizeof(int32_t)},
                    {q->off[5], t.cell_tets.data(), t.cell_tets.size() * sizeof(int32_t)},
                    {q->off[6], t.nbr.data(), t.nbr.size() * sizeof(int32_t)},
-                   {q->off[7], q->centre_nodes.data(), q->centre_nodes.size() * sizeof(int32_t)}};
+                   {q->off[7], q->centre_nodes.data(), q->centre_nodes.size() * sizeof(int32_t)},
+                   {q->off[8], t.bvh_nodes.data(), t.bvh_nodes.size() * sizeof(int32_t)},
+                   {q->off[9], t.bvh_tets.data(), t.bvh_tets.size() * sizeof(int32_t)}};
     hipError_t e = hipSuccess;
     for (const auto& c : copies)
         if (e == hipSuccess && c.bytes > 0)
@@ -2109,6 +2124,7 @@ static vr_status tet_frame(vr_context ctx, int32_t n, const vr_tetpart* parts, i
     f.out = out;
     f.samples = samples;
     f.err = err_word(ctx);
+    f.locator = ctx->tet_locator;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
     hipError_t e = hipSuccess;

@@ -240,6 +240,7 @@ hipError_t launch_rqc_frame(RqcParams p, int cus, hipStream_t stream);
 // (maximal stretches of consecutive lattice samples the part holds) of every
 // ROI pixel's ray.
 constexpr int kMaxTetRuns = 32;
+enum : int32_t { kTetGrid = 0, kTetBvh = 1 };
 constexpr int kMaxTetParts = 64;
 struct TetPartK {
     const double* planes;       // n_tets x 16: per face (nx, ny, nz, c), D = n.p - c >= 0 inside
@@ -248,6 +249,8 @@ struct TetPartK {
     const int32_t* cell_start;  // grid cells + 1
     const int32_t* cell_tets;
     const int32_t* nbr;         // n_tets x 4: tetrahedron across each face (-1: none in the part)
+    const int32_t* bvh_nodes;   // BVH nodes, 8 words each (tet_build.h)
+    const int32_t* bvh_tets;    // leaves' tetrahedra
     double lo[3], hi[3];        // closed bounding box
     double glo[3], ginv[3];     // grid origin, cells per world unit
     int32_t gdim[3];
@@ -271,6 +274,7 @@ struct TetFrameParams {
     float* out;                 // height x width x 4
     unsigned long long* samples;  // optional: += samples held by a tetrahedron (primary and shadow)
     int32_t* err;               // device error word
+    int32_t locator;            // after the walk: kTetGrid or kTetBvh
     // shadow rays (one directional light): per frame entry the first slot of
     // its held primary samples (offsets[n_entries] = total), per slot the
     // sample index and the shadow transmittance

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
+#include <functional>
 
 namespace dpvr {
 namespace {
@@ -54,12 +56,95 @@ bool may_hold(const double* planes, const double ctr[3], const double h[3]) {
     return true;
 }
 
+// BVH over the tetrahedra (median split of the centroids on the longest
+// axis of their bounds, leaves of at most kLeaf), nodes in depth-first
+// order with skip links, so that a point query needs no stack.
+constexpr int kLeaf = 4;
+
+void build_bvh(const double* V, const int32_t* T, int32_t nt, TetTables& out) {
+    out.bvh_nodes.clear();
+    out.bvh_tets.resize(nt);
+    if (nt == 0) return;
+    std::vector<double> box((size_t)nt * 6), cen((size_t)nt * 3);
+    for (int32_t e = 0; e < nt; ++e) {
+        double* b = &box[6 * (size_t)e];
+        for (int c = 0; c < 3; ++c) {
+            b[c] = INFINITY;
+            b[3 + c] = -INFINITY;
+        }
+        for (int j = 0; j < 4; ++j)
+            for (int c = 0; c < 3; ++c) {
+                const double x = V[3 * (size_t)T[4 * (size_t)e + j] + c];
+                b[c] = std::fmin(b[c], x);
+                b[3 + c] = std::fmax(b[3 + c], x);
+            }
+        for (int c = 0; c < 3; ++c) cen[3 * (size_t)e + c] = 0.5 * (b[c] + b[3 + c]);
+        out.bvh_tets[e] = e;
+    }
+    // float32 bounds that contain the float64 box
+    auto down = [](double x) {
+        const float f = (float)x;
+        return (double)f > x ? std::nextafter(f, -INFINITY) : f;
+    };
+    auto up = [](double x) {
+        const float f = (float)x;
+        return (double)f < x ? std::nextafter(f, INFINITY) : f;
+    };
+    auto bits = [](float f) {
+        int32_t i;
+        std::memcpy(&i, &f, sizeof i);
+        return i;
+    };
+    std::function<void(int32_t, int32_t)> rec = [&](int32_t first, int32_t count) {
+        const size_t node = out.bvh_nodes.size() / 8;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int32_t i = first; i < first + count; ++i) {
+            const int32_t e = out.bvh_tets[i];
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = std::fmin(lo[c], box[6 * (size_t)e + c]);
+                hi[c] = std::fmax(hi[c], box[6 * (size_t)e + 3 + c]);
+                clo[c] = std::fmin(clo[c], cen[3 * (size_t)e + c]);
+                chi[c] = std::fmax(chi[c], cen[3 * (size_t)e + c]);
+            }
+        }
+        for (int c = 0; c < 3; ++c) out.bvh_nodes.push_back(bits(down(lo[c])));
+        out.bvh_nodes.push_back(-1);
+        for (int c = 0; c < 3; ++c) out.bvh_nodes.push_back(bits(up(hi[c])));
+        out.bvh_nodes.push_back(-1);
+        if (count <= kLeaf) {
+            out.bvh_nodes[8 * node + 7] = 8 * first + count;
+        } else {
+            int axis = 0;
+            for (int c = 1; c < 3; ++c)
+                if (chi[c] - clo[c] > chi[axis] - clo[axis]) axis = c;
+            const int32_t half = count / 2;
+            std::nth_element(out.bvh_tets.begin() + first, out.bvh_tets.begin() + first + half,
+                             out.bvh_tets.begin() + first + count, [&](int32_t a, int32_t b) {
+                                 const double ca = cen[3 * (size_t)a + axis], cb = cen[3 * (size_t)b + axis];
+                                 return ca < cb || (ca == cb && a < b);
+                             });
+            rec(first, half);
+            rec(first + half, count - half);
+        }
+        out.bvh_nodes[8 * node + 3] = (int32_t)(out.bvh_nodes.size() / 8);   // the node after the subtree
+    };
+    rec(0, nt);
+    const int32_t n_nodes = (int32_t)(out.bvh_nodes.size() / 8);
+    for (int32_t q = 0; q < n_nodes; ++q)
+        if (out.bvh_nodes[8 * (size_t)q + 3] >= n_nodes) out.bvh_nodes[8 * (size_t)q + 3] = -1;
+}
+
 }  // namespace
 
 bool build_tet_tables(const double* V, int32_t nv, const int32_t* T, int32_t nt, TetTables& out,
                       std::string& err) {
     char buf[256];
     out = TetTables{};
+    if (nt >= (1 << 28)) {
+        err = "a part of 2^28 or more tetrahedra (split it into smaller parts)";
+        return false;
+    }
     out.n_tets = nt;
     out.n_vertices = nv;
     out.planes.resize((size_t)nt * 16);
@@ -150,6 +235,7 @@ bool build_tet_tables(const double* V, int32_t nv, const int32_t* T, int32_t nt,
             out.gdim[c] = 1;
         }
         out.cell_start.assign(2, 0);
+        build_bvh(V, T, nt, out);
         return true;
     }
     // Grid: about one cell per tetrahedron, cubic cells, over the box grown
@@ -216,6 +302,7 @@ bool build_tet_tables(const double* V, int32_t nv, const int32_t* T, int32_t nt,
     out.cell_tets.resize((size_t)count[cells]);
     std::vector<int32_t> fill(out.cell_start.begin(), out.cell_start.end() - 1);
     for (int32_t e = 0; e < nt; ++e) for_cells(e, [&](size_t q) { out.cell_tets[fill[q]++] = e; });
+    build_bvh(V, T, nt, out);
     return true;
 }
 

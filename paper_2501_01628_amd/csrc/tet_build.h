@@ -37,6 +37,15 @@ struct TetTables {
     int32_t gdim[3];
     std::vector<int32_t> cell_start;  // gdim product + 1 (exclusive prefix)
     std::vector<int32_t> cell_tets;   // tetrahedra of each cell, ascending
+    // Bounding volume hierarchy over the tetrahedra, nodes in depth-first
+    // order (a node's first child follows it), 8 words each: lo x, y, z
+    // (float32 bits), skip; hi x, y, z (float32 bits), leaf.  The box is
+    // rounded outward, so it holds every float64 point of its tetrahedra's
+    // boxes; skip = the node after the subtree (-1: none); leaf = -1 for an
+    // inner node, else 8 first + count: the leaf's tetrahedra are
+    // bvh_tets[first .. first + count), count <= 4.
+    std::vector<int32_t> bvh_nodes;
+    std::vector<int32_t> bvh_tets;
 };
 
 // Tetrahedra of a part given as mixed cells (host arrays): sizes[c] = 4, 5,

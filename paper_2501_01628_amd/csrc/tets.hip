@@ -114,16 +114,45 @@ __device__ inline void count_held(unsigned long long* counter, unsigned long lon
     if ((threadIdx.x & 63) == 0 && n) atomicAdd(counter, n);
 }
 
+// The tetrahedron of part P that holds p (-1: none) by the BVH: from the
+// root, a node whose box holds p is entered (its first child follows it; a
+// leaf's tetrahedra are tested), any other is skipped through its skip link.
+__device__ inline int bvh_locate(const TetPartK& P, double p0, double p1, double p2, double D[4]) {
+    int node = P.n_tets > 0 ? 0 : -1, face = 0;
+    while (node >= 0) {
+        gint* nd = ((gint*)P.bvh_nodes) + 8 * (long long)node;
+        const int skip = nd[3], leaf = nd[7];
+        const bool in = p0 >= (double)__int_as_float(nd[0]) && p1 >= (double)__int_as_float(nd[1]) &&
+                        p2 >= (double)__int_as_float(nd[2]) && p0 <= (double)__int_as_float(nd[4]) &&
+                        p1 <= (double)__int_as_float(nd[5]) && p2 <= (double)__int_as_float(nd[6]);
+        if (!in) {
+            node = skip;
+        } else if (leaf >= 0) {
+            const int first = leaf >> 3, count = leaf & 7;
+            for (int i = 0; i < count; ++i) {
+                const int e = ((gint*)P.bvh_tets)[first + i];
+                if (holds(P, e, p0, p1, p2, D, &face)) return e;
+            }
+            node = skip;
+        } else {
+            node = node + 1;
+        }
+    }
+    return -1;
+}
+
 // The tetrahedron of part P that holds p (-1: none): one candidate per loop
 // trip, so that the lanes of a wavefront stay on the same code -- first the
 // walk from tetrahedron `from` (kWalkSteps tests, across the first face that
 // rejects p), then the tetrahedra of p's grid cell.  D: its sub-volumes.
+template <int kLocator>
 __device__ inline int locate(const TetPartK& P, int from, double p0, double p1, double p2, double D[4]) {
 #pragma clang fp contract(off)
     int cand = from, face = 0, walk = kWalkSteps, q = 0, qend = 0;
     bool grid = false;
     for (;;) {
         if (cand < 0) {
+            if (kLocator == kTetBvh) return bvh_locate(P, p0, p1, p2, D);
             if (!grid) {
                 grid = true;
                 const double u0 = (p0 - P.glo[0]) * P.ginv[0], u1 = (p1 - P.glo[1]) * P.ginv[1],
@@ -160,7 +189,7 @@ constexpr int kTetThreads = kTetTile * kTetTile;
 // (runs), kTetCount (held samples per frame entry into offsets), kTetRecord
 // (the sample index of every held sample into its slot) and kTetShaded (runs
 // with every held sample's emission scaled by a0 + (1 - a0) S from its slot).
-template <int kMode>
+template <int kMode, int kLocator>
 __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
     constexpr bool kRuns = kMode == kTetMarch || kMode == kTetShaded;
     __shared__ TFTable tft;
@@ -223,7 +252,7 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
         const double t = ((double)k + 0.5) * f.dt;
         const double p0 = r.o[0] + t * r.d[0], p1 = r.o[1] + t * r.d[1], p2 = r.o[2] + t * r.d[2];
         double D[4];
-        const int e = locate(P, last, p0, p1, p2, D);
+        const int e = locate<kLocator>(P, last, p0, p1, p2, D);
         last = e;
         if (e < 0) {
             if (kRuns && in_run) close_run();
@@ -274,6 +303,7 @@ __global__ __launch_bounds__(kTetThreads) void tet_march(TetFrameParams f) {
 // sample (its slot) through part (home + s) mod n, home the part that holds
 // the sample; the slot's transmittance is multiplied by the part's (products
 // commute, so the visiting order does not matter to the value).
+template <int kLocator>
 __global__ __launch_bounds__(256) void tet_shadow_step(TetFrameParams f) {
     __shared__ TFTable tft;
     load_tf(tft, f.tf, f.dt, threadIdx.x, 256);
@@ -315,7 +345,7 @@ __global__ __launch_bounds__(256) void tet_shadow_step(TetFrameParams f) {
                 const double t = ((double)jj + 0.5) * f.dt;
                 const double p0 = sr.o[0] + t * sr.d[0], p1 = sr.o[1] + t * sr.d[1], p2 = sr.o[2] + t * sr.d[2];
                 double D[4];
-                last = locate(at, last, p0, p1, p2, D);
+                last = locate<kLocator>(at, last, p0, p1, p2, D);
                 if (last < 0) continue;
                 S = S * trans_exp2(-classify(tft, tet_value(at, last, D), tf_k, tf_o).a);
                 ++evaluated;
@@ -370,6 +400,23 @@ __global__ __launch_bounds__(256) void tet_resolve(TetFrameParams f) {
         make_float4(fmaf(w, f.bg[0], C0), fmaf(w, f.bg[1], C1), fmaf(w, f.bg[2], C2), fmaf(w, f.bg[3], A));
 }
 
+template <int kLocator>
+void launch_tet_stages(TetFrameParams p, int stages, hipStream_t stream) {
+    const dim3 tiles(p.total_tiles), threads(kTetThreads);
+    if (p.total_tiles <= 0) return;
+    if (stages & kTetCount) hipLaunchKernelGGL((tet_march<kTetCount, kLocator>), tiles, threads, 0, stream, p);
+    if (stages & kTetRecord) hipLaunchKernelGGL((tet_march<kTetRecord, kLocator>), tiles, threads, 0, stream, p);
+    if ((stages & kTetShadow) && p.total > 0) {
+        const unsigned grid = (unsigned)min((p.total + 255) / 256, (long long)65536);
+        for (int s = 0; s < p.n; ++s) {
+            p.step = s;
+            hipLaunchKernelGGL(tet_shadow_step<kLocator>, dim3(grid), dim3(256), 0, stream, p);
+        }
+    }
+    if (stages & kTetMarch) hipLaunchKernelGGL((tet_march<kTetMarch, kLocator>), tiles, threads, 0, stream, p);
+    if (stages & kTetShaded) hipLaunchKernelGGL((tet_march<kTetShaded, kLocator>), tiles, threads, 0, stream, p);
+}
+
 }  // namespace
 
 hipError_t launch_tet_values(const float* vertex_values, int32_t n_input, const int32_t* centre_nodes,
@@ -381,20 +428,10 @@ hipError_t launch_tet_values(const float* vertex_values, int32_t n_input, const 
 }
 
 hipError_t launch_tet_frame(TetFrameParams p, int stages, hipStream_t stream) {
-    const dim3 tiles(p.total_tiles), threads(kTetThreads);
-    if (p.total_tiles > 0) {
-        if (stages & kTetCount) hipLaunchKernelGGL(tet_march<kTetCount>, tiles, threads, 0, stream, p);
-        if (stages & kTetRecord) hipLaunchKernelGGL(tet_march<kTetRecord>, tiles, threads, 0, stream, p);
-        if ((stages & kTetShadow) && p.total > 0) {
-            const unsigned grid = (unsigned)min((p.total + 255) / 256, (long long)65536);
-            for (int s = 0; s < p.n; ++s) {
-                p.step = s;
-                hipLaunchKernelGGL(tet_shadow_step, dim3(grid), dim3(256), 0, stream, p);
-            }
-        }
-        if (stages & kTetMarch) hipLaunchKernelGGL(tet_march<kTetMarch>, tiles, threads, 0, stream, p);
-        if (stages & kTetShaded) hipLaunchKernelGGL(tet_march<kTetShaded>, tiles, threads, 0, stream, p);
-    }
+    if (p.locator == kTetBvh)
+        launch_tet_stages<kTetBvh>(p, stages, stream);
+    else
+        launch_tet_stages<kTetGrid>(p, stages, stream);
     const long long npx = (long long)p.width * p.height;
     if (stages & kTetResolve)
         hipLaunchKernelGGL(tet_resolve, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, stream, p);

@@ -299,7 +299,10 @@ int main() {
         EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg_bad, fw, fb, frame, nullptr) == VR_ERR_INVALID_ARG);
         EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame + 1, nullptr) == VR_ERR_INVALID_ARG);
         EXPECT(vr_render_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame, nullptr) == VR_OK);
+        EXPECT(vr_set_tet_locator(ctx, (vr_tet_locator)7) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_set_tet_locator(ctx, VR_TET_BVH) == VR_OK);
         EXPECT(vr_render_tetparts(ctx, 2, tp + 1, 1, bg, fw, fb, frame, nullptr) == VR_OK);
+        EXPECT(vr_set_tet_locator(ctx, VR_TET_GRID) == VR_OK);
         EXPECT(vr_resolve_tetparts(ctx, 3, tp, 4, bg, fw, fb, frame) == VR_ERR_STATE);   // last march: other parts
         EXPECT(vr_march_tetparts(ctx, 3, tp, 4, fw, fb, nullptr) == VR_OK);
         EXPECT(vr_resolve_tetparts(ctx, 3, tp, 2, bg, fw, fb, frame) == VR_ERR_STATE);   // other max_runs

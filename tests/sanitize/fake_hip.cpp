@@ -145,6 +145,7 @@ hipError_t launch_tet_frame(TetFrameParams f, int stages, hipStream_t) {
                                 P.nbr[4LL * P.n_tets - 1];
             const long long cells = (long long)P.gdim[0] * P.gdim[1] * P.gdim[2];
             const int32_t entries = P.cell_start[cells];
+            x = x + P.bvh_nodes[7] + P.bvh_tets[P.n_tets - 1];
             if (entries > 0) x = x + P.cell_tets[entries - 1];
             (void)x;
         }

@@ -10,6 +10,7 @@
 // 1e-32.)
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <cstdio>
 #include <vector>
 
@@ -100,6 +101,28 @@ static void probe(const TetTables& tab, const int dims[3], const double p[3]) {
         for (int q = tab.cell_start[cell]; q < tab.cell_start[cell + 1]; ++q) listed = listed || tab.cell_tets[q] == first;
         EXPECT(listed);
     }
+    // the BVH walk (boxes entered when they hold p, skip links otherwise)
+    // finds the same tetrahedron
+    int found = -1, node = tab.n_tets > 0 ? 0 : -1;
+    while (node >= 0 && found < 0) {
+        const int32_t* nd = &tab.bvh_nodes[8 * (size_t)node];
+        float b[6];
+        for (int c = 0; c < 3; ++c) {
+            std::memcpy(&b[c], &nd[c], 4);
+            std::memcpy(&b[3 + c], &nd[4 + c], 4);
+        }
+        const bool in = p[0] >= b[0] && p[1] >= b[1] && p[2] >= b[2] && p[0] <= b[3] && p[1] <= b[4] && p[2] <= b[5];
+        if (!in) {
+            node = nd[3];
+        } else if (nd[7] >= 0) {
+            for (int i = 0; i < (nd[7] & 7) && found < 0; ++i)
+                if (holds(tab, tab.bvh_tets[(nd[7] >> 3) + i], p)) found = tab.bvh_tets[(nd[7] >> 3) + i];
+            node = nd[3];
+        } else {
+            node = node + 1;
+        }
+    }
+    EXPECT(found == first);
 }
 
 int main() {

@@ -358,3 +358,54 @@ def test_mixed_cells_linear_field_equals_brick():
     tf, vr, s = _tf()
     ref, _, _ = oracle.render_brick(cam, vox, cells, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), tf, vr, s, 0.27)
     assert np.max(np.abs(img - ref)) <= TOL
+
+
+# ----------------------------------------------------------- BVH locator
+def test_bvh_locator_gives_the_grid_frames_bitwise():
+    """After the walk, the BVH and the grid find the same owner for every
+    sample, so every frame (plain, shadowed, mixed cells) is bit-identical,
+    and the BVH frame matches the oracle."""
+    dp = _dp()
+    cells = (6, 5, 5)
+    vals, parts = _scene(cells, 0.2, 5, 51, rough=True)
+    cam = synth.orbit_camera((0, 0, 0), cells, 47, 39, az_deg=65.0, el_deg=-15.0, radius_factor=1.5)
+    tf, vr, s = _tf()
+    frames = {}
+    for loc in (dp.VR_TET_GRID, dp.VR_TET_BVH):
+        r = dp.TetRenderer([(pv, pt) for pv, pt, _ in parts], tf, vr, s, 0.3, locator=loc)
+        try:
+            for k, (_, _, used) in enumerate(parts):
+                r.set_values(k, vals[used])
+            r.set_camera(cam)
+            r.samples.zero_()
+            plain = r.render(count=True).clone()
+            r.synchronize()
+            held = int(r.samples.item())
+            r.shadow_plan()
+            shadowed = r.render_shadowed((0.4, 1.0, 0.3), 0.2).clone()
+            r.synchronize()
+            frames[loc] = (plain.cpu().numpy(), held, shadowed.cpu().numpy())
+        finally:
+            r.close()
+    g, b = frames[dp.VR_TET_GRID], frames[dp.VR_TET_BVH]
+    assert np.array_equal(g[0], b[0]) and g[1] == b[1] and np.array_equal(g[2], b[2])
+    ref, cnt = _ref(parts, vals, cam, 0.3, (0.0, 0.0, 0.0, 0.0))
+    assert cnt == b[1] and np.max(np.abs(b[0] - ref)) <= TOL
+    # mixed cells
+    rng = np.random.default_rng(52)
+    v, sz, cv = synth.mixed_mesh((5, 4, 4), jitter=0.1, rng=rng)
+    mvals = synth.tet_field(v, rng, (5, 4, 4))
+    mparts = synth.mixed_partitions(v, sz, cv, 3, rng)
+    mcam = synth.orbit_camera((0, 0, 0), (5, 4, 4), 33, 30, az_deg=10.0, el_deg=40.0, radius_factor=1.5)
+    imgs = []
+    for loc in (dp.VR_TET_GRID, dp.VR_TET_BVH):
+        r = dp.TetRenderer(mparts, tf, vr, s, 0.3, locator=loc)
+        try:
+            for k, part in enumerate(mparts):
+                r.set_values(k, mvals[part[-1]])
+            r.set_camera(mcam)
+            imgs.append(r.render().cpu().numpy())
+            r.synchronize()
+        finally:
+            r.close()
+    assert np.array_equal(imgs[0], imgs[1])
