@@ -18,6 +18,7 @@
 
 #include "../../include/dpvr.h"
 #include "dpvr_kernels.h"
+#include "tet_kernels.h"
 #include "tet_build.h"
 
 using namespace dpvr;

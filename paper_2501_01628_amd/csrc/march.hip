@@ -807,9 +807,13 @@ constexpr int ring_bytes() { return 144 * 1024; }
 
 template <int NCW>
 struct RingShared {
-    __align__(1024) unsigned char ring[ring_bytes<NCW>()];
+    // the table first, at LDS address 0: its reads then need no base address
     TFTable tft;
-    int tab[kTabSize];   // walk slice q: byte offset of its slot minus its rectangle's origin
+    __align__(1024) unsigned char ring[ring_bytes<NCW>()];
+    // walk slice q: tab[2 q] = LDS byte address of its slot minus its
+    // rectangle's origin, tab[2 q + 1] = the same for walk slice q + sg (the
+    // next slice along +w), so a sample reads both of its slices' entries at once
+    __align__(8) int tab[2 * kTabSize];
     __align__(16) int src[kTabSize];   // walk slice q: element offset of its rectangle's origin in the brick
     int ready;           // walk slices published by the producer
     __align__(16) int done[NCW];   // per consumer wave: walk slices below this are no longer read
@@ -1041,18 +1045,27 @@ __device__ void ring_tables(const MarchParams& p, RingShared<NCW>& sh, const Lin
     const int w_stride = W == 2 ? sny * pitch : pitch;   // elements (a brick holds < 2^31)
     const int b_stride = W == 2 ? pitch : sny * pitch;
     const int RW = G.RW, RH = G.RH, RWB = RW * 4;   // LDS rows hold float32
-    for (int q = threadIdx.x; q < G.Q; q += (NCW + 1) * 64) {
+    const int ring_off = (int)offsetof(RingShared<NCW>, ring);
+    // rectangle origin (x0, b0) of walk slice q
+    auto origin = [&](int q, int& x0, int& b0) {
         const int w = G.w_start + sg * q;
         double xlo, xhi, blo, bhi;
         slice_bounds(L, (double)w, xlo, xhi, blo, bhi);
         const double xf = fmin(fmax(floor(xlo - kMargin), 0.0), 65536.0);
         const double bf = fmin(fmax(floor(blo - kMargin), 0.0), 65536.0);
-        int x0 = ((int)xf) / V * V;
+        x0 = ((int)xf) / V * V;
         if (x0 + RW > pitch) x0 = pitch - RW;
-        int b0 = (int)bf;
+        b0 = (int)bf;
         if (b0 + RH > snb) b0 = snb - RH;
+    };
+    for (int q = threadIdx.x; q < G.Q; q += (NCW + 1) * 64) {
+        int x0, b0, x1, b1;
+        origin(q, x0, b0);
+        origin(q + sg, x1, b1);   // walk slice q + sg: past either end of the walk it is never sampled
+        const int w = G.w_start + sg * q;
         const int wl = min(max(w, 0), snw - 1);         // slices outside the brick: never sampled
-        sh.tab[q] = (q % G.R) * G.SB - b0 * RWB - x0 * 4;
+        sh.tab[2 * q] = ring_off + (q % G.R) * G.SB - b0 * RWB - x0 * 4;
+        sh.tab[2 * q + 1] = ring_off + ((q + sg) % G.R) * G.SB - b1 * RWB - x1 * 4;
         sh.src[q] = wl * w_stride + b0 * b_stride + x0;
     }
 }
@@ -1227,14 +1240,17 @@ __device__ void ring_consume(const MarchParams& p, RingShared<NCW>& sh, const Ri
     const BrickK& b = p.brick;
     const TFTable& tft = sh.tft;
     const int RWB = G.RW * ESZ;
-    const unsigned lim = (unsigned)(ring_bytes<NCW>() - RWB - 2 * ESZ);
-    const unsigned char* R8 = sh.ring;
+    // ring reads address the LDS from the start of sh (address 0), the slot
+    // bases in tab include the ring's offset
+    const unsigned lim = (unsigned)(offsetof(RingShared<NCW>, ring) + ring_bytes<NCW>() - RWB - 2 * ESZ);
+    const unsigned char* R8 = reinterpret_cast<const unsigned char*>(&sh);
     const Step st = has ? make_step(rs, b, p.dt) : Step{0.f, 0.f, 0.f};
     long long k_cur = has ? rs.kf : 0;
     bool alive = has;
     long long an_blk = kNoBlock, k_anchor = 0;
     Anchor an{};
     int qoff = 0, rbase = 0;
+    const int sgm = sg < 0 ? -1 : 0;                     // sg fw = (fw ^ sgm) - sgm for sg = +-1
     int seen = 0;                                        // last seen value of the ready word
     for (int kk = 0; kk < G.K; ++kk) {
         const long long kap = G.klo + kk;
@@ -1255,7 +1271,7 @@ __device__ void ring_consume(const MarchParams& p, RingShared<NCW>& sh, const Ri
                     an_blk = blk;
                     k_anchor = k_cur;
                     const int ia_w = W == 2 ? an.ia2 : an.ia1, ia_b = W == 2 ? an.ia1 : an.ia2;
-                    qoff = sg * (ia_w - G.w_start);
+                    qoff = sg * (ia_w - G.w_start) - sgm;
                     rbase = ia_b * RWB + an.ia0 * ESZ;
                 }
                 // stage 1: position, cell, and the two slices' table entries
@@ -1275,10 +1291,11 @@ __device__ void ring_consume(const MarchParams& p, RingShared<NCW>& sh, const Ri
                     r.c.fx = fract(x); r.c.fy = fract(y); r.c.fz = fract(z);
                     const int fx_i = floor_int(x);
                     const int fb = floor_int(W == 2 ? y : z), fw = floor_int(W == 2 ? z : y);
-                    const int q = fw * sg + qoff;
+                    const int q = (fw ^ sgm) + qoff;   // sg fw + qoff (a single xor-add)
                     r.row = __mul24(fb, RWB) + fx_i * ESZ + rbase;
-                    r.t0 = sh.tab[q & kTabMask];
-                    r.t1 = sh.tab[(q + sg) & kTabMask];
+                    const int2 tp = reinterpret_cast<const int2*>(sh.tab)[q & kTabMask];
+                    r.t0 = tp.x;
+                    r.t1 = tp.y;
                     return r;
                 };
                 // stage 2: the 8 corner reads (unsigned clamps keep every read

@@ -232,7 +232,13 @@ __device__ inline Step make_step(const RaySetup& rs, const BrickK& b, double dt)
 // floor(x) as an int, and the fraction x - floor(x) (v_fract_f32, which
 // returns the largest float below 1 where that difference would round up
 // to 1).
-__device__ inline int floor_int(float x) { return (int)floorf(x); }
+// floor to int in one instruction (v_cvt_flr_i32_f32: floor, then convert;
+// the same integer as (int)floorf(x) for every x whose floor fits an int)
+__device__ inline int floor_int(float x) {
+    int r;
+    __asm__("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
 __device__ inline float fract(float x) { return __builtin_amdgcn_fractf(x); }
 
 // Position of sample j (fj = j as float) after the anchor: base stored index

@@ -30,6 +30,7 @@
 // Locations use float64 with contraction off (the planes come from the host
 // in float64), so the owner of a sample does not depend on the launch.
 #include "march_common.h"
+#include "tet_kernels.h"
 
 namespace dpvr {
 namespace {

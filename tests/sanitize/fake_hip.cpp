@@ -11,6 +11,7 @@
 #include <cstring>
 
 #include "dpvr_kernels.h"
+#include "tet_kernels.h"
 
 namespace {
 int g_device = 0;
