@@ -100,8 +100,13 @@ __device__ inline bool march_run(const MarchParams& p, const TFTable& tft, const
 // value(G) interpolates -- with the two samples of a pair interleaved stage
 // by stage (scheduling barriers keep both samples' reads of a stage in
 // flight together): three memory round trips per pair instead of six.  The
-// arithmetic of every sample, and the order of accumulation, are those of
-// march_run, so results are bit-identical.
+// loop walks the ray's pairs (aligned to its first owned sample) that
+// overlap [j0, j1), so a run that starts or ends inside a pair takes that
+// pair too, with the sample outside the run located and read (from clamped
+// addresses) but not accumulated: no separate single-sample steps, which a
+// wavefront would otherwise take whenever any of its rays needs one.  The
+// arithmetic of every sample, the order of accumulation and the termination
+// tests are those of march_run, so results are bit-identical.
 template <typename Pre, typename Gather, typename Value>
 __device__ inline bool march_run_pipe(const TFTable& tft, const RaySetup& rs, long long kb, int j0,
                                       int j1, float tf_k, float tf_o, float eps, LaneState& s,
@@ -115,20 +120,10 @@ __device__ inline bool march_run_pipe(const TFTable& tft, const RaySetup& rs, lo
         s.C2 = fmaf(w, e.b, s.C2);
         s.T = Tn;
     };
-    auto one = [&](float fj) { return classify(tft, value(gather(pre(fj))), tf_k, tf_o); };
-    int j = j0;
-    float fj = (float)j0;
-    if (((kb + j0 - rs.kf) & 1) && j < j1) {   // second sample of a pair begun in the previous run
-        accumulate(one(fj));
-        ++j;
-        fj += 1.0f;
-        if (s.T < eps) {
-            s.evaluated += 1;
-            s.stopped = true;
-            return false;
-        }
-    }
-    for (; j + 1 < j1; j += 2, fj += 2.0f) {
+    if (j0 >= j1) return true;
+    // first sample of the pair that holds sample j0
+    for (int j = j0 - (int)((kb + j0 - rs.kf) & 1); j < j1; j += 2) {
+        const float fj = (float)j;
         const auto pa = pre(fj);
         const auto pb = pre(fj + 1.0f);
         __builtin_amdgcn_sched_barrier(0);
@@ -148,16 +143,18 @@ __device__ inline bool march_run_pipe(const TFTable& tft, const RaySetup& rs, lo
         e0.b = fmaf(ph0, d0.z, b0.z); e0.a = fmaf(ph0, d0.w, b0.w);
         e1.r = fmaf(ph1, d1.x, b1.x); e1.g = fmaf(ph1, d1.y, b1.y);
         e1.b = fmaf(ph1, d1.z, b1.z); e1.a = fmaf(ph1, d1.w, b1.w);
-        accumulate(e0);
-        accumulate(e1);
-        if (s.T < eps) {
-            s.evaluated += j - j0 + 2;
-            s.stopped = true;
-            return false;
+        if (j >= j0) accumulate(e0);
+        // the pair's second sample closes it: the termination test follows
+        // it (a run ending after the first sample leaves both to the next run)
+        if (j + 1 < j1) {
+            accumulate(e1);
+            if (s.T < eps) {
+                s.evaluated += j + 2 - j0;
+                s.stopped = true;
+                return false;
+            }
         }
     }
-    // first sample of a pair: its test comes after the next sample (next run)
-    if (j < j1) accumulate(one(fj));
     s.evaluated += j1 - j0;
     return true;
 }
