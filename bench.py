@@ -396,9 +396,10 @@ def c3_oracle(d, frame_list, pix_sets, gpu_px, target_s):
 def bench_batch(args):
     """Batched workload: 14 uneven bricks x 6 time steps x 3 fields x 4 cameras
     at 1024^2 (1008 partial images, 72 frames): the plain path (per frame,
-    one launch per brick + one composite) against the batch (one graph:
-    persistent queued march + one composite launch for all frames), for
-    float32 and float16 storage."""
+    one launch per brick + one composite) and the per-frame path (per frame,
+    one persistent launch over its 14 partials + one composite) against the
+    batch (one graph: persistent queued march + one composite launch for all
+    frames), for float32 and float16 storage."""
     import numpy as np
     import torch
 
@@ -493,8 +494,30 @@ def bench_batch(args):
         e1.record(br.stream)
         torch.cuda.synchronize()
         plain_ms = e0.elapsed_time(e1) / plain_steps
+
+        # the single-frame path a caller without the batch API takes: per
+        # frame, one persistent launch over the frame's partials + a composite
+        fneed = dp.vr_frame_workspace_size(max(len(bs) for _, bs, _, _ in frame_parts))
+        fws = torch.empty(fneed // 4 + 64, dtype=torch.float32, device="cuda")
+        fbase = fws.data_ptr() + ((-fws.data_ptr()) % 256)
+
+        def frame_pass():
+            for c, bricks, parts, outf in frame_parts:
+                dp.set_camera(ctx, d["cameras"][c])
+                dp.vr_render_partials(ctx, bricks, parts, fbase, fneed)
+                dp.vr_composite(ctx, parts, (0.0, 0.0, 0.0, 0.0), outf)
+        frame_pass()
+        torch.cuda.synchronize()
+        e0.record(br.stream)
+        for _ in range(plain_steps):
+            frame_pass()
+        e1.record(br.stream)
+        torch.cuda.synchronize()
+        per_frame_ms = e0.elapsed_time(e1) / plain_steps
+        del fws
         achieved = batch_alg / (batch_ms * 1e-3) / 1e9
-        results[storage] = {"batch_ms": batch_ms, "plain_ms": plain_ms, "samples": samples,
+        results[storage] = {"batch_ms": batch_ms, "plain_ms": plain_ms, "per_frame_launch_ms": per_frame_ms,
+                            "samples": samples,
                             "roofline": {"kernel": "batch graph (march_queue over all 1008 partials "
                                                    "+ composite_many over all 72 frames)",
                                          "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -505,8 +528,10 @@ def bench_batch(args):
                                          "tile_width": tile_w, "chunk_slices": chunk,
                                          "tuned_ms": tuned_ms},
                             "msamples_per_s": samples / (batch_ms * 1e-3) / 1e6,
-                            "speedup_vs_plain": plain_ms / batch_ms}
-        log(f"c3 {storage}: batch {batch_ms:.3f} ms, plain {plain_ms:.3f} ms, {samples} samples, "
+                            "speedup_vs_plain": plain_ms / batch_ms,
+                            "speedup_vs_per_frame_launch": per_frame_ms / batch_ms}
+        log(f"c3 {storage}: batch {batch_ms:.3f} ms, per-frame launches {per_frame_ms:.3f} ms, "
+            f"plain {plain_ms:.3f} ms, {samples} samples, "
             f"wg/cu {wg}, order {order}")
         br.close()
         torch.cuda.empty_cache()
