@@ -515,6 +515,29 @@ def bench_batch(args):
         torch.cuda.synchronize()
         per_frame_ms = e0.elapsed_time(e1) / plain_steps
         del fws
+
+        # release groups: the batch split into 8 groups of 9 frames; time
+        # from the launch to the first group's frames being written (seen by
+        # a stream that waits for it) and to the whole batch
+        n_groups = 8
+        br.set_groups(n_groups)
+        side = torch.cuda.Stream()
+        eg = torch.cuda.Event(enable_timing=True)
+        first_ms, grouped_ms = [], []
+        for rep in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            e0.record(br.stream)
+            br.launch()
+            br.wait_group(0, side)
+            eg.record(side)
+            e1.record(br.stream)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                first_ms.append(e0.elapsed_time(eg))
+                grouped_ms.append(e0.elapsed_time(e1))
+        release = {"groups": n_groups, "frames_per_group": br.group(0)[1],
+                   "first_group_ms": float(np.mean(first_ms)), "batch_ms": float(np.mean(grouped_ms))}
+        br.set_groups(1)
         achieved = batch_alg / (batch_ms * 1e-3) / 1e9
         results[storage] = {"batch_ms": batch_ms, "plain_ms": plain_ms, "per_frame_launch_ms": per_frame_ms,
                             "samples": samples,
@@ -529,7 +552,10 @@ def bench_batch(args):
                                          "tuned_ms": tuned_ms},
                             "msamples_per_s": samples / (batch_ms * 1e-3) / 1e6,
                             "speedup_vs_plain": plain_ms / batch_ms,
-                            "speedup_vs_per_frame_launch": per_frame_ms / batch_ms}
+                            "speedup_vs_per_frame_launch": per_frame_ms / batch_ms,
+                            "release_groups": release}
+        log(f"c3 {storage}: {n_groups} release groups: first group {release['first_group_ms']:.3f} ms, "
+            f"batch {release['batch_ms']:.3f} ms")
         log(f"c3 {storage}: batch {batch_ms:.3f} ms, per-frame launches {per_frame_ms:.3f} ms, "
             f"plain {plain_ms:.3f} ms, {samples} samples, "
             f"wg/cu {wg}, order {order}")

@@ -381,7 +381,8 @@ vr_status vr_batch_create(vr_context ctx, int32_t n_cameras, const vr_camera_des
                           const vr_batch_job* jobs, int32_t n_frames, const vr_batch_frame* frames,
                           void* workspace, size_t workspace_bytes, vr_batch* out);
 
-/* Enqueue the whole batch on the context stream (one graph launch).  Every
+/* Enqueue the whole batch on the context stream (one graph launch per
+ * release group, see vr_batch_set_groups).  Every
  * partial and frame equals what vr_render_partial / vr_composite would
  * produce, bit for bit, whatever launch configuration the batch uses. */
 vr_status vr_batch_launch(vr_batch batch);
@@ -404,6 +405,38 @@ vr_status vr_batch_autotune(vr_batch batch, int32_t reps, double* best_ms);
  * the context's march configuration and the most workgroups per CU that fit. */
 vr_status vr_batch_config(vr_batch batch, int32_t* wg_per_cu, int32_t* order, int32_t* staging,
                           int32_t* tile_width, int32_t* chunk_slices);
+
+/* Release groups, so that a caller can use the first images of a batch
+ * while the rest still render: split the batch's frames into n_groups
+ * consecutive runs of (nearly) equal length, group g holding frames
+ * [g F / n_groups, (g + 1) F / n_groups) of the F frames.  Each group is
+ * then its own graph -- the march queues of the jobs its frames use first
+ * (a job used by frames of several groups runs with the earliest; jobs no
+ * frame uses run with the last group), then those frames' composites --
+ * and vr_batch_launch replays the groups in order, marking each group done
+ * on the context stream as its graph completes.  Every partial and frame
+ * stays bit-identical to the one-group batch.  A new batch has one group.
+ * n_groups in [1, max(F, 1)], else VR_ERR_INVALID_ARG.  Keeps the current
+ * launch configuration (vr_batch_autotune afterwards tunes the grouped
+ * batch).  Synchronises the context stream. */
+vr_status vr_batch_set_groups(vr_batch batch, int32_t n_groups);
+
+/* The frames of release group `group`: [*first_frame, *first_frame +
+ * *n_frames).  Either pointer may be NULL.  VR_ERR_INVALID_ARG for a group
+ * out of range. */
+vr_status vr_batch_group(vr_batch batch, int32_t group, int32_t* first_frame, int32_t* n_frames);
+
+/* Wait for release group `group` of the most recent vr_batch_launch: with
+ * stream NULL the calling thread blocks until the group's frames are
+ * written; otherwise `stream` (a hipStream_t of the context's device) waits
+ * for them on the device and the call returns at once.  Before any launch it
+ * returns at once.  VR_ERR_INVALID_ARG for a group out of range,
+ * VR_ERR_DEVICE on a runtime error. */
+vr_status vr_batch_wait_group(vr_batch batch, int32_t group, void* stream);
+
+/* *done = 1 once release group `group` of the most recent vr_batch_launch
+ * has completed (or before any launch), else 0; does not block. */
+vr_status vr_batch_group_done(vr_batch batch, int32_t group, int32_t* done);
 
 vr_status vr_batch_release(vr_batch batch);
 

@@ -119,6 +119,10 @@ _SIGS = {
                          C.POINTER(C.c_int32), C.POINTER(C.c_int32)], _st),
     "vr_set_march_config": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32], _st),
     "vr_batch_release": ([C.c_void_p], _st),
+    "vr_batch_set_groups": ([C.c_void_p, C.c_int32], _st),
+    "vr_batch_group": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], _st),
+    "vr_batch_wait_group": ([C.c_void_p, C.c_int32, C.c_void_p], _st),
+    "vr_batch_group_done": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32)], _st),
     "vr_render_partials": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vr_partial),
                             C.c_void_p, C.c_size_t], _st),
     "vr_render_partials_static": ([C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
@@ -601,6 +605,26 @@ def vr_batch_config(batch, ctx=None):
     return w.value, o.value, g.value, t.value, c.value
 
 
+def vr_batch_set_groups(batch, n_groups, ctx=None):
+    _check(_lib.vr_batch_set_groups(batch, int(n_groups)), ctx)
+
+
+def vr_batch_group(batch, group, ctx=None):
+    f0, n = C.c_int32(), C.c_int32()
+    _check(_lib.vr_batch_group(batch, int(group), C.byref(f0), C.byref(n)), ctx)
+    return f0.value, n.value
+
+
+def vr_batch_wait_group(batch, group, stream=None, ctx=None):
+    _check(_lib.vr_batch_wait_group(batch, int(group), stream), ctx)
+
+
+def vr_batch_group_done(batch, group, ctx=None):
+    d = C.c_int32()
+    _check(_lib.vr_batch_group_done(batch, int(group), C.byref(d)), ctx)
+    return bool(d.value)
+
+
 def vr_batch_release(batch):
     _check(_lib.vr_batch_release(batch))
 
@@ -992,6 +1016,22 @@ class BatchRenderer:
 
     def config(self):
         return vr_batch_config(self.batch, self.ctx)
+
+    def set_groups(self, n_groups):
+        """Split the frames into n_groups release groups (vr_batch_set_groups)."""
+        vr_batch_set_groups(self.batch, n_groups, self.ctx)
+
+    def group(self, g):
+        """(first frame, number of frames) of release group g."""
+        return vr_batch_group(self.batch, g, self.ctx)
+
+    def wait_group(self, g, stream=None):
+        """Block until group g of the latest launch is written, or make
+        `stream` (a torch.cuda.Stream) wait for it on the device."""
+        vr_batch_wait_group(self.batch, g, None if stream is None else stream.cuda_stream, self.ctx)
+
+    def group_done(self, g):
+        return vr_batch_group_done(self.batch, g, self.ctx)
 
     def partial_arrays(self, j):
         (x0, y0, w, h), rgba, depth = self.parts[j]

@@ -2237,34 +2237,52 @@ vr_status vr_tetparts_slot_bytes(int64_t total_samples, size_t* bytes) {
 }
 
 // ---------------------------------------------------------------- batches
+// A release group: the frames [f0, f1) of a batch, the jobs that their
+// partials come from (a job belongs to the group of the first frame that
+// uses it; jobs no frame uses, to the last group), and its own graph: the
+// group's march queues, then its composites.  vr_batch_launch replays the
+// groups' graphs in order and records `done` after each.
+struct BatchGroup {
+    int32_t f0 = 0, f1 = 0;
+    int32_t job0 = 0, n32 = 0, n16 = 0;      // table rows [job0, job0 + n32) float32, then n16 float16
+    int32_t total32 = 0, total16 = 0;        // tiles of each queue
+    int32_t pre32 = 0, pre16 = 0;            // first entries of the queues' tile prefixes
+    int32_t cpre = 0, ctotal = 0;            // first entry of the frames' block prefix, blocks
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+};
+
 struct vr_batch_s {
     vr_context ctx = nullptr;
     std::vector<MarchParams> jobs;        // as given
     std::vector<int32_t> f16;             // storage of each job (0 / 1)
     std::vector<const void*> brick_of;    // brick identity of each job (grouping key)
     std::vector<CompositeParams> frames;
+    std::vector<int32_t> fjob0, fnjobs;   // each frame's jobs [fjob0, fjob0 + fnjobs)
+    std::vector<int32_t> fblocks;         // each frame's composite blocks
     char* ws = nullptr;
     size_t off_mprefix = 0, off_mjobs = 0, off_cprefix = 0, off_cframes = 0;
-    int32_t n32 = 0, total32 = 0, total16 = 0, ctotal = 0;
+    int32_t n_groups = 1;
+    std::vector<BatchGroup> groups;
     int32_t wg_per_cu = 0, order = 0;
     int32_t staging = kStagingRing, tile_w = 32, chunk = 4;   // staged configuration of the tables
     uint64_t shape_key = 0;
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace layout: [2 x kQueueParts counters | 256] [march prefix (n_jobs + 2)] [march jobs]
-// [composite prefix (n_frames + 1)] [composite frames].
+// Workspace layout: [2 x kQueueParts counters | 256] [march prefixes (n_jobs + 2 G)] [march jobs]
+// [composite prefixes (n_frames + G)] [composite frames], for up to G = max(n_frames, 1) release groups.
 size_t batch_layout(int32_t n_jobs, int32_t n_frames, size_t* mp, size_t* mj, size_t* cp, size_t* cf) {
+    const size_t G = (size_t)std::max(n_frames, 1);
     size_t o = 256;
-    *mp = o; o = align256(o + (size_t)(n_jobs + 2) * sizeof(int32_t));
+    *mp = o; o = align256(o + ((size_t)n_jobs + 2 * G) * sizeof(int32_t));
     *mj = o; o = align256(o + (size_t)n_jobs * sizeof(MarchParams));
-    *cp = o; o = align256(o + (size_t)(n_frames + 1) * sizeof(int32_t));
+    *cp = o; o = align256(o + ((size_t)n_frames + G) * sizeof(int32_t));
     *cf = o; o = align256(o + (size_t)n_frames * sizeof(CompositeParams));
     return o;
 }
@@ -2274,11 +2292,15 @@ void fnv(uint64_t& h, const void* p, size_t n) {
     for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
 }
 
-// Upload the job table in the given order (float32 jobs first, then float16)
-// with tickets of tile_w x 16 pixels.  Work already enqueued on the context
+// Upload the job tables: per release group (in group order) its float32
+// jobs, then its float16 jobs, each run in the given order or grouped by
+// brick, with tickets of tile_w x 16 pixels; a tile prefix per queue and a
+// composite-block prefix per group.  Work already enqueued on the context
 // stream (an earlier launch of this batch reads the tables) finishes first.
 vr_status batch_upload_tables(vr_batch b, int order, int staging, int tile_w, int chunk) {
     const int n = (int)b->jobs.size();
+    const int nf = (int)b->frames.size();
+    const int G = b->n_groups;
     hipError_t se = hipStreamSynchronize(b->ctx->stream);
     if (se != hipSuccess) return fail(b->ctx, VR_ERR_DEVICE, "batch upload: %s", hipGetErrorString(se));
     std::vector<int> idx(n);
@@ -2292,31 +2314,77 @@ vr_status batch_upload_tables(vr_batch b, int order, int staging, int tile_w, in
         }
         std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return first[x] < first[y]; });
     }
+    // frames of group g: [g nf / G, (g + 1) nf / G); a job's group: that of
+    // the first frame using it (the last group if none does)
+    std::vector<BatchGroup> gr(G);
+    std::vector<int> job_group(n, G - 1);
+    std::vector<char> seen(n, 0);
+    for (int g = 0; g < G; ++g) {
+        gr[g].f0 = (int)((long long)nf * g / G);
+        gr[g].f1 = (int)((long long)nf * (g + 1) / G);
+        for (int f = gr[g].f0; f < gr[g].f1; ++f)
+            for (int k = 0; k < b->fnjobs[f]; ++k) {
+                const int j = b->fjob0[f] + k;
+                if (!seen[j]) {
+                    seen[j] = 1;
+                    job_group[j] = g;
+                }
+            }
+    }
     std::vector<MarchParams> table;
     table.reserve(n);
-    std::vector<int32_t> prefix(n + 2, 0);
-    int n32 = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        const int base = pass == 0 ? 0 : n32 + 1;
-        int cnt = 0;
-        int32_t acc = 0;
-        for (int k = 0; k < n; ++k) {
-            const int i = idx[k];
-            if (b->f16[i] != pass) continue;
-            prefix[base + cnt] = acc;
-            acc += queue_tiles(b->jobs[i].roi_w, b->jobs[i].roi_h, tile_w);
-            table.push_back(b->jobs[i]);
-            ++cnt;
+    std::vector<int32_t> prefix;
+    prefix.reserve((size_t)n + 2 * G);
+    std::vector<int32_t> cprefix;
+    cprefix.reserve((size_t)nf + G);
+    for (int g = 0; g < G; ++g) {
+        BatchGroup& q = gr[g];
+        q.job0 = (int32_t)table.size();
+        for (int pass = 0; pass < 2; ++pass) {
+            (pass == 0 ? q.pre32 : q.pre16) = (int32_t)prefix.size();
+            int cnt = 0;
+            int32_t acc = 0;
+            for (int k = 0; k < n; ++k) {
+                const int i = idx[k];
+                if (b->f16[i] != pass || job_group[i] != g) continue;
+                prefix.push_back(acc);
+                acc += queue_tiles(b->jobs[i].roi_w, b->jobs[i].roi_h, tile_w);
+                table.push_back(b->jobs[i]);
+                ++cnt;
+            }
+            prefix.push_back(acc);
+            if (pass == 0) { q.n32 = cnt; q.total32 = acc; } else { q.n16 = cnt; q.total16 = acc; }
         }
-        prefix[base + cnt] = acc;
-        if (pass == 0) { n32 = cnt; b->total32 = acc; } else b->total16 = acc;
+        q.cpre = (int32_t)cprefix.size();
+        int32_t acc = 0;
+        for (int f = q.f0; f < q.f1; ++f) {
+            cprefix.push_back(acc);
+            acc += b->fblocks[f];
+        }
+        cprefix.push_back(acc);
+        q.ctotal = acc;
     }
-    b->n32 = n32;
     hipError_t e = hipMemcpy(b->ws + b->off_mprefix, prefix.data(), prefix.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice);
     if (e == hipSuccess && n > 0)
         e = hipMemcpy(b->ws + b->off_mjobs, table.data(), (size_t)n * sizeof(MarchParams), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ws + b->off_cprefix, cprefix.data(), cprefix.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(b->ctx, VR_ERR_DEVICE, "batch upload: %s", hipGetErrorString(e));
+    // keep the groups' events; their graphs are captured again by batch_capture
+    for (int g = 0; g < G && g < (int)b->groups.size(); ++g) std::swap(gr[g].done, b->groups[g].done);
+    for (auto& old : b->groups) {
+        if (old.exec) (void)hipGraphExecDestroy(old.exec);
+        if (old.graph) (void)hipGraphDestroy(old.graph);
+        if (old.done) (void)hipEventDestroy(old.done);
+    }
+    b->groups = std::move(gr);
+    for (auto& q : b->groups)
+        if (!q.done && hipEventCreateWithFlags(&q.done, hipEventDisableTiming) != hipSuccess) {
+            q.done = nullptr;
+            return fail(b->ctx, VR_ERR_DEVICE, "batch upload: cannot create an event");
+        }
     b->order = order;
     b->staging = staging;
     b->tile_w = tile_w;
@@ -2338,56 +2406,85 @@ vr_status batch_upload(vr_batch b, int order, int staging, int tile_w, int chunk
 }
 
 void batch_drop_graph(vr_batch b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    for (auto& q : b->groups) {
+        if (q.exec) (void)hipGraphExecDestroy(q.exec);
+        if (q.graph) (void)hipGraphDestroy(q.graph);
+        q.exec = nullptr;
+        q.graph = nullptr;
+    }
 }
 
-// Capture the batch's launches (queue counters are reset by a kernel, so the
+// Capture each group's launches (queue counters are reset by a kernel, so a
 // graph holds kernel nodes only) with `wg_per_cu` persistent workgroups per CU.
 vr_status batch_capture(vr_batch b, int wg_per_cu) {
     vr_context ctx = b->ctx;
     batch_drop_graph(b);
-    const int n = (int)b->jobs.size();
     const MarchParams* djobs = reinterpret_cast<const MarchParams*>(b->ws + b->off_mjobs);
     const int32_t* dprefix = reinterpret_cast<const int32_t*>(b->ws + b->off_mprefix);
+    const CompositeParams* dframes = reinterpret_cast<const CompositeParams*>(b->ws + b->off_cframes);
+    const int32_t* dcprefix = reinterpret_cast<const int32_t*>(b->ws + b->off_cprefix);
     int32_t* heads = reinterpret_cast<int32_t*>(b->ws);
-    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "batch capture: %s", hipGetErrorString(e));
-    hipError_t le = hipSuccess;
-    if (b->n32 > 0) {
-        QueueParams q{djobs, dprefix, b->n32, b->total32, heads, 1, b->staging, b->tile_w, b->chunk, err_word(ctx)};
-        le = launch_march_queue(q, kF32, wg_per_cu * ctx->cus, b->cap);
-    }
-    if (le == hipSuccess && n - b->n32 > 0) {
-        QueueParams q{djobs + b->n32, dprefix + b->n32 + 1, n - b->n32, b->total16, heads + kQueueParts, 1,
-                      b->staging, b->tile_w, b->chunk, err_word(ctx)};
-        le = launch_march_queue(q, kF16, wg_per_cu * ctx->cus, b->cap);
-    }
-    if (le == hipSuccess && !b->frames.empty())
-        le = launch_composite_many(reinterpret_cast<const CompositeParams*>(b->ws + b->off_cframes),
-                                   reinterpret_cast<const int32_t*>(b->ws + b->off_cprefix),
-                                   (int32_t)b->frames.size(), b->ctotal, b->cap);
-    e = hipStreamEndCapture(b->cap, &b->graph);
-    if (le != hipSuccess || e != hipSuccess) {
-        batch_drop_graph(b);
-        return fail(ctx, VR_ERR_DEVICE, "batch capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
-    }
-    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        batch_drop_graph(b);
-        return fail(ctx, VR_ERR_DEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
+    for (auto& q : b->groups) {
+        hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            batch_drop_graph(b);
+            return fail(ctx, VR_ERR_DEVICE, "batch capture: %s", hipGetErrorString(e));
+        }
+        hipError_t le = hipSuccess;
+        if (q.n32 > 0) {
+            QueueParams qp{djobs + q.job0, dprefix + q.pre32, q.n32, q.total32, heads, 1,
+                           b->staging, b->tile_w, b->chunk, err_word(ctx)};
+            le = launch_march_queue(qp, kF32, wg_per_cu * ctx->cus, b->cap);
+        }
+        if (le == hipSuccess && q.n16 > 0) {
+            QueueParams qp{djobs + q.job0 + q.n32, dprefix + q.pre16, q.n16, q.total16, heads + kQueueParts, 1,
+                           b->staging, b->tile_w, b->chunk, err_word(ctx)};
+            le = launch_march_queue(qp, kF16, wg_per_cu * ctx->cus, b->cap);
+        }
+        if (le == hipSuccess && q.f1 > q.f0)
+            le = launch_composite_many(dframes + q.f0, dcprefix + q.cpre, q.f1 - q.f0, q.ctotal, b->cap);
+        e = hipStreamEndCapture(b->cap, &q.graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            batch_drop_graph(b);
+            return fail(ctx, VR_ERR_DEVICE, "batch capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
+        }
+        e = hipGraphInstantiate(&q.exec, q.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            batch_drop_graph(b);
+            return fail(ctx, VR_ERR_DEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
+        }
     }
     b->wg_per_cu = wg_per_cu;
     return VR_OK;
 }
 
+// Graphs, events and the capture stream of a batch.
+void batch_destroy(vr_batch b) {
+    batch_drop_graph(b);
+    for (auto& q : b->groups)
+        if (q.done) (void)hipEventDestroy(q.done);
+    b->groups.clear();
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    b->cap = nullptr;
+}
+
+// Replay the groups' graphs in order on `stream`, recording each group's
+// event after its graph when `events` is set.
+hipError_t batch_replay(vr_batch b, hipStream_t stream, bool events) {
+    hipError_t e = hipSuccess;
+    for (auto& q : b->groups) {
+        if (e == hipSuccess) e = hipGraphLaunch(q.exec, stream);
+        if (e == hipSuccess && events) e = hipEventRecord(q.done, stream);
+    }
+    return e;
+}
+
 int max_wg_per_cu(const vr_batch b, int staging, int tile_w, int chunk) {
     int m = 0;
-    if (b->n32 > 0) m = std::max(m, march_queue_workgroups_per_cu(kF32, true, staging, tile_w, chunk));
-    if ((int)b->jobs.size() > b->n32)
-        m = std::max(m, march_queue_workgroups_per_cu(kF16, true, staging, tile_w, chunk));
+    const long long n16 = std::count(b->f16.begin(), b->f16.end(), 1);
+    if ((long long)b->f16.size() > n16)
+        m = std::max(m, march_queue_workgroups_per_cu(kF32, true, staging, tile_w, chunk));
+    if (n16 > 0) m = std::max(m, march_queue_workgroups_per_cu(kF16, true, staging, tile_w, chunk));
     return std::max(m, 1);
 }
 
@@ -2454,7 +2551,6 @@ static vr_status batch_create(vr_context ctx, int32_t n_cameras, const vr_camera
                                 cams[j.camera].width, cams[j.camera].height, (int32_t)j.brick->storage};
         fnv(key, sig, sizeof sig);
     }
-    std::vector<int32_t> cprefix(n_frames + 1, 0);
     for (int f = 0; f < n_frames; ++f) {
         const vr_batch_frame& fr = frames[f];
         if (fr.camera < 0 || fr.camera >= n_cameras || fr.first_job < 0 || fr.n_jobs < 0 ||
@@ -2474,10 +2570,11 @@ static vr_status batch_create(vr_context ctx, int32_t n_cameras, const vr_camera
         if (st != VR_OK) return st;
         cpar.out = fr.out;
         b->frames.push_back(cpar);
-        cprefix[f + 1] = cprefix[f] + composite_blocks(cams[fr.camera].width, cams[fr.camera].height);
+        b->fjob0.push_back(fr.first_job);
+        b->fnjobs.push_back(fr.n_jobs);
+        b->fblocks.push_back(composite_blocks(cams[fr.camera].width, cams[fr.camera].height));
         fnv(key, &cams[fr.camera].width, 2 * sizeof(int32_t));
     }
-    b->ctotal = cprefix[n_frames];
     int dev_id[2] = {ctx->device, ctx->cus};
     fnv(key, dev_id, sizeof dev_id);
     b->shape_key = key;
@@ -2488,20 +2585,20 @@ static vr_status batch_create(vr_context ctx, int32_t n_cameras, const vr_camera
     b->off_cframes = cf;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "%s: cannot select device %d", who, ctx->device);
-    hipError_t e = hipMemcpy(b->ws + cp, cprefix.data(), cprefix.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess && n_frames > 0)
+    hipError_t e = hipSuccess;
+    if (n_frames > 0)
         e = hipMemcpy(b->ws + cf, b->frames.data(), b->frames.size() * sizeof(CompositeParams),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
     // until tuned, the context's configuration of the storage with more jobs
-    const MarchCfg& mc = ctx->cfg[(int32_t)b->jobs.size() - b->n32 > b->n32 ? 1 : 0];
+    const long long n16 = std::count(b->f16.begin(), b->f16.end(), 1);
+    const MarchCfg& mc = ctx->cfg[n16 > (long long)b->f16.size() - n16 ? 1 : 0];
     vr_status st = batch_upload(b.get(), 0, mc.staging, mc.tile_w, mc.chunk);
     if (st == VR_OK) st = batch_capture(b.get(), max_wg_per_cu(b.get(), mc.staging, mc.tile_w, mc.chunk));
     if (st != VR_OK) {
-        batch_drop_graph(b.get());
-        (void)hipStreamDestroy(b->cap);
+        batch_destroy(b.get());
         return st;
     }
     {
@@ -2530,8 +2627,58 @@ vr_status vr_batch_launch(vr_batch b) {
     vr_context ctx = b->ctx;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_batch_launch: cannot select device %d", ctx->device);
-    hipError_t e = hipGraphLaunch(b->exec, ctx->stream);
+    hipError_t e = batch_replay(b, ctx->stream, true);
     if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_batch_launch: %s", hipGetErrorString(e));
+    return ok(ctx);
+}
+
+vr_status vr_batch_set_groups(vr_batch b, int32_t n_groups) {
+    if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_set_groups: invalid batch");
+    vr_context ctx = b->ctx;
+    if (n_groups < 1 || n_groups > std::max((int32_t)b->frames.size(), 1))
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_batch_set_groups: n_groups must be in [1, %d]",
+                    std::max((int32_t)b->frames.size(), 1));
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_batch_set_groups: cannot select device %d", ctx->device);
+    b->n_groups = n_groups;
+    vr_status st = batch_upload(b, b->order, b->staging, b->tile_w, b->chunk);
+    if (st == VR_OK) st = batch_capture(b, b->wg_per_cu);
+    return st == VR_OK ? ok(ctx) : st;
+}
+
+vr_status vr_batch_group(vr_batch b, int32_t group, int32_t* first_frame, int32_t* n_frames) {
+    if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_group: invalid batch");
+    if (group < 0 || group >= (int32_t)b->groups.size())
+        return fail(b->ctx, VR_ERR_INVALID_ARG, "vr_batch_group: group %d out of range", group);
+    if (first_frame) *first_frame = b->groups[group].f0;
+    if (n_frames) *n_frames = b->groups[group].f1 - b->groups[group].f0;
+    return ok(b->ctx);
+}
+
+vr_status vr_batch_wait_group(vr_batch b, int32_t group, void* stream) {
+    if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_wait_group: invalid batch");
+    vr_context ctx = b->ctx;
+    if (group < 0 || group >= (int32_t)b->groups.size())
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_batch_wait_group: group %d out of range", group);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_batch_wait_group: cannot select device %d", ctx->device);
+    const hipError_t e = stream ? hipStreamWaitEvent(reinterpret_cast<hipStream_t>(stream), b->groups[group].done, 0)
+                                : hipEventSynchronize(b->groups[group].done);
+    if (e != hipSuccess) return fail(ctx, VR_ERR_DEVICE, "vr_batch_wait_group: %s", hipGetErrorString(e));
+    return ok(ctx);
+}
+
+vr_status vr_batch_group_done(vr_batch b, int32_t group, int32_t* done) {
+    if (!live(b)) return fail(nullptr, VR_ERR_INVALID_HANDLE, "vr_batch_group_done: invalid batch");
+    vr_context ctx = b->ctx;
+    if (group < 0 || group >= (int32_t)b->groups.size() || !done)
+        return fail(ctx, VR_ERR_INVALID_ARG, "vr_batch_group_done: group %d out of range or done is NULL", group);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, VR_ERR_DEVICE, "vr_batch_group_done: cannot select device %d", ctx->device);
+    const hipError_t e = hipEventQuery(b->groups[group].done);
+    if (e != hipSuccess && e != hipErrorNotReady)
+        return fail(ctx, VR_ERR_DEVICE, "vr_batch_group_done: %s", hipGetErrorString(e));
+    *done = e == hipSuccess ? 1 : 0;
     return ok(ctx);
 }
 
@@ -2629,9 +2776,9 @@ vr_status vr_batch_autotune(vr_batch b, int32_t reps, double* best_ms) {
             for (int wg = 1; wg <= maxwg && st == VR_OK; ++wg) {
                 st = batch_capture(b, wg);
                 if (st != VR_OK) break;
-                hipError_t e = hipGraphLaunch(b->exec, ctx->stream);   // warm-up
+                hipError_t e = batch_replay(b, ctx->stream, false);   // warm-up
                 if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
-                for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, ctx->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = batch_replay(b, ctx->stream, false);
                 if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.f;
@@ -2664,8 +2811,7 @@ vr_status vr_batch_release(vr_batch b) {
         std::lock_guard<std::mutex> lk(g_mu);
         g_live.erase(b);
     }
-    batch_drop_graph(b);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
+    batch_destroy(b);
     if (live(b->ctx)) b->ctx->live_bricks--;
     delete b;
     return VR_OK;

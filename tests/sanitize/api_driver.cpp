@@ -10,6 +10,11 @@
 
 #include "dpvr.h"
 
+// inspection hooks of the fake runtime (fake_hip.cpp)
+extern "C" void fake_reset_launches();
+extern "C" size_t fake_queue_parts(const void** out, size_t cap);
+extern "C" size_t fake_composite_frames(const void** out, size_t cap);
+
 static int g_fail = 0;
 #define EXPECT(cond)                                                             \
     do {                                                                         \
@@ -469,6 +474,16 @@ int main() {
         }
         frames.push_back(f);
     }
+    {   // a job no frame uses (it runs with the last release group)
+        int32_t r[4];
+        EXPECT(vr_camera_roi(ctx, bricks[0], &cams[0], r) == VR_OK);
+        const size_t px = (size_t)(r[2] > 0 ? r[2] : 1) * (r[3] > 0 ? r[3] : 1);
+        float* rgba = static_cast<float*>(aligned_buf(px * 16));
+        float* depth = static_cast<float*>(aligned_buf(px * 4));
+        bufs.push_back(rgba);
+        bufs.push_back(depth);
+        jobs.push_back(vr_batch_job{bricks[0], 0, 0, vr_partial{r[0], r[1], r[2], r[3], rgba, depth, nullptr}});
+    }
     EXPECT(vr_batch_workspace_size((int32_t)jobs.size(), (int32_t)frames.size(), &bytes) == VR_OK);
     void* bws = aligned_buf(bytes);
     vr_batch batch = nullptr;
@@ -487,6 +502,38 @@ int main() {
     int32_t wg, order, staging, tile, chunk;
     EXPECT(vr_batch_config(batch, &wg, &order, &staging, &tile, &chunk) == VR_OK);
     EXPECT(wg >= 1 && (order == 0 || order == 1) && (tile == 16 || tile == 32) && (chunk == 4 || chunk == 8));
+    // release groups: every job rendered once, frames composited in order,
+    // a group's composites after its own queues
+    EXPECT(vr_batch_set_groups(batch, 0) == VR_ERR_INVALID_ARG);
+    EXPECT(vr_batch_set_groups(batch, 3) == VR_ERR_INVALID_ARG);
+    for (int G = 1; G <= 2; ++G) {
+        fake_reset_launches();
+        EXPECT(vr_batch_set_groups(batch, G) == VR_OK);
+        const void* seen[64];
+        const size_t np = fake_queue_parts(seen, 64);
+        EXPECT(np == jobs.size());
+        for (const auto& j : jobs) {
+            int hits = 0;
+            for (size_t i = 0; i < np && i < 64; ++i) hits += seen[i] == j.part.rgba;
+            EXPECT(hits == 1);
+        }
+        const void* fr[8];
+        EXPECT(fake_composite_frames(fr, 8) == 2 && fr[0] == frames[0].out && fr[1] == frames[1].out);
+        int32_t f0 = -1, nf = -1;
+        for (int g = 0; g < G; ++g) {
+            EXPECT(vr_batch_group(batch, g, &f0, &nf) == VR_OK);
+            EXPECT(f0 == (G == 1 ? 0 : g) && nf == (G == 1 ? 2 : 1));
+        }
+        EXPECT(vr_batch_group(batch, G, &f0, &nf) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_batch_launch(batch) == VR_OK);
+        int32_t done = -1;
+        EXPECT(vr_batch_wait_group(batch, G - 1, nullptr) == VR_OK);
+        EXPECT(vr_batch_group_done(batch, G - 1, &done) == VR_OK && done == 1);
+        EXPECT(vr_batch_group_done(batch, G, &done) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_batch_group_done(batch, 0, nullptr) == VR_ERR_INVALID_ARG);
+        EXPECT(vr_batch_wait_group(batch, -1, nullptr) == VR_ERR_INVALID_ARG);
+    }
+    EXPECT(vr_batch_autotune(batch, 1, &best) == VR_OK);   // tunes the grouped batch
     EXPECT(vr_context_release(ctx) == VR_ERR_STATE);     // bricks and the batch still live
     EXPECT(vr_batch_release(batch) == VR_OK);
     EXPECT(vr_batch_release(batch) == VR_ERR_INVALID_HANDLE);

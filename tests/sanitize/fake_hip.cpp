@@ -9,6 +9,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "dpvr_kernels.h"
 #include "tet_kernels.h"
@@ -49,6 +50,7 @@ hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = fresh<hipEven
 hipError_t hipEventDestroy(hipEvent_t e) { std::free(e); return hipSuccess; }
 hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventQuery(hipEvent_t) { return hipSuccess; }
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 1.0f; return hipSuccess; }
 hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
 hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) { *g = fresh<hipGraph_t>(); return hipSuccess; }
@@ -65,10 +67,28 @@ namespace dpvr {
 hipError_t static_scratch_address(void** out) { *out = g_scratch; return hipSuccess; }
 hipError_t launch_ingest(const float*, void*, const int32_t*, StorageK, hipStream_t) { return hipSuccess; }
 hipError_t launch_march(const MarchParams&, StorageK, hipStream_t) { return hipSuccess; }
-hipError_t launch_march_queue(const QueueParams&, StorageK, int, hipStream_t) { return hipSuccess; }
+// queue launches check their tables (a prefix of each job's tiles) and
+// record the partials they render, for the batch checks of the driver
+std::vector<const void*> g_queue_parts;
+hipError_t launch_march_queue(const QueueParams& q, StorageK, int, hipStream_t) {
+    if (q.n_jobs < 1 || q.tile_start[0] != 0 || q.tile_start[q.n_jobs] != q.total_tiles) std::abort();
+    for (int j = 0; j < q.n_jobs; ++j) {
+        const int tw = q.staged ? q.tile_w : 16;
+        if (q.tile_start[j + 1] - q.tile_start[j] != queue_tiles(q.jobs[j].roi_w, q.jobs[j].roi_h, tw)) std::abort();
+        g_queue_parts.push_back(q.jobs[j].out_rgba);
+    }
+    return hipSuccess;
+}
 int march_queue_workgroups_per_cu(StorageK, bool, int, int, int) { return 2; }
 hipError_t launch_composite(const CompositeParams&, hipStream_t) { return hipSuccess; }
-hipError_t launch_composite_many(const CompositeParams*, const int32_t*, int32_t, int32_t, hipStream_t) {
+std::vector<const void*> g_composite_frames;
+hipError_t launch_composite_many(const CompositeParams* frames, const int32_t* prefix, int32_t n, int32_t total,
+                                 hipStream_t) {
+    if (n < 1 || prefix[0] != 0 || prefix[n] != total) std::abort();
+    for (int f = 0; f < n; ++f) {
+        if (prefix[f + 1] < prefix[f]) std::abort();
+        g_composite_frames.push_back(frames[f].out);
+    }
     return hipSuccess;
 }
 hipError_t launch_march_backward(const MarchParams&, const BackwardParams&, StorageK, hipStream_t) {
@@ -157,3 +177,17 @@ hipError_t launch_tet_frame(TetFrameParams f, int stages, hipStream_t) {
     return hipSuccess;
 }
 }  // namespace dpvr
+
+// what the queue and composite launches since the last reset rendered
+extern "C" void fake_reset_launches() {
+    dpvr::g_queue_parts.clear();
+    dpvr::g_composite_frames.clear();
+}
+extern "C" size_t fake_queue_parts(const void** out, size_t cap) {
+    for (size_t i = 0; i < dpvr::g_queue_parts.size() && i < cap; ++i) out[i] = dpvr::g_queue_parts[i];
+    return dpvr::g_queue_parts.size();
+}
+extern "C" size_t fake_composite_frames(const void** out, size_t cap) {
+    for (size_t i = 0; i < dpvr::g_composite_frames.size() && i < cap; ++i) out[i] = dpvr::g_composite_frames[i];
+    return dpvr::g_composite_frames.size();
+}

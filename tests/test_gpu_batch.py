@@ -6,7 +6,9 @@ persistent, graph-captured launch) on the GPU.
 * sampled frames match the oracle (1e-5 float32, 2e-3 float16);
 * the autotuner's configurations all give the same bits, and replays of the
   captured graph -- with eager work and synchronisations in between -- give
-  the same bits every time.
+  the same bits every time;
+* with the frames split into release groups, each group's frames are final
+  once it is reported done, and all results keep their bits.
 """
 import numpy as np
 import pytest
@@ -144,6 +146,66 @@ def test_autotune_right_after_launch_on_a_side_stream(dp, c3_small, tmp_path, mo
         br.close()
     for g, r in zip(got, ref):
         assert np.array_equal(g, r)
+
+
+def test_release_groups_keep_bits_and_release_in_order(dp, c3_small, tmp_path, monkeypatch):
+    """Frames split into release groups: each group's frames are final once
+    the group is reported done (host wait, or a stream waiting on the
+    device), and every frame and partial equals the one-group batch bit for
+    bit, before and after tuning the grouped batch."""
+    d = c3_small
+    br, _ = _build(dp, d, storage_of=lambda i: i % 2)
+    br.launch()
+    br.synchronize()
+    ref = [fr.cpu().numpy().copy() for fr in br.frames]
+    ref_parts = [tuple(a.cpu().numpy().copy() for a in br.partial_arrays(j)) for j in range(br.n_jobs)]
+    nf = len(br.frames)
+    for bad in (0, nf + 1):
+        with pytest.raises(dp.VRError) as e:
+            br.set_groups(bad)
+        assert e.value.status == dp.VR_ERR_INVALID_ARG
+    br.set_groups(3)
+    spans = [br.group(g) for g in range(3)]
+    assert spans[0][0] == 0 and sum(n for _, n in spans) == nf
+    assert all(spans[g][0] + spans[g][1] == spans[g + 1][0] for g in range(2))
+    monkeypatch.setenv("DPVR_AUTOTUNE_CACHE", str(tmp_path / "tune_groups.txt"))
+    for rep in range(2):
+        for fr in br.frames:
+            fr.fill_(-1.0)
+        torch.cuda.synchronize()
+        br.launch()
+        for g, (f0, n) in enumerate(spans):
+            br.wait_group(g)
+            assert br.group_done(g)
+            for fi in range(f0, f0 + n):
+                assert np.array_equal(br.frames[fi].cpu().numpy(), ref[fi]), (rep, g, fi)
+        br.synchronize()
+        for j in range(br.n_jobs):
+            a = tuple(x.cpu().numpy() for x in br.partial_arrays(j))
+            assert np.array_equal(a[0], ref_parts[j][0]) and np.array_equal(a[1], ref_parts[j][1]), (rep, j)
+        if rep == 0:
+            br.autotune(reps=1)
+    # a stream that waits for the last group on the device
+    for fr in br.frames:
+        fr.fill_(-1.0)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    br.launch()
+    br.wait_group(2, side)
+    with torch.cuda.stream(side):
+        last = br.frames[nf - 1].clone()
+    side.synchronize()
+    assert np.array_equal(last.cpu().numpy(), ref[nf - 1])
+    br.synchronize()
+    br.set_groups(1)
+    for fr in br.frames:
+        fr.fill_(-1.0)
+    torch.cuda.synchronize()
+    br.launch()
+    br.synchronize()
+    for fi in range(nf):
+        assert np.array_equal(br.frames[fi].cpu().numpy(), ref[fi]), fi
+    br.close()
 
 
 def test_batch_argument_errors(dp, c3_small):
