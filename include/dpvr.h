@@ -323,7 +323,8 @@ vr_status vr_composite(vr_context ctx, const vr_partial* parts, int32_t n, const
  * frames composited from them, as one unit of work: one persistent march
  * launch per storage precision over a device work queue of (job, tile)
  * tickets, then one launch compositing every frame, captured once into a
- * HIP graph and replayed by vr_batch_launch.  The paper's data-parallel
+ * HIP graph and replayed by vr_batch_launch (one such graph per release
+ * group when the frames are split, see vr_batch_set_groups).  The paper's data-parallel
  * renderers queue and batch work to amortise latency (Sec. 2.2); here the
  * unit is a 16x16 tile of a partial image. */
 typedef struct vr_batch_s* vr_batch;
