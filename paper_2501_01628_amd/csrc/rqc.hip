@@ -147,9 +147,25 @@ __global__ __launch_bounds__(256) void scan_add(long long* v, long long n, const
 }
 
 // ------------------------------------------------------ one brick's samples
+// The 8 corner values of cell c, in lerp3's order.
+template <typename TS>
+__device__ inline void corners(const TS* __restrict__ vox, const Cell& c, int pitch, long long sxy, float (&v)[8]) {
+    const long long base = (long long)c.iz * sxy + (long long)c.iy * pitch + c.ix;
+    v[0] = ld(vox, base);
+    v[1] = ld(vox, base + 1);
+    v[2] = ld(vox, base + pitch);
+    v[3] = ld(vox, base + pitch + 1);
+    v[4] = ld(vox, base + sxy);
+    v[5] = ld(vox, base + sxy + 1);
+    v[6] = ld(vox, base + sxy + pitch);
+    v[7] = ld(vox, base + sxy + pitch + 1);
+}
+
 // The samples kf .. kl of ray rs in brick b, block by block as the partial
-// march takes them (same anchors, same float32 positions), each passed to
-// fn(k, value).  Returns false if fn stops the walk.
+// march takes them (same anchors, same float32 positions, same trilinear
+// arithmetic), each passed to fn(k, value); the next sample's corner loads
+// are issued before fn runs on the current one, so their latency overlaps
+// its work.  Returns false if fn stops the walk.
 template <typename TS, typename Fn>
 __device__ inline bool walk(const BrickK& b, double dt, double inv_dt, const RaySetup& rs, Fn fn) {
     const TS* __restrict__ vox = reinterpret_cast<const TS*>(b.data);
@@ -166,8 +182,19 @@ __device__ inline bool walk(const BrickK& b, double dt, double inv_dt, const Ray
         if (kend >= k) {
             const Anchor an = make_anchor(rs, b, dt, k);
             float fj = 0.0f;
-            for (long long kk = k; kk <= kend; ++kk, fj += 1.0f)
-                if (!fn(kk, trilinear(vox, locate(an, st, fj, snx, sny, snz), pitch, sxy))) return false;
+            Cell c = locate(an, st, fj, snx, sny, snz);
+            float v[8];
+            corners(vox, c, pitch, sxy, v);
+            for (long long kk = k; kk <= kend; ++kk) {
+                const Cell cur = c;
+                const float w[8] = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+                if (kk < kend) {
+                    fj += 1.0f;
+                    c = locate(an, st, fj, snx, sny, snz);
+                    corners(vox, c, pitch, sxy, v);
+                }
+                if (!fn(kk, lerp3(cur, w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]))) return false;
+            }
             k = kend + 1;
         }
         ++n;
