@@ -54,6 +54,23 @@ __device__ inline long long entry_of_slot(const RqcParams& p, long long q) {
     return lo;
 }
 
+// entry_of_slot for the active lanes of a wavefront whose slots are
+// consecutive (lane i holds the lowest active slot + i or fewer): two
+// wavefront-uniform searches bound the entries of the wavefront's slots, and
+// each lane searches only between them.
+__device__ inline long long entry_of_slot_wave(const RqcParams& p, long long q) {
+    const unsigned lo32 = __builtin_amdgcn_readfirstlane((unsigned)q);
+    const unsigned hi32 = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)q >> 32));
+    const long long q0 = (long long)(((unsigned long long)hi32 << 32) | lo32);   // the first active lane's slot
+    long long lo = entry_of_slot(p, q0);
+    long long hi = entry_of_slot(p, q0 + 63);
+    while (lo < hi) {
+        const long long mid = (lo + hi + 1) >> 1;
+        if (p.offsets[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Adds every lane's n to *counter (one atomic per wavefront); all lanes of
 // the wavefront must call it.
 __device__ inline void count_samples(unsigned long long* counter, unsigned long long n) {
@@ -214,7 +231,7 @@ __global__ __launch_bounds__(256) void rqc_shadow_step(RqcParams p) {
     unsigned long long evaluated = 0;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < p.total;
          q += (long long)gridDim.x * blockDim.x) {
-        const long long e = entry_of_slot(p, q);
+        const long long e = entry_of_slot_wave(p, q);
         const int h = brick_of_entry(p, e);
         const RqcBrick& home = p.bricks[h];
         const RqcBrick& at = p.bricks[(h + p.step) % p.n];
