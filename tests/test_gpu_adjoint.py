@@ -76,7 +76,7 @@ def _gpu_grads(dp, field, boxes, cams, tf, targets, scale, interval=64, dt=0.5, 
         img = dr.render(tft, vol, cam, BG)
         loss = ((img.double() - torch.tensor(tgt, device="cuda")) ** 2).sum()
         loss.backward()
-        L += float(loss)
+        L += float(loss.detach())
         imgs.append(img.detach().cpu().numpy())
     torch.cuda.synchronize()
     out = (L, tft.grad.cpu().numpy().astype(np.float64), vol.grad.cpu().numpy().astype(np.float64),
