@@ -312,13 +312,22 @@ __global__ __launch_bounds__(256) void tet_shadow_step(TetFrameParams f) {
     const float tf_k = 255.0f / (f.tf.vmax - f.tf.vmin);
     const float tf_o = -f.tf.vmin * tf_k;
     unsigned long long evaluated = 0;
-    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < f.total; q += (long long)gridDim.x * 256) {
-        // the slot's entry (largest e with offsets[e] <= q) and home part
-        long long elo = 0, ehi = f.n_entries - 1;
-        while (elo < ehi) {
-            const long long mid = (elo + ehi + 1) >> 1;
-            if (f.offsets[mid] <= q) elo = mid; else ehi = mid - 1;
+    // the largest e with offsets[e] <= slot (over [lo, hi])
+    auto entry_in = [&](long long slot, long long lo, long long hi) {
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) >> 1;
+            if (f.offsets[mid] <= slot) lo = mid; else hi = mid - 1;
         }
+        return lo;
+    };
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < f.total; q += (long long)gridDim.x * 256) {
+        // the slot's entry and home part; the active lanes of a wavefront
+        // hold consecutive slots from its first active lane's, so two
+        // wavefront-uniform searches bound every lane's entry
+        const unsigned q_lo = __builtin_amdgcn_readfirstlane((unsigned)q);
+        const unsigned q_hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)q >> 32));
+        const long long q0 = (long long)(((unsigned long long)q_hi << 32) | q_lo);
+        const long long elo = entry_in(q, entry_in(q0, 0, f.n_entries - 1), entry_in(q0 + 63, 0, f.n_entries - 1));
         int hlo = 0, hhi = f.n - 1;
         while (hlo < hhi) {
             const int mid = (hlo + hhi + 1) >> 1;
